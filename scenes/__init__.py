@@ -1,0 +1,407 @@
+"""Seeded synthetic inputs shared by the FP64 oracle and the HIP path.
+
+This module only *produces inputs*: G-buffer planes on an equiangular
+azimuth/elevation raster, beam steering patterns, the beam x receiver pattern
+table and the sensor parameters.  It contains none of the method's
+arithmetic (no footprint weights, no time binning, no pulse shaping, no echo
+detection); both sides of every parity test consume exactly the arrays made
+here.
+
+Raster convention (shared input format, see ``include/lidar_sim.h``):
+  * ``W x H`` pixels, row-major ``[H][W]`` float32 planes;
+  * column ``u`` covers azimuth ``[az_min + u*dphi, az_min + (u+1)*dphi)`` with
+    ``dphi = (az_max - az_min) / W`` (degrees);
+  * row ``v`` covers elevation ``[el_max - (v+1)*de, el_max - v*de)`` with
+    ``de = (el_max - el_min) / H``; row 0 is the top of the image;
+  * the unit direction of azimuth ``phi`` and elevation ``e`` in the sensor
+    frame (x forward, y left, z up) is ``(cos e cos phi, cos e sin phi, sin e)``;
+  * ``depth`` is the radial range in metres along the pixel-centre ray; sky is
+    ``+inf``; normals are unit vectors in the sensor frame.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+import math
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+
+
+@dataclass
+class Raster:
+    width: int
+    height: int
+    az_min: float
+    az_max: float
+    el_min: float
+    el_max: float
+
+    @property
+    def dphi(self) -> float:
+        return (self.az_max - self.az_min) / self.width
+
+    @property
+    def de(self) -> float:
+        return (self.el_max - self.el_min) / self.height
+
+
+@dataclass
+class GBuffer:
+    raster: Raster
+    depth: np.ndarray        # [H][W] float32, radial range (m); inf = no hit
+    reflectance: np.ndarray  # [H][W] float32, diffuse albedo rho
+    retro_gain: np.ndarray   # [H][W] float32, g (1 = not retroreflective)
+    normal: np.ndarray       # [3][H][W] float32, unit surface normal
+
+    def planes(self):
+        return (self.depth, self.reflectance, self.retro_gain,
+                self.normal[0], self.normal[1], self.normal[2])
+
+
+PATTERN_GAUSS = 1
+PATTERN_TABLE = 2
+
+
+@dataclass
+class Pattern:
+    kind: int
+    beam_az: np.ndarray                  # [B] float64, degrees
+    beam_el: np.ndarray                  # [B] float64, degrees
+    sigma_deg: tuple = (0.0, 0.0)        # GAUSS: sigma along az, el
+    trunc_sigmas: float = 3.0            # GAUSS: elliptical cut radius in sigmas
+    table: np.ndarray | None = None      # TABLE: [ny][nx] float32, row 0 = +el
+    half_deg: tuple = (0.0, 0.0)         # TABLE: half extent along az, el
+
+    @property
+    def n_beams(self) -> int:
+        return int(self.beam_az.shape[0])
+
+
+@dataclass
+class SensorParams:
+    n_bins: int
+    bin_ns: float
+    max_echoes: int
+    threshold: float
+    emit_power: float
+    pulse_fwhm_ns: float
+    pulse_trunc_sigmas: float = 4.0
+    ambient_const: float = 0.0
+    sun_irradiance: float = 0.0
+    sun_dir: tuple = (0.0, 0.0, 1.0)
+
+
+@dataclass
+class Workload:
+    name: str
+    gbuffer: GBuffer
+    pattern: Pattern
+    params: SensorParams
+    meta: dict = field(default_factory=dict)
+
+
+# ----------------------------------------------------------------------------
+# geometry helpers (input generation only)
+# ----------------------------------------------------------------------------
+
+def pixel_directions(r: Raster) -> np.ndarray:
+    """Unit pixel-centre directions, [3][H][W] float64."""
+    dphi, de = r.dphi, r.de
+    phi = np.deg2rad(r.az_min + (np.arange(r.width) + 0.5) * dphi)
+    el = np.deg2rad(r.el_max - (np.arange(r.height) + 0.5) * de)
+    ce, se = np.cos(el)[:, None], np.sin(el)[:, None]
+    cp, sp = np.cos(phi)[None, :], np.sin(phi)[None, :]
+    return np.stack([ce * cp, ce * sp, np.broadcast_to(se, (r.height, r.width))])
+
+
+def _orthonormal_basis(a: np.ndarray):
+    """Two unit vectors orthogonal to the unit vectors a ([3][...])."""
+    helper = np.zeros_like(a)
+    use_z = np.abs(a[2]) < 0.9
+    helper[2][use_z] = 1.0
+    helper[0][~use_z] = 1.0
+    t1 = np.cross(a, helper, axis=0)
+    t1 /= np.linalg.norm(t1, axis=0, keepdims=True)
+    t2 = np.cross(a, t1, axis=0)
+    return t1, t2
+
+
+# ----------------------------------------------------------------------------
+# Workload 1: uniform random G-buffer, grid of Gaussian beams
+# ----------------------------------------------------------------------------
+
+def random_gbuffer(raster: Raster, rng: np.random.Generator, depth_range=(5.0, 60.0),
+                   refl_range=(0.05, 0.9), max_tilt_deg=60.0, retro_frac=0.02,
+                   retro_gain=100.0) -> GBuffer:
+    """i.i.d. per-pixel surfaces: depth U(depth_range), reflectance U(refl_range),
+    normals uniform on the cap of half-angle ``max_tilt_deg`` around -view (so
+    cos(theta) ~ U(cos max_tilt, 1)), retroreflective with probability
+    ``retro_frac`` (gain ``retro_gain``, else 1)."""
+    H, W = raster.height, raster.width
+    depth = rng.uniform(depth_range[0], depth_range[1], size=(H, W))
+    refl = rng.uniform(refl_range[0], refl_range[1], size=(H, W))
+    cmin = math.cos(math.radians(max_tilt_deg))
+    cos_t = rng.uniform(cmin, 1.0, size=(H, W))
+    psi = rng.uniform(0.0, 2.0 * math.pi, size=(H, W))
+    retro = rng.uniform(size=(H, W)) < retro_frac
+    view = pixel_directions(raster)
+    a = -view
+    t1, t2 = _orthonormal_basis(a)
+    sin_t = np.sqrt(np.maximum(0.0, 1.0 - cos_t * cos_t))
+    n = a * cos_t + t1 * (sin_t * np.cos(psi)) + t2 * (sin_t * np.sin(psi))
+    n /= np.linalg.norm(n, axis=0, keepdims=True)
+    gain = np.where(retro, retro_gain, 1.0)
+    return GBuffer(raster, depth.astype(np.float32), refl.astype(np.float32),
+                   gain.astype(np.float32), n.astype(np.float32))
+
+
+def grid_beams(raster: Raster, n_az: int, n_el: int, az_range=None, el_range=None):
+    """Beams at the centres of an n_az x n_el grid of cells over the FOV."""
+    a0, a1 = az_range if az_range else (raster.az_min, raster.az_max)
+    e0, e1 = el_range if el_range else (raster.el_min, raster.el_max)
+    az = a0 + (np.arange(n_az) + 0.5) * ((a1 - a0) / n_az)
+    el = e0 + (np.arange(n_el) + 0.5) * ((e1 - e0) / n_el)
+    ee, aa = np.meshgrid(el, az, indexing="ij")   # line-major: [el][az]
+    return aa.ravel().astype(np.float64), ee.ravel().astype(np.float64)
+
+
+def config1(seed: int = 0) -> Workload:
+    """1024x512 px over 60x30 deg, i.i.d. surfaces, 40x25 grid of Gaussian
+    beams (sigma 0.1 deg, cut at 3 sigma), 512 bins of 1 ns, 4 ns FWHM pulse,
+    constant ambient, fixed threshold."""
+    rng = np.random.default_rng(seed)
+    raster = Raster(1024, 512, -30.0, 30.0, -15.0, 15.0)
+    gb = random_gbuffer(raster, rng)
+    az, el = grid_beams(raster, 40, 25)
+    pat = Pattern(PATTERN_GAUSS, az, el, sigma_deg=(0.1, 0.1), trunc_sigmas=3.0)
+    ambient = 1e-7
+    params = SensorParams(n_bins=512, bin_ns=1.0, max_echoes=3,
+                          threshold=ambient + 5e-6, emit_power=1.0,
+                          pulse_fwhm_ns=4.0, pulse_trunc_sigmas=4.0,
+                          ambient_const=ambient, sun_irradiance=0.0)
+    return Workload("plain-1frame-1024x512-1000beams-gauss", gb, pat, params,
+                    {"seed": seed})
+
+
+# ----------------------------------------------------------------------------
+# Workload 2: scanning sensor, road + boxes, tabulated elliptic pattern
+# ----------------------------------------------------------------------------
+
+SENSOR_HEIGHT = 0.5
+
+# Threshold and sun irradiance of the scanning-sensor workload.  T is 5 % of
+# the pulse-convolved peak return of a rho = 0.5 Lambertian face at 100 m
+# that fills the beam at normal incidence; E_sun puts the median per-beam sun
+# floor near 0.2 T.  Both literals were derived with the FP64 oracle and are
+# re-derived by the test suite (tests/test_workloads.py).
+CONFIG2_THRESHOLD = 9.345e-08
+CONFIG2_SUN_IRRADIANCE = 1.335
+
+
+def elliptic_table(nx=256, ny=256, half_deg=(2.0, 2.0), fwhm_deg=(0.1, 0.8),
+                   tail=1e-4, tail_radius_deg=2.0) -> np.ndarray:
+    """Combined beam x receiver pattern on a [ny][nx] grid of cell centres over
+    +-half_deg: elliptic Gaussian core plus a flat tail of relative level
+    ``tail`` inside a disc (blooming tails).  Row 0 is the top (+elevation)."""
+    hx, hy = half_deg
+    x = -hx + (np.arange(nx) + 0.5) * (2.0 * hx / nx)
+    y = hy - (np.arange(ny) + 0.5) * (2.0 * hy / ny)
+    sx = fwhm_deg[0] / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    sy = fwhm_deg[1] / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    yy, xx = np.meshgrid(y, x, indexing="ij")
+    core = np.exp(-0.5 * ((xx / sx) ** 2 + (yy / sy) ** 2))
+    disc = (xx * xx + yy * yy) <= tail_radius_deg ** 2
+    t = core + tail * disc
+    t[t < 1e-30] = 0.0          # no float32 denormals in the table
+    return t.astype(np.float32)
+
+
+@dataclass
+class Box:
+    center: np.ndarray   # (x, y) on the road plane, metres
+    yaw: float           # radians
+    length: float
+    width: float
+    height: float
+    rho: float
+
+
+def _ray_box(dirs, box: Box, z0: float):
+    """Ray-OBB slab intersection for rays from the origin.  Returns (t, normal)
+    with t = inf for misses.  dirs: [3][N]."""
+    c, s = math.cos(box.yaw), math.sin(box.yaw)
+    # box frame: x along length, y along width, z up; origin at box centre
+    cz = z0 + 0.5 * box.height
+    o = np.array([-box.center[0], -box.center[1], -cz])
+    o_l = np.array([c * o[0] + s * o[1], -s * o[0] + c * o[1], o[2]])
+    d_l = np.stack([c * dirs[0] + s * dirs[1], -s * dirs[0] + c * dirs[1], dirs[2]])
+    half = np.array([0.5 * box.length, 0.5 * box.width, 0.5 * box.height])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / d_l
+        t1 = (-half[:, None] - o_l[:, None]) * inv
+        t2 = (half[:, None] - o_l[:, None]) * inv
+    tmin = np.minimum(t1, t2)
+    tmax = np.maximum(t1, t2)
+    tmin = np.where(np.isnan(tmin), -np.inf, tmin)
+    tmax = np.where(np.isnan(tmax), np.inf, tmax)
+    t_near = tmin.max(axis=0)
+    t_far = tmax.min(axis=0)
+    axis = tmin.argmax(axis=0)
+    hit = (t_near <= t_far) & (t_near > 1e-6)
+    t = np.where(hit, t_near, np.inf)
+    # outward normal of the entry face, in the box frame then rotated back
+    sign = -np.sign(np.take_along_axis(d_l, axis[None, :], axis=0)[0])
+    n_l = np.zeros((3, dirs.shape[1]))
+    n_l[axis, np.arange(dirs.shape[1])] = sign
+    n = np.stack([c * n_l[0] - s * n_l[1], s * n_l[0] + c * n_l[1], n_l[2]])
+    return t, n, axis, o_l, d_l
+
+
+def road_scene(raster: Raster, rng: np.random.Generator, n_boxes=24,
+               range_lim=(5.0, 140.0), lateral_lim=(-15.0, 15.0), retro_frac=0.01,
+               retro_gain=500.0):
+    """FP64 ray cast of a road plane (SENSOR_HEIGHT below the sensor) and
+    ``n_boxes`` vehicle-like boxes standing on it (longitudinal position
+    U(range_lim), lateral U(lateral_lim), heading within +-17 deg of the road);
+    sky = inf.  Rectangular retroreflective patches (plates / signs) are added
+    on the box faces until at least ``retro_frac`` of the pixels are
+    retroreflective."""
+    H, W = raster.height, raster.width
+    dirs = pixel_directions(raster)                      # [3][H][W]
+    z0 = -SENSOR_HEIGHT
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t_road = np.where(dirs[2] < 0.0, z0 / dirs[2], np.inf)
+    depth = t_road.copy()
+    normal = np.zeros((3, H, W))
+    normal[2] = 1.0
+    obj = np.where(np.isfinite(t_road), 0, -1).astype(np.int64)
+    rho_road = rng.uniform(0.05, 0.9)
+    boxes = []
+    for i in range(n_boxes):
+        b = Box(center=np.array([rng.uniform(*range_lim), rng.uniform(*lateral_lim)]),
+                yaw=rng.uniform(-0.3, 0.3), length=rng.uniform(4.0, 12.0),
+                width=rng.uniform(1.8, 2.6), height=rng.uniform(1.4, 3.5),
+                rho=rng.uniform(0.05, 0.9))
+        boxes.append(b)
+    # cast each box only over the pixel block spanned by its corners
+    blocks = []
+    for i, b in enumerate(boxes):
+        c, s = math.cos(b.yaw), math.sin(b.yaw)
+        corners = []
+        for sl in (-0.5, 0.5):
+            for sw in (-0.5, 0.5):
+                for sh in (0.0, 1.0):
+                    x = b.center[0] + c * sl * b.length - s * sw * b.width
+                    y = b.center[1] + s * sl * b.length + c * sw * b.width
+                    corners.append((x, y, z0 + sh * b.height))
+        corners = np.array(corners)
+        if np.any(corners[:, 0] <= 0.1):
+            blocks.append(None)
+            continue
+        az = np.degrees(np.arctan2(corners[:, 1], corners[:, 0]))
+        el = np.degrees(np.arctan2(corners[:, 2], np.hypot(corners[:, 0], corners[:, 1])))
+        u0 = max(0, int(math.floor((az.min() - raster.az_min) / raster.dphi)) - 2)
+        u1 = min(W, int(math.ceil((az.max() - raster.az_min) / raster.dphi)) + 2)
+        v0 = max(0, int(math.floor((raster.el_max - el.max()) / raster.de)) - 2)
+        v1 = min(H, int(math.ceil((raster.el_max - el.min()) / raster.de)) + 2)
+        if u0 >= u1 or v0 >= v1:
+            blocks.append(None)
+            continue
+        d = dirs[:, v0:v1, u0:u1].reshape(3, -1)
+        t, n, axis, o_l, d_l = _ray_box(d, b, z0)
+        shape = (v1 - v0, u1 - u0)
+        t = t.reshape(shape)
+        cur = depth[v0:v1, u0:u1]
+        closer = t < cur
+        cur[closer] = t[closer]
+        nn = normal[:, v0:v1, u0:u1]
+        nn[:, closer] = n.reshape(3, *shape)[:, closer]
+        obj[v0:v1, u0:u1][closer] = i + 1
+        blocks.append((v0, v1, u0, u1, axis.reshape(shape), o_l, d_l.reshape(3, *shape)))
+    rho = np.where(obj == 0, rho_road, 0.0)
+    for i, b in enumerate(boxes):
+        rho = np.where(obj == i + 1, b.rho, rho)
+    gain = np.ones((H, W))
+    # retroreflective patches on box faces, in face-local coordinates
+    target = int(math.ceil(retro_frac * H * W))
+    n_retro = 0
+    visible = [i for i in range(n_boxes) if blocks[i] is not None
+               and np.any(obj[blocks[i][0]:blocks[i][1], blocks[i][2]:blocks[i][3]] == i + 1)]
+    guard = 0
+    while n_retro < target and visible and guard < 20000:
+        guard += 1
+        bi = visible[int(rng.integers(0, len(visible)))]
+        b = boxes[bi]
+        v0, v1, u0, u1, axis, o_l, d_l = blocks[bi]
+        mine = obj[v0:v1, u0:u1] == bi + 1
+        dd = depth[v0:v1, u0:u1]
+        p = o_l[:, None, None] + d_l * np.where(mine, dd, 0.0)[None]
+        side = axis[mine]
+        if not np.any(side != 2):
+            continue
+        face = int(rng.choice(side[side != 2]))
+        s_coord = p[1] if face == 0 else p[0]
+        h_coord = p[2] + 0.5 * b.height
+        face_len = b.width if face == 0 else b.length
+        pw = rng.uniform(0.3, 1.2)
+        ph = rng.uniform(0.1, 0.6)
+        s0 = rng.uniform(-0.5 * face_len, max(-0.5 * face_len, 0.5 * face_len - pw))
+        h0 = rng.uniform(0.2, max(0.25, b.height - ph - 0.1))
+        inside = mine & (axis == face) & (s_coord >= s0) & (s_coord <= s0 + pw) & \
+            (h_coord >= h0) & (h_coord <= h0 + ph)
+        g = gain[v0:v1, u0:u1]
+        newly = inside & (g == 1.0)
+        if n_retro > 0 and n_retro + int(newly.sum()) > 1.2 * target:
+            continue            # keep the retroreflective fraction near the target
+        g[newly] = retro_gain
+        n_retro += int(newly.sum())
+    gb = GBuffer(raster, depth.astype(np.float32), rho.astype(np.float32),
+                 gain.astype(np.float32), normal.astype(np.float32))
+    return gb, boxes, obj
+
+
+def config2(seed: int = 0, width: int = 8192, height: int = 512,
+            n_lines: int = 16, n_cols: int = 1800) -> Workload:
+    """Scanning sensor: 8192x512 px over 145 x 3.2 deg, road + 24 boxes, 1 %
+    retroreflective patches with gain 500, 16 x 1800 beams, tabulated 256x256
+    elliptic pattern (FWHM 0.1 x 0.8 deg, 1e-4 tails to 2 deg), 2048 bins of
+    0.5 ns, sun ambient, up to 3 echoes.  ``width``/``height``/``n_lines``/
+    ``n_cols`` shrink the same scene for quick tests (FOV unchanged)."""
+    rng = np.random.default_rng(seed)
+    raster = Raster(width, height, -72.5, 72.5, -1.6, 1.6)
+    gb, boxes, obj = road_scene(raster, rng)
+    az, el = grid_beams(raster, n_cols, n_lines)
+    pat = Pattern(PATTERN_TABLE, az, el, table=elliptic_table(),
+                  half_deg=(2.0, 2.0))
+    se, ce = math.sin(math.radians(30.0)), math.cos(math.radians(30.0))
+    sun = (ce * math.cos(math.radians(45.0)), ce * math.sin(math.radians(45.0)), se)
+    params = SensorParams(n_bins=2048, bin_ns=0.5, max_echoes=3,
+                          threshold=CONFIG2_THRESHOLD, emit_power=1.0,
+                          pulse_fwhm_ns=4.0, pulse_trunc_sigmas=4.0,
+                          ambient_const=0.0,
+                          sun_irradiance=CONFIG2_SUN_IRRADIANCE, sun_dir=sun)
+    name = f"plain-scan-{width}x{height}-{n_lines}x{n_cols}beams-table256"
+    return Workload(name, gb, pat, params, {"seed": seed, "boxes": boxes,
+                                            "object_id": obj})
+
+
+def subset_beams(w: Workload, idx) -> Workload:
+    """The same workload restricted to the beams ``idx`` (beams are independent)."""
+    idx = np.asarray(idx)
+    pat = replace(w.pattern, beam_az=w.pattern.beam_az[idx].copy(),
+                  beam_el=w.pattern.beam_el[idx].copy())
+    return replace(w, pattern=pat)
+
+
+# ----------------------------------------------------------------------------
+# small hand-built inputs for closed-form and edge-case tests
+# ----------------------------------------------------------------------------
+
+def shell_gbuffer(raster: Raster, depth_m: float, rho: float, gain: float = 1.0) -> GBuffer:
+    """Every pixel at the same radial range, facing the sensor (n = -view)."""
+    H, W = raster.height, raster.width
+    n = -pixel_directions(raster)
+    return GBuffer(raster, np.full((H, W), depth_m, np.float32),
+                   np.full((H, W), rho, np.float32),
+                   np.full((H, W), gain, np.float32), n.astype(np.float32))
