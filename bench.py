@@ -1,0 +1,153 @@
+"""Benchmark of the plain beam-iteration hot path on one MI355X.
+
+One step = one frame of the scanning-sensor workload (8192x512 G-buffer over
+145 x 3.2 deg, road plus 24 boxes, 1 % retroreflective patches of gain 500,
+16 x 1800 beams with the tabulated 256x256 elliptic pattern whose 1e-4 tails
+reach 2 deg, 2048 bins of 0.5 ns, sun floor, up to 3 echoes): the G-buffer
+pre-pass plus the fused footprint / time-bin / floor / pulse / echo kernel,
+with the G-buffer already resident in HBM.
+
+Prints one JSON line.  ``value`` is beam-pixel samples per second (in-image
+kernel cells with K > 0, summed over beams, per frame, times frames / time).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "beam-pixel samples/s + beams/s (1 GPU), surrogate vs plain at ≤1-bin range err"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+# algorithmic FP32 operations per beam-pixel sample: the weight
+# S_b * K * Omega * beta * cos(theta) / d^2 (5 multiplies) and its add into the
+# time bin; with the sun term also kappa * Omega * (rho/pi) * max(0, n.s)
+# (3 multiplies) and its add into the floor
+FLOPS_PER_SAMPLE = 6
+FLOPS_PER_SAMPLE_SUN = 4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timing (for profiler runs)")
+    ap.add_argument("--traffic", type=str, default=None,
+                    help="JSON file with per-dispatch HBM bytes of the footprint kernel")
+    return ap.parse_args()
+
+
+def cpu_baseline(w):
+    """The FP64 oracle as it stands, on the host cores: one full frame with
+    every core, plus a 1-core rate on a beam sample."""
+    import numpy as np
+    import oracle
+    cores = os.cpu_count() or 1
+    env_threads = os.environ.get("OMP_NUM_THREADS")
+    threads = int(env_threads) if env_threads and env_threads.isdigit() else cores
+    t0 = time.perf_counter()
+    res = oracle.simulate(w.gbuffer, w.pattern, w.params, want_xi=False, want_xi_hat=False,
+                          n_threads=threads)
+    dt = time.perf_counter() - t0
+    samples = float(res.samples.sum())
+    import scenes
+    sub = scenes.subset_beams(w, np.arange(0, w.pattern.n_beams, 97))
+    t1 = time.perf_counter()
+    r1 = oracle.simulate(w.gbuffer, sub.pattern, sub.params, want_xi=False, want_xi_hat=False,
+                         n_threads=1)
+    d1 = time.perf_counter() - t1
+    return {"value": samples / dt, "unit": "beam-pixel samples/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one full frame ({w.pattern.n_beams} beams, {samples:.3e} samples, "
+                      f"{dt:.2f} s) on {threads} threads",
+            "beams_per_s": w.pattern.n_beams / dt,
+            "one_core_samples_per_s": float(r1.samples.sum()) / d1,
+            "one_core_sample": f"{sub.pattern.n_beams} beams (every 97th), {d1:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the engine "
+              "has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import scenes
+    import paper_2512_05932_amd as lidar
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = scenes.config2(args.seed)
+    stream = torch.cuda.current_stream()
+    planes = lidar.upload_gbuffer(w.gbuffer, "cuda:0")
+    sim = lidar.LidarSim(w.params, stream=stream, profile=True)
+    sim.set_pattern(w.pattern)
+    sim.set_gbuffer(w.gbuffer.raster, planes)
+    for _ in range(args.warmup):
+        sim.simulate_frame()
+    torch.cuda.synchronize()
+    sim.reset_stats()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        sim.simulate_frame()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    st = sim.stats()
+    out = sim.read()
+    sim.close()
+    ms = total_ms / args.steps
+    samples = st["samples_per_frame"]
+    B = w.pattern.n_beams
+    fp_ms = st["footprint_ms"] / max(1, st["footprint_launches"])
+    sun = w.params.sun_irradiance != 0.0
+    flops = samples * (FLOPS_PER_SAMPLE + (FLOPS_PER_SAMPLE_SUN if sun else 0))
+    achieved = flops / (fp_ms * 1e-3) / 1e12
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            traffic = json.load(f).get("bytes_per_launch")
+    rec = {
+        "metric": METRIC,
+        "value": samples * args.steps / (total_ms * 1e-3),
+        "unit": "beam-pixel samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "image": "8192x512", "fov_deg": "145x3.2",
+                   "beams": B, "pattern": "table 256x256, FWHM 0.1x0.8 deg, 1e-4 tails to 2 deg",
+                   "bins": w.params.n_bins, "bin_ns": w.params.bin_ns,
+                   "max_echoes": w.params.max_echoes, "samples_per_frame": samples,
+                   "seed": args.seed},
+        "beams_per_s": B * args.steps / (total_ms * 1e-3),
+        "echoes_per_frame": int(out["n_echoes"].sum()),
+        "roofline": {"bound": "alu", "kernel": "k_footprint", "achieved": achieved,
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+                     "avg_launch_ms": fp_ms,
+                     "flops_per_launch": flops},
+        "prepass_ms": st["prepass_ms"] / max(1, st["prepass_launches"]),
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

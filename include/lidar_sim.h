@@ -1,0 +1,217 @@
+/*
+ * lidar_sim.h -- C-ABI of the MI355X (gfx950) single-bounce LiDAR engine.
+ *
+ * The engine evaluates the beam-iteration form of the single-bounce LiDAR
+ * model ("Physically-Based Simulation of Automotive LiDAR", section II,
+ * Eq. 2-5, Alg. 1): for every beam of a steering pattern it integrates a
+ * rasterised NIR G-buffer over the beam's footprint, bins the weighted returns
+ * by round-trip time, adds the ambient floor, convolves the laser pulse and
+ * thresholds the waveform into echoes with range, intensity and echo pulse
+ * width (section II-C, EPW paragraph).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns a lidar_status; nothing aborts or throws across the
+ *     ABI.  After a failure lidar_sim_last_error() describes it.
+ *   - A handle is not thread-safe; use one handle per stream.  All GPU work is
+ *     enqueued on the hipStream_t given to lidar_sim_create (passed as void*;
+ *     NULL = the default stream).
+ *   - Host inputs (pattern table, beam list) are copied at the call.  Device
+ *     G-buffer planes are borrowed: the caller keeps them alive and unchanged
+ *     until the lidar_sim_simulate_frame that reads them has completed on the
+ *     stream.
+ *   - Results live in library-owned device memory until
+ *     lidar_sim_read_echoes copies them out.
+ *
+ * Raster: an equiangular azimuth/elevation image of width W and height H
+ * (the reprojected spherical raster of section II-C).  Column u covers
+ * azimuth [az_min + u*dphi, az_min + (u+1)*dphi), dphi = (az_max-az_min)/W;
+ * row v covers elevation [el_max - (v+1)*de, el_max - v*de),
+ * de = (el_max-el_min)/H; row 0 is the top.  Angles are in degrees.  The unit
+ * direction of (az, el) in the sensor frame (x forward, y left, z up) is
+ * (cos el cos az, cos el sin az, sin el).
+ */
+#ifndef LIDAR_SIM_H
+#define LIDAR_SIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lidar_sim lidar_sim;   /* opaque, library-owned */
+
+typedef int32_t lidar_status;
+enum {
+    LIDAR_OK = 0,
+    LIDAR_E_INVALID = -1,      /* bad argument (null, out of range, non-finite) */
+    LIDAR_E_STATE = -2,        /* call out of order (e.g. simulate before set_pattern) */
+    LIDAR_E_HIP = -3,          /* a HIP runtime call failed; last_error has its text */
+    LIDAR_E_NOMEM = -4,        /* device or host allocation failed */
+    LIDAR_E_UNSUPPORTED = -5   /* valid request this build does not implement */
+};
+
+/* lidar_sim_params.flags */
+enum {
+    LIDAR_KEEP_WAVEFORMS = 1u,  /* keep xi_hat [n_beams][n_bins] for read_echoes */
+    LIDAR_PROFILE = 2u          /* time the footprint kernel with HIP events */
+};
+
+/* lidar_pattern_desc.kind */
+enum { LIDAR_PATTERN_GAUSS = 1, LIDAR_PATTERN_TABLE = 2 };
+
+/* lidar_sim_simulate_frame mode */
+enum { LIDAR_MODE_PLAIN = 0 };
+
+/* lidar_echo.flags */
+enum { LIDAR_ECHO_AT_FIRST_BIN = 1u, LIDAR_ECHO_AT_LAST_BIN = 2u };
+
+/* Sensor and receiver parameters of one handle (copied at create). */
+typedef struct {
+    uint32_t n_bins;           /* R: time bins of the waveform, 1..8192 */
+    uint32_t max_echoes;       /* echoes kept per beam, 1..8 (all are counted) */
+    double bin_ns;             /* bin width dt (ns), > 0 */
+    double threshold;          /* detection threshold T in waveform units; an echo
+                                  is a maximal run of bins with xi_hat > T */
+    double emit_power;         /* P_e: the footprint weights of a beam sum to P_e
+                                  times the shading over its whole kernel */
+    double pulse_fwhm_ns;      /* FWHM of the Gaussian pulse varpi (ns), > 0 */
+    double pulse_trunc_sigmas; /* pulse taps j with |j| <= ceil(this*sigma/dt) */
+    double ambient_const;      /* constant floor added to every bin */
+    double sun_irradiance;     /* E_sun, 0 = no sun term */
+    double sun_dir[3];         /* unit vector towards the sun, sensor frame */
+    uint32_t flags;            /* LIDAR_KEEP_WAVEFORMS | LIDAR_PROFILE */
+    uint32_t reserved;         /* must be 0 */
+} lidar_sim_params;
+
+/* Combined emitter x collector pattern (kappa*eta, Eq. 5) and the beams. */
+typedef struct {
+    uint32_t kind;             /* LIDAR_PATTERN_GAUSS or LIDAR_PATTERN_TABLE */
+    uint32_t n_beams;          /* >= 1 */
+    double sigma_deg[2];       /* GAUSS: sigma along azimuth, elevation (deg) */
+    double trunc_sigmas;       /* GAUSS: zero outside the ellipse of this radius */
+    const float* table;        /* TABLE: host [ny][nx] row-major, finite, >= 0; row 0
+                                  is +elevation; cell centres span +-half_deg; the
+                                  pattern is bilinear between cell centres and zero
+                                  outside [-half, half] */
+    uint32_t nx, ny;           /* TABLE: table size, >= 2 each */
+    double half_deg[2];        /* TABLE: half extent along azimuth, elevation */
+    const double* beam_az_deg; /* host [n_beams] beam-centre azimuths */
+    const double* beam_el_deg; /* host [n_beams] beam-centre elevations */
+} lidar_pattern_desc;
+
+/* One rendered frame: six float32 device planes [height][pitch] (borrowed). */
+typedef struct {
+    uint32_t width, height;    /* >= 1 */
+    uint64_t pitch;            /* elements between rows, >= width */
+    double az_min_deg, az_max_deg, el_min_deg, el_max_deg;   /* min < max */
+    const float* depth;        /* radial range (m) of the pixel-centre ray; a pixel
+                                  with non-finite or <= 0 depth, or beyond the last
+                                  bin, returns nothing (sky) */
+    const float* reflectance;  /* Lambertian albedo rho */
+    const float* retro_gain;   /* g: the BRDF is g*rho/pi (g = 1: diffuse) */
+    const float* normal_x;     /* unit surface normal, sensor frame */
+    const float* normal_y;
+    const float* normal_z;
+} lidar_gbuffer_desc;
+
+/* One echo (section II-C, EPW paragraph). */
+typedef struct {
+    double range_m;            /* (c/2) (bin_peak + 1/2) dt, computed in FP64 */
+    double time_ns;            /* (bin_peak + 1/2) dt */
+    float intensity;           /* xi_hat at the peak minus the floor A_b */
+    float pulse_width_ns;      /* t_down - t_up from linearly interpolated crossings
+                                  of T between bin centres (edge time at bin 0/R-1) */
+    int32_t bin_peak;          /* first bin of the run holding its maximum */
+    int32_t bin_first;         /* first bin of the run (xi_hat > T) */
+    int32_t bin_last;          /* last bin of the run */
+    uint32_t flags;            /* LIDAR_ECHO_AT_FIRST_BIN | LIDAR_ECHO_AT_LAST_BIN */
+} lidar_echo;
+
+/* Per-beam by-products of the last frame. */
+typedef struct {
+    int32_t pixel_u, pixel_v;  /* pixel containing the beam centre (floor rounding;
+                                  may lie outside the image) */
+    float scale;               /* S_b = P_e / sum_kernel K * Omega (FP64, rounded) */
+    float floor;               /* A_b = ambient_const + E_sun * sum kappa Omega
+                                  (rho/pi) max(0, n.s) over the footprint */
+    uint32_t samples;          /* kernel cells with K > 0 inside the image */
+    uint32_t reserved;
+} lidar_beam_info;
+
+/* Counters of a handle since create or the last reset_stats. */
+typedef struct {
+    uint64_t frames;           /* simulate_frame calls completed */
+    uint64_t n_beams;          /* beams of the current pattern */
+    uint64_t samples_per_frame;/* sum over beams of lidar_beam_info.samples */
+    uint32_t kernel_w, kernel_h;   /* 2M+1, 2N+1 of the current kernel grid */
+    uint32_t n_taps;           /* pulse taps 2J+1 */
+    uint32_t reserved;
+    double footprint_ms;       /* LIDAR_PROFILE: summed footprint kernel time */
+    uint64_t footprint_launches;
+    double prepass_ms;         /* LIDAR_PROFILE: summed G-buffer pre-pass time */
+    uint64_t prepass_launches;
+} lidar_stats;
+
+/* Create a handle with the given parameters on a HIP stream (void* =
+ * hipStream_t, NULL = default stream).  *out receives the handle.
+ * Errors: LIDAR_E_INVALID for null pointers or parameters out of range,
+ * LIDAR_E_HIP, LIDAR_E_NOMEM.  No handle is returned on error. */
+lidar_status lidar_sim_create(const lidar_sim_params* params, void* hip_stream,
+                              lidar_sim** out);
+
+/* Synchronise the stream and free every resource of the handle (NULL is a
+ * no-op). */
+lidar_status lidar_sim_destroy(lidar_sim* h);
+
+/* Copy a pattern and beam list (host memory) into the handle.  The centred
+ * kernel K = (kappa*eta)(Phi - Psi_b) of Eq. 5 is resampled on the pixel-offset
+ * grid of the current raster at the next simulate_frame.
+ * Errors: LIDAR_E_INVALID (null, n_beams = 0, unknown kind, sigma or half
+ * extent <= 0, non-finite or negative table values, all-zero table,
+ * non-finite beam angles), LIDAR_E_NOMEM, LIDAR_E_HIP. */
+lidar_status lidar_sim_set_pattern(lidar_sim* h, const lidar_pattern_desc* pattern);
+
+/* Record the device planes and raster of the next frame (borrowed).
+ * Errors: LIDAR_E_INVALID (null planes, zero size, pitch < width, inverted or
+ * non-finite angle ranges), LIDAR_E_NOMEM, LIDAR_E_HIP. */
+lidar_status lidar_sim_set_gbuffer(lidar_sim* h, const lidar_gbuffer_desc* gbuffer);
+
+/* Enqueue one frame on the handle's stream: kernel/normalisation set-up when
+ * the pattern or raster changed, the G-buffer pre-pass, then the fused
+ * footprint gather / time binning / ambient / pulse / echo kernel.
+ * mode: LIDAR_MODE_PLAIN.  Asynchronous.
+ * Errors: LIDAR_E_STATE (no pattern or G-buffer yet), LIDAR_E_INVALID (kernel
+ * grid too large, pattern integral <= 0 over the kernel),
+ * LIDAR_E_UNSUPPORTED (other modes), LIDAR_E_HIP. */
+lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode);
+
+/* Copy the last frame's results out.  echoes: [n_beams][max_echoes] (unused
+ * slots zeroed), n_echoes: [n_beams] runs found (may exceed max_echoes),
+ * waveforms: [n_beams][n_bins] xi_hat (needs LIDAR_KEEP_WAVEFORMS), beams:
+ * [n_beams].  Any output may be NULL.  dst_is_device != 0: the destinations
+ * are device pointers and the copies are enqueued on the stream; else they are
+ * host pointers and the call synchronises the stream.
+ * Errors: LIDAR_E_STATE (no frame simulated), LIDAR_E_INVALID (waveforms
+ * without LIDAR_KEEP_WAVEFORMS), LIDAR_E_HIP. */
+lidar_status lidar_sim_read_echoes(lidar_sim* h, lidar_echo* echoes, int32_t* n_echoes,
+                                   float* waveforms, lidar_beam_info* beams,
+                                   int dst_is_device);
+
+/* Counters since create or the last reset (synchronises profiling events).
+ * Errors: LIDAR_E_INVALID (null), LIDAR_E_HIP. */
+lidar_status lidar_sim_get_stats(lidar_sim* h, lidar_stats* out);
+
+/* Zero the frame and timing counters.  Errors: LIDAR_E_INVALID (null). */
+lidar_status lidar_sim_reset_stats(lidar_sim* h);
+
+/* Text of the last error of the handle (handle-owned; "" if none).  With a
+ * NULL handle: the last error of a failed lidar_sim_create in this thread. */
+const char* lidar_sim_last_error(const lidar_sim* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIDAR_SIM_H */

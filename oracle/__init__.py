@@ -51,8 +51,8 @@ _lib = None
 
 def build(force: bool = False) -> str:
     """Compile lidar_oracle.c with gcc (FP64, no FMA contraction, OpenMP)."""
-    from . import build as _b
-    return _b.build(force=force)
+    from . import compile as _c
+    return _c.build(force=force)
 
 
 def _load():

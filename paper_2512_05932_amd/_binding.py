@@ -1,0 +1,214 @@
+"""ctypes binding of ``liblidar_sim.so`` (argument marshalling only).
+
+The names mirror ``include/lidar_sim.h``.  Device memory comes from torch
+tensors (``data_ptr()``); every step of the model runs in the HIP kernels.
+The binding raises if the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblidar_sim.so")
+
+LIDAR_OK = 0
+LIDAR_E_INVALID = -1
+LIDAR_E_STATE = -2
+LIDAR_E_HIP = -3
+LIDAR_E_NOMEM = -4
+LIDAR_E_UNSUPPORTED = -5
+
+LIDAR_KEEP_WAVEFORMS = 1
+LIDAR_PROFILE = 2
+LIDAR_PATTERN_GAUSS = 1
+LIDAR_PATTERN_TABLE = 2
+LIDAR_MODE_PLAIN = 0
+
+# every function the header declares
+EXPORTED = ["lidar_sim_create", "lidar_sim_destroy", "lidar_sim_set_pattern",
+            "lidar_sim_set_gbuffer", "lidar_sim_simulate_frame", "lidar_sim_read_echoes",
+            "lidar_sim_get_stats", "lidar_sim_reset_stats", "lidar_sim_last_error"]
+
+
+class lidar_sim_params(C.Structure):
+    _fields_ = [("n_bins", C.c_uint32), ("max_echoes", C.c_uint32), ("bin_ns", C.c_double),
+                ("threshold", C.c_double), ("emit_power", C.c_double),
+                ("pulse_fwhm_ns", C.c_double), ("pulse_trunc_sigmas", C.c_double),
+                ("ambient_const", C.c_double), ("sun_irradiance", C.c_double),
+                ("sun_dir", C.c_double * 3), ("flags", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class lidar_pattern_desc(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("n_beams", C.c_uint32), ("sigma_deg", C.c_double * 2),
+                ("trunc_sigmas", C.c_double), ("table", C.POINTER(C.c_float)),
+                ("nx", C.c_uint32), ("ny", C.c_uint32), ("half_deg", C.c_double * 2),
+                ("beam_az_deg", C.POINTER(C.c_double)), ("beam_el_deg", C.POINTER(C.c_double))]
+
+
+class lidar_gbuffer_desc(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("pitch", C.c_uint64),
+                ("az_min_deg", C.c_double), ("az_max_deg", C.c_double),
+                ("el_min_deg", C.c_double), ("el_max_deg", C.c_double),
+                ("depth", C.c_void_p), ("reflectance", C.c_void_p), ("retro_gain", C.c_void_p),
+                ("normal_x", C.c_void_p), ("normal_y", C.c_void_p), ("normal_z", C.c_void_p)]
+
+
+class lidar_stats(C.Structure):
+    _fields_ = [("frames", C.c_uint64), ("n_beams", C.c_uint64),
+                ("samples_per_frame", C.c_uint64), ("kernel_w", C.c_uint32),
+                ("kernel_h", C.c_uint32), ("n_taps", C.c_uint32), ("reserved", C.c_uint32),
+                ("footprint_ms", C.c_double), ("footprint_launches", C.c_uint64),
+                ("prepass_ms", C.c_double), ("prepass_launches", C.c_uint64)]
+
+
+ECHO_DTYPE = np.dtype([("range_m", "<f8"), ("time_ns", "<f8"), ("intensity", "<f4"),
+                       ("pulse_width_ns", "<f4"), ("bin_peak", "<i4"), ("bin_first", "<i4"),
+                       ("bin_last", "<i4"), ("flags", "<u4")])
+BEAM_DTYPE = np.dtype([("pixel_u", "<i4"), ("pixel_v", "<i4"), ("scale", "<f4"),
+                       ("floor", "<f4"), ("samples", "<u4"), ("reserved", "<u4")])
+assert ECHO_DTYPE.itemsize == 40 and BEAM_DTYPE.itemsize == 24
+
+_lib = None
+
+
+class LidarError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"lidar_sim error {status}: {message}")
+        self.status = status
+
+
+def load():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, V = C.POINTER, C.c_void_p
+    lib.lidar_sim_create.argtypes = [P(lidar_sim_params), V, P(V)]
+    lib.lidar_sim_destroy.argtypes = [V]
+    lib.lidar_sim_set_pattern.argtypes = [V, P(lidar_pattern_desc)]
+    lib.lidar_sim_set_gbuffer.argtypes = [V, P(lidar_gbuffer_desc)]
+    lib.lidar_sim_simulate_frame.argtypes = [V, C.c_uint32]
+    lib.lidar_sim_read_echoes.argtypes = [V, V, V, V, V, C.c_int]
+    lib.lidar_sim_get_stats.argtypes = [V, P(lidar_stats)]
+    lib.lidar_sim_reset_stats.argtypes = [V]
+    lib.lidar_sim_last_error.argtypes = [V]
+    lib.lidar_sim_last_error.restype = C.c_char_p
+    for name in EXPORTED[:-1]:
+        getattr(lib, name).restype = C.c_int32
+    _lib = lib
+    return lib
+
+
+def make_params(p, flags: int = 0) -> lidar_sim_params:
+    """lidar_sim_params from any object with the fields of the C struct."""
+    return lidar_sim_params(int(p.n_bins), int(p.max_echoes), float(p.bin_ns),
+                            float(p.threshold), float(p.emit_power), float(p.pulse_fwhm_ns),
+                            float(p.pulse_trunc_sigmas), float(p.ambient_const),
+                            float(p.sun_irradiance), (C.c_double * 3)(*map(float, p.sun_dir)),
+                            int(flags), 0)
+
+
+class LidarSim:
+    """One engine handle on one HIP stream."""
+
+    def __init__(self, params, stream=None, keep_waveforms: bool = False,
+                 profile: bool = False):
+        self._lib = load()
+        self.params = params
+        flags = (LIDAR_KEEP_WAVEFORMS if keep_waveforms else 0) | \
+            (LIDAR_PROFILE if profile else 0)
+        self._prm = make_params(params, flags)
+        self._h = C.c_void_p()
+        s = C.c_void_p(stream.cuda_stream if stream is not None else 0)
+        rc = self._lib.lidar_sim_create(C.byref(self._prm), s, C.byref(self._h))
+        if rc != LIDAR_OK:
+            raise LidarError(rc, self._lib.lidar_sim_last_error(None).decode())
+        self.n_beams = 0
+        self.keep_waveforms = keep_waveforms
+        self._keep = []
+
+    def _check(self, rc):
+        if rc != LIDAR_OK:
+            raise LidarError(rc, self._lib.lidar_sim_last_error(self._h).decode())
+
+    def close(self):
+        if self._h:
+            self._lib.lidar_sim_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_pattern(self, pattern):
+        az = np.ascontiguousarray(pattern.beam_az, dtype=np.float64)
+        el = np.ascontiguousarray(pattern.beam_el, dtype=np.float64)
+        d = lidar_pattern_desc()
+        d.kind = int(pattern.kind)
+        d.n_beams = az.shape[0]
+        d.beam_az_deg = az.ctypes.data_as(C.POINTER(C.c_double))
+        d.beam_el_deg = el.ctypes.data_as(C.POINTER(C.c_double))
+        table = None
+        if pattern.kind == LIDAR_PATTERN_GAUSS:
+            d.sigma_deg = (C.c_double * 2)(*map(float, pattern.sigma_deg))
+            d.trunc_sigmas = float(pattern.trunc_sigmas)
+        else:
+            table = np.ascontiguousarray(pattern.table, dtype=np.float32)
+            d.table = table.ctypes.data_as(C.POINTER(C.c_float))
+            d.ny, d.nx = table.shape
+            d.half_deg = (C.c_double * 2)(*map(float, pattern.half_deg))
+        self._check(self._lib.lidar_sim_set_pattern(self._h, C.byref(d)))
+        self.n_beams = d.n_beams
+
+    def set_gbuffer(self, raster, planes, pitch: int | None = None):
+        """planes: (depth, reflectance, retro_gain, normal_x, normal_y, normal_z),
+        float32 device tensors [H][pitch] (kept alive by this object until the
+        next call)."""
+        ptrs = [int(t.data_ptr()) for t in planes]
+        d = lidar_gbuffer_desc(int(raster.width), int(raster.height),
+                               int(pitch if pitch is not None else raster.width),
+                               float(raster.az_min), float(raster.az_max),
+                               float(raster.el_min), float(raster.el_max), *ptrs)
+        self._check(self._lib.lidar_sim_set_gbuffer(self._h, C.byref(d)))
+        self._keep = list(planes)
+
+    def simulate_frame(self, mode: int = LIDAR_MODE_PLAIN):
+        self._check(self._lib.lidar_sim_simulate_frame(self._h, int(mode)))
+
+    def read(self, waveforms: bool = False, beams: bool = True):
+        """Copy the last frame's results to host numpy arrays (synchronises)."""
+        B, E, R = self.n_beams, int(self.params.max_echoes), int(self.params.n_bins)
+        ech = np.zeros((B, E), dtype=ECHO_DTYPE)
+        cnt = np.zeros(B, dtype=np.int32)
+        wav = np.zeros((B, R), dtype=np.float32) if waveforms else None
+        bi = np.zeros(B, dtype=BEAM_DTYPE) if beams else None
+        self._check(self._lib.lidar_sim_read_echoes(
+            self._h, ech.ctypes.data, cnt.ctypes.data,
+            wav.ctypes.data if wav is not None else None,
+            bi.ctypes.data if bi is not None else None, 0))
+        return {"echoes": ech, "n_echoes": cnt, "waveforms": wav, "beams": bi}
+
+    def read_device(self, echoes=None, n_echoes=None, waveforms=None, beams=None):
+        """Enqueue device-to-device copies into torch tensors (no sync)."""
+        p = lambda t: int(t.data_ptr()) if t is not None else None
+        self._check(self._lib.lidar_sim_read_echoes(self._h, p(echoes), p(n_echoes),
+                                                    p(waveforms), p(beams), 1))
+
+    def stats(self) -> dict:
+        s = lidar_stats()
+        self._check(self._lib.lidar_sim_get_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in s._fields_ if f != "reserved"}
+
+    def reset_stats(self):
+        self._check(self._lib.lidar_sim_reset_stats(self._h))
+
+    def last_error(self) -> str:
+        return self._lib.lidar_sim_last_error(self._h).decode()

@@ -1,0 +1,94 @@
+// Internal declarations of the gfx950 LiDAR engine (kernels and launchers).
+// Only the library's own translation units include this file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "../../include/lidar_sim.h"
+
+namespace lidar {
+
+constexpr double kLight = 299792458.0;          // m/s
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr int kMaxBins = 8000;                  // 2 waveforms of R floats + taps in 64 KiB LDS
+constexpr int kMaxTaps = 257;
+constexpr int kFootprintThreads = 256;          // 4 waves of 64
+constexpr int kXcds = 8;                        // MI355X: 8 XCDs, round-robin dispatch
+
+// Pattern as the set-up kernels see it (device copy of the table).
+struct PatternDev {
+    int kind;                   // LIDAR_PATTERN_GAUSS / LIDAR_PATTERN_TABLE
+    double sx, sy, trunc;       // Gaussian sigma (deg), cut radius (sigmas)
+    const float* table;         // [ny][nx]
+    int nx, ny;
+    double hx, hy;              // table half extents (deg)
+};
+
+// Raster geometry in FP64 (degrees).
+struct RasterDev {
+    int W, H;
+    double az_min, el_max;
+    double dphi, de;
+};
+
+// Kernel grid geometry: offsets m in [-M, M] (columns), n in [-N, N] (rows).
+struct KernelDev {
+    int M, N, KW, KH;
+};
+
+// ---- set-up (FP64 resample of the pattern and per-beam normalisation) ----
+hipError_t launch_kernel_grid(hipStream_t s, PatternDev p, RasterDev r, KernelDev k,
+                              double* K64, float* Kt);
+hipError_t launch_kernel_rows(hipStream_t s, KernelDev k, const double* K64, double* rowsum,
+                              double* rowmax, int2* rowrange, int32_t* prefix);
+hipError_t launch_kernel_peak(hipStream_t s, KernelDev k, const double* rowsum,
+                              const double* rowmax, double* kinfo);
+hipError_t launch_raster_tables(hipStream_t s, RasterDev r, float2* colcs, float4* rowtab);
+hipError_t launch_beam_setup(hipStream_t s, RasterDev r, KernelDev k, const double* az,
+                             const double* el, int B, const double* rowsum,
+                             const int32_t* prefix, double emit_power, lidar_beam_info* beams);
+hipError_t launch_pulse_taps(hipStream_t s, float sigma_ns, float bin_ns, int J, float* taps);
+
+// ---- per frame ----
+struct PrepassArgs {
+    const float *depth, *refl, *gain, *nx, *ny, *nz;
+    long pitch;
+    int W, H;
+    const float2* colcs;        // [W] (cos az, sin az) of pixel centres
+    const float4* rowtab;       // [H] (cos el, sin el, Omega, 0) of pixel rows
+    double to_bin;              // 2 / (c dt), FP64
+    int R;
+    float sun_x, sun_y, sun_z;
+    int2* pix;                  // [W][H] {bin, shade bits}, column-major
+    float* sun;                 // [W][H] sun shading, column-major (or null)
+};
+hipError_t launch_prepass(hipStream_t s, const PrepassArgs& a, bool with_sun);
+
+struct FootprintArgs {
+    const int2* pix;            // [W][H]
+    const float* sun;           // [W][H] or null
+    int W, H;
+    const float* Kt;            // [KW][KH]: K(m, n) at (m+M)*KH + n+N
+    const int2* rowrange;       // [KH] first/last m with K > 0 (empty row: INT_MAX, INT_MIN)
+    int M, N, KH;
+    const int32_t* order;       // [B] beam schedule (spatially sorted)
+    int B, chunk;               // chunk = ceil(B / kXcds)
+    lidar_beam_info* beams;     // [B] in: pixel, scale; out: floor
+    const float* taps;          // [2J+1]
+    int J;
+    int R;
+    float threshold;
+    float ambient;
+    float sun_scale;            // E_sun / max K (0: no sun term)
+    int E;
+    lidar_echo* echoes;         // [B][E]
+    int32_t* counts;            // [B]
+    float* waves;               // [B][R] or null
+    double half_c_dt;           // (c/2) dt in metres, FP64
+    double bin_ns;
+};
+hipError_t launch_footprint(hipStream_t s, const FootprintArgs& a);
+
+}  // namespace lidar

@@ -1,0 +1,248 @@
+// Set-up kernels, run once per (pattern, raster): resample the combined
+// emitter x collector pattern onto the pixel-offset grid (Eq. 5's centred
+// kernel kappa*eta, Alg. 1 input of size (2M+1) x (2N+1)), reduce it per row,
+// and compute every beam's containing pixel and normalisation in FP64.
+//
+// Floating-point contraction is off in this file: every FP64 decision that
+// selects an integer (beam pixel, kernel support) uses plain IEEE operations
+// in the order written.
+#pragma clang fp contract(off)
+
+#include <climits>
+
+#include "engine.h"
+
+namespace lidar {
+
+// Pattern value at an angular offset (x along azimuth, y along elevation, deg)
+// from the beam centre.  Gaussian: exp(-q/2) inside the ellipse q <= trunc^2.
+// Table: zero outside [-hx, hx] x [-hy, hy]; inside, bilinear between cell
+// centres (row 0 = +elevation) with zero beyond the outermost centres.
+__device__ static double pattern_at(const PatternDev& p, double x, double y)
+{
+    if (p.kind == LIDAR_PATTERN_GAUSS) {
+        double a = x / p.sx;
+        double b = y / p.sy;
+        double q = a * a + b * b;
+        return q > p.trunc * p.trunc ? 0.0 : exp(-0.5 * q);
+    }
+    if (fabs(x) > p.hx || fabs(y) > p.hy) return 0.0;
+    double cx = 2.0 * p.hx / (double)p.nx;
+    double cy = 2.0 * p.hy / (double)p.ny;
+    double fx = (x + p.hx) / cx - 0.5;
+    double fy = (p.hy - y) / cy - 0.5;
+    double ix = floor(fx);
+    double iy = floor(fy);
+    double tx = fx - ix;
+    double ty = fy - iy;
+    int i = (int)ix, j = (int)iy;
+    auto at = [&](int ii, int jj) -> double {
+        return (ii < 0 || jj < 0 || ii >= p.nx || jj >= p.ny)
+                   ? 0.0 : (double)p.table[(long)jj * p.nx + ii];
+    };
+    double top = (1.0 - tx) * at(i, j) + tx * at(i + 1, j);
+    double bot = (1.0 - tx) * at(i, j + 1) + tx * at(i + 1, j + 1);
+    return (1.0 - ty) * top + ty * bot;
+}
+
+// Solid angle of a pixel of row v (any integer v): dphi (sin e_top - sin e_bot).
+__device__ static double row_omega(const RasterDev& r, long v)
+{
+    const double d2r = kPi / 180.0;
+    double e_top = r.el_max - (double)v * r.de;
+    double e_bot = r.el_max - (double)(v + 1) * r.de;
+    return (r.dphi * d2r) * (sin(e_top * d2r) - sin(e_bot * d2r));
+}
+
+// K64[n+N][m+M] (row-major, FP64) and Kt[m+M][n+N] (column-major, FP32).
+__global__ void k_kernel_grid(PatternDev p, RasterDev r, KernelDev k, double* K64, float* Kt)
+{
+    long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long total = (long)k.KW * k.KH;
+    if (idx >= total) return;
+    int row = (int)(idx / k.KW), col = (int)(idx % k.KW);
+    int n = row - k.N, m = col - k.M;
+    double v = pattern_at(p, (double)m * r.dphi, -(double)n * r.de);
+    K64[idx] = v;
+    Kt[(long)col * k.KH + row] = (float)v;
+}
+
+// Per kernel row: FP64 sum, max, first/last non-zero column offset, and the
+// prefix counts of non-zero cells (prefix[row][c] = non-zero cells in
+// columns [0, c) of the row).
+__global__ void k_kernel_rows(KernelDev k, const double* K64, double* rowsum, double* rowmax,
+                              int2* rowrange, int32_t* prefix)
+{
+    int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= k.KH) return;
+    const double* kr = K64 + (long)row * k.KW;
+    int32_t* pr = prefix + (long)row * (k.KW + 1);
+    double s = 0.0, mx = 0.0;
+    int lo = k.KW, hi = -1, cnt = 0;
+    pr[0] = 0;
+    for (int c = 0; c < k.KW; ++c) {
+        double v = kr[c];
+        s += v;
+        if (v > mx) mx = v;
+        if (v > 0.0) {
+            if (c < lo) lo = c;
+            hi = c;
+            ++cnt;
+        }
+        pr[c + 1] = cnt;
+    }
+    rowsum[row] = s;
+    rowmax[row] = mx;
+    rowrange[row] = hi < 0 ? make_int2(INT_MAX, INT_MIN) : make_int2(lo - k.M, hi - k.M);
+}
+
+// kinfo[0] = max K, kinfo[1] = sum K over the grid (one block).
+__global__ void k_kernel_peak(KernelDev k, const double* rowsum, const double* rowmax,
+                              double* kinfo)
+{
+    __shared__ double smax[256], ssum[256];
+    double mx = 0.0, s = 0.0;
+    for (int i = threadIdx.x; i < k.KH; i += blockDim.x) {
+        mx = fmax(mx, rowmax[i]);
+        s += rowsum[i];
+    }
+    smax[threadIdx.x] = mx;
+    ssum[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
+            ssum[threadIdx.x] += ssum[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        kinfo[0] = smax[0];
+        kinfo[1] = ssum[0];
+    }
+}
+
+// Pixel-centre direction tables: colcs[u] = (cos az_u, sin az_u),
+// rowtab[v] = (cos el_v, sin el_v, Omega_v, 0).  The solid angle is FP64
+// (same integral as the normalisation) and stored in FP32.
+__global__ void k_raster_tables(RasterDev r, float2* colcs, float4* rowtab)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const float d2r = (float)(kPi / 180.0);
+    if (i < r.W) {
+        float a = (float)(r.az_min + ((double)i + 0.5) * r.dphi) * d2r;
+        float sa, ca;
+        sincosf(a, &sa, &ca);
+        colcs[i] = make_float2(ca, sa);
+    }
+    if (i < r.H) {
+        float e = (float)(r.el_max - ((double)i + 0.5) * r.de) * d2r;
+        float se, ce;
+        sincosf(e, &se, &ce);
+        rowtab[i] = make_float4(ce, se, (float)row_omega(r, i), 0.0f);
+    }
+}
+
+// Per beam: containing pixel (floor rounding), FP64 normalisation over every
+// kernel cell (on- and off-image rows), scale S_b = P_e / N_b, and the number
+// of non-zero kernel cells inside the image.
+__global__ void k_beam_setup(RasterDev r, KernelDev k, const double* az, const double* el,
+                             int B, const double* rowsum, const int32_t* prefix,
+                             double emit_power, lidar_beam_info* beams)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double fu = floor((az[b] - r.az_min) / r.dphi);
+    double fv = floor((r.el_max - el[b]) / r.de);
+    // beams far outside the image keep an empty footprint
+    const double lim = 1073741824.0;
+    fu = fmin(fmax(fu, -lim), lim);
+    fv = fmin(fmax(fv, -lim), lim);
+    long ub = (long)fu, vb = (long)fv;
+    double nb = 0.0;
+    for (int n = -k.N; n <= k.N; ++n) nb += rowsum[n + k.N] * row_omega(r, vb + n);
+    uint32_t samples = 0;
+    long c_lo = (long)-k.M > -ub ? (long)-k.M : -ub;
+    long c_hi = (long)k.M < (long)r.W - 1 - ub ? (long)k.M : (long)r.W - 1 - ub;
+    if (c_lo <= c_hi) {
+        for (int n = -k.N; n <= k.N; ++n) {
+            long v = vb + n;
+            if (v < 0 || v >= r.H) continue;
+            const int32_t* pr = prefix + (long)(n + k.N) * (k.KW + 1);
+            samples += (uint32_t)(pr[c_hi + k.M + 1] - pr[c_lo + k.M]);
+        }
+    }
+    lidar_beam_info bi;
+    bi.pixel_u = (int32_t)ub;
+    bi.pixel_v = (int32_t)vb;
+    bi.scale = (float)(emit_power / nb);
+    bi.floor = 0.0f;
+    bi.samples = samples;
+    bi.reserved = 0;
+    beams[b] = bi;
+}
+
+// Centred Gaussian pulse sampled at the bin pitch, unit sum (FP32).
+__global__ void k_pulse_taps(float sigma_ns, float bin_ns, int J, float* taps)
+{
+    __shared__ float w[kMaxTaps];
+    int j = threadIdx.x;
+    if (j <= 2 * J) {
+        float t = (float)(j - J) * bin_ns;
+        w[j] = expf(-(t * t) / (2.0f * sigma_ns * sigma_ns));
+    }
+    __syncthreads();
+    if (j <= 2 * J) {
+        float s = 0.0f;
+        for (int i = 0; i <= 2 * J; ++i) s += w[i];
+        taps[j] = w[j] / s;
+    }
+}
+
+hipError_t launch_kernel_grid(hipStream_t s, PatternDev p, RasterDev r, KernelDev k,
+                              double* K64, float* Kt)
+{
+    long total = (long)k.KW * k.KH;
+    int blocks = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(k_kernel_grid, dim3(blocks), dim3(256), 0, s, p, r, k, K64, Kt);
+    return hipGetLastError();
+}
+
+hipError_t launch_kernel_rows(hipStream_t s, KernelDev k, const double* K64, double* rowsum,
+                              double* rowmax, int2* rowrange, int32_t* prefix)
+{
+    hipLaunchKernelGGL(k_kernel_rows, dim3((k.KH + 63) / 64), dim3(64), 0, s, k, K64, rowsum,
+                       rowmax, rowrange, prefix);
+    return hipGetLastError();
+}
+
+hipError_t launch_kernel_peak(hipStream_t s, KernelDev k, const double* rowsum,
+                              const double* rowmax, double* kinfo)
+{
+    hipLaunchKernelGGL(k_kernel_peak, dim3(1), dim3(256), 0, s, k, rowsum, rowmax, kinfo);
+    return hipGetLastError();
+}
+
+hipError_t launch_raster_tables(hipStream_t s, RasterDev r, float2* colcs, float4* rowtab)
+{
+    int n = r.W > r.H ? r.W : r.H;
+    hipLaunchKernelGGL(k_raster_tables, dim3((n + 255) / 256), dim3(256), 0, s, r, colcs, rowtab);
+    return hipGetLastError();
+}
+
+hipError_t launch_beam_setup(hipStream_t s, RasterDev r, KernelDev k, const double* az,
+                             const double* el, int B, const double* rowsum,
+                             const int32_t* prefix, double emit_power, lidar_beam_info* beams)
+{
+    hipLaunchKernelGGL(k_beam_setup, dim3((B + 127) / 128), dim3(128), 0, s, r, k, az, el, B,
+                       rowsum, prefix, emit_power, beams);
+    return hipGetLastError();
+}
+
+hipError_t launch_pulse_taps(hipStream_t s, float sigma_ns, float bin_ns, int J, float* taps)
+{
+    hipLaunchKernelGGL(k_pulse_taps, dim3(1), dim3(kMaxTaps), 0, s, sigma_ns, bin_ns, J, taps);
+    return hipGetLastError();
+}
+
+}  // namespace lidar
