@@ -43,7 +43,22 @@ def parse():
                     help="skip the oracle timing (for profiler runs)")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with per-dispatch HBM bytes of the footprint kernel")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times) and exit: the "
+                         "reference for scaling the HBM byte counters")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
 
 
 def cpu_baseline(w):
@@ -80,6 +95,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the engine "
               "has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
     import scenes

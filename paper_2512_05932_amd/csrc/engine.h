@@ -73,8 +73,8 @@ struct FootprintArgs {
     const float* Kt;            // [KW][KH]: K(m, n) at (m+M)*KH + n+N
     const int2* rowrange;       // [KH] first/last m with K > 0 (empty row: INT_MAX, INT_MIN)
     int M, N, KH;
-    const int32_t* order;       // [B] beam schedule (spatially sorted)
-    int B, chunk;               // chunk = ceil(B / kXcds)
+    const int32_t* groups;      // [n_groups][G] beam indices, -1 = empty slot
+    int n_groups, G, chunk;     // chunk = ceil(n_groups / kXcds)
     lidar_beam_info* beams;     // [B] in: pixel, scale; out: floor
     const float* taps;          // [2J+1]
     int J;
@@ -90,5 +90,7 @@ struct FootprintArgs {
     double bin_ns;
 };
 hipError_t launch_footprint(hipStream_t s, const FootprintArgs& a);
+// whether G histograms of R bins plus the pulse taps fit the LDS budget
+bool footprint_group_fits(int G, int R, int J);
 
 }  // namespace lidar

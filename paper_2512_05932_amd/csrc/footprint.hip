@@ -1,19 +1,30 @@
-// Fused per-beam kernel: footprint gather -> time-bin histogram in LDS ->
-// ambient floor -> pulse convolution -> wavefront-ballot echo detection.
+// Fused kernel for a group of G nearby beams: footprint gather -> per-beam
+// time-bin histograms in LDS -> ambient floor -> pulse convolution ->
+// wavefront-ballot echo detection.
 //
-// One workgroup (4 waves of 64) per beam.  The beam's footprint (the kernel
-// window of Eq. 5 / Alg. 1, clipped to the image) is cut into strips of 64
-// kernel rows; in a strip every lane owns one row and the wave walks the
-// strip's columns together, so each step reads 64 consecutive entries of the
-// column-major kernel and pixel records (one coalesced load each).  A lane
-// keeps a run accumulator (bin, sum) and only touches the LDS histogram when
-// the time bin of its row changes: surfaces that are smooth along azimuth
-// (road rows, box faces) collapse many samples into one LDS atomic, and the
-// sky costs no atomics at all.
+// Work decomposition.  One workgroup (4 waves of 64) takes a group of up to
+// G beams (formed by the host scheduler from beams that are close on the
+// raster).  The union of their footprints (kernel windows of Eq. 5 / Alg. 1,
+// clipped to the image) is cut into strips of 64 image rows; in a strip every
+// lane owns one row and the wave walks the strip's columns together, so each
+// step reads 64 consecutive column-major pixel records and, per beam, 64
+// consecutive kernel values (coalesced loads).  A pixel's time bin does not
+// depend on the beam, so the pixel record, its bin comparison and the sun
+// shading are shared by the G beams; only the kernel value and one FMA are
+// per beam.
 //
-// The histogram holds sum K * shade; the beam scale S_b is applied once in
-// the pulse convolution.  Echoes are maximal runs of xi_hat > T found with
-// 64-bin ballots (section II-C, EPW paragraph).
+// Run accumulation.  A lane sums the weights of consecutive pixels of its row
+// that fall into the same bin in registers (one sum per beam) and adds them
+// to the LDS histograms when the bin changes.  Rows that cross the same
+// surface change bin at the same column, so the lanes that flush usually
+// share their bin: they are reduced across the wave with DPP (one LDS atomic
+// per bin and beam instead of one per lane, which would serialise on the
+// shared address); the remaining lanes add individually.
+//
+// The histograms hold sum K * shade; the beam scale S_b is applied in the
+// pulse convolution (sliding register window, in place).  Echoes are maximal
+// runs of xi_hat > T found with 64-bin ballots, one wave per beam
+// (section II-C, EPW paragraph).
 #include <climits>
 
 #include "engine.h"
@@ -21,6 +32,8 @@
 namespace lidar {
 
 namespace {
+
+constexpr int kWaves = kFootprintThreads / 64;
 
 __device__ inline int wave_min(int x)
 {
@@ -36,224 +49,402 @@ __device__ inline int wave_max(int x)
     return x;
 }
 
-__device__ inline float wave_sum(float x)
+template <int CTRL, int ROW_MASK>
+__device__ inline float dpp_add(float v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL,
+                                                          ROW_MASK, 0xf, false));
 }
 
-constexpr int kWaves = kFootprintThreads / 64;
+// Sum over the 64 lanes (all lanes must be active); the total is returned in
+// every lane as a uniform value.
+__device__ inline float wave_total(float v)
+{
+    v = dpp_add<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v = dpp_add<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xf>(v);   // row_half_mirror
+    v = dpp_add<0x140, 0xf>(v);   // row_mirror: every lane holds its row's sum
+    v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Flush the lanes in `fm` (lanes whose run ended) into the histograms.
+template <int G>
+__device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const float* acc,
+                                  float* hist, int R, int lane)
+{
+    unsigned long long m = fm;
+    // lanes sharing a bin are reduced across the wave (a few bins per step)
+#pragma unroll 1
+    for (int peel = 0; peel < 4 && m; ++peel) {
+        const int leader = __builtin_ctzll(m);
+        const int key = __builtin_amdgcn_readlane(cur, leader);
+        const unsigned long long same = __ballot(fl && cur == key) & m;
+        if (__popcll(same) < 3) break;
+        const bool in = (same >> lane) & 1ull;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const float s = wave_total(in ? acc[g] : 0.0f);
+            if (lane == 0 && s != 0.0f) atomicAdd(&hist[g * R + key], s);
+        }
+        m &= ~same;
+    }
+    if ((m >> lane) & 1ull) {
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            if (acc[g] != 0.0f) atomicAdd(&hist[g * R + cur], acc[g]);
+    }
+}
 
 }  // namespace
 
-template <bool SUN, bool KEEP>
+template <int G, bool SUN, bool KEEP>
 __global__ __launch_bounds__(kFootprintThreads)
 void k_footprint(FootprintArgs a)
 {
     extern __shared__ float lds[];
-    float* hist = lds;              // [R] sum K * shade per bin
-    float* xh = lds + a.R;          // [R] xi_hat
-    float* taps = lds + 2 * a.R;    // [2J+1]
-    __shared__ float red[kWaves];
+    float* hist = lds;                  // [G][R]: sum K * shade, then xi_hat
+    float* taps = lds + G * a.R;        // [2J+1]
+    __shared__ float red[G][kWaves];
 
     // XCD-aware schedule: workgroups go round-robin over the 8 XCDs, so slot
-    // s runs on XCD s % 8; each XCD takes one contiguous, spatially sorted
-    // chunk of beams and the beams in flight on it share their pixels in L2.
+    // s runs on XCD s % 8; each XCD takes one contiguous run of the
+    // spatially ordered groups, and the groups in flight on it share their
+    // pixels in its L2.
     const int slot = blockIdx.x;
-    const int idx = (slot % kXcds) * a.chunk + slot / kXcds;
-    if (idx >= a.B) return;
-    const int b = a.order[idx];
+    const int gi = (slot % kXcds) * a.chunk + slot / kXcds;
+    if (gi >= a.n_groups) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    for (int k = tid; k < a.R; k += kFootprintThreads) hist[k] = 0.0f;
+    int beam[G], ub[G], vb[G];
+    float scale[G];
+    bool have[G];
+    int umin = INT_MAX, umax = INT_MIN, vmin = INT_MAX, vmax = INT_MIN;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        beam[g] = a.groups[gi * G + g];
+        have[g] = beam[g] >= 0;
+        ub[g] = vb[g] = 0;
+        scale[g] = 0.0f;
+        if (have[g]) {
+            const lidar_beam_info bi = a.beams[beam[g]];
+            ub[g] = bi.pixel_u;
+            vb[g] = bi.pixel_v;
+            scale[g] = bi.scale;
+            umin = min(umin, ub[g]);
+            umax = max(umax, ub[g]);
+            vmin = min(vmin, vb[g]);
+            vmax = max(vmax, vb[g]);
+        }
+    }
+    for (int k = tid; k < G * a.R; k += kFootprintThreads) hist[k] = 0.0f;
     for (int j = tid; j <= 2 * a.J; j += kFootprintThreads) taps[j] = a.taps[j];
     __syncthreads();
 
-    const lidar_beam_info bi = a.beams[b];
-    const int ub = bi.pixel_u, vb = bi.pixel_v;
-    const int n0 = max(-a.N, -vb), n1 = min(a.N, a.H - 1 - vb);
-    const int c0 = max(-a.M, -ub), c1 = min(a.M, a.W - 1 - ub);
-    float sacc = 0.0f;
-    if (n0 <= n1 && c0 <= c1) {
-        const int nrows = n1 - n0 + 1;
+    // union window of the group's footprints, clipped to the image
+    // (64-bit arithmetic: beams may lie far outside the image)
+    const int r0 = (int)max(0L, (long)vmin - a.N), r1 = (int)min((long)a.H - 1, (long)vmax + a.N);
+    const int q0 = (int)max(0L, (long)umin - a.M), q1 = (int)min((long)a.W - 1, (long)umax + a.M);
+    float sacc[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) sacc[g] = 0.0f;
+    if (r0 <= r1 && q0 <= q1) {
+        const int nrows = r1 - r0 + 1;
         const int nstrips = (nrows + 63) >> 6;
-        const int ncols = c1 - c0 + 1;
-        // at least 2 items per wave when the footprint is wide enough
+        const int ncols = q1 - q0 + 1;
+        // at least 2 items per wave when the window is wide enough
         int nchunk = (2 * kWaves + nstrips - 1) / nstrips;
         nchunk = min(nchunk, max(1, ncols / 32));
         const int cw = (ncols + nchunk - 1) / nchunk;
         const int items = nstrips * nchunk;
         for (int it = wave; it < items; it += kWaves) {
             const int s = it / nchunk, ch = it - s * nchunk;
-            const int n = n0 + s * 64 + lane;
-            const bool rowok = n <= n1;
-            const int nn = rowok ? n : n1;          // in-bounds row for idle lanes
-            int2 rr = a.rowrange[nn + a.N];
-            if (!rowok) rr = make_int2(INT_MAX, INT_MIN);
-            const int mb = max(c0 + ch * cw, wave_min(rr.x));
-            const int me = min(min(c1, c0 + ch * cw + cw - 1), wave_max(rr.y));
-            if (mb > me) continue;
-            const int koff = nn + a.N;
-            const int poff = vb + nn;
-            const float kmask = rowok ? 1.0f : 0.0f;
-            const float* kcol = a.Kt + (long)(mb + a.M) * a.KH;
-            const int2* pcol = a.pix + (long)(ub + mb) * a.H;
-            const float* scol = SUN ? a.sun + (long)(ub + mb) * a.H : nullptr;
+            const int v = r0 + s * 64 + lane;
+            const bool rowok = v <= r1;
+            const int vv = rowok ? v : r1;                  // in-bounds row for idle lanes
+            unsigned koff[G];
+            float kmask[G];
+            int lo[G], hi[G];
+            int cb = INT_MAX, ce = INT_MIN;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int n = vv - vb[g];
+                const bool ok = rowok && have[g] && n >= -a.N && n <= a.N;
+                const int kr = min(max(n + a.N, 0), a.KH - 1);
+                koff[g] = (unsigned)kr;
+                kmask[g] = ok ? 1.0f : 0.0f;
+                int2 rr = a.rowrange[kr];
+                if (!ok) rr = make_int2(INT_MAX, INT_MIN);
+                const int wlo = wave_min(rr.x), whi = wave_max(rr.y);
+                // absolute columns where this beam can have K > 0 in the strip
+                lo[g] = __builtin_amdgcn_readfirstlane(wlo == INT_MAX ? INT_MAX : wlo + ub[g]);
+                hi[g] = __builtin_amdgcn_readfirstlane(whi == INT_MIN ? INT_MIN : whi + ub[g]);
+                cb = min(cb, lo[g]);
+                ce = max(ce, hi[g]);
+            }
+            cb = max(cb, q0 + ch * cw);
+            ce = min(ce, min(q1, q0 + ch * cw + cw - 1));
+            if (cb > ce) continue;
+            const unsigned poff = (unsigned)vv;
+            const int2* pcol = a.pix + (size_t)cb * a.H;
+            const float* scol = SUN ? a.sun + (size_t)cb * a.H : nullptr;
             int cur = -1;
-            float acc = 0.0f;
-            for (int m = mb; m <= me; ++m) {
-                const float kv = kcol[koff] * kmask;
-                const int2 rec = pcol[poff];
-                const float t = kv * __int_as_float(rec.y);
-                if (rec.x != cur && rec.x >= 0 && kv != 0.0f) {
-                    if (acc != 0.0f) atomicAdd(&hist[cur], acc);
-                    cur = rec.x;
-                    acc = t;
-                } else {
-                    acc += t;
+            float acc[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[g] = 0.0f;
+
+            // one column step of the lane's row for all beams of the group
+            auto step = [&](const float* kv, int2 rec, float sv) {
+                const float sh = __int_as_float(rec.y);
+                const bool nr = rec.x != cur;
+                float tot = 0.0f;
+#pragma unroll
+                for (int g = 0; g < G; ++g) tot += acc[g];
+                const bool fl = nr && tot != 0.0f;
+                const unsigned long long fm = __ballot(fl);
+                if (fm) flush_runs<G>(fm, fl, cur, acc, hist, a.R, lane);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    acc[g] = (nr ? 0.0f : acc[g]) + kv[g] * sh;
+                    if (SUN) sacc[g] += kv[g] * sv;
                 }
-                if (SUN) sacc += kv * scol[poff];
-                kcol += a.KH;
+                cur = rec.x;
+            };
+            auto kload = [&](int u, int g) -> float {
+                // uniform test: the column lies in beam g's kernel window
+                if (u < lo[g] || u > hi[g]) return 0.0f;
+                const float* kc = a.Kt + (size_t)(u - ub[g] + a.M) * a.KH;
+                return kc[koff[g]] * kmask[g];
+            };
+            constexpr int U = 4;
+            int u = cb;
+            for (; u + U - 1 <= ce; u += U) {
+                float kv[U][G], sv[U];
+                int2 rec[U];
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    rec[j] = pcol[(size_t)j * a.H + poff];
+                    sv[j] = SUN ? scol[(size_t)j * a.H + poff] : 0.0f;
+#pragma unroll
+                    for (int g = 0; g < G; ++g) kv[j][g] = kload(u + j, g);
+                }
+#pragma unroll
+                for (int j = 0; j < U; ++j) step(kv[j], rec[j], sv[j]);
+                pcol += (size_t)U * a.H;
+                if (SUN) scol += (size_t)U * a.H;
+            }
+            for (; u <= ce; ++u) {
+                float kv[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) kv[g] = kload(u, g);
+                step(kv, pcol[poff], SUN ? scol[poff] : 0.0f);
                 pcol += a.H;
                 if (SUN) scol += a.H;
             }
-            if (acc != 0.0f) atomicAdd(&hist[cur], acc);
+            float tot = 0.0f;
+#pragma unroll
+            for (int g = 0; g < G; ++g) tot += acc[g];
+            const bool fl = tot != 0.0f;
+            const unsigned long long fm = __ballot(fl);
+            if (fm) flush_runs<G>(fm, fl, cur, acc, hist, a.R, lane);
         }
     }
     if (SUN) {
-        const float w = wave_sum(sacc);
-        if (lane == 0) red[wave] = w;
-    }
-    __syncthreads();
-    float floor_b = a.ambient;
-    if (SUN) {
-        float tot = 0.0f;
 #pragma unroll
-        for (int i = 0; i < kWaves; ++i) tot += red[i];
-        floor_b += a.sun_scale * tot;
-    }
-
-    // pulse convolution (zero outside [0, R)) plus the floor
-    const float S = bi.scale;
-    for (int k = tid; k < a.R; k += kFootprintThreads) {
-        const int jlo = max(-a.J, k - (a.R - 1)), jhi = min(a.J, k);
-        float s = 0.0f;
-        for (int j = jlo; j <= jhi; ++j) s += taps[j + a.J] * hist[k - j];
-        const float v = S * s + floor_b;
-        xh[k] = v;
-        if (KEEP) a.waves[(long)b * a.R + k] = v;
+        for (int g = 0; g < G; ++g) {
+            const float w = wave_total(sacc[g]);
+            if (lane == 0) red[g][wave] = w;
+        }
     }
     __syncthreads();
-    if (wave != 0) return;
 
-    // echo detection: runs of xi_hat > T, 64 bins per ballot
+    // pulse convolution in place, 8 consecutive bins per thread and pass with
+    // a sliding register window: xi_hat = S_b (varpi * hist) + A_b
+    float floor_b[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        float f = a.ambient;
+        if (SUN) {
+            float t = 0.0f;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) t += red[g][w];
+            f += a.sun_scale * t;
+        }
+        floor_b[g] = f;
+    }
+    constexpr int kPass = 8 * kFootprintThreads;        // bins per pass
+    constexpr int kMaxPass = (kMaxBins + kPass - 1) / kPass;
+#pragma unroll 1
+    for (int g = 0; g < G; ++g) {
+        if (!have[g]) continue;                          // uniform
+        float* h = hist + g * a.R;
+        float o[kMaxPass][8];
+#pragma unroll
+        for (int p = 0; p < kMaxPass; ++p) {
+            const int k0 = p * kPass + tid * 8;
+            if (k0 >= a.R) continue;
+            auto H = [&](int i) -> float { return (i >= 0 && i < a.R) ? h[i] : 0.0f; };
+            float win[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                win[q] = H(k0 + q + a.J);
+                o[p][q] = 0.0f;
+            }
+            for (int t = 0; t <= 2 * a.J; ++t) {
+                const float wt = taps[t];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) o[p][q] += wt * win[q];
+#pragma unroll
+                for (int q = 7; q > 0; --q) win[q] = win[q - 1];
+                win[0] = H(k0 + a.J - t - 1);
+            }
+        }
+        __syncthreads();                                 // every read of h is done
+#pragma unroll
+        for (int p = 0; p < kMaxPass; ++p) {
+            const int k0 = p * kPass + tid * 8;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int k = k0 + q;
+                if (k < a.R) {
+                    const float val = scale[g] * o[p][q] + floor_b[g];
+                    h[k] = val;
+                    if (KEEP) a.waves[(size_t)beam[g] * a.R + k] = val;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // echo detection: wave w takes beams w, w + 4, ...
     const float T = a.threshold;
     const float dt = (float)a.bin_ns;
-    lidar_echo* out = a.echoes + (long)b * a.E;
-    int count = 0;
-    int k0 = -1;                                    // first bin of the open run
-    for (int base = 0; base < a.R; base += 64) {
-        const int k = base + lane;
-        const bool above = k < a.R && xh[k] > T;
-        const unsigned long long mask = __ballot(above);
-        const bool next_above = base + 64 < a.R && xh[base + 64] > T;
-        const unsigned long long prev = (mask << 1) | (k0 >= 0 ? 1ull : 0ull);
-        const unsigned long long nxt = (mask >> 1) | (next_above ? (1ull << 63) : 0ull);
-        unsigned long long starts = mask & ~prev;
-        unsigned long long ends = mask & ~nxt;
-        while (starts | ends) {
-            const int ps = starts ? __ffsll((long long)starts) - 1 : 64;
-            const int pe = ends ? __ffsll((long long)ends) - 1 : 64;
-            if (ps <= pe) {
-                k0 = base + ps;
-                starts &= starts - 1;
-                continue;
-            }
-            ends &= ends - 1;
-            const int k1 = base + pe;
-            if (count < a.E) {
-                // first maximum of the run
-                float best = -INFINITY;
-                int bk = INT_MAX;
-                for (int s = k0; s <= k1; s += 64) {
-                    const int kk = s + lane;
-                    if (kk <= k1) {
-                        const float x = xh[kk];
-                        if (x > best) {
-                            best = x;
-                            bk = kk;
+#pragma unroll 1
+    for (int g = wave; g < G; g += kWaves) {
+        if (!have[g]) continue;
+        const float* xh = hist + g * a.R;
+        lidar_echo* out = a.echoes + (size_t)beam[g] * a.E;
+        int count = 0;
+        int k0 = -1;                                     // first bin of the open run
+        for (int base = 0; base < a.R; base += 64) {
+            const int k = base + lane;
+            const bool above = k < a.R && xh[k] > T;
+            const unsigned long long mask = __ballot(above);
+            const bool next_above = base + 64 < a.R && xh[base + 64] > T;
+            const unsigned long long prev = (mask << 1) | (k0 >= 0 ? 1ull : 0ull);
+            const unsigned long long nxt = (mask >> 1) | (next_above ? (1ull << 63) : 0ull);
+            unsigned long long starts = mask & ~prev;
+            unsigned long long ends = mask & ~nxt;
+            while (starts | ends) {
+                const int ps = starts ? __builtin_ctzll(starts) : 64;
+                const int pe = ends ? __builtin_ctzll(ends) : 64;
+                if (ps <= pe) {
+                    k0 = base + ps;
+                    starts &= starts - 1;
+                    continue;
+                }
+                ends &= ends - 1;
+                const int k1 = base + pe;
+                if (count < a.E) {
+                    // first maximum of the run
+                    float best = -INFINITY;
+                    int bk = INT_MAX;
+                    for (int s = k0; s <= k1; s += 64) {
+                        const int kk = s + lane;
+                        if (kk <= k1) {
+                            const float x = xh[kk];
+                            if (x > best) {
+                                best = x;
+                                bk = kk;
+                            }
                         }
                     }
-                }
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    const float ob = __shfl_xor(best, o);
-                    const int oi = __shfl_xor(bk, o);
-                    if (ob > best || (ob == best && oi < bk)) {
-                        best = ob;
-                        bk = oi;
+                    for (int o = 32; o > 0; o >>= 1) {
+                        const float ob = __shfl_xor(best, o);
+                        const int oi = __shfl_xor(bk, o);
+                        if (ob > best || (ob == best && oi < bk)) {
+                            best = ob;
+                            bk = oi;
+                        }
+                    }
+                    if (lane == 0) {
+                        // threshold crossings between bin centres, as
+                        // fractions of a bin from the centre of the bin before
+                        // the run and from the centre of its last bin
+                        float f_up, f_dn;
+                        uint32_t flags = 0;
+                        if (k0 == 0) {
+                            f_up = 0.5f;
+                            flags |= LIDAR_ECHO_AT_FIRST_BIN;
+                        } else {
+                            const float xa = xh[k0 - 1], xb = xh[k0];
+                            f_up = (T - xa) / (xb - xa);
+                        }
+                        if (k1 == a.R - 1) {
+                            f_dn = 0.5f;
+                            flags |= LIDAR_ECHO_AT_LAST_BIN;
+                        } else {
+                            const float xa = xh[k1], xb = xh[k1 + 1];
+                            f_dn = (xa - T) / (xa - xb);
+                        }
+                        lidar_echo e;
+                        e.range_m = ((double)bk + 0.5) * a.half_c_dt;
+                        e.time_ns = ((double)bk + 0.5) * a.bin_ns;
+                        e.intensity = best - floor_b[g];
+                        e.pulse_width_ns = ((float)(k1 - k0 + 1) + f_dn - f_up) * dt;
+                        e.bin_peak = bk;
+                        e.bin_first = k0;
+                        e.bin_last = k1;
+                        e.flags = flags;
+                        out[count] = e;
                     }
                 }
-                if (lane == 0) {
-                    // threshold crossings between bin centres, as fractions of
-                    // a bin measured from the centre of the bin before the run
-                    // and from the centre of its last bin
-                    float f_up, f_dn;
-                    uint32_t flags = 0;
-                    if (k0 == 0) {
-                        f_up = 0.5f;
-                        flags |= LIDAR_ECHO_AT_FIRST_BIN;
-                    } else {
-                        const float xa = xh[k0 - 1], xb = xh[k0];
-                        f_up = (T - xa) / (xb - xa);
-                    }
-                    if (k1 == a.R - 1) {
-                        f_dn = 0.5f;
-                        flags |= LIDAR_ECHO_AT_LAST_BIN;
-                    } else {
-                        const float xa = xh[k1], xb = xh[k1 + 1];
-                        f_dn = (xa - T) / (xa - xb);
-                    }
-                    lidar_echo e;
-                    e.range_m = ((double)bk + 0.5) * a.half_c_dt;
-                    e.time_ns = ((double)bk + 0.5) * a.bin_ns;
-                    e.intensity = best - floor_b;
-                    e.pulse_width_ns = ((float)(k1 - k0 + 1) + f_dn - f_up) * dt;
-                    e.bin_peak = bk;
-                    e.bin_first = k0;
-                    e.bin_last = k1;
-                    e.flags = flags;
-                    out[count] = e;
-                }
+                ++count;
+                k0 = -1;
             }
-            ++count;
-            k0 = -1;
+        }
+        if (lane == 0) {
+            a.counts[beam[g]] = count;
+            a.beams[beam[g]].floor = floor_b[g];
+            lidar_echo z = {};
+            for (int i = count; i < a.E; ++i) out[i] = z;
         }
     }
-    if (lane == 0) {
-        a.counts[b] = count;
-        a.beams[b].floor = floor_b;
-        lidar_echo z = {};
-        for (int i = count; i < a.E; ++i) out[i] = z;
-    }
+}
+
+template <int G>
+static hipError_t launch_g(hipStream_t s, const FootprintArgs& a)
+{
+    const int grid = kXcds * a.chunk;
+    const size_t lds = sizeof(float) * ((size_t)G * a.R + 2 * (size_t)a.J + 1);
+    const bool sun = a.sun != nullptr;
+    const bool keep = a.waves != nullptr;
+    if (sun && keep)
+        hipLaunchKernelGGL((k_footprint<G, true, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    else if (sun)
+        hipLaunchKernelGGL((k_footprint<G, true, false>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    else if (keep)
+        hipLaunchKernelGGL((k_footprint<G, false, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_footprint<G, false, false>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+bool footprint_group_fits(int G, int R, int J)
+{
+    return sizeof(float) * ((size_t)G * R + 2 * (size_t)J + 1) + 64 * sizeof(float) <= 65536;
 }
 
 hipError_t launch_footprint(hipStream_t s, const FootprintArgs& a)
 {
-    const int grid = kXcds * a.chunk;
-    const size_t lds = sizeof(float) * (2 * (size_t)a.R + 2 * (size_t)a.J + 1);
-    const bool sun = a.sun != nullptr;
-    const bool keep = a.waves != nullptr;
-    if (sun && keep)
-        hipLaunchKernelGGL((k_footprint<true, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
-    else if (sun)
-        hipLaunchKernelGGL((k_footprint<true, false>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
-    else if (keep)
-        hipLaunchKernelGGL((k_footprint<false, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
-    else
-        hipLaunchKernelGGL((k_footprint<false, false>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
-    return hipGetLastError();
+    switch (a.G) {
+    case 1: return launch_g<1>(s, a);
+    case 2: return launch_g<2>(s, a);
+    case 4: return launch_g<4>(s, a);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace lidar

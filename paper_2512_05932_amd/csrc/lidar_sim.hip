@@ -70,7 +70,8 @@ struct lidar_sim {
     std::vector<double> az, el;
     DevBuf<float> d_table;
     DevBuf<double> d_az, d_el;
-    DevBuf<int32_t> d_order;
+    DevBuf<int32_t> d_groups;
+    int G = 1, n_groups = 0;
 
     // raster of the current G-buffer
     bool have_gbuffer = false;
@@ -199,17 +200,65 @@ void kernel_extent(const lidar_sim* h, const RasterDev& r, double* M, double* N)
     }
 }
 
-// Beam schedule: sort by azimuth column, then elevation, so consecutive
-// beams share most of their footprint.
-void build_order(const std::vector<double>& az, const std::vector<double>& el,
-                 std::vector<int32_t>& order)
+// Beam scheduler.  Beams are grouped G at a time so that one workgroup can
+// share the pixel reads of nearby footprints: beams are sorted by their
+// (approximate) pixel row band, then column, and a group takes consecutive
+// beams of one band whose columns lie within one kernel width.  The groups
+// are then ordered by column so that the groups in flight on one XCD cover a
+// narrow band of the image.  Scheduling only: the exact pixel of each beam is
+// computed on the GPU.
+void build_groups(const std::vector<double>& az, const std::vector<double>& el,
+                  const RasterDev& r, const KernelDev& k, int G, std::vector<int32_t>& out,
+                  int* n_groups)
 {
-    order.resize(az.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-        if (az[x] != az[y]) return az[x] < az[y];
-        return el[x] > el[y];
+    const size_t B = az.size();
+    std::vector<double> uf(B), vf(B);
+    for (size_t i = 0; i < B; ++i) {
+        uf[i] = std::floor((az[i] - r.az_min) / r.dphi);
+        vf[i] = std::floor((r.el_max - el[i]) / r.de);
+    }
+    auto make = [&](double band, std::vector<std::vector<int32_t>>& groups) {
+        std::vector<int32_t> idx(B);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+            double bx = std::floor(vf[x] / band), by = std::floor(vf[y] / band);
+            if (bx != by) return bx < by;
+            return uf[x] < uf[y];
+        });
+        groups.clear();
+        std::vector<int32_t> cur;
+        double cur_band = 0, cur_u0 = 0;
+        for (int32_t i : idx) {
+            double bi = std::floor(vf[i] / band);
+            bool fits = !cur.empty() && (int)cur.size() < G && bi == cur_band &&
+                        uf[i] - cur_u0 <= (double)k.KW;
+            if (!fits && !cur.empty()) {
+                groups.push_back(cur);
+                cur.clear();
+            }
+            if (cur.empty()) {
+                cur_band = bi;
+                cur_u0 = uf[i];
+            }
+            cur.push_back(i);
+        }
+        if (!cur.empty()) groups.push_back(cur);
+    };
+    std::vector<std::vector<int32_t>> groups;
+    make(1.0, groups);
+    if (G > 1 && groups.size() * 2 > B) {
+        // few beams share a pixel row: group across a band of rows
+        make(std::max(1.0, std::floor(k.KH / 8.0)), groups);
+    }
+    std::stable_sort(groups.begin(), groups.end(), [&](const std::vector<int32_t>& x,
+                                                       const std::vector<int32_t>& y) {
+        if (uf[x[0]] != uf[y[0]]) return uf[x[0]] < uf[y[0]];
+        return vf[x[0]] < vf[y[0]];
     });
+    out.assign(groups.size() * G, -1);
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+        for (size_t j = 0; j < groups[gi].size(); ++j) out[gi * G + j] = groups[gi][j];
+    *n_groups = (int)groups.size();
 }
 
 lidar_status run_setup(lidar_sim* h)
@@ -272,6 +321,18 @@ lidar_status run_setup(lidar_sim* h)
                                         "(kernel narrower than one pixel or all-zero table)");
     uint64_t total = 0;
     for (auto& x : bi) total += x.samples;
+    // beam groups for the footprint kernel
+    int G = 4;
+    while (G > 1 && !footprint_group_fits(G, (int)h->prm.n_bins, h->J)) G /= 2;
+    std::vector<int32_t> groups;
+    int n_groups = 0;
+    build_groups(h->az, h->el, r, k, G, groups, &n_groups);
+    HIP_TRY(h, h->d_groups.ensure(groups.size()), "allocate beam groups");
+    HIP_TRY(h, hipMemcpyAsync(h->d_groups.p, groups.data(), groups.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s), "copy beam groups");
+    HIP_TRY(h, hipStreamSynchronize(s), "set-up synchronise");
+    h->G = G;
+    h->n_groups = n_groups;
     h->kgeom = k;
     h->kmax = kinfo[0];
     h->samples = total;
@@ -357,7 +418,7 @@ lidar_status lidar_sim_destroy(lidar_sim* h)
             (void)hipEventDestroy(p.a);
             (void)hipEventDestroy(p.b);
         }
-    h->d_table.release(); h->d_az.release(); h->d_el.release(); h->d_order.release();
+    h->d_table.release(); h->d_az.release(); h->d_el.release(); h->d_groups.release();
     h->d_K64.release(); h->d_rowsum.release(); h->d_rowmax.release(); h->d_kinfo.release();
     h->d_Kt.release(); h->d_rowrange.release(); h->d_prefix.release();
     h->d_colcs.release(); h->d_rowtab.release(); h->d_beams.release(); h->d_taps.release();
@@ -401,16 +462,12 @@ lidar_status lidar_sim_set_pattern(lidar_sim* h, const lidar_pattern_desc* pd)
     const size_t B = pd->n_beams;
     h->az.assign(pd->beam_az_deg, pd->beam_az_deg + B);
     h->el.assign(pd->beam_el_deg, pd->beam_el_deg + B);
-    std::vector<int32_t> order;
-    build_order(h->az, h->el, order);
     HIP_TRY(h, h->d_az.ensure(B), "allocate beams");
     HIP_TRY(h, h->d_el.ensure(B), "allocate beams");
-    HIP_TRY(h, h->d_order.ensure(B), "allocate beams");
     hipStream_t s = h->stream;
     // pageable sources: these copies complete before the call returns
     HIP_TRY(h, hipMemcpyAsync(h->d_az.p, h->az.data(), B * sizeof(double), hipMemcpyHostToDevice, s), "copy beams");
     HIP_TRY(h, hipMemcpyAsync(h->d_el.p, h->el.data(), B * sizeof(double), hipMemcpyHostToDevice, s), "copy beams");
-    HIP_TRY(h, hipMemcpyAsync(h->d_order.p, order.data(), B * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy beam order");
     h->kind = pd->kind;
     if (pd->kind == LIDAR_PATTERN_GAUSS) {
         h->sigma[0] = pd->sigma_deg[0];
@@ -511,9 +568,10 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
     fa.M = h->kgeom.M;
     fa.N = h->kgeom.N;
     fa.KH = h->kgeom.KH;
-    fa.order = h->d_order.p;
-    fa.B = (int)B;
-    fa.chunk = (int)((B + kXcds - 1) / kXcds);
+    fa.groups = h->d_groups.p;
+    fa.n_groups = h->n_groups;
+    fa.G = h->G;
+    fa.chunk = (h->n_groups + kXcds - 1) / kXcds;
     fa.beams = h->d_beams.p;
     fa.taps = h->d_taps.p;
     fa.J = h->J;
