@@ -40,7 +40,8 @@ struct KernelDev {
 
 // ---- set-up (FP64 resample of the pattern and per-beam normalisation) ----
 hipError_t launch_kernel_grid(hipStream_t s, PatternDev p, RasterDev r, KernelDev k,
-                              double* K64, float* Kt);
+                              double* K64);
+hipError_t launch_kernel_blocks(hipStream_t s, KernelDev k, const double* K64, float* Kb);
 hipError_t launch_kernel_rows(hipStream_t s, KernelDev k, const double* K64, double* rowsum,
                               double* rowmax, int2* rowrange, int32_t* prefix);
 hipError_t launch_kernel_peak(hipStream_t s, KernelDev k, const double* rowsum,
@@ -61,18 +62,26 @@ struct PrepassArgs {
     double to_bin;              // 2 / (c dt), FP64
     int R;
     float sun_x, sun_y, sun_z;
-    int2* pix;                  // [W][H] {bin, shade bits}, column-major
-    float* sun;                 // [W][H] sun shading, column-major (or null)
+    int2* pix;                  // [W4/4][H][4] {bin, shade bits}, 4-column blocks
+    float* sun;                 // [W4/4][H][4] sun shading, 4-column blocks (or null)
+    int W4;                     // W rounded up to a multiple of 4 (padding: sky)
 };
 hipError_t launch_prepass(hipStream_t s, const PrepassArgs& a, bool with_sun);
 
+// Kernel table in 4-column blocks, in four copies shifted by one column:
+// copy s, block b, row n holds K(c, n) for the kernel columns
+// c = 4(b - 2) + s + j, j = 0..3 (zero outside [0, KW) and in the guard row
+// n = KH).  Block 0 and block NB-1 of every copy are all zero.
+constexpr int kBlockPad = 2;
+__host__ __device__ inline int kernel_blocks(int KW) { return (KW + 12) / 4 + 1; }
+
 struct FootprintArgs {
-    const int2* pix;            // [W][H]
-    const float* sun;           // [W][H] or null
+    const int2* pix;            // [W4/4][H][4]
+    const float* sun;           // [W4/4][H][4] or null
     int W, H;
-    const float* Kt;            // [KW][KH]: K(m, n) at (m+M)*KH + n+N
+    const float* Kb;            // [4][NB][KH+1][4], see kernel_blocks
     const int2* rowrange;       // [KH] first/last m with K > 0 (empty row: INT_MAX, INT_MIN)
-    int M, N, KH;
+    int M, N, KW, KH, NB;
     const int32_t* groups;      // [n_groups][G] beam indices, -1 = empty slot
     int n_groups, G, chunk;     // chunk = ceil(n_groups / kXcds)
     lidar_beam_info* beams;     // [B] in: pixel, scale; out: floor

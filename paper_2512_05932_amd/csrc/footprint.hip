@@ -35,6 +35,14 @@ namespace {
 
 constexpr int kWaves = kFootprintThreads / 64;
 
+// 16-byte load at a uniform base plus a per-lane byte offset (the bases
+// derive from kernel arguments, so these become global loads).
+template <typename T>
+__device__ inline T ld16(const char* base, unsigned byte_off)
+{
+    return *(const T*)(base + byte_off);
+}
+
 __device__ inline int wave_min(int x)
 {
 #pragma unroll
@@ -115,23 +123,26 @@ void k_footprint(FootprintArgs a)
     const int slot = blockIdx.x;
     const int gi = (slot % kXcds) * a.chunk + slot / kXcds;
     if (gi >= a.n_groups) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
+    // group members (uniform over the workgroup: kept in scalar registers)
     int beam[G], ub[G], vb[G];
     float scale[G];
     bool have[G];
     int umin = INT_MAX, umax = INT_MIN, vmin = INT_MAX, vmax = INT_MIN;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        beam[g] = a.groups[gi * G + g];
+        beam[g] = __builtin_amdgcn_readfirstlane(a.groups[gi * G + g]);
         have[g] = beam[g] >= 0;
         ub[g] = vb[g] = 0;
         scale[g] = 0.0f;
         if (have[g]) {
             const lidar_beam_info bi = a.beams[beam[g]];
-            ub[g] = bi.pixel_u;
-            vb[g] = bi.pixel_v;
-            scale[g] = bi.scale;
+            ub[g] = __builtin_amdgcn_readfirstlane(bi.pixel_u);
+            vb[g] = __builtin_amdgcn_readfirstlane(bi.pixel_v);
+            scale[g] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                __builtin_bit_cast(int, bi.scale)));
             umin = min(umin, ub[g]);
             umax = max(umax, ub[g]);
             vmin = min(vmin, vb[g]);
@@ -152,30 +163,31 @@ void k_footprint(FootprintArgs a)
     if (r0 <= r1 && q0 <= q1) {
         const int nrows = r1 - r0 + 1;
         const int nstrips = (nrows + 63) >> 6;
-        const int ncols = q1 - q0 + 1;
+        const int q0a = q0 & ~3;                        // batches are aligned 4-column blocks
+        const int ncols = q1 - q0a + 1;
         // at least 2 items per wave when the window is wide enough
         int nchunk = (2 * kWaves + nstrips - 1) / nstrips;
         nchunk = min(nchunk, max(1, ncols / 32));
-        const int cw = (ncols + nchunk - 1) / nchunk;
+        const int cw = (((ncols + nchunk - 1) / nchunk) + 3) & ~3;
         const int items = nstrips * nchunk;
+        const size_t khp16 = (size_t)(a.KH + 1) * 16u;          // block stride in a copy
+        const size_t copy_bytes = (size_t)a.NB * khp16;
+        const size_t pstep = (size_t)a.H * 32u, sstep = (size_t)a.H * 16u;
         for (int it = wave; it < items; it += kWaves) {
             const int s = it / nchunk, ch = it - s * nchunk;
             const int v = r0 + s * 64 + lane;
             const bool rowok = v <= r1;
             const int vv = rowok ? v : r1;                  // in-bounds row for idle lanes
-            unsigned koff[G];
-            float kmask[G];
+            unsigned kvo[G];                                // lane offset in a kernel block
             int lo[G], hi[G];
             int cb = INT_MAX, ce = INT_MIN;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int n = vv - vb[g];
                 const bool ok = rowok && have[g] && n >= -a.N && n <= a.N;
-                const int kr = min(max(n + a.N, 0), a.KH - 1);
-                koff[g] = (unsigned)kr;
-                kmask[g] = ok ? 1.0f : 0.0f;
-                int2 rr = a.rowrange[kr];
-                if (!ok) rr = make_int2(INT_MAX, INT_MIN);
+                // lanes with nothing to add read the zero guard row
+                kvo[g] = (unsigned)(ok ? n + a.N : a.KH) * 16u;
+                const int2 rr = ok ? a.rowrange[n + a.N] : make_int2(INT_MAX, INT_MIN);
                 const int wlo = wave_min(rr.x), whi = wave_max(rr.y);
                 // absolute columns where this beam can have K > 0 in the strip
                 lo[g] = __builtin_amdgcn_readfirstlane(wlo == INT_MAX ? INT_MAX : wlo + ub[g]);
@@ -183,69 +195,85 @@ void k_footprint(FootprintArgs a)
                 cb = min(cb, lo[g]);
                 ce = max(ce, hi[g]);
             }
-            cb = max(cb, q0 + ch * cw);
-            ce = min(ce, min(q1, q0 + ch * cw + cw - 1));
+            cb = max(cb, q0a + ch * cw);
+            ce = min(ce, min(q1, q0a + ch * cw + cw - 1));
             if (cb > ce) continue;
-            const unsigned poff = (unsigned)vv;
-            const int2* pcol = a.pix + (size_t)cb * a.H;
-            const float* scol = SUN ? a.sun + (size_t)cb * a.H : nullptr;
+            // whole 4-column blocks [cb/4, ce/4]; the extra columns lie outside
+            // every beam's kernel support (or past the image: sky padding)
+            const int blk0 = cb >> 2, nblk = (ce >> 2) - blk0 + 1;
+            const char* pbase = (const char*)(a.pix + (size_t)blk0 * a.H * 4);
+            const char* sbase = SUN ? (const char*)(a.sun + (size_t)blk0 * a.H * 4) : nullptr;
+            const unsigned pvo = (unsigned)vv * 32u, svo = (unsigned)vv * 16u;
+            // per beam: kernel copy (shift) and block of the first batch
+            const char* kcopy[G];
+            int kblk[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int c0 = 4 * blk0 - ub[g] + a.M;      // kernel column of column 4*blk0
+                const int sft = c0 & 3;
+                kcopy[g] = (const char*)a.Kb + (size_t)sft * copy_bytes;
+                kblk[g] = ((c0 - sft) >> 2) + kBlockPad;
+            }
             int cur = -1;
             float acc[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) acc[g] = 0.0f;
-
-            // one column step of the lane's row for all beams of the group
-            auto step = [&](const float* kv, int2 rec, float sv) {
-                const float sh = __int_as_float(rec.y);
-                const bool nr = rec.x != cur;
-                float tot = 0.0f;
-#pragma unroll
-                for (int g = 0; g < G; ++g) tot += acc[g];
-                const bool fl = nr && tot != 0.0f;
-                const unsigned long long fm = __ballot(fl);
-                if (fm) flush_runs<G>(fm, fl, cur, acc, hist, a.R, lane);
+            for (int i = 0; i < nblk; ++i) {
+                // all loads of the 4-column batch first
+                const char* pb = pbase + (size_t)i * pstep;
+                const int4 ra = ld16<int4>(pb, pvo);
+                const int4 rb = ld16<int4>(pb, pvo + 16u);
+                float4 sq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (SUN) sq = ld16<float4>(sbase + (size_t)i * sstep, svo);
+                const float sv[4] = {sq.x, sq.y, sq.z, sq.w};
+                float kv[4][G];
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    acc[g] = (nr ? 0.0f : acc[g]) + kv[g] * sh;
-                    if (SUN) sacc[g] += kv[g] * sv;
+                    const int b = min(max(kblk[g] + i, 0), a.NB - 1);
+                    const float4 kq = ld16<float4>(kcopy[g] + (size_t)b * khp16, kvo[g]);
+                    kv[0][g] = kq.x;
+                    kv[1][g] = kq.y;
+                    kv[2][g] = kq.z;
+                    kv[3][g] = kq.w;
                 }
-                cur = rec.x;
-            };
-            auto kload = [&](int u, int g) -> float {
-                // uniform test: the column lies in beam g's kernel window
-                if (u < lo[g] || u > hi[g]) return 0.0f;
-                const float* kc = a.Kt + (size_t)(u - ub[g] + a.M) * a.KH;
-                return kc[koff[g]] * kmask[g];
-            };
-            constexpr int U = 4;
-            int u = cb;
-            for (; u + U - 1 <= ce; u += U) {
-                float kv[U][G], sv[U];
-                int2 rec[U];
+                const int bin[4] = {ra.x, ra.z, rb.x, rb.z};
+                const float sh[4] = {__int_as_float(ra.y), __int_as_float(ra.w),
+                                     __int_as_float(rb.y), __int_as_float(rb.w)};
+                // four branch-free column steps; the state before each step is
+                // kept for the flush below
+                int curb[4];
+                float accb[4][G];
+                unsigned long long nrm = 0;
 #pragma unroll
-                for (int j = 0; j < U; ++j) {
-                    rec[j] = pcol[(size_t)j * a.H + poff];
-                    sv[j] = SUN ? scol[(size_t)j * a.H + poff] : 0.0f;
+                for (int j = 0; j < 4; ++j) {
+                    const bool nr = bin[j] != cur;
+                    nrm |= __ballot(nr);
+                    curb[j] = cur;
 #pragma unroll
-                    for (int g = 0; g < G; ++g) kv[j][g] = kload(u + j, g);
+                    for (int g = 0; g < G; ++g) {
+                        accb[j][g] = acc[g];
+                        acc[g] = (nr ? 0.0f : acc[g]) + kv[j][g] * sh[j];
+                        if (SUN) sacc[g] += kv[j][g] * sv[j];
+                    }
+                    cur = bin[j];
                 }
+                // runs that ended in this batch go to the histograms
+                if (nrm) {
 #pragma unroll
-                for (int j = 0; j < U; ++j) step(kv[j], rec[j], sv[j]);
-                pcol += (size_t)U * a.H;
-                if (SUN) scol += (size_t)U * a.H;
+                    for (int j = 0; j < 4; ++j) {
+                        unsigned any = __builtin_bit_cast(unsigned, accb[j][0]);
+#pragma unroll
+                        for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, accb[j][g]);
+                        const bool fl = bin[j] != curb[j] && any != 0u;   // sums are >= 0
+                        const unsigned long long fm = __ballot(fl);
+                        if (fm) flush_runs<G>(fm, fl, curb[j], accb[j], hist, a.R, lane);
+                    }
+                }
             }
-            for (; u <= ce; ++u) {
-                float kv[G];
+            unsigned any = __builtin_bit_cast(unsigned, acc[0]);
 #pragma unroll
-                for (int g = 0; g < G; ++g) kv[g] = kload(u, g);
-                step(kv, pcol[poff], SUN ? scol[poff] : 0.0f);
-                pcol += a.H;
-                if (SUN) scol += a.H;
-            }
-            float tot = 0.0f;
-#pragma unroll
-            for (int g = 0; g < G; ++g) tot += acc[g];
-            const bool fl = tot != 0.0f;
+            for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, acc[g]);
+            const bool fl = any != 0u;
             const unsigned long long fm = __ballot(fl);
             if (fm) flush_runs<G>(fm, fl, cur, acc, hist, a.R, lane);
         }

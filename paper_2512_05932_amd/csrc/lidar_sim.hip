@@ -85,7 +85,7 @@ struct lidar_sim {
     double kmax = 0.0;
     uint64_t samples = 0;
     DevBuf<double> d_K64, d_rowsum, d_rowmax, d_kinfo;
-    DevBuf<float> d_Kt;
+    DevBuf<float> d_Kb;
     DevBuf<int2> d_rowrange;
     DevBuf<int32_t> d_prefix;
     DevBuf<float2> d_colcs;
@@ -270,6 +270,11 @@ lidar_status run_setup(lidar_sim* h)
     if (!(Mf >= 0 && Nf >= 0) || Mf > 4096 || Nf > 4096 || (2 * Mf + 1) * (2 * Nf + 1) > 16.0e6)
         return fail(h, LIDAR_E_INVALID, "kernel grid too large for this raster (more than 16M "
                                         "cells or 8193 columns/rows)");
+    // the footprint kernel addresses one group window of pixel records with
+    // 32-bit byte offsets
+    if ((4.0 * Mf + 8.0) * (double)g.height * 8.0 >= 2147483648.0)
+        return fail(h, LIDAR_E_INVALID, "kernel window times image height too large "
+                                        "(4*M+8)*height*8 must stay below 2^31 bytes");
     KernelDev k;
     k.M = (int)Mf;
     k.N = (int)Nf;
@@ -277,7 +282,8 @@ lidar_status run_setup(lidar_sim* h)
     k.KH = 2 * k.N + 1;
     const size_t cells = (size_t)k.KW * k.KH;
     HIP_TRY(h, h->d_K64.ensure(cells), "allocate kernel");
-    HIP_TRY(h, h->d_Kt.ensure(cells), "allocate kernel");
+    HIP_TRY(h, h->d_Kb.ensure((size_t)4 * kernel_blocks(k.KW) * (k.KH + 1) * 4),
+            "allocate kernel blocks");
     HIP_TRY(h, h->d_rowsum.ensure(k.KH), "allocate kernel rows");
     HIP_TRY(h, h->d_rowmax.ensure(k.KH), "allocate kernel rows");
     HIP_TRY(h, h->d_rowrange.ensure(k.KH), "allocate kernel rows");
@@ -298,7 +304,8 @@ lidar_status run_setup(lidar_sim* h)
     p.hx = h->half[0];
     p.hy = h->half[1];
     hipStream_t s = h->stream;
-    HIP_TRY(h, launch_kernel_grid(s, p, r, k, h->d_K64.p, h->d_Kt.p), "kernel grid launch");
+    HIP_TRY(h, launch_kernel_grid(s, p, r, k, h->d_K64.p), "kernel grid launch");
+    HIP_TRY(h, launch_kernel_blocks(s, k, h->d_K64.p, h->d_Kb.p), "kernel blocks launch");
     HIP_TRY(h, launch_kernel_rows(s, k, h->d_K64.p, h->d_rowsum.p, h->d_rowmax.p,
                                   h->d_rowrange.p, h->d_prefix.p), "kernel rows launch");
     HIP_TRY(h, launch_kernel_peak(s, k, h->d_rowsum.p, h->d_rowmax.p, h->d_kinfo.p),
@@ -420,7 +427,7 @@ lidar_status lidar_sim_destroy(lidar_sim* h)
         }
     h->d_table.release(); h->d_az.release(); h->d_el.release(); h->d_groups.release();
     h->d_K64.release(); h->d_rowsum.release(); h->d_rowmax.release(); h->d_kinfo.release();
-    h->d_Kt.release(); h->d_rowrange.release(); h->d_prefix.release();
+    h->d_Kb.release(); h->d_rowrange.release(); h->d_prefix.release();
     h->d_colcs.release(); h->d_rowtab.release(); h->d_beams.release(); h->d_taps.release();
     h->d_pix.release(); h->d_sun.release(); h->d_echoes.release(); h->d_counts.release();
     h->d_waves.release();
@@ -524,7 +531,8 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
         if (st != LIDAR_OK) return st;
     }
     const lidar_gbuffer_desc& g = h->gb;
-    const size_t npix = (size_t)g.width * g.height;
+    const int W4 = (int)((g.width + 3) & ~3u);
+    const size_t npix = (size_t)W4 * g.height;
     const size_t B = h->az.size();
     const uint32_t R = h->prm.n_bins, E = h->prm.max_echoes;
     const bool sun = h->prm.sun_irradiance != 0.0;
@@ -557,16 +565,19 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
     pa.sun_z = (float)h->prm.sun_dir[2];
     pa.pix = h->d_pix.p;
     pa.sun = sun ? h->d_sun.p : nullptr;
+    pa.W4 = W4;
 
     FootprintArgs fa;
     fa.pix = h->d_pix.p;
     fa.sun = sun ? h->d_sun.p : nullptr;
     fa.W = r.W;
     fa.H = r.H;
-    fa.Kt = h->d_Kt.p;
+    fa.Kb = h->d_Kb.p;
+    fa.NB = kernel_blocks(h->kgeom.KW);
     fa.rowrange = h->d_rowrange.p;
     fa.M = h->kgeom.M;
     fa.N = h->kgeom.N;
+    fa.KW = h->kgeom.KW;
     fa.KH = h->kgeom.KH;
     fa.groups = h->d_groups.p;
     fa.n_groups = h->n_groups;

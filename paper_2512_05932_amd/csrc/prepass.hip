@@ -6,9 +6,11 @@
 // Eq. 2), and the pixel's time bin k = floor(2 d / (c dt)) (the Dirac delta
 // of Eq. 3) is taken once per pixel in FP64.  Sky, non-finite or
 // non-positive depths and ranges beyond the last bin get bin -1 and zero
-// shade.  The records are written column-major ([u][v], v contiguous) so that
-// the footprint kernel's lanes, which walk rows in parallel, read them
-// coalesced; the transpose goes through a 32x32 LDS tile.
+// shade.  The records are written in blocks of 4 columns ([u/4][v][u%4]) so
+// that a footprint-kernel lane, which owns one row, reads 4 consecutive
+// columns of its row with one 16-byte access, and the 64 lanes of a wave
+// (64 consecutive rows) read one contiguous span; the transpose goes through
+// a 32x32 LDS tile.  Columns between W and the next multiple of 4 are sky.
 #include "engine.h"
 
 namespace lidar {
@@ -60,22 +62,25 @@ void k_prepass(PrepassArgs a)
         if (SUN) tsun[vl][tx] = sunv;
     }
     __syncthreads();
-    // write columns (coalesced along v)
+    // write 8 blocks of 4 columns x 32 rows, each contiguous in memory
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int p = 0; p < kTile / kRowsPerPass; ++p) {
-        int ul = ty + p * kRowsPerPass;
-        int u = u0 + ul, v = v0 + tx;
-        if (u < a.W && v < a.H) {
-            long o = (long)u * a.H + v;
-            a.pix[o] = trec[tx][ul];
-            if (SUN) a.sun[o] = tsun[tx][ul];
+    for (int p = 0; p < (kTile * kTile) / (kTile * kRowsPerPass); ++p) {
+        const int e = p * kTile * kRowsPerPass + tid;     // 0 .. 1023
+        const int bi = e / (4 * kTile), r = (e / 4) % kTile, j = e % 4;
+        const int u = u0 + bi * 4 + j, v = v0 + r;
+        if (u < a.W4 && v < a.H) {
+            const long o = (((long)(u >> 2) * a.H + v) << 2) + (u & 3);
+            // columns past W (padding) were staged as sky above
+            a.pix[o] = trec[r][bi * 4 + j];
+            if (SUN) a.sun[o] = tsun[r][bi * 4 + j];
         }
     }
 }
 
 hipError_t launch_prepass(hipStream_t s, const PrepassArgs& a, bool with_sun)
 {
-    dim3 grid((a.W + kTile - 1) / kTile, (a.H + kTile - 1) / kTile);
+    dim3 grid((a.W4 + kTile - 1) / kTile, (a.H + kTile - 1) / kTile);
     dim3 block(kTile * kRowsPerPass);
     if (with_sun)
         hipLaunchKernelGGL(k_prepass<true>, grid, block, 0, s, a);

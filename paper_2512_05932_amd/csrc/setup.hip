@@ -54,17 +54,36 @@ __device__ static double row_omega(const RasterDev& r, long v)
     return (r.dphi * d2r) * (sin(e_top * d2r) - sin(e_bot * d2r));
 }
 
-// K64[n+N][m+M] (row-major, FP64) and Kt[m+M][n+N] (column-major, FP32).
-__global__ void k_kernel_grid(PatternDev p, RasterDev r, KernelDev k, double* K64, float* Kt)
+// K64[n+N][m+M]: the kernel on the pixel-offset grid (row-major, FP64).
+__global__ void k_kernel_grid(PatternDev p, RasterDev r, KernelDev k, double* K64)
 {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     long total = (long)k.KW * k.KH;
     if (idx >= total) return;
     int row = (int)(idx / k.KW), col = (int)(idx % k.KW);
     int n = row - k.N, m = col - k.M;
-    double v = pattern_at(p, (double)m * r.dphi, -(double)n * r.de);
-    K64[idx] = v;
-    Kt[(long)col * k.KH + row] = (float)v;
+    K64[idx] = pattern_at(p, (double)m * r.dphi, -(double)n * r.de);
+}
+
+// FP32 copy of the kernel in the blocked, shifted layout the footprint
+// kernel reads (see kernel_blocks in engine.h).
+__global__ void k_kernel_blocks(KernelDev k, const double* K64, float* Kb)
+{
+    const int NB = kernel_blocks(k.KW);
+    const long khp = (long)k.KH + 1;
+    long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long total = 4L * NB * khp * 4;
+    if (idx >= total) return;
+    int j = (int)(idx % 4);
+    long t = idx / 4;
+    int n = (int)(t % khp);
+    t /= khp;
+    int b = (int)(t % NB);
+    int sft = (int)(t / NB);
+    int c = 4 * (b - kBlockPad) + sft + j;
+    float v = 0.0f;
+    if (n < k.KH && c >= 0 && c < k.KW) v = (float)K64[(long)n * k.KW + c];
+    Kb[idx] = v;
 }
 
 // Per kernel row: FP64 sum, max, first/last non-zero column offset, and the
@@ -200,11 +219,19 @@ __global__ void k_pulse_taps(float sigma_ns, float bin_ns, int J, float* taps)
 }
 
 hipError_t launch_kernel_grid(hipStream_t s, PatternDev p, RasterDev r, KernelDev k,
-                              double* K64, float* Kt)
+                              double* K64)
 {
     long total = (long)k.KW * k.KH;
     int blocks = (int)((total + 255) / 256);
-    hipLaunchKernelGGL(k_kernel_grid, dim3(blocks), dim3(256), 0, s, p, r, k, K64, Kt);
+    hipLaunchKernelGGL(k_kernel_grid, dim3(blocks), dim3(256), 0, s, p, r, k, K64);
+    return hipGetLastError();
+}
+
+hipError_t launch_kernel_blocks(hipStream_t s, KernelDev k, const double* K64, float* Kb)
+{
+    long total = 4L * kernel_blocks(k.KW) * ((long)k.KH + 1) * 4;
+    int blocks = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(k_kernel_blocks, dim3(blocks), dim3(256), 0, s, k, K64, Kb);
     return hipGetLastError();
 }
 
