@@ -41,8 +41,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (for profiler runs)")
-    ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with per-dispatch HBM bytes of the footprint kernel")
+    ap.add_argument("--traffic", type=str,
+                    default=os.path.join(ROOT, "profiles", "k_footprint_scan8192x512_traffic.json"),
+                    help="JSON file with per-dispatch HBM bytes of the footprint kernel "
+                         "(ignored when it was taken with another kernel source)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the "
                          "reference for scaling the HBM byte counters")
@@ -59,6 +61,24 @@ def copy_calibration(mib: int):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
+
+
+def measured_traffic(path):
+    """HBM bytes per launch of the footprint kernel from rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (scaled by a plain-copy calibration), or None when the
+    counters were taken with a different kernel source."""
+    import hashlib
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, rec.get("source", ""))
+    if not os.path.exists(src):
+        return None
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec.get("source_sha256"):
+            return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(w):
@@ -136,10 +156,7 @@ def main():
     sun = w.params.sun_irradiance != 0.0
     flops = samples * (FLOPS_PER_SAMPLE + (FLOPS_PER_SAMPLE_SUN if sun else 0))
     achieved = flops / (fp_ms * 1e-3) / 1e12
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+    traffic = measured_traffic(args.traffic)
     rec = {
         "metric": METRIC,
         "value": samples * args.steps / (total_ms * 1e-3),

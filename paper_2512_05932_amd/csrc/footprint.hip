@@ -218,56 +218,70 @@ void k_footprint(FootprintArgs a)
             float acc[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) acc[g] = 0.0f;
+            const char* pb = pbase;
+            const char* sb = sbase;
             for (int i = 0; i < nblk; ++i) {
-                // all loads of the 4-column batch first
-                const char* pb = pbase + (size_t)i * pstep;
+                // all loads of the 4-column batch first (uniform bases, per-lane offsets)
                 const int4 ra = ld16<int4>(pb, pvo);
                 const int4 rb = ld16<int4>(pb, pvo + 16u);
                 float4 sq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (SUN) sq = ld16<float4>(sbase + (size_t)i * sstep, svo);
+                if (SUN) sq = ld16<float4>(sb, svo);
                 const float sv[4] = {sq.x, sq.y, sq.z, sq.w};
                 float kv[4][G];
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     const int b = min(max(kblk[g] + i, 0), a.NB - 1);
-                    const float4 kq = ld16<float4>(kcopy[g] + (size_t)b * khp16, kvo[g]);
+                    const float4 kq = ld16<float4>(kcopy[g] + (unsigned)(b * (int)khp16), kvo[g]);
                     kv[0][g] = kq.x;
                     kv[1][g] = kq.y;
                     kv[2][g] = kq.z;
                     kv[3][g] = kq.w;
                 }
+                pb += pstep;
+                if (SUN) sb += sstep;
                 const int bin[4] = {ra.x, ra.z, rb.x, rb.z};
                 const float sh[4] = {__int_as_float(ra.y), __int_as_float(ra.w),
                                      __int_as_float(rb.y), __int_as_float(rb.w)};
-                // four branch-free column steps; the state before each step is
-                // kept for the flush below
-                int curb[4];
-                float accb[4][G];
+                // fast path: no run ends in this batch for most lanes and
+                // batches, so accumulate without resets and detect breaks
+                const int cur0 = cur;
+                float acc0[G];
                 unsigned long long nrm = 0;
 #pragma unroll
+                for (int g = 0; g < G; ++g) acc0[g] = acc[g];
+#pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const bool nr = bin[j] != cur;
-                    nrm |= __ballot(nr);
-                    curb[j] = cur;
+                    nrm |= __ballot(bin[j] != (j == 0 ? cur0 : bin[j - 1]));
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
-                        accb[j][g] = acc[g];
-                        acc[g] = (nr ? 0.0f : acc[g]) + kv[j][g] * sh[j];
+                        acc[g] += kv[j][g] * sh[j];
                         if (SUN) sacc[g] += kv[j][g] * sv[j];
                     }
-                    cur = bin[j];
                 }
-                // runs that ended in this batch go to the histograms
+                cur = bin[3];
                 if (nrm) {
+                    // some run ended: replay the batch from its start with the
+                    // resets, flushing every run that ends (same summation order
+                    // as the fast path where no run ends)
+                    float r[G];
+                    int c = cur0;
+#pragma unroll
+                    for (int g = 0; g < G; ++g) r[g] = acc0[g];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        unsigned any = __builtin_bit_cast(unsigned, accb[j][0]);
+                        const bool nr = bin[j] != c;
+                        unsigned any = __builtin_bit_cast(unsigned, r[0]);
 #pragma unroll
-                        for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, accb[j][g]);
-                        const bool fl = bin[j] != curb[j] && any != 0u;   // sums are >= 0
+                        for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, r[g]);
+                        const bool fl = nr && any != 0u;            // sums are >= 0
                         const unsigned long long fm = __ballot(fl);
-                        if (fm) flush_runs<G>(fm, fl, curb[j], accb[j], hist, a.R, lane);
+                        if (fm) flush_runs<G>(fm, fl, c, r, hist, a.R, lane);
+#pragma unroll
+                        for (int g = 0; g < G; ++g) r[g] = (nr ? 0.0f : r[g]) + kv[j][g] * sh[j];
+                        c = bin[j];
                     }
+#pragma unroll
+                    for (int g = 0; g < G; ++g) acc[g] = r[g];
                 }
             }
             unsigned any = __builtin_bit_cast(unsigned, acc[0]);
