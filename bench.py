@@ -81,6 +81,58 @@ def measured_traffic(path):
     return rec.get("bytes_per_launch")
 
 
+def precision_report(w, planes, n_sample=240, seed=7):
+    """Error of every output field against the FP64 oracle on a seeded sample
+    of the frame's beams (the GPU runs the whole frame with waveforms kept)."""
+    import numpy as np
+    import torch
+    import oracle
+    import scenes
+    import paper_2512_05932_amd as lidar
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(w.pattern.n_beams, size=min(n_sample, w.pattern.n_beams),
+                             replace=False))
+    sim = lidar.LidarSim(w.params, stream=torch.cuda.current_stream(), keep_waveforms=True)
+    sim.set_pattern(w.pattern)
+    sim.set_gbuffer(w.gbuffer.raster, planes)
+    sim.simulate_frame()
+    got = sim.read(waveforms=True)
+    sim.close()
+    sub = scenes.subset_beams(w, idx)
+    ref = oracle.simulate(w.gbuffer, sub.pattern, sub.params, want_xi=False)
+    T, E = w.params.threshold, w.params.max_echoes
+    peak = ref.xi_hat.max(axis=1)
+    wav = got["waveforms"][idx].astype(np.float64)
+    wave_err = np.abs(wav - ref.xi_hat).max(axis=1) / peak
+    amb = (np.abs(ref.xi_hat - T) <= 1e-5 * peak[:, None]).any(axis=1)
+    cnt = got["n_echoes"][idx]
+    bi = got["beams"][idx]
+    rng_bins, int_err, epw_err, n_e = [], [], [], 0
+    for k in np.nonzero(~amb)[0]:
+        for i in range(min(int(ref.n_echoes[k]), E)):
+            ge, re = got["echoes"][idx[k], i], ref.echoes[k, i]
+            n_e += 1
+            rng_bins.append(abs(int(ge["bin_peak"]) - int(re["bin_peak"])))
+            int_err.append(abs(float(ge["intensity"]) - re["intensity"]) / peak[k])
+            epw_err.append(abs(float(ge["pulse_width_ns"]) - re["pulse_width_ns"]))
+    return {"beams": int(len(idx)), "threshold_ambiguous_beams": int(amb.sum()),
+            "waveform_max_rel_err": float(wave_err.max()),
+            "waveform_mean_rel_err": float(wave_err.mean()),
+            "echo_count_exact_frac": float((cnt[~amb] == ref.n_echoes[~amb]).mean()),
+            "echoes_compared": n_e,
+            "range_max_bin_err": int(max(rng_bins) if rng_bins else 0),
+            "range_exact_frac": float(np.mean(np.array(rng_bins) == 0) if rng_bins else 1.0),
+            "intensity_max_rel_err": float(max(int_err) if int_err else 0.0),
+            "epw_max_abs_err_ns": float(max(epw_err) if epw_err else 0.0),
+            "floor_max_rel_err": float((np.abs(bi["floor"] - ref.floor) /
+                                        np.maximum(ref.floor, 1e-300)).max()),
+            "scale_max_rel_err": float((np.abs(bi["scale"] - ref.scale) / ref.scale).max()),
+            "pixel_exact": bool(np.array_equal(bi["pixel_u"], ref.pixel[:, 0]) and
+                                np.array_equal(bi["pixel_v"], ref.pixel[:, 1])),
+            "samples_exact": bool(np.array_equal(bi["samples"], ref.samples)),
+            "reference": "FP64 CPU oracle"}
+
+
 def cpu_baseline(w):
     """The FP64 oracle as it stands, on the host cores: one full frame with
     every core, plus a 1-core rate on a beam sample."""
@@ -180,6 +232,7 @@ def main():
         "prepass_ms": st["prepass_ms"] / max(1, st["prepass_launches"]),
     }
     if not args.no_cpu_baseline:
+        rec["precision"] = precision_report(w, planes)
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)
 

@@ -55,7 +55,9 @@ enum {
 /* lidar_sim_params.flags */
 enum {
     LIDAR_KEEP_WAVEFORMS = 1u,  /* keep xi_hat [n_beams][n_bins] for read_echoes */
-    LIDAR_PROFILE = 2u          /* time the footprint kernel with HIP events */
+    LIDAR_PROFILE = 2u,         /* time the footprint kernel with HIP events */
+    LIDAR_AUTOTUNE = 4u         /* batches: time the tile candidates per kernel-size
+                                   class when a batch is set up, keep the fastest */
 };
 
 /* lidar_pattern_desc.kind */
@@ -69,7 +71,7 @@ enum { LIDAR_ECHO_AT_FIRST_BIN = 1u, LIDAR_ECHO_AT_LAST_BIN = 2u };
 
 /* Sensor and receiver parameters of one handle (copied at create). */
 typedef struct {
-    uint32_t n_bins;           /* R: time bins of the waveform, 1..8192 */
+    uint32_t n_bins;           /* R: time bins of the waveform, 1..8000 */
     uint32_t max_echoes;       /* echoes kept per beam, 1..8 (all are counted) */
     double bin_ns;             /* bin width dt (ns), > 0 */
     double threshold;          /* detection threshold T in waveform units; an echo
@@ -81,7 +83,7 @@ typedef struct {
     double ambient_const;      /* constant floor added to every bin */
     double sun_irradiance;     /* E_sun, 0 = no sun term */
     double sun_dir[3];         /* unit vector towards the sun, sensor frame */
-    uint32_t flags;            /* LIDAR_KEEP_WAVEFORMS | LIDAR_PROFILE */
+    uint32_t flags;            /* LIDAR_KEEP_WAVEFORMS | LIDAR_PROFILE | LIDAR_AUTOTUNE */
     uint32_t reserved;         /* must be 0 */
 } lidar_sim_params;
 
@@ -140,9 +142,23 @@ typedef struct {
     uint32_t reserved;
 } lidar_beam_info;
 
+/* How a batch is scheduled (lidar_sim_batch_info). */
+typedef struct {
+    uint32_t n_frames;
+    uint32_t group_size;       /* G: beams per workgroup item */
+    uint64_t n_beams;          /* sum over frames */
+    uint64_t n_items;          /* (frame, beam group) work items */
+    uint64_t samples;          /* sum over frames of beam-pixel samples */
+    uint32_t grid;             /* workgroups of the persistent launch */
+    uint32_t graph;            /* 1 when the batch replays a captured HIP graph */
+    uint32_t autotuned;        /* 1 when the tiles came from timed trials */
+    uint32_t reserved;
+    double autotune_ms;        /* time spent in the trials */
+} lidar_batch_info;
+
 /* Counters of a handle since create or the last reset_stats. */
 typedef struct {
-    uint64_t frames;           /* simulate_frame calls completed */
+    uint64_t frames;           /* frames enqueued (simulate_frame calls plus batch frames) */
     uint64_t n_beams;          /* beams of the current pattern */
     uint64_t samples_per_frame;/* sum over beams of lidar_beam_info.samples */
     uint32_t kernel_w, kernel_h;   /* 2M+1, 2N+1 of the current kernel grid */
@@ -152,6 +168,8 @@ typedef struct {
     uint64_t footprint_launches;
     double prepass_ms;         /* LIDAR_PROFILE: summed G-buffer pre-pass time */
     uint64_t prepass_launches;
+    double batch_ms;           /* LIDAR_PROFILE: summed batch graph time (pre-passes included) */
+    uint64_t batch_launches;
 } lidar_stats;
 
 /* Create a handle with the given parameters on a HIP stream (void* =
@@ -198,6 +216,41 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode);
 lidar_status lidar_sim_read_echoes(lidar_sim* h, lidar_echo* echoes, int32_t* n_echoes,
                                    float* waveforms, lidar_beam_info* beams,
                                    int dst_is_device);
+
+/* Extension: many frames in one launch.  frames[i] and patterns[i] describe
+ * frame i (its own raster, device G-buffer planes, pattern and beams); every
+ * frame uses the handle's sensor parameters.  The first call with a set of
+ * descriptors copies the patterns, resamples every frame's kernel, forms the
+ * beam groups of all frames into one work list ordered by estimated cost
+ * (costliest first), optionally autotunes the strip height of each
+ * kernel-size class (LIDAR_AUTOTUNE), and captures the whole batch - per-frame
+ * pre-passes plus one persistent footprint launch that takes work items from
+ * a queue - into a HIP graph.  Later calls with identical descriptors (same
+ * pointers, sizes and values) only replay the graph; the caller may change the
+ * contents of the G-buffer planes between calls, but not the host pattern or
+ * beam arrays (call lidar_sim_reset_batch after changing those in place).
+ * Results of frame i are read with lidar_sim_read_batch.  Asynchronous except
+ * for the first call of a new batch.
+ * Errors: as set_pattern / set_gbuffer for any frame (the message names it),
+ * LIDAR_E_INVALID (n_frames = 0 or a null array), LIDAR_E_HIP, LIDAR_E_NOMEM. */
+lidar_status lidar_sim_simulate_batch(lidar_sim* h, const lidar_gbuffer_desc* frames,
+                                      const lidar_pattern_desc* patterns, uint32_t n_frames);
+
+/* Results of frame `frame` of the last batch, laid out as in
+ * lidar_sim_read_echoes for that frame's beams.
+ * Errors: LIDAR_E_STATE (no batch simulated), LIDAR_E_INVALID (frame out of
+ * range, waveforms without LIDAR_KEEP_WAVEFORMS), LIDAR_E_HIP. */
+lidar_status lidar_sim_read_batch(lidar_sim* h, uint32_t frame, lidar_echo* echoes,
+                                  int32_t* n_echoes, float* waveforms, lidar_beam_info* beams,
+                                  int dst_is_device);
+
+/* Schedule of the current batch.  Errors: LIDAR_E_INVALID (null),
+ * LIDAR_E_STATE (no batch). */
+lidar_status lidar_sim_batch_info(lidar_sim* h, lidar_batch_info* out);
+
+/* Forget the cached batch (set-up, schedule, graph); the next
+ * simulate_batch sets it up again.  Errors: LIDAR_E_INVALID (null). */
+lidar_status lidar_sim_reset_batch(lidar_sim* h);
 
 /* Counters since create or the last reset (synchronises profiling events).
  * Errors: LIDAR_E_INVALID (null), LIDAR_E_HIP. */

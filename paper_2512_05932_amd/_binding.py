@@ -23,6 +23,7 @@ LIDAR_E_UNSUPPORTED = -5
 
 LIDAR_KEEP_WAVEFORMS = 1
 LIDAR_PROFILE = 2
+LIDAR_AUTOTUNE = 4
 LIDAR_PATTERN_GAUSS = 1
 LIDAR_PATTERN_TABLE = 2
 LIDAR_MODE_PLAIN = 0
@@ -30,7 +31,9 @@ LIDAR_MODE_PLAIN = 0
 # every function the header declares
 EXPORTED = ["lidar_sim_create", "lidar_sim_destroy", "lidar_sim_set_pattern",
             "lidar_sim_set_gbuffer", "lidar_sim_simulate_frame", "lidar_sim_read_echoes",
-            "lidar_sim_get_stats", "lidar_sim_reset_stats", "lidar_sim_last_error"]
+            "lidar_sim_simulate_batch", "lidar_sim_read_batch", "lidar_sim_batch_info",
+            "lidar_sim_reset_batch", "lidar_sim_get_stats", "lidar_sim_reset_stats",
+            "lidar_sim_last_error"]
 
 
 class lidar_sim_params(C.Structure):
@@ -61,7 +64,15 @@ class lidar_stats(C.Structure):
                 ("samples_per_frame", C.c_uint64), ("kernel_w", C.c_uint32),
                 ("kernel_h", C.c_uint32), ("n_taps", C.c_uint32), ("reserved", C.c_uint32),
                 ("footprint_ms", C.c_double), ("footprint_launches", C.c_uint64),
-                ("prepass_ms", C.c_double), ("prepass_launches", C.c_uint64)]
+                ("prepass_ms", C.c_double), ("prepass_launches", C.c_uint64),
+                ("batch_ms", C.c_double), ("batch_launches", C.c_uint64)]
+
+
+class lidar_batch_info(C.Structure):
+    _fields_ = [("n_frames", C.c_uint32), ("group_size", C.c_uint32), ("n_beams", C.c_uint64),
+                ("n_items", C.c_uint64), ("samples", C.c_uint64), ("grid", C.c_uint32),
+                ("graph", C.c_uint32), ("autotuned", C.c_uint32), ("reserved", C.c_uint32),
+                ("autotune_ms", C.c_double)]
 
 
 ECHO_DTYPE = np.dtype([("range_m", "<f8"), ("time_ns", "<f8"), ("intensity", "<f4"),
@@ -95,6 +106,11 @@ def load():
     lib.lidar_sim_set_gbuffer.argtypes = [V, P(lidar_gbuffer_desc)]
     lib.lidar_sim_simulate_frame.argtypes = [V, C.c_uint32]
     lib.lidar_sim_read_echoes.argtypes = [V, V, V, V, V, C.c_int]
+    lib.lidar_sim_simulate_batch.argtypes = [V, P(lidar_gbuffer_desc), P(lidar_pattern_desc),
+                                             C.c_uint32]
+    lib.lidar_sim_read_batch.argtypes = [V, C.c_uint32, V, V, V, V, C.c_int]
+    lib.lidar_sim_batch_info.argtypes = [V, P(lidar_batch_info)]
+    lib.lidar_sim_reset_batch.argtypes = [V]
     lib.lidar_sim_get_stats.argtypes = [V, P(lidar_stats)]
     lib.lidar_sim_reset_stats.argtypes = [V]
     lib.lidar_sim_last_error.argtypes = [V]
@@ -114,15 +130,72 @@ def make_params(p, flags: int = 0) -> lidar_sim_params:
                             int(flags), 0)
 
 
+def pattern_desc(pattern, keep: list) -> lidar_pattern_desc:
+    """Descriptor of a pattern; the host arrays it points to go into `keep`."""
+    az = np.ascontiguousarray(pattern.beam_az, dtype=np.float64)
+    el = np.ascontiguousarray(pattern.beam_el, dtype=np.float64)
+    d = lidar_pattern_desc()
+    d.kind = int(pattern.kind)
+    d.n_beams = az.shape[0]
+    d.beam_az_deg = az.ctypes.data_as(C.POINTER(C.c_double))
+    d.beam_el_deg = el.ctypes.data_as(C.POINTER(C.c_double))
+    keep += [az, el]
+    if pattern.kind == LIDAR_PATTERN_GAUSS:
+        d.sigma_deg = (C.c_double * 2)(*map(float, pattern.sigma_deg))
+        d.trunc_sigmas = float(pattern.trunc_sigmas)
+    else:
+        table = np.ascontiguousarray(pattern.table, dtype=np.float32)
+        d.table = table.ctypes.data_as(C.POINTER(C.c_float))
+        d.ny, d.nx = table.shape
+        d.half_deg = (C.c_double * 2)(*map(float, pattern.half_deg))
+        keep.append(table)
+    return d
+
+
+def gbuffer_desc(raster, planes, pitch: int | None = None) -> lidar_gbuffer_desc:
+    """Descriptor of six float32 device planes [H][pitch] (torch tensors)."""
+    ptrs = [int(t.data_ptr()) for t in planes]
+    return lidar_gbuffer_desc(int(raster.width), int(raster.height),
+                              int(pitch if pitch is not None else raster.width),
+                              float(raster.az_min), float(raster.az_max),
+                              float(raster.el_min), float(raster.el_max), *ptrs)
+
+
+class Batch:
+    """Descriptor arrays of a batch of frames, built once so that repeated
+    simulate_batch calls pass identical descriptors (and replay the captured
+    graph).  frames: list of (raster, planes) or (raster, planes, pitch);
+    patterns: one pattern per frame (the same object may repeat)."""
+
+    def __init__(self, frames, patterns):
+        if len(frames) != len(patterns) or not frames:
+            raise ValueError("need one pattern per frame and at least one frame")
+        n = len(frames)
+        self.n_frames = n
+        self.gb = (lidar_gbuffer_desc * n)()
+        self.pd = (lidar_pattern_desc * n)()
+        self._keep: list = []
+        cache = {}
+        for i, (fr, pat) in enumerate(zip(frames, patterns)):
+            raster, planes = fr[0], fr[1]
+            pitch = fr[2] if len(fr) > 2 else None
+            self.gb[i] = gbuffer_desc(raster, planes, pitch)
+            self._keep.append(planes)
+            if id(pat) not in cache:
+                cache[id(pat)] = pattern_desc(pat, self._keep)
+            self.pd[i] = cache[id(pat)]
+        self.n_beams = [int(self.pd[i].n_beams) for i in range(n)]
+
+
 class LidarSim:
     """One engine handle on one HIP stream."""
 
     def __init__(self, params, stream=None, keep_waveforms: bool = False,
-                 profile: bool = False):
+                 profile: bool = False, autotune: bool = False):
         self._lib = load()
         self.params = params
         flags = (LIDAR_KEEP_WAVEFORMS if keep_waveforms else 0) | \
-            (LIDAR_PROFILE if profile else 0)
+            (LIDAR_PROFILE if profile else 0) | (LIDAR_AUTOTUNE if autotune else 0)
         self._prm = make_params(params, flags)
         self._h = C.c_void_p()
         s = C.c_void_p(stream.cuda_stream if stream is not None else 0)
@@ -149,22 +222,8 @@ class LidarSim:
             pass
 
     def set_pattern(self, pattern):
-        az = np.ascontiguousarray(pattern.beam_az, dtype=np.float64)
-        el = np.ascontiguousarray(pattern.beam_el, dtype=np.float64)
-        d = lidar_pattern_desc()
-        d.kind = int(pattern.kind)
-        d.n_beams = az.shape[0]
-        d.beam_az_deg = az.ctypes.data_as(C.POINTER(C.c_double))
-        d.beam_el_deg = el.ctypes.data_as(C.POINTER(C.c_double))
-        table = None
-        if pattern.kind == LIDAR_PATTERN_GAUSS:
-            d.sigma_deg = (C.c_double * 2)(*map(float, pattern.sigma_deg))
-            d.trunc_sigmas = float(pattern.trunc_sigmas)
-        else:
-            table = np.ascontiguousarray(pattern.table, dtype=np.float32)
-            d.table = table.ctypes.data_as(C.POINTER(C.c_float))
-            d.ny, d.nx = table.shape
-            d.half_deg = (C.c_double * 2)(*map(float, pattern.half_deg))
+        keep: list = []
+        d = pattern_desc(pattern, keep)
         self._check(self._lib.lidar_sim_set_pattern(self._h, C.byref(d)))
         self.n_beams = d.n_beams
 
@@ -172,11 +231,7 @@ class LidarSim:
         """planes: (depth, reflectance, retro_gain, normal_x, normal_y, normal_z),
         float32 device tensors [H][pitch] (kept alive by this object until the
         next call)."""
-        ptrs = [int(t.data_ptr()) for t in planes]
-        d = lidar_gbuffer_desc(int(raster.width), int(raster.height),
-                               int(pitch if pitch is not None else raster.width),
-                               float(raster.az_min), float(raster.az_max),
-                               float(raster.el_min), float(raster.el_max), *ptrs)
+        d = gbuffer_desc(raster, planes, pitch)
         self._check(self._lib.lidar_sim_set_gbuffer(self._h, C.byref(d)))
         self._keep = list(planes)
 
@@ -201,6 +256,32 @@ class LidarSim:
         p = lambda t: int(t.data_ptr()) if t is not None else None
         self._check(self._lib.lidar_sim_read_echoes(self._h, p(echoes), p(n_echoes),
                                                     p(waveforms), p(beams), 1))
+
+    def simulate_batch(self, batch: Batch):
+        self._check(self._lib.lidar_sim_simulate_batch(self._h, batch.gb, batch.pd,
+                                                       batch.n_frames))
+        self._batch = batch
+
+    def read_batch(self, frame: int, waveforms: bool = False, beams: bool = True):
+        """Frame `frame` of the last batch as host numpy arrays (synchronises)."""
+        B, E, R = self._batch.n_beams[frame], int(self.params.max_echoes), int(self.params.n_bins)
+        ech = np.zeros((B, E), dtype=ECHO_DTYPE)
+        cnt = np.zeros(B, dtype=np.int32)
+        wav = np.zeros((B, R), dtype=np.float32) if waveforms else None
+        bi = np.zeros(B, dtype=BEAM_DTYPE) if beams else None
+        self._check(self._lib.lidar_sim_read_batch(
+            self._h, int(frame), ech.ctypes.data, cnt.ctypes.data,
+            wav.ctypes.data if wav is not None else None,
+            bi.ctypes.data if bi is not None else None, 0))
+        return {"echoes": ech, "n_echoes": cnt, "waveforms": wav, "beams": bi}
+
+    def batch_info(self) -> dict:
+        s = lidar_batch_info()
+        self._check(self._lib.lidar_sim_batch_info(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in s._fields_ if f != "reserved"}
+
+    def reset_batch(self):
+        self._check(self._lib.lidar_sim_reset_batch(self._h))
 
     def stats(self) -> dict:
         s = lidar_stats()

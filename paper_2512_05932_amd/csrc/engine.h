@@ -75,30 +75,53 @@ hipError_t launch_prepass(hipStream_t s, const PrepassArgs& a, bool with_sun);
 constexpr int kBlockPad = 2;
 __host__ __device__ inline int kernel_blocks(int KW) { return (KW + 12) / 4 + 1; }
 
-struct FootprintArgs {
-    const int2* pix;            // [W4/4][H][4]
+// One frame as the footprint kernels see it.  Beam indices in groups are
+// local to the frame; the output pointers are already offset to the frame.
+struct FrameDev {
+    const int2* pix;            // [W4/4][H][4] {bin, shade bits}
     const float* sun;           // [W4/4][H][4] or null
     int W, H;
     const float* Kb;            // [4][NB][KH+1][4], see kernel_blocks
     const int2* rowrange;       // [KH] first/last m with K > 0 (empty row: INT_MAX, INT_MIN)
     int M, N, KW, KH, NB;
-    const int32_t* groups;      // [n_groups][G] beam indices, -1 = empty slot
-    int n_groups, G, chunk;     // chunk = ceil(n_groups / kXcds)
-    lidar_beam_info* beams;     // [B] in: pixel, scale; out: floor
-    const float* taps;          // [2J+1]
-    int J;
-    int R;
-    float threshold;
-    float ambient;
+    int tile;                   // strip height: 64, 16 or 4 rows (64/tile column phases)
     float sun_scale;            // E_sun / max K (0: no sun term)
-    int E;
+    lidar_beam_info* beams;     // [B] in: pixel, scale; out: floor
     lidar_echo* echoes;         // [B][E]
     int32_t* counts;            // [B]
     float* waves;               // [B][R] or null
+};
+
+// Parameters shared by every frame of a handle.
+struct PathDev {
+    const float* taps;          // [2J+1]
+    int J, R, E;
+    float threshold;
+    float ambient;
     double half_c_dt;           // (c/2) dt in metres, FP64
     double bin_ns;
 };
+
+struct FootprintArgs {
+    FrameDev f;
+    PathDev p;
+    const int32_t* groups;      // [n_groups][G] beam indices, -1 = empty slot
+    int n_groups, G, chunk;     // chunk = ceil(n_groups / kXcds)
+};
 hipError_t launch_footprint(hipStream_t s, const FootprintArgs& a);
+
+// Persistent launch over the (frame, group) items of a batch.
+struct BatchArgs {
+    const FrameDev* frames;     // [n_frames]
+    PathDev p;
+    const int32_t* groups;      // [total groups][G]: each frame's groups, concatenated
+    const int2* items;          // [n_items] {frame, global group index}, costliest first
+    int n_items, G;
+    int* next_item;             // work-queue counter (zeroed by k_reset_queue)
+};
+hipError_t launch_footprint_batch(hipStream_t s, const BatchArgs& a, int grid, bool sun,
+                                  bool keep);
+hipError_t launch_reset_queue(hipStream_t s, int* counter);
 // whether G histograms of R bins plus the pulse taps fit the LDS budget
 bool footprint_group_fits(int G, int R, int J);
 

@@ -1,25 +1,30 @@
-// Fused kernel for a group of G nearby beams: footprint gather -> per-beam
+// Fused processing of a group of G nearby beams: footprint gather -> per-beam
 // time-bin histograms in LDS -> ambient floor -> pulse convolution ->
-// wavefront-ballot echo detection.
+// wavefront-ballot echo detection.  Two kernels share the group body: one
+// workgroup per group of one frame (`k_footprint`), and a persistent kernel
+// that takes (frame, group) items of a whole batch from a work queue
+// (`k_footprint_batch`).
 //
-// Work decomposition.  One workgroup (4 waves of 64) takes a group of up to
-// G beams (formed by the host scheduler from beams that are close on the
-// raster).  The union of their footprints (kernel windows of Eq. 5 / Alg. 1,
-// clipped to the image) is cut into strips of 64 image rows; in a strip every
-// lane owns one row and the wave walks the strip's columns together, so each
-// step reads 64 consecutive column-major pixel records and, per beam, 64
-// consecutive kernel values (coalesced loads).  A pixel's time bin does not
-// depend on the beam, so the pixel record, its bin comparison and the sun
-// shading are shared by the G beams; only the kernel value and one FMA are
-// per beam.
+// Work decomposition.  A workgroup (4 waves of 64) takes a group of up to G
+// beams formed by the host scheduler from beams close on the raster.  The
+// union of their footprints (kernel windows of Eq. 5 / Alg. 1, clipped to the
+// image) is cut into strips of `tile` image rows.  With tile = 64 every lane
+// owns one row; with tile = 16 or 4 the 64 lanes are tile rows x 64/tile
+// column phases, for small kernels.  A lane walks its row in aligned batches
+// of 4 columns: pixel records, sun shading and the kernel are stored in
+// 4-column blocks, so a batch is one 16-byte load per stream (per beam for the
+// kernel).  A pixel's time bin does not depend on the beam, so the pixel
+// record, the bin comparison and the sun shading are shared by the G beams;
+// only the kernel value and two FMAs are per beam.
 //
 // Run accumulation.  A lane sums the weights of consecutive pixels of its row
-// that fall into the same bin in registers (one sum per beam) and adds them
-// to the LDS histograms when the bin changes.  Rows that cross the same
-// surface change bin at the same column, so the lanes that flush usually
-// share their bin: they are reduced across the wave with DPP (one LDS atomic
-// per bin and beam instead of one per lane, which would serialise on the
-// shared address); the remaining lanes add individually.
+// that fall into the same bin in registers (one sum per beam) and adds them to
+// the LDS histograms when the bin changes.  Batches in which no lane's bin
+// changes (most of them) take a branch-free fast path; otherwise the batch is
+// replayed with the resets and the ended runs are flushed.  Rows that cross
+// the same surface change bin together, so the flushing lanes usually share a
+// bin: they are summed across the wave with DPP (one LDS atomic per bin and
+// beam instead of one per lane, which would serialise on the shared address).
 //
 // The histograms hold sum K * shade; the beam scale S_b is applied in the
 // pulse convolution (sliding register window, in place).  Echoes are maximal
@@ -34,14 +39,6 @@ namespace lidar {
 namespace {
 
 constexpr int kWaves = kFootprintThreads / 64;
-
-// 16-byte load at a uniform base plus a per-lane byte offset (the bases
-// derive from kernel arguments, so these become global loads).
-template <typename T>
-__device__ inline T ld16(const char* base, unsigned byte_off)
-{
-    return *(const T*)(base + byte_off);
-}
 
 __device__ inline int wave_min(int x)
 {
@@ -105,26 +102,170 @@ __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const
     }
 }
 
-}  // namespace
-
-template <int G, bool SUN, bool KEEP>
-__global__ __launch_bounds__(kFootprintThreads)
-void k_footprint(FootprintArgs a)
+// 16-byte load at a uniform base plus a per-lane byte offset (the bases
+// derive from kernel arguments, so these become global loads).
+template <typename T>
+__device__ inline T ld16(const char* base, unsigned byte_off)
 {
-    extern __shared__ float lds[];
-    float* hist = lds;                  // [G][R]: sum K * shade, then xi_hat
-    float* taps = lds + G * a.R;        // [2J+1]
-    __shared__ float red[G][kWaves];
+    return *(const T*)(base + byte_off);
+}
 
-    // XCD-aware schedule: workgroups go round-robin over the 8 XCDs, so slot
-    // s runs on XCD s % 8; each XCD takes one contiguous run of the
-    // spatially ordered groups, and the groups in flight on it share their
-    // pixels in its L2.
-    const int slot = blockIdx.x;
-    const int gi = (slot % kXcds) * a.chunk + slot / kXcds;
-    if (gi >= a.n_groups) return;
+// Gather of one group's union footprint into the G histograms (strips of
+// SH rows, 64/SH column phases); adds this lane's per-beam sun sums to sacc.
+template <int G, int SH, bool SUN>
+__device__ inline void gather_group(const FrameDev& f, const int* ub, const int* vb,
+                                    const bool* have, int r0, int r1, int q0, int q1,
+                                    float* hist, int R, int lane, int wave, float* sacc)
+{
+    constexpr int P = 64 / SH;                      // column phases per strip
+    const int row_in = lane % SH, phase = lane / SH;
+    const int nrows = r1 - r0 + 1;
+    const int nstrips = (nrows + SH - 1) / SH;
+    const int q0a = q0 & ~3;                        // batches are aligned 4-column blocks
+    const int ncols = q1 - q0a + 1;
+    // column chunks give every wave work when a group has few strips (a
+    // chunk spans at least 32 columns and two rounds of the column phases)
+    int nchunk = (2 * kWaves + nstrips - 1) / nstrips;
+    nchunk = min(nchunk, max(1, ncols / max(32, 8 * P)));
+    const int cw = (((ncols + nchunk - 1) / nchunk) + 3) & ~3;
+    const int items = nstrips * nchunk;
+    const size_t khp16 = (size_t)(f.KH + 1) * 16u;          // block stride in a copy
+    const size_t copy_bytes = (size_t)f.NB * khp16;
+    const size_t pstep = (size_t)f.H * 32u, sstep = (size_t)f.H * 16u;
+    for (int it = wave; it < items; it += kWaves) {
+        const int s = it / nchunk, ch = it - s * nchunk;
+        const int v = r0 + s * SH + row_in;
+        const bool rowok = v <= r1;
+        const int vv = rowok ? v : r1;                      // in-bounds row for idle lanes
+        unsigned kvo[G];                                    // lane offset in a kernel block
+        int lo[G], hi[G];
+        int cb = INT_MAX, ce = INT_MIN;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int n = vv - vb[g];
+            const bool ok = rowok && have[g] && n >= -f.N && n <= f.N;
+            // lanes with nothing to add read the zero guard row
+            kvo[g] = (unsigned)(ok ? n + f.N : f.KH) * 16u;
+            const int2 rr = ok ? f.rowrange[n + f.N] : make_int2(INT_MAX, INT_MIN);
+            const int wlo = wave_min(rr.x), whi = wave_max(rr.y);
+            // absolute columns where this beam can have K > 0 in the strip
+            lo[g] = __builtin_amdgcn_readfirstlane(wlo == INT_MAX ? INT_MAX : wlo + ub[g]);
+            hi[g] = __builtin_amdgcn_readfirstlane(whi == INT_MIN ? INT_MIN : whi + ub[g]);
+            cb = min(cb, lo[g]);
+            ce = max(ce, hi[g]);
+        }
+        cb = max(cb, q0a + ch * cw);
+        ce = min(ce, min(q1, q0a + ch * cw + cw - 1));
+        if (cb > ce) continue;
+        // whole 4-column blocks [cb/4, ce/4]; the extra columns lie outside
+        // every beam's kernel support (or past the image: sky padding)
+        const int blk0 = cb >> 2, nblk = (ce >> 2) - blk0 + 1;
+        const int niter = (nblk + P - 1) / P;
+        const char* pbase = (const char*)(f.pix + (size_t)blk0 * f.H * 4);
+        const char* sbase = SUN ? (const char*)(f.sun + (size_t)blk0 * f.H * 4) : nullptr;
+        const unsigned pvo = (unsigned)vv * 32u, svo = (unsigned)vv * 16u;
+        // per beam: kernel copy (shift) and block of the first batch
+        const char* kcopy[G];
+        int kblk[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int c0 = 4 * blk0 - ub[g] + f.M;          // kernel column of column 4*blk0
+            const int sft = c0 & 3;
+            kcopy[g] = (const char*)f.Kb + (size_t)sft * copy_bytes;
+            kblk[g] = ((c0 - sft) >> 2) + kBlockPad;
+        }
+        int cur = -1;
+        float acc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] = 0.0f;
+        const char* pb = pbase + (size_t)phase * pstep;
+        const char* sb = SUN ? sbase + (size_t)phase * sstep : nullptr;
+        for (int i = 0; i < niter; ++i) {
+            // this lane's block; with column phases the last round may run
+            // past the span: such lanes re-read the last block with K = 0
+            const int bi = i * P + phase;
+            const bool act = P == 1 || bi < nblk;
+            const size_t back = act ? 0 : (size_t)(bi - (nblk - 1));
+            const int4 ra = ld16<int4>(pb - back * pstep, pvo);
+            const int4 rb = ld16<int4>(pb - back * pstep, pvo + 16u);
+            float4 sq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (SUN) sq = ld16<float4>(sb - back * sstep, svo);
+            const float sv[4] = {sq.x, sq.y, sq.z, sq.w};
+            float kv[4][G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int b = min(max(kblk[g] + bi, 0), f.NB - 1);
+                const unsigned ko = act ? kvo[g] : (unsigned)f.KH * 16u;
+                const float4 kq = ld16<float4>(kcopy[g] + (unsigned)(b * (int)khp16), ko);
+                kv[0][g] = kq.x;
+                kv[1][g] = kq.y;
+                kv[2][g] = kq.z;
+                kv[3][g] = kq.w;
+            }
+            pb += (size_t)P * pstep;
+            if (SUN) sb += (size_t)P * sstep;
+            const int bin[4] = {ra.x, ra.z, rb.x, rb.z};
+            const float sh[4] = {__int_as_float(ra.y), __int_as_float(ra.w),
+                                 __int_as_float(rb.y), __int_as_float(rb.w)};
+            // fast path: accumulate without resets and detect breaks
+            const int cur0 = cur;
+            float acc0[G];
+            unsigned long long nrm = 0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc0[g] = acc[g];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                nrm |= __ballot(bin[j] != (j == 0 ? cur0 : bin[j - 1]));
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    acc[g] += kv[j][g] * sh[j];
+                    if (SUN) sacc[g] += kv[j][g] * sv[j];
+                }
+            }
+            cur = bin[3];
+            if (nrm) {
+                // some run ended: replay the batch from its start with the
+                // resets, flushing every run that ends (same summation order
+                // as the fast path where no run ends)
+                float r[G];
+                int c = cur0;
+#pragma unroll
+                for (int g = 0; g < G; ++g) r[g] = acc0[g];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bool nr = bin[j] != c;
+                    unsigned any = __builtin_bit_cast(unsigned, r[0]);
+#pragma unroll
+                    for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, r[g]);
+                    const bool fl = nr && any != 0u;            // sums are >= 0
+                    const unsigned long long fm = __ballot(fl);
+                    if (fm) flush_runs<G>(fm, fl, c, r, hist, R, lane);
+#pragma unroll
+                    for (int g = 0; g < G; ++g) r[g] = (nr ? 0.0f : r[g]) + kv[j][g] * sh[j];
+                    c = bin[j];
+                }
+#pragma unroll
+                for (int g = 0; g < G; ++g) acc[g] = r[g];
+            }
+        }
+        unsigned any = __builtin_bit_cast(unsigned, acc[0]);
+#pragma unroll
+        for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, acc[g]);
+        const bool fl = any != 0u;
+        const unsigned long long fm = __ballot(fl);
+        if (fm) flush_runs<G>(fm, fl, cur, acc, hist, R, lane);
+    }
+}
+
+// The whole group after the histograms were zeroed: gather, floor, pulse,
+// echoes.  All threads of the workgroup call it with the same group.
+template <int G, bool SUN, bool KEEP>
+__device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t* grp,
+                              float* hist, const float* taps, float (*red)[kWaves])
+{
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int R = p.R;
 
     // group members (uniform over the workgroup: kept in scalar registers)
     int beam[G], ub[G], vb[G];
@@ -133,12 +274,12 @@ void k_footprint(FootprintArgs a)
     int umin = INT_MAX, umax = INT_MIN, vmin = INT_MAX, vmax = INT_MIN;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        beam[g] = __builtin_amdgcn_readfirstlane(a.groups[gi * G + g]);
+        beam[g] = __builtin_amdgcn_readfirstlane(grp[g]);
         have[g] = beam[g] >= 0;
         ub[g] = vb[g] = 0;
         scale[g] = 0.0f;
         if (have[g]) {
-            const lidar_beam_info bi = a.beams[beam[g]];
+            const lidar_beam_info bi = f.beams[beam[g]];
             ub[g] = __builtin_amdgcn_readfirstlane(bi.pixel_u);
             vb[g] = __builtin_amdgcn_readfirstlane(bi.pixel_v);
             scale[g] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
@@ -149,148 +290,20 @@ void k_footprint(FootprintArgs a)
             vmax = max(vmax, vb[g]);
         }
     }
-    for (int k = tid; k < G * a.R; k += kFootprintThreads) hist[k] = 0.0f;
-    for (int j = tid; j <= 2 * a.J; j += kFootprintThreads) taps[j] = a.taps[j];
-    __syncthreads();
-
     // union window of the group's footprints, clipped to the image
     // (64-bit arithmetic: beams may lie far outside the image)
-    const int r0 = (int)max(0L, (long)vmin - a.N), r1 = (int)min((long)a.H - 1, (long)vmax + a.N);
-    const int q0 = (int)max(0L, (long)umin - a.M), q1 = (int)min((long)a.W - 1, (long)umax + a.M);
+    const int r0 = (int)max(0L, (long)vmin - f.N), r1 = (int)min((long)f.H - 1, (long)vmax + f.N);
+    const int q0 = (int)max(0L, (long)umin - f.M), q1 = (int)min((long)f.W - 1, (long)umax + f.M);
     float sacc[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) sacc[g] = 0.0f;
     if (r0 <= r1 && q0 <= q1) {
-        const int nrows = r1 - r0 + 1;
-        const int nstrips = (nrows + 63) >> 6;
-        const int q0a = q0 & ~3;                        // batches are aligned 4-column blocks
-        const int ncols = q1 - q0a + 1;
-        // at least 2 items per wave when the window is wide enough
-        int nchunk = (2 * kWaves + nstrips - 1) / nstrips;
-        nchunk = min(nchunk, max(1, ncols / 32));
-        const int cw = (((ncols + nchunk - 1) / nchunk) + 3) & ~3;
-        const int items = nstrips * nchunk;
-        const size_t khp16 = (size_t)(a.KH + 1) * 16u;          // block stride in a copy
-        const size_t copy_bytes = (size_t)a.NB * khp16;
-        const size_t pstep = (size_t)a.H * 32u, sstep = (size_t)a.H * 16u;
-        for (int it = wave; it < items; it += kWaves) {
-            const int s = it / nchunk, ch = it - s * nchunk;
-            const int v = r0 + s * 64 + lane;
-            const bool rowok = v <= r1;
-            const int vv = rowok ? v : r1;                  // in-bounds row for idle lanes
-            unsigned kvo[G];                                // lane offset in a kernel block
-            int lo[G], hi[G];
-            int cb = INT_MAX, ce = INT_MIN;
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int n = vv - vb[g];
-                const bool ok = rowok && have[g] && n >= -a.N && n <= a.N;
-                // lanes with nothing to add read the zero guard row
-                kvo[g] = (unsigned)(ok ? n + a.N : a.KH) * 16u;
-                const int2 rr = ok ? a.rowrange[n + a.N] : make_int2(INT_MAX, INT_MIN);
-                const int wlo = wave_min(rr.x), whi = wave_max(rr.y);
-                // absolute columns where this beam can have K > 0 in the strip
-                lo[g] = __builtin_amdgcn_readfirstlane(wlo == INT_MAX ? INT_MAX : wlo + ub[g]);
-                hi[g] = __builtin_amdgcn_readfirstlane(whi == INT_MIN ? INT_MIN : whi + ub[g]);
-                cb = min(cb, lo[g]);
-                ce = max(ce, hi[g]);
-            }
-            cb = max(cb, q0a + ch * cw);
-            ce = min(ce, min(q1, q0a + ch * cw + cw - 1));
-            if (cb > ce) continue;
-            // whole 4-column blocks [cb/4, ce/4]; the extra columns lie outside
-            // every beam's kernel support (or past the image: sky padding)
-            const int blk0 = cb >> 2, nblk = (ce >> 2) - blk0 + 1;
-            const char* pbase = (const char*)(a.pix + (size_t)blk0 * a.H * 4);
-            const char* sbase = SUN ? (const char*)(a.sun + (size_t)blk0 * a.H * 4) : nullptr;
-            const unsigned pvo = (unsigned)vv * 32u, svo = (unsigned)vv * 16u;
-            // per beam: kernel copy (shift) and block of the first batch
-            const char* kcopy[G];
-            int kblk[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int c0 = 4 * blk0 - ub[g] + a.M;      // kernel column of column 4*blk0
-                const int sft = c0 & 3;
-                kcopy[g] = (const char*)a.Kb + (size_t)sft * copy_bytes;
-                kblk[g] = ((c0 - sft) >> 2) + kBlockPad;
-            }
-            int cur = -1;
-            float acc[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) acc[g] = 0.0f;
-            const char* pb = pbase;
-            const char* sb = sbase;
-            for (int i = 0; i < nblk; ++i) {
-                // all loads of the 4-column batch first (uniform bases, per-lane offsets)
-                const int4 ra = ld16<int4>(pb, pvo);
-                const int4 rb = ld16<int4>(pb, pvo + 16u);
-                float4 sq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (SUN) sq = ld16<float4>(sb, svo);
-                const float sv[4] = {sq.x, sq.y, sq.z, sq.w};
-                float kv[4][G];
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const int b = min(max(kblk[g] + i, 0), a.NB - 1);
-                    const float4 kq = ld16<float4>(kcopy[g] + (unsigned)(b * (int)khp16), kvo[g]);
-                    kv[0][g] = kq.x;
-                    kv[1][g] = kq.y;
-                    kv[2][g] = kq.z;
-                    kv[3][g] = kq.w;
-                }
-                pb += pstep;
-                if (SUN) sb += sstep;
-                const int bin[4] = {ra.x, ra.z, rb.x, rb.z};
-                const float sh[4] = {__int_as_float(ra.y), __int_as_float(ra.w),
-                                     __int_as_float(rb.y), __int_as_float(rb.w)};
-                // fast path: no run ends in this batch for most lanes and
-                // batches, so accumulate without resets and detect breaks
-                const int cur0 = cur;
-                float acc0[G];
-                unsigned long long nrm = 0;
-#pragma unroll
-                for (int g = 0; g < G; ++g) acc0[g] = acc[g];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    nrm |= __ballot(bin[j] != (j == 0 ? cur0 : bin[j - 1]));
-#pragma unroll
-                    for (int g = 0; g < G; ++g) {
-                        acc[g] += kv[j][g] * sh[j];
-                        if (SUN) sacc[g] += kv[j][g] * sv[j];
-                    }
-                }
-                cur = bin[3];
-                if (nrm) {
-                    // some run ended: replay the batch from its start with the
-                    // resets, flushing every run that ends (same summation order
-                    // as the fast path where no run ends)
-                    float r[G];
-                    int c = cur0;
-#pragma unroll
-                    for (int g = 0; g < G; ++g) r[g] = acc0[g];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const bool nr = bin[j] != c;
-                        unsigned any = __builtin_bit_cast(unsigned, r[0]);
-#pragma unroll
-                        for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, r[g]);
-                        const bool fl = nr && any != 0u;            // sums are >= 0
-                        const unsigned long long fm = __ballot(fl);
-                        if (fm) flush_runs<G>(fm, fl, c, r, hist, a.R, lane);
-#pragma unroll
-                        for (int g = 0; g < G; ++g) r[g] = (nr ? 0.0f : r[g]) + kv[j][g] * sh[j];
-                        c = bin[j];
-                    }
-#pragma unroll
-                    for (int g = 0; g < G; ++g) acc[g] = r[g];
-                }
-            }
-            unsigned any = __builtin_bit_cast(unsigned, acc[0]);
-#pragma unroll
-            for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, acc[g]);
-            const bool fl = any != 0u;
-            const unsigned long long fm = __ballot(fl);
-            if (fm) flush_runs<G>(fm, fl, cur, acc, hist, a.R, lane);
-        }
+        if (f.tile == 64)
+            gather_group<G, 64, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, R, lane, wave, sacc);
+        else if (f.tile == 16)
+            gather_group<G, 16, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, R, lane, wave, sacc);
+        else
+            gather_group<G, 4, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, R, lane, wave, sacc);
     }
     if (SUN) {
 #pragma unroll
@@ -306,53 +319,53 @@ void k_footprint(FootprintArgs a)
     float floor_b[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        float f = a.ambient;
+        float fl = p.ambient;
         if (SUN) {
             float t = 0.0f;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) t += red[g][w];
-            f += a.sun_scale * t;
+            fl += f.sun_scale * t;
         }
-        floor_b[g] = f;
+        floor_b[g] = fl;
     }
     constexpr int kPass = 8 * kFootprintThreads;        // bins per pass
     constexpr int kMaxPass = (kMaxBins + kPass - 1) / kPass;
 #pragma unroll 1
     for (int g = 0; g < G; ++g) {
         if (!have[g]) continue;                          // uniform
-        float* h = hist + g * a.R;
+        float* h = hist + g * R;
         float o[kMaxPass][8];
 #pragma unroll
-        for (int p = 0; p < kMaxPass; ++p) {
-            const int k0 = p * kPass + tid * 8;
-            if (k0 >= a.R) continue;
-            auto H = [&](int i) -> float { return (i >= 0 && i < a.R) ? h[i] : 0.0f; };
+        for (int ps = 0; ps < kMaxPass; ++ps) {
+            const int k0 = ps * kPass + tid * 8;
+            if (k0 >= R) continue;
+            auto H = [&](int i) -> float { return (i >= 0 && i < R) ? h[i] : 0.0f; };
             float win[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                win[q] = H(k0 + q + a.J);
-                o[p][q] = 0.0f;
+                win[q] = H(k0 + q + p.J);
+                o[ps][q] = 0.0f;
             }
-            for (int t = 0; t <= 2 * a.J; ++t) {
+            for (int t = 0; t <= 2 * p.J; ++t) {
                 const float wt = taps[t];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) o[p][q] += wt * win[q];
+                for (int q = 0; q < 8; ++q) o[ps][q] += wt * win[q];
 #pragma unroll
                 for (int q = 7; q > 0; --q) win[q] = win[q - 1];
-                win[0] = H(k0 + a.J - t - 1);
+                win[0] = H(k0 + p.J - t - 1);
             }
         }
         __syncthreads();                                 // every read of h is done
 #pragma unroll
-        for (int p = 0; p < kMaxPass; ++p) {
-            const int k0 = p * kPass + tid * 8;
+        for (int ps = 0; ps < kMaxPass; ++ps) {
+            const int k0 = ps * kPass + tid * 8;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int k = k0 + q;
-                if (k < a.R) {
-                    const float val = scale[g] * o[p][q] + floor_b[g];
+                if (k < R) {
+                    const float val = scale[g] * o[ps][q] + floor_b[g];
                     h[k] = val;
-                    if (KEEP) a.waves[(size_t)beam[g] * a.R + k] = val;
+                    if (KEEP) f.waves[(size_t)beam[g] * R + k] = val;
                 }
             }
         }
@@ -360,20 +373,20 @@ void k_footprint(FootprintArgs a)
     __syncthreads();
 
     // echo detection: wave w takes beams w, w + 4, ...
-    const float T = a.threshold;
-    const float dt = (float)a.bin_ns;
+    const float T = p.threshold;
+    const float dt = (float)p.bin_ns;
 #pragma unroll 1
     for (int g = wave; g < G; g += kWaves) {
         if (!have[g]) continue;
-        const float* xh = hist + g * a.R;
-        lidar_echo* out = a.echoes + (size_t)beam[g] * a.E;
+        const float* xh = hist + g * R;
+        lidar_echo* out = f.echoes + (size_t)beam[g] * p.E;
         int count = 0;
         int k0 = -1;                                     // first bin of the open run
-        for (int base = 0; base < a.R; base += 64) {
+        for (int base = 0; base < R; base += 64) {
             const int k = base + lane;
-            const bool above = k < a.R && xh[k] > T;
+            const bool above = k < R && xh[k] > T;
             const unsigned long long mask = __ballot(above);
-            const bool next_above = base + 64 < a.R && xh[base + 64] > T;
+            const bool next_above = base + 64 < R && xh[base + 64] > T;
             const unsigned long long prev = (mask << 1) | (k0 >= 0 ? 1ull : 0ull);
             const unsigned long long nxt = (mask >> 1) | (next_above ? (1ull << 63) : 0ull);
             unsigned long long starts = mask & ~prev;
@@ -388,7 +401,7 @@ void k_footprint(FootprintArgs a)
                 }
                 ends &= ends - 1;
                 const int k1 = base + pe;
-                if (count < a.E) {
+                if (count < p.E) {
                     // first maximum of the run
                     float best = -INFINITY;
                     int bk = INT_MAX;
@@ -424,7 +437,7 @@ void k_footprint(FootprintArgs a)
                             const float xa = xh[k0 - 1], xb = xh[k0];
                             f_up = (T - xa) / (xb - xa);
                         }
-                        if (k1 == a.R - 1) {
+                        if (k1 == R - 1) {
                             f_dn = 0.5f;
                             flags |= LIDAR_ECHO_AT_LAST_BIN;
                         } else {
@@ -432,8 +445,8 @@ void k_footprint(FootprintArgs a)
                             f_dn = (xa - T) / (xa - xb);
                         }
                         lidar_echo e;
-                        e.range_m = ((double)bk + 0.5) * a.half_c_dt;
-                        e.time_ns = ((double)bk + 0.5) * a.bin_ns;
+                        e.range_m = ((double)bk + 0.5) * p.half_c_dt;
+                        e.time_ns = ((double)bk + 0.5) * p.bin_ns;
                         e.intensity = best - floor_b[g];
                         e.pulse_width_ns = ((float)(k1 - k0 + 1) + f_dn - f_up) * dt;
                         e.bin_peak = bk;
@@ -448,21 +461,79 @@ void k_footprint(FootprintArgs a)
             }
         }
         if (lane == 0) {
-            a.counts[beam[g]] = count;
-            a.beams[beam[g]].floor = floor_b[g];
+            f.counts[beam[g]] = count;
+            f.beams[beam[g]].floor = floor_b[g];
             lidar_echo z = {};
-            for (int i = count; i < a.E; ++i) out[i] = z;
+            for (int i = count; i < p.E; ++i) out[i] = z;
         }
     }
+}
+
+}  // namespace
+
+template <int G, bool SUN, bool KEEP>
+__global__ __launch_bounds__(kFootprintThreads)
+void k_footprint(FootprintArgs a)
+{
+    extern __shared__ float lds[];
+    float* hist = lds;                  // [G][R]: sum K * shade, then xi_hat
+    float* taps = lds + G * a.p.R;      // [2J+1]
+    __shared__ float red[G][kWaves];
+
+    // XCD-aware schedule: workgroups go round-robin over the 8 XCDs, so slot
+    // s runs on XCD s % 8; each XCD takes one contiguous run of the
+    // spatially ordered groups, and the groups in flight on it share their
+    // pixels in its L2.
+    const int slot = blockIdx.x;
+    const int gi = (slot % kXcds) * a.chunk + slot / kXcds;
+    if (gi >= a.n_groups) return;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < G * a.p.R; k += kFootprintThreads) hist[k] = 0.0f;
+    for (int j = tid; j <= 2 * a.p.J; j += kFootprintThreads) taps[j] = a.p.taps[j];
+    __syncthreads();
+    process_group<G, SUN, KEEP>(a.f, a.p, a.groups + (size_t)gi * G, hist, taps, red);
+}
+
+// Persistent kernel over the items of a batch: each workgroup repeatedly
+// takes the next item from the queue (costliest items first), so frames of
+// very different sizes share the GPU without a tail of idle CUs.  Every
+// workgroup exits once the queue is exhausted.
+template <int G, bool SUN, bool KEEP>
+__global__ __launch_bounds__(kFootprintThreads)
+void k_footprint_batch(BatchArgs a)
+{
+    extern __shared__ float lds[];
+    float* hist = lds;
+    float* taps = lds + G * a.p.R;
+    __shared__ float red[G][kWaves];
+    __shared__ int item_sh;
+    const int tid = threadIdx.x;
+    for (int j = tid; j <= 2 * a.p.J; j += kFootprintThreads) taps[j] = a.p.taps[j];
+    for (;;) {
+        if (tid == 0) item_sh = atomicAdd(a.next_item, 1);
+        for (int k = tid; k < G * a.p.R; k += kFootprintThreads) hist[k] = 0.0f;
+        __syncthreads();
+        const int item = item_sh;
+        if (item >= a.n_items) break;                    // uniform: every wave exits
+        const int2 it = a.items[item];
+        const FrameDev f = a.frames[it.x];
+        process_group<G, SUN, KEEP>(f, a.p, a.groups + (size_t)it.y * G, hist, taps, red);
+        __syncthreads();                                 // histograms and item_sh reused
+    }
+}
+
+__global__ void k_reset_queue(int* counter)
+{
+    if (threadIdx.x == 0) *counter = 0;
 }
 
 template <int G>
 static hipError_t launch_g(hipStream_t s, const FootprintArgs& a)
 {
     const int grid = kXcds * a.chunk;
-    const size_t lds = sizeof(float) * ((size_t)G * a.R + 2 * (size_t)a.J + 1);
-    const bool sun = a.sun != nullptr;
-    const bool keep = a.waves != nullptr;
+    const size_t lds = sizeof(float) * ((size_t)G * a.p.R + 2 * (size_t)a.p.J + 1);
+    const bool sun = a.f.sun != nullptr;
+    const bool keep = a.f.waves != nullptr;
     if (sun && keep)
         hipLaunchKernelGGL((k_footprint<G, true, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
     else if (sun)
@@ -471,6 +542,21 @@ static hipError_t launch_g(hipStream_t s, const FootprintArgs& a)
         hipLaunchKernelGGL((k_footprint<G, false, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
     else
         hipLaunchKernelGGL((k_footprint<G, false, false>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int G>
+static hipError_t launch_batch_g(hipStream_t s, const BatchArgs& a, int grid, bool sun, bool keep)
+{
+    const size_t lds = sizeof(float) * ((size_t)G * a.p.R + 2 * (size_t)a.p.J + 1);
+    if (sun && keep)
+        hipLaunchKernelGGL((k_footprint_batch<G, true, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    else if (sun)
+        hipLaunchKernelGGL((k_footprint_batch<G, true, false>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    else if (keep)
+        hipLaunchKernelGGL((k_footprint_batch<G, false, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_footprint_batch<G, false, false>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -487,6 +573,22 @@ hipError_t launch_footprint(hipStream_t s, const FootprintArgs& a)
     case 4: return launch_g<4>(s, a);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_footprint_batch(hipStream_t s, const BatchArgs& a, int grid, bool sun, bool keep)
+{
+    switch (a.G) {
+    case 1: return launch_batch_g<1>(s, a, grid, sun, keep);
+    case 2: return launch_batch_g<2>(s, a, grid, sun, keep);
+    case 4: return launch_batch_g<4>(s, a, grid, sun, keep);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reset_queue(hipStream_t s, int* counter)
+{
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, counter);
+    return hipGetLastError();
 }
 
 }  // namespace lidar

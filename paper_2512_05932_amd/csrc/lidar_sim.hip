@@ -1,7 +1,8 @@
 // Engine and C-ABI of the gfx950 LiDAR library (declared in
 // include/lidar_sim.h).  The host side validates arguments, owns device
-// buffers, decides sizes and the beam schedule, and enqueues kernels on the
-// caller's stream; every step of the model itself runs in the kernels.
+// buffers, decides sizes, forms and orders the beam groups, captures batches
+// into HIP graphs and autotunes them, and enqueues kernels on the caller's
+// stream; every step of the model itself runs in the kernels.
 //
 // Floating-point contraction is off in this file so that the host's FP64
 // decisions (kernel extent M, N and pulse half-width J) use plain IEEE
@@ -9,9 +10,12 @@
 #pragma clang fp contract(off)
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <new>
 #include <numeric>
 #include <string>
@@ -29,14 +33,14 @@ template <typename T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
     hipError_t ensure(size_t count)
     {
         if (count <= n && p) return hipSuccess;
-        if (p) {
-            (void)hipFree(p);
-            p = nullptr;
-            n = 0;
-        }
+        release();
         if (count == 0) return hipSuccess;
         hipError_t e = hipMalloc(&p, sizeof(T) * count);
         if (e == hipSuccess) n = count;
@@ -54,34 +58,24 @@ struct EventPair {
     hipEvent_t a, b;
 };
 
-}  // namespace
-
-struct lidar_sim {
-    lidar_sim_params prm{};
-    hipStream_t stream = nullptr;
-    std::string err;
-
-    // pattern (host copies + device copies)
-    bool have_pattern = false;
-    uint64_t pattern_version = 0;
+// Host copy of a pattern and its beams.
+struct PatternHost {
     uint32_t kind = 0;
     double sigma[2] = {0, 0}, trunc = 0, half[2] = {0, 0};
     uint32_t nx = 0, ny = 0;
+    std::vector<float> table;
     std::vector<double> az, el;
+};
+
+// One frame's device state: pattern copy, kernel set-up for its raster,
+// pixel records and beam groups.  The per-beam outputs live with the caller
+// of setup_frame (the handle in single-frame mode, the batch otherwise).
+struct FrameState {
+    PatternHost pat;
+    lidar_gbuffer_desc gb{};
     DevBuf<float> d_table;
     DevBuf<double> d_az, d_el;
-    DevBuf<int32_t> d_groups;
-    int G = 1, n_groups = 0;
-
-    // raster of the current G-buffer
-    bool have_gbuffer = false;
-    lidar_gbuffer_desc gb{};
-
-    // derived set-up, valid for (pattern_version, raster)
-    bool setup_ok = false;
-    uint64_t setup_version = ~0ull;
-    lidar_gbuffer_desc setup_gb{};
-    KernelDev kgeom{};
+    KernelDev k{};
     double kmax = 0.0;
     uint64_t samples = 0;
     DevBuf<double> d_K64, d_rowsum, d_rowmax, d_kinfo;
@@ -90,23 +84,56 @@ struct lidar_sim {
     DevBuf<int32_t> d_prefix;
     DevBuf<float2> d_colcs;
     DevBuf<float4> d_rowtab;
-    DevBuf<lidar_beam_info> d_beams;
-
-    // pulse
-    int J = 0;
-    DevBuf<float> d_taps;
-
-    // per frame
     DevBuf<int2> d_pix;
     DevBuf<float> d_sun;
+    std::vector<int32_t> groups;       // [n_groups][G], -1 = empty slot
+    std::vector<uint64_t> group_cost;  // samples of the group's beams
+    int n_groups = 0;
+    int tile = 64;
+};
+
+}  // namespace
+
+struct lidar_sim {
+    lidar_sim_params prm{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    int J = 0;
+    int G = 4;                         // beams per group (LDS budget)
+    DevBuf<float> d_taps;
+
+    // single-frame mode
+    bool have_pattern = false, have_gbuffer = false, setup_ok = false, have_result = false;
+    FrameState single;
+    DevBuf<lidar_beam_info> d_beams;
     DevBuf<lidar_echo> d_echoes;
-    DevBuf<int32_t> d_counts;
+    DevBuf<int32_t> d_counts, d_groups;
     DevBuf<float> d_waves;
-    bool have_result = false;
+
+    // batch mode
+    bool batch_ok = false, batch_result = false;
+    std::vector<lidar_gbuffer_desc> batch_gb;
+    std::vector<lidar_pattern_desc> batch_pd;
+    std::vector<std::unique_ptr<FrameState>> frames;
+    std::vector<uint64_t> beam_off;    // [n_frames + 1]
+    DevBuf<lidar_beam_info> b_beams;
+    DevBuf<lidar_echo> b_echoes;
+    DevBuf<int32_t> b_counts, b_groups, b_queue;
+    DevBuf<float> b_waves;
+    DevBuf<FrameDev> b_frames;
+    DevBuf<int2> b_items;
+    uint64_t b_items_n = 0, b_samples = 0;
+    int b_grid = 0;
+    bool b_autotuned = false;
+    double b_autotune_ms = 0.0;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::map<int, int> tuned_tile;     // kernel-height class -> strip height
 
     // stats
     lidar_stats st{};
-    std::vector<EventPair> pending_fp, pending_pp, pool;
+    std::vector<EventPair> pending_fp, pending_pp, pending_bt, pool;
 };
 
 namespace {
@@ -128,6 +155,12 @@ lidar_status hip_fail(lidar_sim* h, hipError_t e, const char* what)
     do {                                                              \
         hipError_t e_ = (expr);                                       \
         if (e_ != hipSuccess) return hip_fail((h), e_, (what));       \
+    } while (0)
+
+#define LIDAR_TRY(expr)                                               \
+    do {                                                              \
+        lidar_status s_ = (expr);                                     \
+        if (s_ != LIDAR_OK) return s_;                                \
     } while (0)
 
 bool is_fin(double x) { return std::isfinite(x); }
@@ -164,6 +197,7 @@ lidar_status drain_events(lidar_sim* h)
     };
     HIP_TRY(h, drain(h->pending_fp, h->st.footprint_ms, h->st.footprint_launches), "event timing");
     HIP_TRY(h, drain(h->pending_pp, h->st.prepass_ms, h->st.prepass_launches), "event timing");
+    HIP_TRY(h, drain(h->pending_bt, h->st.batch_ms, h->st.batch_launches), "event timing");
     return LIDAR_OK;
 }
 
@@ -186,166 +220,71 @@ bool same_raster(const lidar_gbuffer_desc& a, const lidar_gbuffer_desc& b)
            a.el_max_deg == b.el_max_deg;
 }
 
-// Kernel extent on the pixel-offset grid: M = floor(extent_az / dphi),
-// N = floor(extent_el / de), extent = trunc * sigma (Gaussian) or the table's
-// half extent.
-void kernel_extent(const lidar_sim* h, const RasterDev& r, double* M, double* N)
+bool same_gbuffer(const lidar_gbuffer_desc& a, const lidar_gbuffer_desc& b)
 {
-    if (h->kind == LIDAR_PATTERN_GAUSS) {
-        *M = std::floor(h->trunc * h->sigma[0] / r.dphi);
-        *N = std::floor(h->trunc * h->sigma[1] / r.de);
-    } else {
-        *M = std::floor(h->half[0] / r.dphi);
-        *N = std::floor(h->half[1] / r.de);
-    }
+    return same_raster(a, b) && a.pitch == b.pitch && a.depth == b.depth &&
+           a.reflectance == b.reflectance && a.retro_gain == b.retro_gain &&
+           a.normal_x == b.normal_x && a.normal_y == b.normal_y && a.normal_z == b.normal_z;
 }
 
-// Beam scheduler.  Beams are grouped G at a time so that one workgroup can
-// share the pixel reads of nearby footprints: beams are sorted by their
-// (approximate) pixel row band, then column, and a group takes consecutive
-// beams of one band whose columns lie within one kernel width.  The groups
-// are then ordered by column so that the groups in flight on one XCD cover a
-// narrow band of the image.  Scheduling only: the exact pixel of each beam is
-// computed on the GPU.
-void build_groups(const std::vector<double>& az, const std::vector<double>& el,
-                  const RasterDev& r, const KernelDev& k, int G, std::vector<int32_t>& out,
-                  int* n_groups)
+bool same_pattern(const lidar_pattern_desc& a, const lidar_pattern_desc& b)
 {
-    const size_t B = az.size();
-    std::vector<double> uf(B), vf(B);
-    for (size_t i = 0; i < B; ++i) {
-        uf[i] = std::floor((az[i] - r.az_min) / r.dphi);
-        vf[i] = std::floor((r.el_max - el[i]) / r.de);
-    }
-    auto make = [&](double band, std::vector<std::vector<int32_t>>& groups) {
-        std::vector<int32_t> idx(B);
-        std::iota(idx.begin(), idx.end(), 0);
-        std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
-            double bx = std::floor(vf[x] / band), by = std::floor(vf[y] / band);
-            if (bx != by) return bx < by;
-            return uf[x] < uf[y];
-        });
-        groups.clear();
-        std::vector<int32_t> cur;
-        double cur_band = 0, cur_u0 = 0;
-        for (int32_t i : idx) {
-            double bi = std::floor(vf[i] / band);
-            bool fits = !cur.empty() && (int)cur.size() < G && bi == cur_band &&
-                        uf[i] - cur_u0 <= (double)k.KW;
-            if (!fits && !cur.empty()) {
-                groups.push_back(cur);
-                cur.clear();
-            }
-            if (cur.empty()) {
-                cur_band = bi;
-                cur_u0 = uf[i];
-            }
-            cur.push_back(i);
+    return a.kind == b.kind && a.n_beams == b.n_beams && a.sigma_deg[0] == b.sigma_deg[0] &&
+           a.sigma_deg[1] == b.sigma_deg[1] && a.trunc_sigmas == b.trunc_sigmas &&
+           a.table == b.table && a.nx == b.nx && a.ny == b.ny &&
+           a.half_deg[0] == b.half_deg[0] && a.half_deg[1] == b.half_deg[1] &&
+           a.beam_az_deg == b.beam_az_deg && a.beam_el_deg == b.beam_el_deg;
+}
+
+// ---- validation --------------------------------------------------------
+
+lidar_status check_pattern(lidar_sim* h, const lidar_pattern_desc* pd, const std::string& w)
+{
+    if (!pd) return fail(h, LIDAR_E_INVALID, w + "pattern is NULL");
+    if (pd->n_beams == 0 || !pd->beam_az_deg || !pd->beam_el_deg)
+        return fail(h, LIDAR_E_INVALID, w + "pattern needs n_beams >= 1 and beam angle arrays");
+    if (pd->n_beams > (1u << 26)) return fail(h, LIDAR_E_INVALID, w + "too many beams (max 2^26)");
+    for (uint32_t i = 0; i < pd->n_beams; ++i)
+        if (!is_fin(pd->beam_az_deg[i]) || !is_fin(pd->beam_el_deg[i]))
+            return fail(h, LIDAR_E_INVALID, w + "non-finite beam angle");
+    if (pd->kind == LIDAR_PATTERN_GAUSS) {
+        if (!(pd->sigma_deg[0] > 0) || !(pd->sigma_deg[1] > 0) || !is_fin(pd->sigma_deg[0]) ||
+            !is_fin(pd->sigma_deg[1]) || !(pd->trunc_sigmas > 0) || !is_fin(pd->trunc_sigmas))
+            return fail(h, LIDAR_E_INVALID, w + "Gaussian pattern needs sigma > 0 and trunc_sigmas > 0");
+    } else if (pd->kind == LIDAR_PATTERN_TABLE) {
+        if (!pd->table || pd->nx < 2 || pd->ny < 2 || (uint64_t)pd->nx * pd->ny > (1u << 24))
+            return fail(h, LIDAR_E_INVALID, w + "table pattern needs a table of at least 2x2 (max 16M cells)");
+        if (!(pd->half_deg[0] > 0) || !(pd->half_deg[1] > 0) || !is_fin(pd->half_deg[0]) ||
+            !is_fin(pd->half_deg[1]))
+            return fail(h, LIDAR_E_INVALID, w + "table pattern needs half extents > 0");
+        bool any = false;
+        for (uint64_t i = 0; i < (uint64_t)pd->nx * pd->ny; ++i) {
+            float v = pd->table[i];
+            if (!std::isfinite(v) || v < 0.0f)
+                return fail(h, LIDAR_E_INVALID, w + "table values must be finite and >= 0");
+            any |= v > 0.0f;
         }
-        if (!cur.empty()) groups.push_back(cur);
-    };
-    std::vector<std::vector<int32_t>> groups;
-    make(1.0, groups);
-    if (G > 1 && groups.size() * 2 > B) {
-        // few beams share a pixel row: group across a band of rows
-        make(std::max(1.0, std::floor(k.KH / 8.0)), groups);
+        if (!any) return fail(h, LIDAR_E_INVALID, w + "table is all zero (pattern integral is 0)");
+    } else {
+        return fail(h, LIDAR_E_INVALID, w + "unknown pattern kind");
     }
-    std::stable_sort(groups.begin(), groups.end(), [&](const std::vector<int32_t>& x,
-                                                       const std::vector<int32_t>& y) {
-        if (uf[x[0]] != uf[y[0]]) return uf[x[0]] < uf[y[0]];
-        return vf[x[0]] < vf[y[0]];
-    });
-    out.assign(groups.size() * G, -1);
-    for (size_t gi = 0; gi < groups.size(); ++gi)
-        for (size_t j = 0; j < groups[gi].size(); ++j) out[gi * G + j] = groups[gi][j];
-    *n_groups = (int)groups.size();
+    return LIDAR_OK;
 }
 
-lidar_status run_setup(lidar_sim* h)
+lidar_status check_gbuffer(lidar_sim* h, const lidar_gbuffer_desc* g, const std::string& w)
 {
-    const lidar_gbuffer_desc& g = h->gb;
-    RasterDev r = raster_of(g);
-    double Mf, Nf;
-    kernel_extent(h, r, &Mf, &Nf);
-    if (!(Mf >= 0 && Nf >= 0) || Mf > 4096 || Nf > 4096 || (2 * Mf + 1) * (2 * Nf + 1) > 16.0e6)
-        return fail(h, LIDAR_E_INVALID, "kernel grid too large for this raster (more than 16M "
-                                        "cells or 8193 columns/rows)");
-    // the footprint kernel addresses one group window of pixel records with
-    // 32-bit byte offsets
-    if ((4.0 * Mf + 8.0) * (double)g.height * 8.0 >= 2147483648.0)
-        return fail(h, LIDAR_E_INVALID, "kernel window times image height too large "
-                                        "(4*M+8)*height*8 must stay below 2^31 bytes");
-    KernelDev k;
-    k.M = (int)Mf;
-    k.N = (int)Nf;
-    k.KW = 2 * k.M + 1;
-    k.KH = 2 * k.N + 1;
-    const size_t cells = (size_t)k.KW * k.KH;
-    HIP_TRY(h, h->d_K64.ensure(cells), "allocate kernel");
-    HIP_TRY(h, h->d_Kb.ensure((size_t)4 * kernel_blocks(k.KW) * (k.KH + 1) * 4),
-            "allocate kernel blocks");
-    HIP_TRY(h, h->d_rowsum.ensure(k.KH), "allocate kernel rows");
-    HIP_TRY(h, h->d_rowmax.ensure(k.KH), "allocate kernel rows");
-    HIP_TRY(h, h->d_rowrange.ensure(k.KH), "allocate kernel rows");
-    HIP_TRY(h, h->d_prefix.ensure((size_t)k.KH * (k.KW + 1)), "allocate kernel rows");
-    HIP_TRY(h, h->d_kinfo.ensure(2), "allocate kernel info");
-    HIP_TRY(h, h->d_colcs.ensure(g.width), "allocate raster tables");
-    HIP_TRY(h, h->d_rowtab.ensure(g.height), "allocate raster tables");
-    HIP_TRY(h, h->d_beams.ensure(h->az.size()), "allocate beams");
-
-    PatternDev p;
-    p.kind = (int)h->kind;
-    p.sx = h->sigma[0];
-    p.sy = h->sigma[1];
-    p.trunc = h->trunc;
-    p.table = h->d_table.p;
-    p.nx = (int)h->nx;
-    p.ny = (int)h->ny;
-    p.hx = h->half[0];
-    p.hy = h->half[1];
-    hipStream_t s = h->stream;
-    HIP_TRY(h, launch_kernel_grid(s, p, r, k, h->d_K64.p), "kernel grid launch");
-    HIP_TRY(h, launch_kernel_blocks(s, k, h->d_K64.p, h->d_Kb.p), "kernel blocks launch");
-    HIP_TRY(h, launch_kernel_rows(s, k, h->d_K64.p, h->d_rowsum.p, h->d_rowmax.p,
-                                  h->d_rowrange.p, h->d_prefix.p), "kernel rows launch");
-    HIP_TRY(h, launch_kernel_peak(s, k, h->d_rowsum.p, h->d_rowmax.p, h->d_kinfo.p),
-            "kernel peak launch");
-    HIP_TRY(h, launch_raster_tables(s, r, h->d_colcs.p, h->d_rowtab.p), "raster tables launch");
-    HIP_TRY(h, launch_beam_setup(s, r, k, h->d_az.p, h->d_el.p, (int)h->az.size(),
-                                 h->d_rowsum.p, h->d_prefix.p, h->prm.emit_power,
-                                 h->d_beams.p), "beam setup launch");
-    // the pattern's integral over the grid must be positive: checked once per
-    // (pattern, raster), which synchronises the stream
-    double kinfo[2];
-    HIP_TRY(h, hipMemcpyAsync(kinfo, h->d_kinfo.p, sizeof(kinfo), hipMemcpyDeviceToHost, s),
-            "copy kernel info");
-    std::vector<lidar_beam_info> bi(h->az.size());
-    HIP_TRY(h, hipMemcpyAsync(bi.data(), h->d_beams.p, sizeof(lidar_beam_info) * bi.size(),
-                              hipMemcpyDeviceToHost, s), "copy beam info");
-    HIP_TRY(h, hipStreamSynchronize(s), "set-up synchronise");
-    if (!(kinfo[1] > 0.0) || !is_fin(kinfo[1]) || !(kinfo[0] > 0.0))
-        return fail(h, LIDAR_E_INVALID, "pattern integral over the kernel grid is not positive "
-                                        "(kernel narrower than one pixel or all-zero table)");
-    uint64_t total = 0;
-    for (auto& x : bi) total += x.samples;
-    // beam groups for the footprint kernel
-    int G = 4;
-    while (G > 1 && !footprint_group_fits(G, (int)h->prm.n_bins, h->J)) G /= 2;
-    std::vector<int32_t> groups;
-    int n_groups = 0;
-    build_groups(h->az, h->el, r, k, G, groups, &n_groups);
-    HIP_TRY(h, h->d_groups.ensure(groups.size()), "allocate beam groups");
-    HIP_TRY(h, hipMemcpyAsync(h->d_groups.p, groups.data(), groups.size() * sizeof(int32_t),
-                              hipMemcpyHostToDevice, s), "copy beam groups");
-    HIP_TRY(h, hipStreamSynchronize(s), "set-up synchronise");
-    h->G = G;
-    h->n_groups = n_groups;
-    h->kgeom = k;
-    h->kmax = kinfo[0];
-    h->samples = total;
-    h->setup_gb = g;
-    h->setup_version = h->pattern_version;
-    h->setup_ok = true;
+    if (!g) return fail(h, LIDAR_E_INVALID, w + "gbuffer is NULL");
+    if (g->width == 0 || g->height == 0 || g->pitch < g->width)
+        return fail(h, LIDAR_E_INVALID, w + "gbuffer needs width, height >= 1 and pitch >= width");
+    if ((uint64_t)g->width * g->height > (1ull << 31))
+        return fail(h, LIDAR_E_INVALID, w + "gbuffer larger than 2^31 pixels");
+    if (!g->depth || !g->reflectance || !g->retro_gain || !g->normal_x || !g->normal_y || !g->normal_z)
+        return fail(h, LIDAR_E_INVALID, w + "gbuffer plane pointer is NULL");
+    if (!is_fin(g->az_min_deg) || !is_fin(g->az_max_deg) || !is_fin(g->el_min_deg) ||
+        !is_fin(g->el_max_deg) || !(g->az_min_deg < g->az_max_deg) || !(g->el_min_deg < g->el_max_deg))
+        return fail(h, LIDAR_E_INVALID, w + "gbuffer angle ranges must be finite with min < max");
+    if (g->el_min_deg < -90.0 || g->el_max_deg > 90.0)
+        return fail(h, LIDAR_E_INVALID, w + "gbuffer elevations must lie in [-90, 90]");
     return LIDAR_OK;
 }
 
@@ -368,11 +307,525 @@ lidar_status check_params(const lidar_sim_params* p, std::string& why)
     }
     for (double c : p->sun_dir)
         if (!is_fin(c)) { why = "sun_dir must be finite"; return LIDAR_E_INVALID; }
-    if (p->flags & ~(uint32_t)(LIDAR_KEEP_WAVEFORMS | LIDAR_PROFILE)) { why = "unknown flags"; return LIDAR_E_INVALID; }
+    if (p->flags & ~(uint32_t)(LIDAR_KEEP_WAVEFORMS | LIDAR_PROFILE | LIDAR_AUTOTUNE)) {
+        why = "unknown flags";
+        return LIDAR_E_INVALID;
+    }
     if (p->reserved != 0) { why = "reserved must be 0"; return LIDAR_E_INVALID; }
     double sigma = p->pulse_fwhm_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
     double J = std::ceil(p->pulse_trunc_sigmas * sigma / p->bin_ns);
     if (!(2.0 * J + 1.0 <= kMaxTaps)) { why = "pulse longer than 257 taps"; return LIDAR_E_INVALID; }
+    return LIDAR_OK;
+}
+
+// ---- pattern copies and kernel set-up -----------------------------------
+
+lidar_status copy_pattern(lidar_sim* h, FrameState& fs, const lidar_pattern_desc* pd)
+{
+    PatternHost& p = fs.pat;
+    const size_t B = pd->n_beams;
+    p.kind = pd->kind;
+    p.az.assign(pd->beam_az_deg, pd->beam_az_deg + B);
+    p.el.assign(pd->beam_el_deg, pd->beam_el_deg + B);
+    if (pd->kind == LIDAR_PATTERN_GAUSS) {
+        p.sigma[0] = pd->sigma_deg[0];
+        p.sigma[1] = pd->sigma_deg[1];
+        p.trunc = pd->trunc_sigmas;
+        p.nx = p.ny = 0;
+        p.table.clear();
+    } else {
+        p.nx = pd->nx;
+        p.ny = pd->ny;
+        p.half[0] = pd->half_deg[0];
+        p.half[1] = pd->half_deg[1];
+        p.table.assign(pd->table, pd->table + (size_t)pd->nx * pd->ny);
+    }
+    hipStream_t s = h->stream;
+    HIP_TRY(h, fs.d_az.ensure(B), "allocate beams");
+    HIP_TRY(h, fs.d_el.ensure(B), "allocate beams");
+    HIP_TRY(h, hipMemcpyAsync(fs.d_az.p, p.az.data(), B * sizeof(double), hipMemcpyHostToDevice, s), "copy beams");
+    HIP_TRY(h, hipMemcpyAsync(fs.d_el.p, p.el.data(), B * sizeof(double), hipMemcpyHostToDevice, s), "copy beams");
+    if (p.kind == LIDAR_PATTERN_TABLE) {
+        HIP_TRY(h, fs.d_table.ensure(p.table.size()), "allocate table");
+        HIP_TRY(h, hipMemcpyAsync(fs.d_table.p, p.table.data(), p.table.size() * sizeof(float),
+                                  hipMemcpyHostToDevice, s), "copy table");
+    }
+    HIP_TRY(h, hipStreamSynchronize(s), "pattern copy synchronise");
+    return LIDAR_OK;
+}
+
+// Kernel extent on the pixel-offset grid: M = floor(extent_az / dphi),
+// N = floor(extent_el / de), extent = trunc * sigma (Gaussian) or the table's
+// half extent.
+void kernel_extent(const PatternHost& p, const RasterDev& r, double* M, double* N)
+{
+    if (p.kind == LIDAR_PATTERN_GAUSS) {
+        *M = std::floor(p.trunc * p.sigma[0] / r.dphi);
+        *N = std::floor(p.trunc * p.sigma[1] / r.de);
+    } else {
+        *M = std::floor(p.half[0] / r.dphi);
+        *N = std::floor(p.half[1] / r.de);
+    }
+}
+
+// Strip height for a kernel of KH rows when no tuned value exists: 64-row
+// strips for tall kernels, 16 or 4 rows (with 4 or 16 column phases) for
+// short ones.
+int default_tile(int KH) { return KH >= 40 ? 64 : (KH >= 10 ? 16 : 4); }
+
+// Kernel-height class of the autotuner (next power of two).
+int height_class(int KH)
+{
+    int c = 1;
+    while (c < KH && c < (1 << 14)) c <<= 1;
+    return c;
+}
+
+// Beam scheduler.  Beams are grouped G at a time so that one workgroup can
+// share the pixel reads of nearby footprints: beams are sorted by their
+// (approximate) pixel row band, then column, and a group takes consecutive
+// beams of one band whose columns lie within one kernel width.  The groups
+// are then ordered by column so that the groups in flight on one XCD cover a
+// narrow band of the image.  Scheduling only: the exact pixel of each beam is
+// computed on the GPU.
+void build_groups(FrameState& fs, const RasterDev& r, int G,
+                  const std::vector<lidar_beam_info>& bi)
+{
+    const PatternHost& p = fs.pat;
+    const KernelDev& k = fs.k;
+    const size_t B = p.az.size();
+    std::vector<double> uf(B), vf(B);
+    for (size_t i = 0; i < B; ++i) {
+        uf[i] = std::floor((p.az[i] - r.az_min) / r.dphi);
+        vf[i] = std::floor((r.el_max - p.el[i]) / r.de);
+    }
+    auto make = [&](double band, std::vector<std::vector<int32_t>>& groups) {
+        std::vector<int32_t> idx(B);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+            double bx = std::floor(vf[x] / band), by = std::floor(vf[y] / band);
+            if (bx != by) return bx < by;
+            return uf[x] < uf[y];
+        });
+        groups.clear();
+        std::vector<int32_t> cur;
+        double cur_band = 0, cur_u0 = 0;
+        for (int32_t i : idx) {
+            double b = std::floor(vf[i] / band);
+            bool fits = !cur.empty() && (int)cur.size() < G && b == cur_band &&
+                        uf[i] - cur_u0 <= (double)k.KW;
+            if (!fits && !cur.empty()) {
+                groups.push_back(cur);
+                cur.clear();
+            }
+            if (cur.empty()) {
+                cur_band = b;
+                cur_u0 = uf[i];
+            }
+            cur.push_back(i);
+        }
+        if (!cur.empty()) groups.push_back(cur);
+    };
+    std::vector<std::vector<int32_t>> groups;
+    make(1.0, groups);
+    if (G > 1 && groups.size() * 2 > B) {
+        // few beams share a pixel row: group across a band of rows
+        make(std::max(1.0, std::floor(k.KH / 8.0)), groups);
+    }
+    std::stable_sort(groups.begin(), groups.end(), [&](const std::vector<int32_t>& x,
+                                                       const std::vector<int32_t>& y) {
+        if (uf[x[0]] != uf[y[0]]) return uf[x[0]] < uf[y[0]];
+        return vf[x[0]] < vf[y[0]];
+    });
+    fs.groups.assign(groups.size() * G, -1);
+    fs.group_cost.assign(groups.size(), 0);
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        uint64_t cost = 0;
+        for (size_t j = 0; j < groups[gi].size(); ++j) {
+            fs.groups[gi * G + j] = groups[gi][j];
+            cost += bi[groups[gi][j]].samples;
+        }
+        fs.group_cost[gi] = cost;
+    }
+    fs.n_groups = (int)groups.size();
+}
+
+// Resample the frame's kernel on its raster, per-row data, raster tables and
+// per-beam set-up (pixel, scale, sample count) into `beams`; synchronises
+// once to check the pattern integral and to form the beam groups.
+lidar_status setup_frame(lidar_sim* h, FrameState& fs, lidar_beam_info* beams, const std::string& w)
+{
+    const lidar_gbuffer_desc& g = fs.gb;
+    RasterDev r = raster_of(g);
+    double Mf, Nf;
+    kernel_extent(fs.pat, r, &Mf, &Nf);
+    if (!(Mf >= 0 && Nf >= 0) || Mf > 4096 || Nf > 4096 || (2 * Mf + 1) * (2 * Nf + 1) > 16.0e6)
+        return fail(h, LIDAR_E_INVALID, w + "kernel grid too large for this raster (more than 16M "
+                                            "cells or 8193 columns/rows)");
+    // the footprint kernel addresses one group window of pixel records with
+    // 32-bit byte offsets
+    if ((4.0 * Mf + 8.0) * (double)g.height * 8.0 >= 2147483648.0)
+        return fail(h, LIDAR_E_INVALID, w + "kernel window times image height too large "
+                                            "(4*M+8)*height*8 must stay below 2^31 bytes");
+    KernelDev k;
+    k.M = (int)Mf;
+    k.N = (int)Nf;
+    k.KW = 2 * k.M + 1;
+    k.KH = 2 * k.N + 1;
+    const size_t cells = (size_t)k.KW * k.KH;
+    const size_t B = fs.pat.az.size();
+    HIP_TRY(h, fs.d_K64.ensure(cells), "allocate kernel");
+    HIP_TRY(h, fs.d_Kb.ensure((size_t)4 * kernel_blocks(k.KW) * (k.KH + 1) * 4),
+            "allocate kernel blocks");
+    HIP_TRY(h, fs.d_rowsum.ensure(k.KH), "allocate kernel rows");
+    HIP_TRY(h, fs.d_rowmax.ensure(k.KH), "allocate kernel rows");
+    HIP_TRY(h, fs.d_rowrange.ensure(k.KH), "allocate kernel rows");
+    HIP_TRY(h, fs.d_prefix.ensure((size_t)k.KH * (k.KW + 1)), "allocate kernel rows");
+    HIP_TRY(h, fs.d_kinfo.ensure(2), "allocate kernel info");
+    HIP_TRY(h, fs.d_colcs.ensure(g.width), "allocate raster tables");
+    HIP_TRY(h, fs.d_rowtab.ensure(g.height), "allocate raster tables");
+
+    PatternDev p;
+    p.kind = (int)fs.pat.kind;
+    p.sx = fs.pat.sigma[0];
+    p.sy = fs.pat.sigma[1];
+    p.trunc = fs.pat.trunc;
+    p.table = fs.d_table.p;
+    p.nx = (int)fs.pat.nx;
+    p.ny = (int)fs.pat.ny;
+    p.hx = fs.pat.half[0];
+    p.hy = fs.pat.half[1];
+    hipStream_t s = h->stream;
+    HIP_TRY(h, launch_kernel_grid(s, p, r, k, fs.d_K64.p), "kernel grid launch");
+    HIP_TRY(h, launch_kernel_blocks(s, k, fs.d_K64.p, fs.d_Kb.p), "kernel blocks launch");
+    HIP_TRY(h, launch_kernel_rows(s, k, fs.d_K64.p, fs.d_rowsum.p, fs.d_rowmax.p,
+                                  fs.d_rowrange.p, fs.d_prefix.p), "kernel rows launch");
+    HIP_TRY(h, launch_kernel_peak(s, k, fs.d_rowsum.p, fs.d_rowmax.p, fs.d_kinfo.p),
+            "kernel peak launch");
+    HIP_TRY(h, launch_raster_tables(s, r, fs.d_colcs.p, fs.d_rowtab.p), "raster tables launch");
+    HIP_TRY(h, launch_beam_setup(s, r, k, fs.d_az.p, fs.d_el.p, (int)B, fs.d_rowsum.p,
+                                 fs.d_prefix.p, h->prm.emit_power, beams), "beam setup launch");
+    // the pattern's integral over the grid must be positive: checked once per
+    // (pattern, raster), which synchronises the stream
+    double kinfo[2];
+    HIP_TRY(h, hipMemcpyAsync(kinfo, fs.d_kinfo.p, sizeof(kinfo), hipMemcpyDeviceToHost, s),
+            "copy kernel info");
+    std::vector<lidar_beam_info> bi(B);
+    HIP_TRY(h, hipMemcpyAsync(bi.data(), beams, sizeof(lidar_beam_info) * B,
+                              hipMemcpyDeviceToHost, s), "copy beam info");
+    HIP_TRY(h, hipStreamSynchronize(s), "set-up synchronise");
+    if (!(kinfo[1] > 0.0) || !is_fin(kinfo[1]) || !(kinfo[0] > 0.0))
+        return fail(h, LIDAR_E_INVALID, w + "pattern integral over the kernel grid is not positive "
+                                            "(kernel narrower than one pixel or all-zero table)");
+    uint64_t total = 0;
+    for (auto& x : bi) total += x.samples;
+    fs.k = k;
+    fs.kmax = kinfo[0];
+    fs.samples = total;
+    fs.tile = default_tile(k.KH);
+    build_groups(fs, r, h->G, bi);
+    return LIDAR_OK;
+}
+
+lidar_status alloc_pixels(lidar_sim* h, FrameState& fs)
+{
+    const size_t W4 = (fs.gb.width + 3) & ~3u;
+    const size_t npix = W4 * fs.gb.height;
+    HIP_TRY(h, fs.d_pix.ensure(npix), "allocate pixel records");
+    if (h->prm.sun_irradiance != 0.0) HIP_TRY(h, fs.d_sun.ensure(npix), "allocate sun shading");
+    return LIDAR_OK;
+}
+
+lidar_status enqueue_prepass(lidar_sim* h, FrameState& fs, hipStream_t s)
+{
+    const lidar_gbuffer_desc& g = fs.gb;
+    const bool sun = h->prm.sun_irradiance != 0.0;
+    PrepassArgs pa;
+    pa.depth = g.depth;
+    pa.refl = g.reflectance;
+    pa.gain = g.retro_gain;
+    pa.nx = g.normal_x;
+    pa.ny = g.normal_y;
+    pa.nz = g.normal_z;
+    pa.pitch = (long)g.pitch;
+    pa.W = (int)g.width;
+    pa.H = (int)g.height;
+    pa.W4 = (int)((g.width + 3) & ~3u);
+    pa.colcs = fs.d_colcs.p;
+    pa.rowtab = fs.d_rowtab.p;
+    pa.to_bin = 2.0 / (kLight * (h->prm.bin_ns * 1e-9));
+    pa.R = (int)h->prm.n_bins;
+    pa.sun_x = (float)h->prm.sun_dir[0];
+    pa.sun_y = (float)h->prm.sun_dir[1];
+    pa.sun_z = (float)h->prm.sun_dir[2];
+    pa.pix = fs.d_pix.p;
+    pa.sun = sun ? fs.d_sun.p : nullptr;
+    HIP_TRY(h, launch_prepass(s, pa, sun), "pre-pass launch");
+    return LIDAR_OK;
+}
+
+FrameDev frame_view(const lidar_sim* h, const FrameState& fs, lidar_beam_info* beams,
+                    lidar_echo* echoes, int32_t* counts, float* waves)
+{
+    const bool sun = h->prm.sun_irradiance != 0.0;
+    FrameDev f;
+    f.pix = fs.d_pix.p;
+    f.sun = sun ? fs.d_sun.p : nullptr;
+    f.W = (int)fs.gb.width;
+    f.H = (int)fs.gb.height;
+    f.Kb = fs.d_Kb.p;
+    f.rowrange = fs.d_rowrange.p;
+    f.M = fs.k.M;
+    f.N = fs.k.N;
+    f.KW = fs.k.KW;
+    f.KH = fs.k.KH;
+    f.NB = kernel_blocks(fs.k.KW);
+    f.tile = fs.tile;
+    f.sun_scale = sun ? (float)(h->prm.sun_irradiance / fs.kmax) : 0.0f;
+    f.beams = beams;
+    f.echoes = echoes;
+    f.counts = counts;
+    f.waves = waves;
+    return f;
+}
+
+PathDev path_view(const lidar_sim* h)
+{
+    PathDev p;
+    p.taps = h->d_taps.p;
+    p.J = h->J;
+    p.R = (int)h->prm.n_bins;
+    p.E = (int)h->prm.max_echoes;
+    p.threshold = (float)h->prm.threshold;
+    p.ambient = (float)h->prm.ambient_const;
+    p.half_c_dt = 0.5 * kLight * (h->prm.bin_ns * 1e-9);
+    p.bin_ns = h->prm.bin_ns;
+    return p;
+}
+
+// ---- batches ---------------------------------------------------------------
+
+void free_graph(lidar_sim* h)
+{
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->graph_exec = nullptr;
+    h->graph = nullptr;
+}
+
+// Enqueue the batch on s: the pre-pass of every frame (optional), the queue
+// reset and the persistent footprint launch over `items`.
+lidar_status enqueue_batch(lidar_sim* h, hipStream_t s, const int2* items, uint64_t n_items,
+                           bool with_prepass)
+{
+    if (with_prepass)
+        for (auto& fs : h->frames) LIDAR_TRY(enqueue_prepass(h, *fs, s));
+    HIP_TRY(h, launch_reset_queue(s, h->b_queue.p), "queue reset launch");
+    BatchArgs ba;
+    ba.frames = h->b_frames.p;
+    ba.p = path_view(h);
+    ba.groups = h->b_groups.p;
+    ba.items = items;
+    ba.n_items = (int)n_items;
+    ba.G = h->G;
+    ba.next_item = h->b_queue.p;
+    const bool sun = h->prm.sun_irradiance != 0.0;
+    const bool keep = (h->prm.flags & LIDAR_KEEP_WAVEFORMS) != 0;
+    HIP_TRY(h, launch_footprint_batch(s, ba, h->b_grid, sun, keep), "batch footprint launch");
+    return LIDAR_OK;
+}
+
+// Device table of the frames (pointers into the batch outputs, current tiles).
+lidar_status upload_frame_table(lidar_sim* h)
+{
+    const bool keep = (h->prm.flags & LIDAR_KEEP_WAVEFORMS) != 0;
+    const size_t E = h->prm.max_echoes, R = h->prm.n_bins;
+    std::vector<FrameDev> fd(h->frames.size());
+    for (size_t i = 0; i < h->frames.size(); ++i) {
+        const uint64_t o = h->beam_off[i];
+        fd[i] = frame_view(h, *h->frames[i], h->b_beams.p + o, h->b_echoes.p + o * E,
+                           h->b_counts.p + o, keep ? h->b_waves.p + o * R : nullptr);
+    }
+    HIP_TRY(h, h->b_frames.ensure(fd.size()), "allocate frame table");
+    HIP_TRY(h, hipMemcpyAsync(h->b_frames.p, fd.data(), fd.size() * sizeof(FrameDev),
+                              hipMemcpyHostToDevice, h->stream), "copy frame table");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "frame table synchronise");
+    return LIDAR_OK;
+}
+
+// Autotuner: for every kernel-height class of the batch, time the persistent
+// launch over that class's items alone with each candidate strip height and
+// keep the fastest.  The pixel records are computed once first; the results
+// are remembered by the handle for later batches.
+lidar_status autotune_batch(lidar_sim* h, const std::vector<int2>& items)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = h->stream;
+    for (auto& fs : h->frames) LIDAR_TRY(enqueue_prepass(h, *fs, s));
+    std::map<int, std::vector<int2>> by_class;
+    for (const int2& it : items) by_class[height_class(h->frames[it.x]->k.KH)].push_back(it);
+    DevBuf<int2> d_trial;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    lidar_status st = he == hipSuccess ? LIDAR_OK : hip_fail(h, he, "autotune events");
+    for (auto& kv : by_class) {
+        if (st != LIDAR_OK) break;
+        const int cls = kv.first;
+        const std::vector<int2>& its = kv.second;
+        he = d_trial.ensure(its.size());
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(d_trial.p, its.data(), its.size() * sizeof(int2),
+                                hipMemcpyHostToDevice, s);
+        if (he != hipSuccess) {
+            st = hip_fail(h, he, "autotune items");
+            break;
+        }
+        float best = 1e30f;
+        int best_tile = default_tile(cls);
+        for (int tile : {64, 16, 4}) {
+            if (tile == 64 && cls < 16) continue;   // strips 4x taller than the kernel
+            for (auto& fs : h->frames)
+                if (height_class(fs->k.KH) == cls) fs->tile = tile;
+            if ((st = upload_frame_table(h)) != LIDAR_OK) break;
+            float ms = 0.0f;
+            for (int rep = 0; rep < 2 && st == LIDAR_OK; ++rep) {
+                he = hipEventRecord(e0, s);
+                if (he != hipSuccess) { st = hip_fail(h, he, "autotune event"); break; }
+                if ((st = enqueue_batch(h, s, d_trial.p, its.size(), false)) != LIDAR_OK) break;
+                he = hipEventRecord(e1, s);
+                if (he == hipSuccess) he = hipEventSynchronize(e1);
+                if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                if (he != hipSuccess) { st = hip_fail(h, he, "autotune timing"); break; }
+            }
+            if (st != LIDAR_OK) break;
+            if (ms < best) {
+                best = ms;
+                best_tile = tile;
+            }
+        }
+        if (st != LIDAR_OK) break;
+        h->tuned_tile[cls] = best_tile;
+        for (auto& fs : h->frames)
+            if (height_class(fs->k.KH) == cls) fs->tile = best_tile;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    LIDAR_TRY(st);
+    LIDAR_TRY(upload_frame_table(h));
+    h->b_autotuned = true;
+    h->b_autotune_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return LIDAR_OK;
+}
+
+lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lidar_pattern_desc* pds,
+                         uint32_t n)
+{
+    // a previous batch may still run on the stream with these buffers
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "batch synchronise");
+    h->batch_ok = false;
+    h->batch_result = false;
+    free_graph(h);
+    for (uint32_t i = 0; i < n; ++i) {
+        const std::string who = "frame " + std::to_string(i) + ": ";
+        LIDAR_TRY(check_pattern(h, &pds[i], who));
+        LIDAR_TRY(check_gbuffer(h, &gbs[i], who));
+    }
+    h->frames.resize(n);
+    h->beam_off.assign(n + 1, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!h->frames[i]) h->frames[i].reset(new (std::nothrow) FrameState());
+        if (!h->frames[i]) return fail(h, LIDAR_E_NOMEM, "out of host memory");
+        h->beam_off[i + 1] = h->beam_off[i] + pds[i].n_beams;
+    }
+    const uint64_t B = h->beam_off[n];
+    const size_t E = h->prm.max_echoes, R = h->prm.n_bins;
+    HIP_TRY(h, h->b_beams.ensure(B), "allocate batch beams");
+    HIP_TRY(h, h->b_echoes.ensure(B * E), "allocate batch echoes");
+    HIP_TRY(h, h->b_counts.ensure(B), "allocate batch counts");
+    if (h->prm.flags & LIDAR_KEEP_WAVEFORMS) HIP_TRY(h, h->b_waves.ensure(B * R), "allocate batch waveforms");
+    HIP_TRY(h, h->b_queue.ensure(1), "allocate work queue");
+    std::vector<uint64_t> group_off(n + 1, 0);
+    uint64_t samples = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const std::string who = "frame " + std::to_string(i) + ": ";
+        FrameState& fs = *h->frames[i];
+        fs.gb = gbs[i];
+        LIDAR_TRY(copy_pattern(h, fs, &pds[i]));
+        LIDAR_TRY(setup_frame(h, fs, h->b_beams.p + h->beam_off[i], who));
+        auto it = h->tuned_tile.find(height_class(fs.k.KH));
+        if (it != h->tuned_tile.end()) fs.tile = it->second;
+        LIDAR_TRY(alloc_pixels(h, fs));
+        group_off[i + 1] = group_off[i] + fs.n_groups;
+        samples += fs.samples;
+    }
+    const uint64_t total_groups = group_off[n];
+    if (total_groups >= (1ull << 31)) return fail(h, LIDAR_E_INVALID, "batch has more than 2^31 beam groups");
+    // every frame's groups in one table; work items ordered by estimated
+    // cost, costliest first (gather samples plus the convolution and
+    // detection work of the group's R bins)
+    const int G = h->G;
+    std::vector<int32_t> groups(total_groups * G);
+    std::vector<int2> items(total_groups);
+    std::vector<uint64_t> cost(total_groups);
+    const uint64_t bin_cost = (uint64_t)G * R * (2 * h->J + 1) / 8;
+    for (uint32_t i = 0; i < n; ++i) {
+        FrameState& fs = *h->frames[i];
+        std::copy(fs.groups.begin(), fs.groups.end(), groups.begin() + group_off[i] * G);
+        for (int gi = 0; gi < fs.n_groups; ++gi) {
+            const uint64_t gidx = group_off[i] + gi;
+            items[gidx] = make_int2((int)i, (int)gidx);
+            cost[gidx] = fs.group_cost[gi] + bin_cost;
+        }
+    }
+    std::vector<size_t> order(total_groups);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    std::vector<int2> sorted(total_groups);
+    for (size_t j = 0; j < total_groups; ++j) sorted[j] = items[order[j]];
+    HIP_TRY(h, h->b_groups.ensure(groups.size()), "allocate batch groups");
+    HIP_TRY(h, h->b_items.ensure(sorted.size()), "allocate batch items");
+    HIP_TRY(h, hipMemcpyAsync(h->b_groups.p, groups.data(), groups.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, h->stream), "copy batch groups");
+    HIP_TRY(h, hipMemcpyAsync(h->b_items.p, sorted.data(), sorted.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, h->stream), "copy batch items");
+    h->b_items_n = total_groups;
+    h->b_samples = samples;
+    // persistent grid: as many workgroups as the CUs hold at the LDS-bound
+    // occupancy (extra workgroups would find the queue empty and exit)
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    const size_t lds = sizeof(float) * ((size_t)G * R + 2 * h->J + 1) + 1024;
+    const size_t per_cu = std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
+    h->b_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * per_cu, total_groups));
+    LIDAR_TRY(upload_frame_table(h));
+    h->b_autotuned = false;
+    h->b_autotune_ms = 0.0;
+    if (h->prm.flags & LIDAR_AUTOTUNE) LIDAR_TRY(autotune_batch(h, sorted));
+    // capture the batch into a graph on a private stream; it is launched on
+    // the handle's stream
+    if (!h->capture_stream)
+        HIP_TRY(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking),
+                "create capture stream");
+    HIP_TRY(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal),
+            "begin graph capture");
+    lidar_status st = enqueue_batch(h, h->capture_stream, h->b_items.p, h->b_items_n, true);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(h->capture_stream, &graph);
+    if (st != LIDAR_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    HIP_TRY(h, e, "end graph capture");
+    h->graph = graph;
+    HIP_TRY(h, hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0), "instantiate graph");
+    h->batch_gb.assign(gbs, gbs + n);
+    h->batch_pd.assign(pds, pds + n);
+    h->batch_ok = true;
     return LIDAR_OK;
 }
 
@@ -403,6 +856,8 @@ lidar_status lidar_sim_create(const lidar_sim_params* params, void* hip_stream, 
     h->stream = (hipStream_t)hip_stream;
     double sigma = params->pulse_fwhm_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
     h->J = (int)std::ceil(params->pulse_trunc_sigmas * sigma / params->bin_ns);
+    h->G = 4;
+    while (h->G > 1 && !footprint_group_fits(h->G, (int)params->n_bins, h->J)) h->G /= 2;
     hipError_t e = h->d_taps.ensure(2 * h->J + 1);
     if (e == hipSuccess)
         e = launch_pulse_taps(h->stream, (float)sigma, (float)params->bin_ns, h->J, h->d_taps.p);
@@ -420,80 +875,23 @@ lidar_status lidar_sim_destroy(lidar_sim* h)
 {
     if (!h) return LIDAR_OK;
     (void)hipStreamSynchronize(h->stream);
-    for (auto* v : {&h->pending_fp, &h->pending_pp, &h->pool})
+    for (auto* v : {&h->pending_fp, &h->pending_pp, &h->pending_bt, &h->pool})
         for (auto& p : *v) {
             (void)hipEventDestroy(p.a);
             (void)hipEventDestroy(p.b);
         }
-    h->d_table.release(); h->d_az.release(); h->d_el.release(); h->d_groups.release();
-    h->d_K64.release(); h->d_rowsum.release(); h->d_rowmax.release(); h->d_kinfo.release();
-    h->d_Kb.release(); h->d_rowrange.release(); h->d_prefix.release();
-    h->d_colcs.release(); h->d_rowtab.release(); h->d_beams.release(); h->d_taps.release();
-    h->d_pix.release(); h->d_sun.release(); h->d_echoes.release(); h->d_counts.release();
-    h->d_waves.release();
-    delete h;
+    free_graph(h);
+    if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    delete h;   // the device buffers free themselves
     return LIDAR_OK;
 }
 
 lidar_status lidar_sim_set_pattern(lidar_sim* h, const lidar_pattern_desc* pd)
 {
     if (!h) return LIDAR_E_INVALID;
-    if (!pd) return fail(h, LIDAR_E_INVALID, "pattern is NULL");
-    if (pd->n_beams == 0 || !pd->beam_az_deg || !pd->beam_el_deg)
-        return fail(h, LIDAR_E_INVALID, "pattern needs n_beams >= 1 and beam angle arrays");
-    if (pd->n_beams > (1u << 26)) return fail(h, LIDAR_E_INVALID, "too many beams (max 2^26)");
-    for (uint32_t i = 0; i < pd->n_beams; ++i)
-        if (!is_fin(pd->beam_az_deg[i]) || !is_fin(pd->beam_el_deg[i]))
-            return fail(h, LIDAR_E_INVALID, "non-finite beam angle");
-    if (pd->kind == LIDAR_PATTERN_GAUSS) {
-        if (!(pd->sigma_deg[0] > 0) || !(pd->sigma_deg[1] > 0) || !is_fin(pd->sigma_deg[0]) ||
-            !is_fin(pd->sigma_deg[1]) || !(pd->trunc_sigmas > 0) || !is_fin(pd->trunc_sigmas))
-            return fail(h, LIDAR_E_INVALID, "Gaussian pattern needs sigma > 0 and trunc_sigmas > 0");
-    } else if (pd->kind == LIDAR_PATTERN_TABLE) {
-        if (!pd->table || pd->nx < 2 || pd->ny < 2 || (uint64_t)pd->nx * pd->ny > (1u << 24))
-            return fail(h, LIDAR_E_INVALID, "table pattern needs a table of at least 2x2 (max 16M cells)");
-        if (!(pd->half_deg[0] > 0) || !(pd->half_deg[1] > 0) || !is_fin(pd->half_deg[0]) ||
-            !is_fin(pd->half_deg[1]))
-            return fail(h, LIDAR_E_INVALID, "table pattern needs half extents > 0");
-        bool any = false;
-        for (uint64_t i = 0; i < (uint64_t)pd->nx * pd->ny; ++i) {
-            float v = pd->table[i];
-            if (!std::isfinite(v) || v < 0.0f)
-                return fail(h, LIDAR_E_INVALID, "table values must be finite and >= 0");
-            any |= v > 0.0f;
-        }
-        if (!any) return fail(h, LIDAR_E_INVALID, "table is all zero (pattern integral is 0)");
-    } else {
-        return fail(h, LIDAR_E_INVALID, "unknown pattern kind");
-    }
-    const size_t B = pd->n_beams;
-    h->az.assign(pd->beam_az_deg, pd->beam_az_deg + B);
-    h->el.assign(pd->beam_el_deg, pd->beam_el_deg + B);
-    HIP_TRY(h, h->d_az.ensure(B), "allocate beams");
-    HIP_TRY(h, h->d_el.ensure(B), "allocate beams");
-    hipStream_t s = h->stream;
-    // pageable sources: these copies complete before the call returns
-    HIP_TRY(h, hipMemcpyAsync(h->d_az.p, h->az.data(), B * sizeof(double), hipMemcpyHostToDevice, s), "copy beams");
-    HIP_TRY(h, hipMemcpyAsync(h->d_el.p, h->el.data(), B * sizeof(double), hipMemcpyHostToDevice, s), "copy beams");
-    h->kind = pd->kind;
-    if (pd->kind == LIDAR_PATTERN_GAUSS) {
-        h->sigma[0] = pd->sigma_deg[0];
-        h->sigma[1] = pd->sigma_deg[1];
-        h->trunc = pd->trunc_sigmas;
-        h->nx = h->ny = 0;
-    } else {
-        const size_t cells = (size_t)pd->nx * pd->ny;
-        HIP_TRY(h, h->d_table.ensure(cells), "allocate table");
-        HIP_TRY(h, hipMemcpyAsync(h->d_table.p, pd->table, cells * sizeof(float),
-                                  hipMemcpyHostToDevice, s), "copy table");
-        h->nx = pd->nx;
-        h->ny = pd->ny;
-        h->half[0] = pd->half_deg[0];
-        h->half[1] = pd->half_deg[1];
-    }
-    HIP_TRY(h, hipStreamSynchronize(s), "set_pattern synchronise");
+    LIDAR_TRY(check_pattern(h, pd, ""));
+    LIDAR_TRY(copy_pattern(h, h->single, pd));
     h->have_pattern = true;
-    ++h->pattern_version;
     h->setup_ok = false;
     h->have_result = false;
     return LIDAR_OK;
@@ -502,21 +900,10 @@ lidar_status lidar_sim_set_pattern(lidar_sim* h, const lidar_pattern_desc* pd)
 lidar_status lidar_sim_set_gbuffer(lidar_sim* h, const lidar_gbuffer_desc* g)
 {
     if (!h) return LIDAR_E_INVALID;
-    if (!g) return fail(h, LIDAR_E_INVALID, "gbuffer is NULL");
-    if (g->width == 0 || g->height == 0 || g->pitch < g->width)
-        return fail(h, LIDAR_E_INVALID, "gbuffer needs width, height >= 1 and pitch >= width");
-    if ((uint64_t)g->width * g->height > (1ull << 31))
-        return fail(h, LIDAR_E_INVALID, "gbuffer larger than 2^31 pixels");
-    if (!g->depth || !g->reflectance || !g->retro_gain || !g->normal_x || !g->normal_y || !g->normal_z)
-        return fail(h, LIDAR_E_INVALID, "gbuffer plane pointer is NULL");
-    if (!is_fin(g->az_min_deg) || !is_fin(g->az_max_deg) || !is_fin(g->el_min_deg) ||
-        !is_fin(g->el_max_deg) || !(g->az_min_deg < g->az_max_deg) || !(g->el_min_deg < g->el_max_deg))
-        return fail(h, LIDAR_E_INVALID, "gbuffer angle ranges must be finite with min < max");
-    if (g->el_min_deg < -90.0 || g->el_max_deg > 90.0)
-        return fail(h, LIDAR_E_INVALID, "gbuffer elevations must lie in [-90, 90]");
-    h->gb = *g;
+    LIDAR_TRY(check_gbuffer(h, g, ""));
+    if (h->setup_ok && !same_raster(h->single.gb, *g)) h->setup_ok = false;
+    h->single.gb = *g;
     h->have_gbuffer = true;
-    if (h->setup_ok && !same_raster(h->setup_gb, *g)) h->setup_ok = false;
     return LIDAR_OK;
 }
 
@@ -526,76 +913,35 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
     if (mode != LIDAR_MODE_PLAIN) return fail(h, LIDAR_E_UNSUPPORTED, "only LIDAR_MODE_PLAIN is implemented");
     if (!h->have_pattern) return fail(h, LIDAR_E_STATE, "simulate_frame before set_pattern");
     if (!h->have_gbuffer) return fail(h, LIDAR_E_STATE, "simulate_frame before set_gbuffer");
-    if (!h->setup_ok || h->setup_version != h->pattern_version) {
-        lidar_status st = run_setup(h);
-        if (st != LIDAR_OK) return st;
-    }
-    const lidar_gbuffer_desc& g = h->gb;
-    const int W4 = (int)((g.width + 3) & ~3u);
-    const size_t npix = (size_t)W4 * g.height;
-    const size_t B = h->az.size();
+    FrameState& fs = h->single;
+    const size_t B = fs.pat.az.size();
     const uint32_t R = h->prm.n_bins, E = h->prm.max_echoes;
-    const bool sun = h->prm.sun_irradiance != 0.0;
     const bool keep = (h->prm.flags & LIDAR_KEEP_WAVEFORMS) != 0;
     const bool prof = (h->prm.flags & LIDAR_PROFILE) != 0;
-    HIP_TRY(h, h->d_pix.ensure(npix), "allocate pixel records");
-    if (sun) HIP_TRY(h, h->d_sun.ensure(npix), "allocate sun shading");
+    if (!h->setup_ok) {
+        HIP_TRY(h, h->d_beams.ensure(B), "allocate beams");
+        LIDAR_TRY(setup_frame(h, fs, h->d_beams.p, ""));
+        HIP_TRY(h, h->d_groups.ensure(fs.groups.size()), "allocate beam groups");
+        HIP_TRY(h, hipMemcpyAsync(h->d_groups.p, fs.groups.data(), fs.groups.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, h->stream), "copy beam groups");
+        HIP_TRY(h, hipStreamSynchronize(h->stream), "set-up synchronise");
+        auto it = h->tuned_tile.find(height_class(fs.k.KH));
+        if (it != h->tuned_tile.end()) fs.tile = it->second;
+        h->setup_ok = true;
+    }
+    LIDAR_TRY(alloc_pixels(h, fs));
     HIP_TRY(h, h->d_echoes.ensure(B * E), "allocate echoes");
     HIP_TRY(h, h->d_counts.ensure(B), "allocate counts");
     if (keep) HIP_TRY(h, h->d_waves.ensure(B * (size_t)R), "allocate waveforms");
 
     hipStream_t s = h->stream;
-    RasterDev r = raster_of(g);
-    PrepassArgs pa;
-    pa.depth = g.depth;
-    pa.refl = g.reflectance;
-    pa.gain = g.retro_gain;
-    pa.nx = g.normal_x;
-    pa.ny = g.normal_y;
-    pa.nz = g.normal_z;
-    pa.pitch = (long)g.pitch;
-    pa.W = r.W;
-    pa.H = r.H;
-    pa.colcs = h->d_colcs.p;
-    pa.rowtab = h->d_rowtab.p;
-    pa.to_bin = 2.0 / (kLight * (h->prm.bin_ns * 1e-9));
-    pa.R = (int)R;
-    pa.sun_x = (float)h->prm.sun_dir[0];
-    pa.sun_y = (float)h->prm.sun_dir[1];
-    pa.sun_z = (float)h->prm.sun_dir[2];
-    pa.pix = h->d_pix.p;
-    pa.sun = sun ? h->d_sun.p : nullptr;
-    pa.W4 = W4;
-
     FootprintArgs fa;
-    fa.pix = h->d_pix.p;
-    fa.sun = sun ? h->d_sun.p : nullptr;
-    fa.W = r.W;
-    fa.H = r.H;
-    fa.Kb = h->d_Kb.p;
-    fa.NB = kernel_blocks(h->kgeom.KW);
-    fa.rowrange = h->d_rowrange.p;
-    fa.M = h->kgeom.M;
-    fa.N = h->kgeom.N;
-    fa.KW = h->kgeom.KW;
-    fa.KH = h->kgeom.KH;
+    fa.f = frame_view(h, fs, h->d_beams.p, h->d_echoes.p, h->d_counts.p, keep ? h->d_waves.p : nullptr);
+    fa.p = path_view(h);
     fa.groups = h->d_groups.p;
-    fa.n_groups = h->n_groups;
+    fa.n_groups = fs.n_groups;
     fa.G = h->G;
-    fa.chunk = (h->n_groups + kXcds - 1) / kXcds;
-    fa.beams = h->d_beams.p;
-    fa.taps = h->d_taps.p;
-    fa.J = h->J;
-    fa.R = (int)R;
-    fa.threshold = (float)h->prm.threshold;
-    fa.ambient = (float)h->prm.ambient_const;
-    fa.sun_scale = sun ? (float)(h->prm.sun_irradiance / h->kmax) : 0.0f;
-    fa.E = (int)E;
-    fa.echoes = h->d_echoes.p;
-    fa.counts = h->d_counts.p;
-    fa.waves = keep ? h->d_waves.p : nullptr;
-    fa.half_c_dt = 0.5 * kLight * (h->prm.bin_ns * 1e-9);
-    fa.bin_ns = h->prm.bin_ns;
+    fa.chunk = (fs.n_groups + kXcds - 1) / kXcds;
 
     EventPair pp{}, fp{};
     if (prof) {
@@ -606,7 +952,7 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
         HIP_TRY(h, e, "create events");
         HIP_TRY(h, hipEventRecord(pp.a, s), "record event");
     }
-    HIP_TRY(h, launch_prepass(s, pa, sun), "pre-pass launch");
+    LIDAR_TRY(enqueue_prepass(h, fs, s));
     if (prof) {
         HIP_TRY(h, hipEventRecord(pp.b, s), "record event");
         HIP_TRY(h, hipEventRecord(fp.a, s), "record event");
@@ -629,7 +975,7 @@ lidar_status lidar_sim_read_echoes(lidar_sim* h, lidar_echo* echoes, int32_t* n_
     if (!h->have_result) return fail(h, LIDAR_E_STATE, "read_echoes before simulate_frame");
     if (waveforms && !(h->prm.flags & LIDAR_KEEP_WAVEFORMS))
         return fail(h, LIDAR_E_INVALID, "waveforms requested without LIDAR_KEEP_WAVEFORMS");
-    const size_t B = h->az.size();
+    const size_t B = h->single.pat.az.size();
     const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     hipStream_t s = h->stream;
     if (echoes)
@@ -647,15 +993,103 @@ lidar_status lidar_sim_read_echoes(lidar_sim* h, lidar_echo* echoes, int32_t* n_
     return LIDAR_OK;
 }
 
+lidar_status lidar_sim_simulate_batch(lidar_sim* h, const lidar_gbuffer_desc* frames,
+                                      const lidar_pattern_desc* patterns, uint32_t n_frames)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!frames || !patterns || n_frames == 0)
+        return fail(h, LIDAR_E_INVALID, "simulate_batch needs n_frames >= 1 and both arrays");
+    if (n_frames > 65536) return fail(h, LIDAR_E_INVALID, "too many frames (max 65536)");
+    bool same = h->batch_ok && h->batch_gb.size() == n_frames;
+    for (uint32_t i = 0; same && i < n_frames; ++i)
+        same = same_gbuffer(h->batch_gb[i], frames[i]) && same_pattern(h->batch_pd[i], patterns[i]);
+    if (!same) LIDAR_TRY(setup_batch(h, frames, patterns, n_frames));
+    const bool prof = (h->prm.flags & LIDAR_PROFILE) != 0;
+    EventPair bt{};
+    if (prof) {
+        hipError_t e;
+        bt = take_pair(h, &e);
+        HIP_TRY(h, e, "create events");
+        HIP_TRY(h, hipEventRecord(bt.a, h->stream), "record event");
+    }
+    HIP_TRY(h, hipGraphLaunch(h->graph_exec, h->stream), "graph launch");
+    if (prof) {
+        HIP_TRY(h, hipEventRecord(bt.b, h->stream), "record event");
+        h->pending_bt.push_back(bt);
+    }
+    h->batch_result = true;
+    h->st.frames += n_frames;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_read_batch(lidar_sim* h, uint32_t frame, lidar_echo* echoes,
+                                  int32_t* n_echoes, float* waveforms, lidar_beam_info* beams,
+                                  int dst_is_device)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!h->batch_result) return fail(h, LIDAR_E_STATE, "read_batch before simulate_batch");
+    if (frame >= h->frames.size()) return fail(h, LIDAR_E_INVALID, "frame index out of range");
+    if (waveforms && !(h->prm.flags & LIDAR_KEEP_WAVEFORMS))
+        return fail(h, LIDAR_E_INVALID, "waveforms requested without LIDAR_KEEP_WAVEFORMS");
+    const uint64_t o = h->beam_off[frame], B = h->beam_off[frame + 1] - o;
+    const size_t E = h->prm.max_echoes, R = h->prm.n_bins;
+    const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    hipStream_t s = h->stream;
+    if (echoes)
+        HIP_TRY(h, hipMemcpyAsync(echoes, h->b_echoes.p + o * E, B * E * sizeof(lidar_echo), kind, s),
+                "copy echoes");
+    if (n_echoes)
+        HIP_TRY(h, hipMemcpyAsync(n_echoes, h->b_counts.p + o, B * sizeof(int32_t), kind, s), "copy counts");
+    if (waveforms)
+        HIP_TRY(h, hipMemcpyAsync(waveforms, h->b_waves.p + o * R, B * R * sizeof(float), kind, s),
+                "copy waveforms");
+    if (beams)
+        HIP_TRY(h, hipMemcpyAsync(beams, h->b_beams.p + o, B * sizeof(lidar_beam_info), kind, s),
+                "copy beam info");
+    if (!dst_is_device) HIP_TRY(h, hipStreamSynchronize(s), "read synchronise");
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_batch_info(lidar_sim* h, lidar_batch_info* out)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!out) return fail(h, LIDAR_E_INVALID, "out is NULL");
+    if (!h->batch_ok) return fail(h, LIDAR_E_STATE, "no batch has been set up");
+    lidar_batch_info bi{};
+    bi.n_frames = (uint32_t)h->frames.size();
+    bi.group_size = (uint32_t)h->G;
+    bi.n_beams = h->beam_off.back();
+    bi.n_items = h->b_items_n;
+    bi.samples = h->b_samples;
+    bi.grid = (uint32_t)h->b_grid;
+    bi.graph = h->graph_exec ? 1u : 0u;
+    bi.autotuned = h->b_autotuned ? 1u : 0u;
+    bi.autotune_ms = h->b_autotune_ms;
+    *out = bi;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_reset_batch(lidar_sim* h)
+{
+    if (!h) return LIDAR_E_INVALID;
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "reset synchronise");
+    free_graph(h);
+    h->batch_ok = false;
+    h->batch_result = false;
+    h->batch_gb.clear();
+    h->batch_pd.clear();
+    return LIDAR_OK;
+}
+
 lidar_status lidar_sim_get_stats(lidar_sim* h, lidar_stats* out)
 {
-    if (!h || !out) return h ? fail(h, LIDAR_E_INVALID, "out is NULL") : LIDAR_E_INVALID;
-    lidar_status st = drain_events(h);
-    if (st != LIDAR_OK) return st;
-    h->st.n_beams = h->az.size();
-    h->st.samples_per_frame = h->setup_ok ? h->samples : 0;
-    h->st.kernel_w = h->setup_ok ? (uint32_t)h->kgeom.KW : 0;
-    h->st.kernel_h = h->setup_ok ? (uint32_t)h->kgeom.KH : 0;
+    if (!h) return LIDAR_E_INVALID;
+    if (!out) return fail(h, LIDAR_E_INVALID, "out is NULL");
+    LIDAR_TRY(drain_events(h));
+    h->st.n_beams = h->single.pat.az.size();
+    h->st.samples_per_frame = h->setup_ok ? h->single.samples : 0;
+    h->st.kernel_w = h->setup_ok ? (uint32_t)h->single.k.KW : 0;
+    h->st.kernel_h = h->setup_ok ? (uint32_t)h->single.k.KH : 0;
     *out = h->st;
     return LIDAR_OK;
 }
@@ -663,13 +1097,14 @@ lidar_status lidar_sim_get_stats(lidar_sim* h, lidar_stats* out)
 lidar_status lidar_sim_reset_stats(lidar_sim* h)
 {
     if (!h) return LIDAR_E_INVALID;
-    lidar_status st = drain_events(h);
-    if (st != LIDAR_OK) return st;
+    LIDAR_TRY(drain_events(h));
     h->st.frames = 0;
     h->st.footprint_ms = 0.0;
     h->st.footprint_launches = 0;
     h->st.prepass_ms = 0.0;
     h->st.prepass_launches = 0;
+    h->st.batch_ms = 0.0;
+    h->st.batch_launches = 0;
     return LIDAR_OK;
 }
 

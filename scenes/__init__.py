@@ -405,3 +405,112 @@ def shell_gbuffer(raster: Raster, depth_m: float, rho: float, gain: float = 1.0)
     return GBuffer(raster, np.full((H, W), depth_m, np.float32),
                    np.full((H, W), rho, np.float32),
                    np.full((H, W), gain, np.float32), n.astype(np.float32))
+
+
+# ----------------------------------------------------------------------------
+# Workload 3: a batch of uneven frames
+# ----------------------------------------------------------------------------
+
+@dataclass
+class BatchWorkload:
+    name: str
+    frames: list            # of Workload, all with the same SensorParams
+    params: SensorParams
+    meta: dict = field(default_factory=dict)
+
+
+def lissajous_beams(raster: Raster, n: int, p: int, q: int, fill: float = 0.95):
+    """n beams along a Lissajous figure over the FOV: az = A_az sin(2 pi p t +
+    pi/2), el = A_el sin(2 pi q t), t = i / n (centred on the FOV)."""
+    t = np.arange(n, dtype=np.float64) / n
+    ca = 0.5 * (raster.az_min + raster.az_max)
+    cel = 0.5 * (raster.el_min + raster.el_max)
+    A_az = 0.5 * fill * (raster.az_max - raster.az_min)
+    A_el = 0.5 * fill * (raster.el_max - raster.el_min)
+    az = ca + A_az * np.sin(2.0 * math.pi * p * t + 0.5 * math.pi)
+    el = cel + A_el * np.sin(2.0 * math.pi * q * t)
+    return az, el
+
+
+def jitter_beams(raster: Raster, n_az: int, n_el: int, rng: np.random.Generator):
+    """Grid beams moved by U(-1/2, 1/2) of the grid spacing in each angle."""
+    az, el = grid_beams(raster, n_az, n_el)
+    da = (raster.az_max - raster.az_min) / n_az
+    de = (raster.el_max - raster.el_min) / n_el
+    az = az + rng.uniform(-0.5, 0.5, az.shape) * da
+    el = el + rng.uniform(-0.5, 0.5, el.shape) * de
+    return az, el
+
+
+CONFIG3_SIZES = ((512, 256), (1024, 512), (2048, 1024), (4096, 2048))
+
+
+def config3_params() -> SensorParams:
+    """Sensor of the batch workload: the scanning sensor's waveform (2048 bins
+    of 0.5 ns, 4 ns pulse, threshold) with a constant ambient term instead of
+    the sun (the sun floor grows with the footprint's solid angle, which here
+    spans three decades)."""
+    return SensorParams(n_bins=2048, bin_ns=0.5, max_echoes=3,
+                        threshold=CONFIG2_THRESHOLD, emit_power=1.0,
+                        pulse_fwhm_ns=4.0, pulse_trunc_sigmas=4.0,
+                        ambient_const=1e-8, sun_irradiance=0.0)
+
+
+def config3(seed: int = 0, n_frames: int = 64, sizes=CONFIG3_SIZES,
+            beams=(5000, 100000), footprint_px=(20.0, 20000.0),
+            fov=(60.0, 30.0), threads: int = 8) -> BatchWorkload:
+    """Batch of ``n_frames`` frames: sizes cycled through ``sizes`` (equal
+    counts, shuffled), scenes alternating between i.i.d. surfaces (as the
+    1-frame workload) and the road + boxes ray cast (as the scanning sensor)
+    over a ``fov`` (deg) field of view, steering cycling through grid,
+    Lissajous (coprime p, q) and jittered grid, beam count ~ log-U(``beams``)
+    and Gaussian footprints of F ~ log-U(``footprint_px``) pixels (radius
+    sqrt(F / pi) px = 3 sigma).  Smaller ``sizes``/``beams``/``footprint_px``
+    give the same recipe at test scale."""
+    rng = np.random.default_rng(seed)
+    params = config3_params()
+    size_idx = np.repeat(np.arange(len(sizes)), int(math.ceil(n_frames / len(sizes))))[:n_frames]
+    rng.shuffle(size_idx)
+
+    def frame(i):
+        W, H = sizes[size_idx[i]]
+        raster = Raster(W, H, -0.5 * fov[0], 0.5 * fov[0], -0.5 * fov[1], 0.5 * fov[1])
+        frng = np.random.default_rng([seed, i])
+        if i % 2 == 0:
+            gb = random_gbuffer(raster, frng)
+            style = "iid"
+        else:
+            gb = road_scene(raster, frng)[0]
+            style = "road"
+        B = int(round(math.exp(frng.uniform(math.log(beams[0]), math.log(beams[1])))))
+        F = math.exp(frng.uniform(math.log(footprint_px[0]), math.log(footprint_px[1])))
+        sigma_px = math.sqrt(F / math.pi) / 3.0
+        steer = ("grid", "lissajous", "jitter")[i % 3]
+        n_el = max(1, int(round(math.sqrt(B * H / W))))
+        n_az = max(1, int(round(B / n_el)))
+        if steer == "grid":
+            az, el = grid_beams(raster, n_az, n_el)
+        elif steer == "jitter":
+            az, el = jitter_beams(raster, n_az, n_el, frng)
+        else:
+            p = int(frng.integers(50, 400))
+            q = int(frng.integers(int(0.6 * p), int(0.9 * p)))
+            while math.gcd(p, q) != 1:
+                q += 1
+            az, el = lissajous_beams(raster, B, p, q)
+        pat = Pattern(PATTERN_GAUSS, az, el,
+                      sigma_deg=(sigma_px * raster.dphi, sigma_px * raster.de),
+                      trunc_sigmas=3.0)
+        return Workload(f"frame{i}-{W}x{H}-{style}-{steer}", gb, pat, params,
+                        {"footprint_px": F, "steering": steer, "scene": style})
+
+    # every frame draws from its own seeded generator: threads do not change
+    # the result
+    if threads > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            frames = list(ex.map(frame, range(n_frames)))
+    else:
+        frames = [frame(i) for i in range(n_frames)]
+    return BatchWorkload(f"batch-{n_frames}frames-uneven", frames, params,
+                         {"seed": seed, "sizes": [sizes[k] for k in size_idx]})

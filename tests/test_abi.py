@@ -46,7 +46,8 @@ def test_struct_layout_matches_header(binding, tmp_path):
     structs = {"lidar_sim_params": binding.lidar_sim_params,
                "lidar_pattern_desc": binding.lidar_pattern_desc,
                "lidar_gbuffer_desc": binding.lidar_gbuffer_desc,
-               "lidar_stats": binding.lidar_stats}
+               "lidar_stats": binding.lidar_stats,
+               "lidar_batch_info": binding.lidar_batch_info}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"',
              "int main(void) {"]
     for sname, cls in structs.items():
@@ -111,3 +112,7 @@ def test_null_arguments_are_rejected(binding):
     assert lib.lidar_sim_simulate_frame(None, 0) == binding.LIDAR_E_INVALID
     assert lib.lidar_sim_read_echoes(None, None, None, None, None, 0) == binding.LIDAR_E_INVALID
     assert lib.lidar_sim_get_stats(None, None) == binding.LIDAR_E_INVALID
+    assert lib.lidar_sim_simulate_batch(None, None, None, 0) == binding.LIDAR_E_INVALID
+    assert lib.lidar_sim_read_batch(None, 0, None, None, None, None, 0) == binding.LIDAR_E_INVALID
+    assert lib.lidar_sim_batch_info(None, None) == binding.LIDAR_E_INVALID
+    assert lib.lidar_sim_reset_batch(None) == binding.LIDAR_E_INVALID

@@ -1,0 +1,201 @@
+"""Parity of the batched path (one persistent launch over many uneven frames,
+replayed from a captured HIP graph) with the FP64 oracle, through the C-ABI.
+"""
+from dataclasses import replace
+import math
+
+import numpy as np
+import pytest
+
+import scenes
+from scenes import PATTERN_TABLE, Pattern
+
+from .parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_05932_amd as lidar
+    lidar.load()
+
+
+def _small_batch(seed=0, n_frames=12):
+    """The batch recipe at test scale: 4 raster sizes (ragged, not multiples
+    of 4 or 64), 150-1500 beams, footprints of 20-4000 pixels."""
+    return scenes.config3(seed, n_frames=n_frames,
+                          sizes=((130, 66), (258, 129), (517, 250), (301, 301)),
+                          beams=(150, 1500), footprint_px=(20.0, 4000.0))
+
+
+def _upload(bw):
+    import paper_2512_05932_amd as lidar
+    return [lidar.upload_gbuffer(f.gbuffer, "cuda") for f in bw.frames]
+
+
+def _check_all(sim, bw, params, oracle_mod, tag, waveforms=True, idx=None):
+    reps = []
+    for i, f in enumerate(bw.frames):
+        got = sim.read_batch(i, waveforms=waveforms)
+        pat = f.pattern if idx is None else scenes.subset_beams(f, idx[i]).pattern
+        ref = oracle_mod.simulate(f.gbuffer, pat, params, want_xi=False)
+        reps.append(compare(got, ref, params, beam_idx=None if idx is None else idx[i],
+                            check_waveforms=waveforms))
+    n = sum(r.n_beams for r in reps)
+    e = sum(r.echoes_compared for r in reps)
+    w = max(r.max_wave_err for r in reps)
+    print(f"[batch] {tag}: frames={len(reps)} beams={n} echoes={e} max_wave_err={w:.2e}",
+          flush=True)
+    return reps
+
+
+def test_batch_every_beam_matches_oracle(oracle_mod):
+    import torch
+    import paper_2512_05932_amd as lidar
+    bw = _small_batch(0)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(bw.params, stream=torch.cuda.current_stream(), keep_waveforms=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        sim.simulate_batch(batch)
+        info = sim.batch_info()
+        assert info["n_frames"] == len(bw.frames) and info["graph"] == 1
+        assert info["n_beams"] == sum(f.pattern.n_beams for f in bw.frames)
+        reps = _check_all(sim, bw, bw.params, oracle_mod, "small-12")
+        assert sum(r.echoes_compared for r in reps) > 3000
+    finally:
+        sim.close()
+
+
+def test_batch_graph_replays_follow_changed_gbuffers(oracle_mod):
+    """The captured graph is replayed three times; between replays the
+    G-buffer contents change in place (eager torch work and a synchronise):
+    every replay must match the oracle on the current contents, without a new
+    set-up."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    bw = _small_batch(1, n_frames=6)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(bw.params, stream=torch.cuda.current_stream(), keep_waveforms=True,
+                         profile=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        for rep in range(3):
+            scale = np.float32(1.0 + 0.15 * rep)
+            for f, p in zip(bw.frames, planes):
+                p[0].copy_(torch.from_numpy(f.gbuffer.depth * scale).cuda())
+            torch.cuda.synchronize()
+            sim.simulate_batch(batch)
+            info = sim.batch_info()
+            cur = scenes.BatchWorkload(bw.name, [
+                replace(f, gbuffer=replace(f.gbuffer, depth=f.gbuffer.depth * scale))
+                for f in bw.frames], bw.params)
+            # the reference sees the same float32 depths as the device
+            for f, p in zip(cur.frames, planes):
+                assert np.array_equal(p[0].cpu().numpy(), f.gbuffer.depth)
+            _check_all(sim, cur, bw.params, oracle_mod, f"replay{rep}")
+        st = sim.stats()
+        assert st["batch_launches"] == 3 and st["batch_ms"] > 0.0
+        assert info["graph"] == 1
+    finally:
+        sim.close()
+
+
+def test_batch_autotuned_tiles_and_table_patterns_with_sun(oracle_mod):
+    """Autotuned strip heights; frames mixing Gaussian and tabulated
+    patterns; the sun term on (every pre-pass of the graph writes sun
+    shading)."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    bw = _small_batch(2, n_frames=8)
+    rng = np.random.default_rng(5)
+    frames = []
+    for i, f in enumerate(bw.frames):
+        if i % 2:
+            t = rng.uniform(0.0, 1.0, size=(9, 11)).astype(np.float32)
+            r = f.gbuffer.raster
+            pat = Pattern(PATTERN_TABLE, f.pattern.beam_az, f.pattern.beam_el, table=t,
+                          half_deg=(7.0 * r.dphi, 5.0 * r.de))
+            f = replace(f, pattern=pat)
+        frames.append(f)
+    bw = replace(bw, frames=frames)
+    se = math.sin(math.radians(40.0))
+    params = replace(bw.params, sun_irradiance=0.02,
+                     sun_dir=(math.sqrt(1 - se * se) * 0.6, math.sqrt(1 - se * se) * 0.8, se))
+    planes = _upload(bw)
+    sim = lidar.LidarSim(params, stream=torch.cuda.current_stream(), keep_waveforms=True,
+                         autotune=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        sim.simulate_batch(batch)
+        info = sim.batch_info()
+        assert info["autotuned"] == 1 and info["autotune_ms"] > 0.0
+        _check_all(sim, bw, params, oracle_mod, "autotune-sun-table")
+        floors = np.concatenate([sim.read_batch(i)["beams"]["floor"] for i in range(len(frames))])
+        assert np.count_nonzero(floors > params.ambient_const) > 0.3 * floors.size
+    finally:
+        sim.close()
+
+
+def test_batch_full_size_sampled_beams(oracle_mod):
+    """The full batch workload (64 frames of 512x256 to 4096x2048, 5k-100k
+    beams, footprints of 20-20,000 pixels) in one graph launch; 24 beams of
+    every frame are checked against the oracle one by one."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    bw = scenes.config3(0)
+    print(f"[batch] full: generated {len(bw.frames)} frames", flush=True)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(bw.params, stream=torch.cuda.current_stream(), keep_waveforms=False)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        sim.simulate_batch(batch)
+        torch.cuda.synchronize()
+        info = sim.batch_info()
+        print(f"[batch] full: {info}", flush=True)
+        # footprints clipped at the image edges hold fewer samples
+        nominal = sum(f.pattern.n_beams * f.meta["footprint_px"] for f in bw.frames)
+        assert 0.8 * nominal < info["samples"] < 1.05 * nominal
+        rng = np.random.default_rng(9)
+        idx = [np.sort(rng.choice(f.pattern.n_beams, size=24, replace=False)) for f in bw.frames]
+        reps = _check_all(sim, bw, bw.params, oracle_mod, "full-64", waveforms=False, idx=idx)
+        assert sum(r.echoes_compared for r in reps) > 500
+    finally:
+        sim.close()
+        del planes
+        torch.cuda.empty_cache()
+
+
+def test_batch_errors_name_the_frame():
+    import torch
+    import paper_2512_05932_amd as lidar
+    bw = _small_batch(3, n_frames=3)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(bw.params, stream=torch.cuda.current_stream())
+    try:
+        with pytest.raises(lidar.LidarError, match="before simulate_batch"):
+            sim._batch = None
+            sim._check(sim._lib.lidar_sim_read_batch(sim._h, 0, None, None, None, None, 0))
+        bad = replace(bw.frames[2].pattern, sigma_deg=(0.0, 1.0))
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames[:2]] + [bad])
+        with pytest.raises(lidar.LidarError, match="frame 2: Gaussian pattern"):
+            sim.simulate_batch(batch)
+        good = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                           [f.pattern for f in bw.frames])
+        sim.simulate_batch(good)
+        with pytest.raises(lidar.LidarError, match="frame index out of range"):
+            sim._check(sim._lib.lidar_sim_read_batch(sim._h, 3, None, None, None, None, 0))
+        sim.reset_batch()
+        with pytest.raises(lidar.LidarError, match="no batch"):
+            sim.batch_info()
+    finally:
+        sim.close()
