@@ -252,6 +252,63 @@ lidar_status lidar_sim_batch_info(lidar_sim* h, lidar_batch_info* out);
  * simulate_batch sets it up again.  Errors: LIDAR_E_INVALID (null). */
 lidar_status lidar_sim_reset_batch(lidar_sim* h);
 
+/* ---- Extension: learned surrogate ----------------------------------------
+ * A multilayer perceptron 1056 -> 256 -> 256 -> 256 -> 16 with GELU
+ * activations (inputs 1030..1055 and outputs 13..15 are zero padding),
+ * trained with AdamW on echoes that the plain path produced.  Products run
+ * in BF16 on the matrix cores with FP32 accumulation; the optimiser keeps
+ * FP32 weights.  Parameters are one flat FP32 vector of LIDAR_SUR_PARAMS
+ * values: W1 [1056][256] (row-major, input x output), b1 [256], W2 [256][256],
+ * b2, W3 [256][256], b3, W4 [256][16], b4 [16].
+ * Outputs y[0..2]: existence logits of echoes 1..3 (in time order);
+ * y[3..5]: peak bin minus the beam's reference bin, in units of 16 bins;
+ * y[6..8]: log10(intensity / T); y[9..11]: pulse width / 4 ns; y[12]:
+ * confidence logit.  Label rows use the same layout (existence as 0 / 1,
+ * y[12..15] unused). */
+#define LIDAR_SUR_IN 1056u
+#define LIDAR_SUR_OUT 16u
+#define LIDAR_SUR_PARAMS 406288u
+
+typedef struct {
+    double lr, beta1, beta2, eps;
+    double weight_decay;       /* decoupled, applied to W1..W4 only */
+} lidar_train_hparams;
+
+/* Load parameters (host, n_params = LIDAR_SUR_PARAMS values, finite) and
+ * reset the optimiser state (moments and step count).
+ * Errors: LIDAR_E_INVALID (null, wrong count, non-finite value), LIDAR_E_HIP,
+ * LIDAR_E_NOMEM. */
+lidar_status lidar_sim_surrogate_set_weights(lidar_sim* h, const float* params, uint64_t n_params);
+
+/* Copy the current FP32 parameters to the host (synchronises).
+ * Errors: LIDAR_E_INVALID, LIDAR_E_STATE (no weights), LIDAR_E_HIP. */
+lidar_status lidar_sim_surrogate_get_weights(lidar_sim* h, float* params, uint64_t n_params);
+
+/* Network outputs for n input rows.  x: device, [n][1056] bfloat16 bit
+ * patterns (uint16); y: device, [n][16] FP32.  Asynchronous.
+ * Errors: LIDAR_E_INVALID (null, n = 0), LIDAR_E_STATE (no weights),
+ * LIDAR_E_HIP, LIDAR_E_NOMEM. */
+lidar_status lidar_sim_surrogate_forward(lidar_sim* h, const void* x, float* y, uint32_t n);
+
+/* Mean loss over the n rows (the sum over echoes of the existence
+ * cross-entropy and, for existing echoes, 64 (dk' - dk)^2 + (li' - li)^2 +
+ * (w' - w)^2, plus the confidence cross-entropy against "every existence
+ * right and every existing peak in its bin") and its gradient with respect
+ * to the parameters, without an update.  labels: device [n][16]; grads:
+ * device [LIDAR_SUR_PARAMS] (nullable); loss: device [1] (nullable).
+ * Errors: as lidar_sim_surrogate_forward. */
+lidar_status lidar_sim_surrogate_gradients(lidar_sim* h, const void* x, const float* labels,
+                                           uint32_t n, float* grads, float* loss);
+
+/* One AdamW step on the mean loss of the n rows (bias-corrected moments;
+ * theta <- theta (1 - lr wd) for weights, then theta -= lr m_hat /
+ * (sqrt(v_hat) + eps)).  loss: device [1] (nullable), the loss before the
+ * step.  Errors: as lidar_sim_surrogate_forward, LIDAR_E_INVALID for
+ * hyper-parameters out of range. */
+lidar_status lidar_sim_surrogate_train_step(lidar_sim* h, const void* x, const float* labels,
+                                            uint32_t n, const lidar_train_hparams* hp,
+                                            float* loss);
+
 /* Counters since create or the last reset (synchronises profiling events).
  * Errors: LIDAR_E_INVALID (null), LIDAR_E_HIP. */
 lidar_status lidar_sim_get_stats(lidar_sim* h, lidar_stats* out);

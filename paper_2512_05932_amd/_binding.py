@@ -32,8 +32,12 @@ LIDAR_MODE_PLAIN = 0
 EXPORTED = ["lidar_sim_create", "lidar_sim_destroy", "lidar_sim_set_pattern",
             "lidar_sim_set_gbuffer", "lidar_sim_simulate_frame", "lidar_sim_read_echoes",
             "lidar_sim_simulate_batch", "lidar_sim_read_batch", "lidar_sim_batch_info",
-            "lidar_sim_reset_batch", "lidar_sim_get_stats", "lidar_sim_reset_stats",
-            "lidar_sim_last_error"]
+            "lidar_sim_reset_batch", "lidar_sim_surrogate_set_weights",
+            "lidar_sim_surrogate_get_weights", "lidar_sim_surrogate_forward",
+            "lidar_sim_surrogate_gradients", "lidar_sim_surrogate_train_step",
+            "lidar_sim_get_stats", "lidar_sim_reset_stats", "lidar_sim_last_error"]
+
+SUR_IN, SUR_OUT, SUR_PARAMS = 1056, 16, 406288
 
 
 class lidar_sim_params(C.Structure):
@@ -66,6 +70,11 @@ class lidar_stats(C.Structure):
                 ("footprint_ms", C.c_double), ("footprint_launches", C.c_uint64),
                 ("prepass_ms", C.c_double), ("prepass_launches", C.c_uint64),
                 ("batch_ms", C.c_double), ("batch_launches", C.c_uint64)]
+
+
+class lidar_train_hparams(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("weight_decay", C.c_double)]
 
 
 class lidar_batch_info(C.Structure):
@@ -111,6 +120,11 @@ def load():
     lib.lidar_sim_read_batch.argtypes = [V, C.c_uint32, V, V, V, V, C.c_int]
     lib.lidar_sim_batch_info.argtypes = [V, P(lidar_batch_info)]
     lib.lidar_sim_reset_batch.argtypes = [V]
+    lib.lidar_sim_surrogate_set_weights.argtypes = [V, V, C.c_uint64]
+    lib.lidar_sim_surrogate_get_weights.argtypes = [V, V, C.c_uint64]
+    lib.lidar_sim_surrogate_forward.argtypes = [V, V, V, C.c_uint32]
+    lib.lidar_sim_surrogate_gradients.argtypes = [V, V, V, C.c_uint32, V, V]
+    lib.lidar_sim_surrogate_train_step.argtypes = [V, V, V, C.c_uint32, P(lidar_train_hparams), V]
     lib.lidar_sim_get_stats.argtypes = [V, P(lidar_stats)]
     lib.lidar_sim_reset_stats.argtypes = [V]
     lib.lidar_sim_last_error.argtypes = [V]
@@ -282,6 +296,33 @@ class LidarSim:
 
     def reset_batch(self):
         self._check(self._lib.lidar_sim_reset_batch(self._h))
+
+    # ---- surrogate network (device tensors: x int16 [n][1056] holding bfloat16
+    # bit patterns, labels / outputs float32 [n][16]) ----
+    def set_weights(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self._lib.lidar_sim_surrogate_set_weights(self._h, p.ctypes.data, p.size))
+
+    def get_weights(self) -> np.ndarray:
+        p = np.zeros(SUR_PARAMS, dtype=np.float32)
+        self._check(self._lib.lidar_sim_surrogate_get_weights(self._h, p.ctypes.data, p.size))
+        return p
+
+    def surrogate_forward(self, x, y):
+        self._check(self._lib.lidar_sim_surrogate_forward(self._h, x.data_ptr(), y.data_ptr(),
+                                                          x.shape[0]))
+
+    def surrogate_gradients(self, x, labels, grads=None, loss=None):
+        p = lambda t: int(t.data_ptr()) if t is not None else None
+        self._check(self._lib.lidar_sim_surrogate_gradients(
+            self._h, x.data_ptr(), labels.data_ptr(), x.shape[0], p(grads), p(loss)))
+
+    def train_step(self, x, labels, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                   weight_decay=1e-4, loss=None):
+        hp = lidar_train_hparams(lr, beta1, beta2, eps, weight_decay)
+        self._check(self._lib.lidar_sim_surrogate_train_step(
+            self._h, x.data_ptr(), labels.data_ptr(), x.shape[0], C.byref(hp),
+            int(loss.data_ptr()) if loss is not None else None))
 
     def stats(self) -> dict:
         s = lidar_stats()

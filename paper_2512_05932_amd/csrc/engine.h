@@ -125,4 +125,99 @@ hipError_t launch_reset_queue(hipStream_t s, int* counter);
 // whether G histograms of R bins plus the pulse taps fit the LDS budget
 bool footprint_group_fits(int G, int R, int J);
 
+// ---- host utility: a growable device buffer -----------------------------
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    hipError_t ensure(size_t count)
+    {
+        if (count <= n && p) return hipSuccess;
+        release();
+        if (count == 0) return hipSuccess;
+        hipError_t e = hipMalloc(&p, sizeof(T) * count);
+        if (e == hipSuccess) n = count;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+// ---- surrogate network ---------------------------------------------------
+// 1056 -> 256 -> 256 -> 256 -> 16; flat FP32 parameters [W1 (row-major
+// in x out), b1, W2, b2, W3, b3, W4, b4].
+constexpr int kSurIn = 1056, kSurInUsed = 1030, kSurHid = 256, kSurOut = 16, kSurOutUsed = 13;
+constexpr long kSurOffW1 = 0;
+constexpr long kSurOffB1 = kSurOffW1 + (long)kSurIn * kSurHid;
+constexpr long kSurOffW2 = kSurOffB1 + kSurHid;
+constexpr long kSurOffB2 = kSurOffW2 + (long)kSurHid * kSurHid;
+constexpr long kSurOffW3 = kSurOffB2 + kSurHid;
+constexpr long kSurOffB3 = kSurOffW3 + (long)kSurHid * kSurHid;
+constexpr long kSurOffW4 = kSurOffB3 + kSurHid;
+constexpr long kSurOffB4 = kSurOffW4 + (long)kSurHid * kSurOut;
+constexpr long kSurParams = kSurOffB4 + kSurOut;
+// loss: peak-bin outputs in units of 16 bins, squared-error weights
+constexpr float kSurBinScale = 16.0f, kSurWBin = 64.0f, kSurWInt = 1.0f, kSurWEpw = 1.0f;
+
+__host__ __device__ inline bool sur_is_weight(long i)
+{
+    return i < kSurOffB1 || (i >= kSurOffW2 && i < kSurOffB2) ||
+           (i >= kSurOffW3 && i < kSurOffB3) || (i >= kSurOffW4 && i < kSurOffB4);
+}
+
+// C[M][N] (FP32, row stride ldc) = sum_k A(i, k) B(k, j), BF16 operands with
+// A(i, k) = A[i sam + k sak] and B(k, j) = B[k sbk + j sbn].
+struct GemmArgs {
+    const uint16_t* A;
+    long sam, sak;
+    const uint16_t* B;
+    long sbk, sbn;
+    float* C;
+    long ldc;
+    int M, N, K;
+};
+struct AdamArgs {
+    float lr, beta1, beta2, eps;
+    float decay_factor;         // 1 - lr * weight_decay
+    float inv_bc1, inv_bc2;     // 1 / (1 - beta^t)
+};
+hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g);
+hipError_t launch_bias_gelu(hipStream_t s, float* Z, const float* bias, uint16_t* H, long n, int C);
+hipError_t launch_bias(hipStream_t s, float* Y, const float* bias, long n, int C);
+hipError_t launch_loss(hipStream_t s, const float* Y, const float* lab, long n, uint16_t* dYb,
+                       float* loss_sum);
+hipError_t launch_gelu_back(hipStream_t s, const float* dH, const float* Z, uint16_t* dZb, long count);
+hipError_t launch_colsum(hipStream_t s, const uint16_t* D, long n, int C, float* out);
+hipError_t launch_zero_f32(hipStream_t s, float* p, long n);
+hipError_t launch_adamw(hipStream_t s, float* theta, const float* grad, float* m, float* v,
+                        uint16_t* theta_b, long n, const AdamArgs& a);
+hipError_t launch_to_bf16(hipStream_t s, const float* x, uint16_t* y, long n);
+
+struct SurNet {
+    DevBuf<float> theta, m, v, grad;    // FP32 [kSurParams]
+    DevBuf<uint16_t> theta_b;           // BF16 operand copy
+    long step = 0;
+    bool ready = false;
+};
+struct SurWork {                        // activations of up to `cap` rows
+    long cap = 0;
+    DevBuf<float> Z1, Z2, Z3, Y, dH, loss;
+    DevBuf<uint16_t> H1, H2, H3, dYb, dZb;
+    hipError_t ensure(long n);
+};
+// Y (w.Y, [n][16] FP32) of the rows X ([n][1056] BF16)
+hipError_t sur_forward(hipStream_t s, const SurNet& net, const uint16_t* X, long n, SurWork& w);
+// loss (added into w.loss[0]) and parameter gradient (net.grad) of rows X
+// with labels lab ([n][16]); runs the forward pass first
+hipError_t sur_gradients(hipStream_t s, SurNet& net, const uint16_t* X, const float* lab, long n,
+                         SurWork& w);
+
 }  // namespace lidar

@@ -29,31 +29,6 @@ namespace {
 
 thread_local std::string g_create_error;
 
-template <typename T>
-struct DevBuf {
-    T* p = nullptr;
-    size_t n = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-    ~DevBuf() { release(); }
-    hipError_t ensure(size_t count)
-    {
-        if (count <= n && p) return hipSuccess;
-        release();
-        if (count == 0) return hipSuccess;
-        hipError_t e = hipMalloc(&p, sizeof(T) * count);
-        if (e == hipSuccess) n = count;
-        return e;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        n = 0;
-    }
-};
-
 struct EventPair {
     hipEvent_t a, b;
 };
@@ -130,6 +105,10 @@ struct lidar_sim {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::map<int, int> tuned_tile;     // kernel-height class -> strip height
+
+    // surrogate network
+    SurNet net;
+    SurWork work;
 
     // stats
     lidar_stats st{};
@@ -1078,6 +1057,112 @@ lidar_status lidar_sim_reset_batch(lidar_sim* h)
     h->batch_result = false;
     h->batch_gb.clear();
     h->batch_pd.clear();
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_surrogate_set_weights(lidar_sim* h, const float* params, uint64_t n_params)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!params || n_params != (uint64_t)kSurParams)
+        return fail(h, LIDAR_E_INVALID, "surrogate weights need LIDAR_SUR_PARAMS values");
+    for (uint64_t i = 0; i < n_params; ++i)
+        if (!std::isfinite(params[i])) return fail(h, LIDAR_E_INVALID, "non-finite surrogate weight");
+    SurNet& n = h->net;
+    const size_t P = (size_t)kSurParams;
+    HIP_TRY(h, n.theta.ensure(P), "allocate surrogate weights");
+    HIP_TRY(h, n.m.ensure(P), "allocate surrogate weights");
+    HIP_TRY(h, n.v.ensure(P), "allocate surrogate weights");
+    HIP_TRY(h, n.grad.ensure(P), "allocate surrogate weights");
+    HIP_TRY(h, n.theta_b.ensure(P), "allocate surrogate weights");
+    hipStream_t s = h->stream;
+    HIP_TRY(h, hipMemcpyAsync(n.theta.p, params, P * sizeof(float), hipMemcpyHostToDevice, s),
+            "copy surrogate weights");
+    HIP_TRY(h, launch_zero_f32(s, n.m.p, (long)P), "zero moments");
+    HIP_TRY(h, launch_zero_f32(s, n.v.p, (long)P), "zero moments");
+    HIP_TRY(h, launch_to_bf16(s, n.theta.p, n.theta_b.p, (long)P), "weight copy");
+    HIP_TRY(h, hipStreamSynchronize(s), "weights synchronise");
+    n.step = 0;
+    n.ready = true;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_surrogate_get_weights(lidar_sim* h, float* params, uint64_t n_params)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!params || n_params != (uint64_t)kSurParams)
+        return fail(h, LIDAR_E_INVALID, "surrogate weights need LIDAR_SUR_PARAMS values");
+    if (!h->net.ready) return fail(h, LIDAR_E_STATE, "no surrogate weights set");
+    HIP_TRY(h, hipMemcpyAsync(params, h->net.theta.p, (size_t)kSurParams * sizeof(float),
+                              hipMemcpyDeviceToHost, h->stream), "copy surrogate weights");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "weights synchronise");
+    return LIDAR_OK;
+}
+
+static lidar_status sur_check(lidar_sim* h, const void* x, const void* y, uint32_t n)
+{
+    if (!x || !y || n == 0) return fail(h, LIDAR_E_INVALID, "surrogate call needs x, outputs and n >= 1");
+    if (!h->net.ready) return fail(h, LIDAR_E_STATE, "no surrogate weights set");
+    HIP_TRY(h, h->work.ensure((long)n), "allocate surrogate workspace");
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_surrogate_forward(lidar_sim* h, const void* x, float* y, uint32_t n)
+{
+    if (!h) return LIDAR_E_INVALID;
+    LIDAR_TRY(sur_check(h, x, y, n));
+    HIP_TRY(h, sur_forward(h->stream, h->net, (const uint16_t*)x, (long)n, h->work), "surrogate forward");
+    HIP_TRY(h, hipMemcpyAsync(y, h->work.Y.p, (size_t)n * kSurOut * sizeof(float),
+                              hipMemcpyDeviceToDevice, h->stream), "copy outputs");
+    return LIDAR_OK;
+}
+
+static lidar_status sur_grads(lidar_sim* h, const void* x, const float* labels, uint32_t n)
+{
+    LIDAR_TRY(sur_check(h, x, labels, n));
+    HIP_TRY(h, launch_zero_f32(h->stream, h->work.loss.p, 1), "zero loss");
+    HIP_TRY(h, sur_gradients(h->stream, h->net, (const uint16_t*)x, labels, (long)n, h->work),
+            "surrogate gradients");
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_surrogate_gradients(lidar_sim* h, const void* x, const float* labels,
+                                           uint32_t n, float* grads, float* loss)
+{
+    if (!h) return LIDAR_E_INVALID;
+    LIDAR_TRY(sur_grads(h, x, labels, n));
+    if (grads)
+        HIP_TRY(h, hipMemcpyAsync(grads, h->net.grad.p, (size_t)kSurParams * sizeof(float),
+                                  hipMemcpyDeviceToDevice, h->stream), "copy gradients");
+    if (loss)
+        HIP_TRY(h, hipMemcpyAsync(loss, h->work.loss.p, sizeof(float), hipMemcpyDeviceToDevice,
+                                  h->stream), "copy loss");
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_surrogate_train_step(lidar_sim* h, const void* x, const float* labels,
+                                            uint32_t n, const lidar_train_hparams* hp, float* loss)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!hp || !(hp->lr > 0) || !(hp->beta1 >= 0 && hp->beta1 < 1) || !(hp->beta2 >= 0 && hp->beta2 < 1) ||
+        !(hp->eps > 0) || !(hp->weight_decay >= 0) || !is_fin(hp->lr) || !is_fin(hp->eps) ||
+        !is_fin(hp->weight_decay))
+        return fail(h, LIDAR_E_INVALID, "hyper-parameters out of range");
+    LIDAR_TRY(sur_grads(h, x, labels, n));
+    SurNet& net = h->net;
+    const long t = ++net.step;
+    AdamArgs a;
+    a.lr = (float)hp->lr;
+    a.beta1 = (float)hp->beta1;
+    a.beta2 = (float)hp->beta2;
+    a.eps = (float)hp->eps;
+    a.decay_factor = (float)(1.0 - hp->lr * hp->weight_decay);
+    a.inv_bc1 = (float)(1.0 / (1.0 - std::pow(hp->beta1, (double)t)));
+    a.inv_bc2 = (float)(1.0 / (1.0 - std::pow(hp->beta2, (double)t)));
+    HIP_TRY(h, launch_adamw(h->stream, net.theta.p, net.grad.p, net.m.p, net.v.p, net.theta_b.p,
+                            kSurParams, a), "AdamW launch");
+    if (loss)
+        HIP_TRY(h, hipMemcpyAsync(loss, h->work.loss.p, sizeof(float), hipMemcpyDeviceToDevice,
+                                  h->stream), "copy loss");
     return LIDAR_OK;
 }
 

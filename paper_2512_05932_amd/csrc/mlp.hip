@@ -1,0 +1,382 @@
+// Surrogate network kernels: BF16 matrix products on the MFMA units with
+// FP32 accumulation, the elementwise steps around them (bias, GELU and its
+// derivative, the loss and its gradient, bias gradients) and the AdamW update.
+//
+// Network: 1056 -> 256 -> 256 -> 256 -> 16 (inputs 1030..1055 and outputs
+// 13..15 are padding), GELU(z) = z/2 (1 + erf(z / sqrt 2)).  Weights are
+// kept in FP32 (the optimiser's copy) and in BF16 (the operands of the
+// products); activations between layers and the backward operands are BF16.
+#include "engine.h"
+
+namespace lidar {
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTileM = 64, kTileN = 64, kTileK = 32;
+constexpr int kLdsK = kTileK + 8;         // row stride in LDS (elements)
+
+__device__ inline uint16_t to_bf16(float f)
+{
+    // round to nearest, ties to even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// C = A B over a 64 x 64 tile per workgroup (4 waves of 32 x 32, each 2 x 2
+// MFMA 16x16x16 blocks), K in steps of 32 staged through LDS.  Both operands
+// are stored in LDS with K contiguous ([row][k] for A, [col][k] for B), so
+// every lane's 4 consecutive K values are one 8-byte read.
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
+{
+    __shared__ uint16_t As[kTileM][kLdsK];
+    __shared__ uint16_t Bs[kTileN][kLdsK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * kTileM, n0 = blockIdx.x * kTileN;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // load mapping: consecutive threads walk the operand's unit-stride axis
+    const bool a_kfast = g.sak == 1;
+    const bool b_kfast = g.sbk == 1;
+    for (int k0 = 0; k0 < g.K; k0 += kTileK) {
+#pragma unroll
+        for (int q = 0; q < (kTileM * kTileK) / 256; ++q) {
+            const int e = tid + 256 * q;
+            const int r = a_kfast ? e / kTileK : e % kTileM;
+            const int k = a_kfast ? e % kTileK : e / kTileM;
+            const int gi = m0 + r, gk = k0 + k;
+            As[r][k] = (gi < g.M && gk < g.K) ? g.A[(long)gi * g.sam + (long)gk * g.sak] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int q = 0; q < (kTileN * kTileK) / 256; ++q) {
+            const int e = tid + 256 * q;
+            const int c = b_kfast ? e / kTileK : e % kTileN;
+            const int k = b_kfast ? e % kTileK : e / kTileN;
+            const int gj = n0 + c, gk = k0 + k;
+            Bs[c][k] = (gj < g.N && gk < g.K) ? g.B[(long)gk * g.sbk + (long)gj * g.sbn] : (uint16_t)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kTileK; kk += 16) {
+            const int kq = kk + 4 * (lane >> 4);
+            bf16x4 a[2], b[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                a[t] = *(const bf16x4*)&As[wm * 32 + t * 16 + (lane & 15)][kq];
+                b[t] = *(const bf16x4*)&Bs[wn * 32 + t * 16 + (lane & 15)][kq];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D block: lane holds column lane % 16, rows 4 (lane / 16) + r
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                if (row < g.M && col < g.N) g.C[(long)row * g.ldc + col] = acc[i][j][r];
+            }
+        }
+}
+
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+__device__ inline float gelu_prime(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+           z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// Z += bias (in place); H = bf16(gelu(Z)).
+__global__ void k_bias_gelu(float* Z, const float* bias, uint16_t* H, long n, int C)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * C) return;
+    const float z = Z[i] + bias[i % C];
+    Z[i] = z;
+    H[i] = to_bf16(gelu(z));
+}
+
+__global__ void k_bias(float* Y, const float* bias, long n, int C)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * C) return;
+    Y[i] += bias[i % C];
+}
+
+__device__ inline float bce(float z, float t) { return fmaxf(z, 0.0f) - z * t + log1pf(expf(-fabsf(z))); }
+__device__ inline float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// Per-row loss and gradient (scaled by 1/n) with respect to the 16 outputs.
+__global__ void k_loss(const float* Y, const float* lab, long n, float inv_n, uint16_t* dYb,
+                       float* loss_sum)
+{
+    const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    float L = 0.0f;
+    if (r < n) {
+        const float* y = Y + r * 16;
+        const float* l = lab + r * 16;
+        float d[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) d[j] = 0.0f;
+        bool ok = true;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const float ex = l[e];
+            const bool te = ex > 0.5f;
+            ok = ok && ((y[e] > 0.0f) == te);
+            ok = ok && !(te && fabsf(y[3 + e] - l[3 + e]) * kSurBinScale > 0.5f);
+            L += bce(y[e], ex);
+            d[e] = sigm(y[e]) - ex;
+            const float dk = y[3 + e] - l[3 + e];
+            const float di = y[6 + e] - l[6 + e];
+            const float dw = y[9 + e] - l[9 + e];
+            L += ex * (kSurWBin * dk * dk + kSurWInt * di * di + kSurWEpw * dw * dw);
+            d[3 + e] = ex * 2.0f * kSurWBin * dk;
+            d[6 + e] = ex * 2.0f * kSurWInt * di;
+            d[9 + e] = ex * 2.0f * kSurWEpw * dw;
+        }
+        const float okf = ok ? 1.0f : 0.0f;
+        L += bce(y[12], okf);
+        d[12] = sigm(y[12]) - okf;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dYb[r * 16 + j] = to_bf16(d[j] * inv_n);
+    }
+    // block sum of the row losses, one atomic per block
+    __shared__ float part[256];
+    part[threadIdx.x] = L;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss_sum) atomicAdd(loss_sum, part[0] * inv_n);
+}
+
+// dZ = bf16(dH * gelu'(Z))
+__global__ void k_gelu_back(const float* dH, const float* Z, uint16_t* dZb, long count)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    dZb[i] = to_bf16(dH[i] * gelu_prime(Z[i]));
+}
+
+// db[j] = sum over rows of the BF16 operand dZ[r][j]
+__global__ void k_colsum(const uint16_t* D, long n, int C, float* out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= C) return;
+    float s = 0.0f;
+    for (long r = 0; r < n; ++r) s += from_bf16(D[r * C + j]);
+    out[j] = s;
+}
+
+__global__ void k_zero_f32(float* p, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+// AdamW (decoupled weight decay on the weights, not on the biases), then
+// the BF16 operand copy of the parameter.
+__global__ void k_adamw(float* theta, const float* grad, float* m, float* v, uint16_t* theta_b,
+                        long n, AdamArgs a)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool decay = sur_is_weight(i);
+    float t = theta[i];
+    if (decay) t *= a.decay_factor;
+    const float g = grad[i];
+    const float mi = a.beta1 * m[i] + (1.0f - a.beta1) * g;
+    const float vi = a.beta2 * v[i] + (1.0f - a.beta2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    t -= a.lr * (mi * a.inv_bc1) / (sqrtf(vi * a.inv_bc2) + a.eps);
+    theta[i] = t;
+    theta_b[i] = to_bf16(t);
+}
+
+__global__ void k_to_bf16(const float* x, uint16_t* y, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = to_bf16(x[i]);
+}
+
+inline unsigned blocks(long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g)
+{
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    dim3 grid((g.N + kTileN - 1) / kTileN, (g.M + kTileM - 1) / kTileM);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_bias_gelu(hipStream_t s, float* Z, const float* bias, uint16_t* H, long n, int C)
+{
+    if (n * C == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bias_gelu, dim3(blocks(n * C, 256)), dim3(256), 0, s, Z, bias, H, n, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_bias(hipStream_t s, float* Y, const float* bias, long n, int C)
+{
+    if (n * C == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bias, dim3(blocks(n * C, 256)), dim3(256), 0, s, Y, bias, n, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss(hipStream_t s, const float* Y, const float* lab, long n, uint16_t* dYb,
+                       float* loss_sum)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_loss, dim3(blocks(n, 256)), dim3(256), 0, s, Y, lab, n, 1.0f / (float)n,
+                       dYb, loss_sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_gelu_back(hipStream_t s, const float* dH, const float* Z, uint16_t* dZb, long count)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gelu_back, dim3(blocks(count, 256)), dim3(256), 0, s, dH, Z, dZb, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(hipStream_t s, const uint16_t* D, long n, int C, float* out)
+{
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(C, 64)), dim3(64), 0, s, D, n, C, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f32(hipStream_t s, float* p, long n)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_f32, dim3(blocks(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_adamw(hipStream_t s, float* theta, const float* grad, float* m, float* v,
+                        uint16_t* theta_b, long n, const AdamArgs& a)
+{
+    hipLaunchKernelGGL(k_adamw, dim3(blocks(n, 256)), dim3(256), 0, s, theta, grad, m, v, theta_b, n, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(hipStream_t s, const float* x, uint16_t* y, long n)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks(n, 256)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+}  // namespace lidar
+
+namespace lidar {
+
+hipError_t SurWork::ensure(long n)
+{
+    if (n <= cap) return hipSuccess;
+    hipError_t e;
+    const size_t nh = (size_t)n * kSurHid, no = (size_t)n * kSurOut;
+    if ((e = Z1.ensure(nh)) || (e = Z2.ensure(nh)) || (e = Z3.ensure(nh)) || (e = dH.ensure(nh)) ||
+        (e = H1.ensure(nh)) || (e = H2.ensure(nh)) || (e = H3.ensure(nh)) || (e = dZb.ensure(nh)) ||
+        (e = Y.ensure(no)) || (e = dYb.ensure(no)) || (e = loss.ensure(1)))
+        return e;
+    cap = n;
+    return hipSuccess;
+}
+
+#define TRY(x)                                        \
+    do {                                              \
+        hipError_t e_ = (x);                          \
+        if (e_ != hipSuccess) return e_;              \
+    } while (0)
+
+// Z = A W (+ bias, GELU) with A [n][k] row-major BF16 and W [k][c] BF16
+static hipError_t dense(hipStream_t s, const uint16_t* A, int k, const uint16_t* W, int c, long n,
+                        float* Z)
+{
+    GemmArgs g{A, k, 1, W, c, 1, Z, c, (int)n, c, k};
+    return launch_gemm_bf16(s, g);
+}
+
+hipError_t sur_forward(hipStream_t s, const SurNet& net, const uint16_t* X, long n, SurWork& w)
+{
+    const uint16_t* Wb = net.theta_b.p;
+    const float* th = net.theta.p;
+    TRY(dense(s, X, kSurIn, Wb + kSurOffW1, kSurHid, n, w.Z1.p));
+    TRY(launch_bias_gelu(s, w.Z1.p, th + kSurOffB1, w.H1.p, n, kSurHid));
+    TRY(dense(s, w.H1.p, kSurHid, Wb + kSurOffW2, kSurHid, n, w.Z2.p));
+    TRY(launch_bias_gelu(s, w.Z2.p, th + kSurOffB2, w.H2.p, n, kSurHid));
+    TRY(dense(s, w.H2.p, kSurHid, Wb + kSurOffW3, kSurHid, n, w.Z3.p));
+    TRY(launch_bias_gelu(s, w.Z3.p, th + kSurOffB3, w.H3.p, n, kSurHid));
+    TRY(dense(s, w.H3.p, kSurHid, Wb + kSurOffW4, kSurOut, n, w.Y.p));
+    TRY(launch_bias(s, w.Y.p, th + kSurOffB4, n, kSurOut));
+    return hipSuccess;
+}
+
+// dW = A^T D (A [n][in] BF16 activations, D [n][out] BF16), db = column sums
+static hipError_t weight_grad(hipStream_t s, const uint16_t* A, int in, const uint16_t* D, int out,
+                              long n, float* dW, float* db)
+{
+    GemmArgs g{A, 1, in, D, out, 1, dW, out, in, out, (int)n};
+    TRY(launch_gemm_bf16(s, g));
+    return launch_colsum(s, D, n, out, db);
+}
+
+// dH = D W^T (D [n][out], W [in][out]) in FP32
+static hipError_t input_grad(hipStream_t s, const uint16_t* D, int out, const uint16_t* W, int in,
+                             long n, float* dH)
+{
+    GemmArgs g{D, out, 1, W, 1, out, dH, in, (int)n, in, out};
+    return launch_gemm_bf16(s, g);
+}
+
+hipError_t sur_gradients(hipStream_t s, SurNet& net, const uint16_t* X, const float* lab, long n,
+                         SurWork& w)
+{
+    TRY(sur_forward(s, net, X, n, w));
+    TRY(launch_loss(s, w.Y.p, lab, n, w.dYb.p, w.loss.p));
+    const uint16_t* Wb = net.theta_b.p;
+    float* g = net.grad.p;
+    const long nh = n * kSurHid;
+    // layer 4
+    TRY(weight_grad(s, w.H3.p, kSurHid, w.dYb.p, kSurOut, n, g + kSurOffW4, g + kSurOffB4));
+    TRY(input_grad(s, w.dYb.p, kSurOut, Wb + kSurOffW4, kSurHid, n, w.dH.p));
+    TRY(launch_gelu_back(s, w.dH.p, w.Z3.p, w.dZb.p, nh));
+    // layer 3
+    TRY(weight_grad(s, w.H2.p, kSurHid, w.dZb.p, kSurHid, n, g + kSurOffW3, g + kSurOffB3));
+    TRY(input_grad(s, w.dZb.p, kSurHid, Wb + kSurOffW3, kSurHid, n, w.dH.p));
+    TRY(launch_gelu_back(s, w.dH.p, w.Z2.p, w.dZb.p, nh));
+    // layer 2
+    TRY(weight_grad(s, w.H1.p, kSurHid, w.dZb.p, kSurHid, n, g + kSurOffW2, g + kSurOffB2));
+    TRY(input_grad(s, w.dZb.p, kSurHid, Wb + kSurOffW2, kSurHid, n, w.dH.p));
+    TRY(launch_gelu_back(s, w.dH.p, w.Z1.p, w.dZb.p, nh));
+    // layer 1
+    TRY(weight_grad(s, X, kSurIn, w.dZb.p, kSurHid, n, g + kSurOffW1, g + kSurOffB1));
+    return hipSuccess;
+}
+
+#undef TRY
+
+}  // namespace lidar

@@ -514,3 +514,54 @@ def config3(seed: int = 0, n_frames: int = 64, sizes=CONFIG3_SIZES,
         frames = [frame(i) for i in range(n_frames)]
     return BatchWorkload(f"batch-{n_frames}frames-uneven", frames, params,
                          {"seed": seed, "sizes": [sizes[k] for k in size_idx]})
+
+
+# ----------------------------------------------------------------------------
+# surrogate network: seeded initial weights (an input of training)
+# ----------------------------------------------------------------------------
+
+SURROGATE_LAYERS = ((1056, 1030, 256), (256, 256, 256), (256, 256, 256), (256, 256, 16))
+SURROGATE_OUT_USED = 13
+
+
+def surrogate_init(seed: int = 0) -> np.ndarray:
+    """Flat FP32 parameters [W1 (1056x256, row-major in x out), b1, W2, b2, W3,
+    b3, W4 (256x16), b4]: weights U(-sqrt(3/fan_in), sqrt(3/fan_in)) (unit
+    variance per unit-variance input), zero biases; the padding rows of W1
+    (inputs 1030..1055) and columns of W4 (outputs 13..15) are zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for li, (n_in, fan_in, n_out) in enumerate(SURROGATE_LAYERS):
+        a = math.sqrt(3.0 / fan_in)
+        W = rng.uniform(-a, a, size=(n_in, n_out))
+        W[fan_in:, :] = 0.0
+        if li == len(SURROGATE_LAYERS) - 1:
+            W[:, SURROGATE_OUT_USED:] = 0.0
+        parts += [W.ravel(), np.zeros(n_out)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def random_bf16_bits(seed: int, n: int, cols: int = 1056, used: int = 1030,
+                     scale: float = 1.0) -> np.ndarray:
+    """[n][cols] bfloat16 bit patterns (uint16) of N(0, scale^2) draws
+    truncated to bfloat16 (the low 16 bits of the binary32 value dropped);
+    columns from ``used`` on are zero."""
+    rng = np.random.default_rng(seed)
+    x = (rng.standard_normal((n, cols)) * scale).astype(np.float32)
+    x[:, used:] = 0.0
+    return (x.view(np.uint32) >> np.uint32(16)).astype(np.uint16)
+
+
+def bf16_bits_to_float(b: np.ndarray) -> np.ndarray:
+    """The float32 values of bfloat16 bit patterns (exact)."""
+    return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << np.uint32(16)).view(np.float32)
+
+
+def random_surrogate_labels(seed: int, n: int) -> np.ndarray:
+    """[n][16] label rows: random existence flags and targets of moderate size."""
+    rng = np.random.default_rng(seed)
+    lab = np.zeros((n, 16), dtype=np.float32)
+    lab[:, :3] = rng.integers(0, 2, size=(n, 3))
+    lab[:, 3:12] = (rng.standard_normal((n, 9)) * 0.5).astype(np.float32)
+    lab[:, 3:12] *= np.tile(lab[:, :3], 3)
+    return lab
