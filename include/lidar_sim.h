@@ -63,11 +63,14 @@ enum {
 /* lidar_pattern_desc.kind */
 enum { LIDAR_PATTERN_GAUSS = 1, LIDAR_PATTERN_TABLE = 2 };
 
-/* lidar_sim_simulate_frame mode */
-enum { LIDAR_MODE_PLAIN = 0 };
+/* lidar_sim_simulate_frame mode: the plain method, or the learned surrogate
+ * with the plain method as fallback (extension) */
+enum { LIDAR_MODE_PLAIN = 0, LIDAR_MODE_SURROGATE = 1 };
 
-/* lidar_echo.flags */
-enum { LIDAR_ECHO_AT_FIRST_BIN = 1u, LIDAR_ECHO_AT_LAST_BIN = 2u };
+/* lidar_echo.flags; LIDAR_ECHO_SURROGATE marks echoes predicted by the
+ * surrogate network (bin_first / bin_last then follow from the predicted
+ * width) */
+enum { LIDAR_ECHO_AT_FIRST_BIN = 1u, LIDAR_ECHO_AT_LAST_BIN = 2u, LIDAR_ECHO_SURROGATE = 4u };
 
 /* Sensor and receiver parameters of one handle (copied at create). */
 typedef struct {
@@ -170,6 +173,10 @@ typedef struct {
     uint64_t prepass_launches;
     double batch_ms;           /* LIDAR_PROFILE: summed batch graph time (pre-passes included) */
     uint64_t batch_launches;
+    uint64_t surrogate_beams;  /* beams of LIDAR_MODE_SURROGATE frames */
+    uint64_t fallback_beams;   /* of those, beams simulated by the plain path */
+    double surrogate_ms;       /* LIDAR_PROFILE: summed surrogate frame time (all kernels) */
+    uint64_t surrogate_frames;
 } lidar_stats;
 
 /* Create a handle with the given parameters on a HIP stream (void* =
@@ -199,10 +206,15 @@ lidar_status lidar_sim_set_gbuffer(lidar_sim* h, const lidar_gbuffer_desc* gbuff
 /* Enqueue one frame on the handle's stream: kernel/normalisation set-up when
  * the pattern or raster changed, the G-buffer pre-pass, then the fused
  * footprint gather / time binning / ambient / pulse / echo kernel.
- * mode: LIDAR_MODE_PLAIN.  Asynchronous.
+ * mode LIDAR_MODE_SURROGATE (extension; needs surrogate weights): the
+ * network predicts every beam's echoes from its inputs (see
+ * lidar_sim_surrogate_features), the gate (lidar_sim_surrogate_set_gate)
+ * keeps the confident ones and the plain kernel runs on the groups of the
+ * others, on the device without a host round trip.  Asynchronous.
  * Errors: LIDAR_E_STATE (no pattern or G-buffer yet), LIDAR_E_INVALID (kernel
  * grid too large, pattern integral <= 0 over the kernel),
- * LIDAR_E_UNSUPPORTED (other modes), LIDAR_E_HIP. */
+ * LIDAR_E_UNSUPPORTED (other modes), LIDAR_E_STATE (surrogate mode without
+ * weights), LIDAR_E_HIP. */
 lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode);
 
 /* Copy the last frame's results out.  echoes: [n_beams][max_echoes] (unused
@@ -308,6 +320,28 @@ lidar_status lidar_sim_surrogate_gradients(lidar_sim* h, const void* x, const fl
 lidar_status lidar_sim_surrogate_train_step(lidar_sim* h, const void* x, const float* labels,
                                             uint32_t n, const lidar_train_hparams* hp,
                                             float* loss);
+
+/* Gate of LIDAR_MODE_SURROGATE: a beam keeps the network's echoes when its
+ * confidence sigmoid(y[12]) >= c_min and its tail estimate E_tail (the
+ * largest per-bin energy the pattern outside its core box can add, from
+ * super-cells of the frame) is below alpha times the margin (T - A_b, or,
+ * with the floor A_b above T, the predicted peak above the floor); every
+ * other beam runs the plain path.  c_min = 1 sends every beam to the plain
+ * path; alpha >= 1e30 (or infinity) switches the tail check off, so c_min = 0
+ * with such an alpha keeps every prediction.  Defaults: 0.5, 0.5.
+ * Errors: LIDAR_E_INVALID (c_min outside [0, 1], alpha < 0 or NaN). */
+lidar_status lidar_sim_surrogate_set_gate(lidar_sim* h, double c_min, double alpha);
+
+/* Network inputs of the current frame (pattern and G-buffer as set): x,
+ * device [n_beams][1056] bfloat16; aux (nullable), device [n_beams][4] FP32
+ * {reference bin, E_tail, estimated floor A_b, accepted by the last
+ * surrogate frame}; labels (nullable), device [n_beams][16] FP32 training
+ * targets from the echoes of the last simulate_frame, which must have run
+ * in LIDAR_MODE_PLAIN on the same inputs (existence, (peak bin - reference
+ * bin) / 16, log10(max(intensity, 1e-3 T) / T), pulse width / 4 ns).
+ * Asynchronous.  Errors: LIDAR_E_STATE (no pattern, G-buffer, or - for
+ * labels - plain frame), LIDAR_E_INVALID, LIDAR_E_HIP, LIDAR_E_NOMEM. */
+lidar_status lidar_sim_surrogate_features(lidar_sim* h, void* x, float* labels, float* aux);
 
 /* Counters since create or the last reset (synchronises profiling events).
  * Errors: LIDAR_E_INVALID (null), LIDAR_E_HIP. */

@@ -6,7 +6,8 @@ C-ABI of ``include/lidar_sim.h``); this package is its thin ctypes binding.
 from ._binding import (LidarSim, LidarError, Batch, load, ECHO_DTYPE, BEAM_DTYPE, EXPORTED,  # noqa: F401
                        LIDAR_OK, LIDAR_E_INVALID, LIDAR_E_STATE, LIDAR_E_HIP, LIDAR_E_NOMEM,
                        LIDAR_E_UNSUPPORTED, LIDAR_PATTERN_GAUSS, LIDAR_PATTERN_TABLE,
-                       LIDAR_MODE_PLAIN, LIDAR_AUTOTUNE, LIB_PATH)
+                       LIDAR_MODE_PLAIN, LIDAR_MODE_SURROGATE, LIDAR_ECHO_SURROGATE, LIDAR_AUTOTUNE,
+                       LIB_PATH)
 
 
 def upload_gbuffer(gbuffer, device="cuda"):

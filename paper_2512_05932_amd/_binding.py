@@ -27,6 +27,8 @@ LIDAR_AUTOTUNE = 4
 LIDAR_PATTERN_GAUSS = 1
 LIDAR_PATTERN_TABLE = 2
 LIDAR_MODE_PLAIN = 0
+LIDAR_MODE_SURROGATE = 1
+LIDAR_ECHO_SURROGATE = 4
 
 # every function the header declares
 EXPORTED = ["lidar_sim_create", "lidar_sim_destroy", "lidar_sim_set_pattern",
@@ -35,7 +37,7 @@ EXPORTED = ["lidar_sim_create", "lidar_sim_destroy", "lidar_sim_set_pattern",
             "lidar_sim_reset_batch", "lidar_sim_surrogate_set_weights",
             "lidar_sim_surrogate_get_weights", "lidar_sim_surrogate_forward",
             "lidar_sim_surrogate_gradients", "lidar_sim_surrogate_train_step",
-            "lidar_sim_get_stats", "lidar_sim_reset_stats", "lidar_sim_last_error"]
+            "lidar_sim_surrogate_set_gate", "lidar_sim_surrogate_features", "lidar_sim_get_stats", "lidar_sim_reset_stats", "lidar_sim_last_error"]
 
 SUR_IN, SUR_OUT, SUR_PARAMS = 1056, 16, 406288
 
@@ -69,7 +71,9 @@ class lidar_stats(C.Structure):
                 ("kernel_h", C.c_uint32), ("n_taps", C.c_uint32), ("reserved", C.c_uint32),
                 ("footprint_ms", C.c_double), ("footprint_launches", C.c_uint64),
                 ("prepass_ms", C.c_double), ("prepass_launches", C.c_uint64),
-                ("batch_ms", C.c_double), ("batch_launches", C.c_uint64)]
+                ("batch_ms", C.c_double), ("batch_launches", C.c_uint64),
+                ("surrogate_beams", C.c_uint64), ("fallback_beams", C.c_uint64),
+                ("surrogate_ms", C.c_double), ("surrogate_frames", C.c_uint64)]
 
 
 class lidar_train_hparams(C.Structure):
@@ -125,6 +129,8 @@ def load():
     lib.lidar_sim_surrogate_forward.argtypes = [V, V, V, C.c_uint32]
     lib.lidar_sim_surrogate_gradients.argtypes = [V, V, V, C.c_uint32, V, V]
     lib.lidar_sim_surrogate_train_step.argtypes = [V, V, V, C.c_uint32, P(lidar_train_hparams), V]
+    lib.lidar_sim_surrogate_set_gate.argtypes = [V, C.c_double, C.c_double]
+    lib.lidar_sim_surrogate_features.argtypes = [V, V, V, V]
     lib.lidar_sim_get_stats.argtypes = [V, P(lidar_stats)]
     lib.lidar_sim_reset_stats.argtypes = [V]
     lib.lidar_sim_last_error.argtypes = [V]
@@ -323,6 +329,15 @@ class LidarSim:
         self._check(self._lib.lidar_sim_surrogate_train_step(
             self._h, x.data_ptr(), labels.data_ptr(), x.shape[0], C.byref(hp),
             int(loss.data_ptr()) if loss is not None else None))
+
+    def set_gate(self, c_min: float = 0.5, alpha: float = 0.5):
+        self._check(self._lib.lidar_sim_surrogate_set_gate(self._h, float(c_min), float(alpha)))
+
+    def surrogate_features(self, x, labels=None, aux=None):
+        """x: int16 device tensor [n_beams][1056] (bfloat16 bits); labels,
+        aux: float32 device tensors [n_beams][16] / [n_beams][4] or None."""
+        p = lambda t: int(t.data_ptr()) if t is not None else None
+        self._check(self._lib.lidar_sim_surrogate_features(self._h, x.data_ptr(), p(labels), p(aux)))
 
     def stats(self) -> dict:
         s = lidar_stats()

@@ -118,10 +118,11 @@ struct BatchArgs {
     const int2* items;          // [n_items] {frame, global group index}, costliest first
     int n_items, G;
     int* next_item;             // work-queue counter (zeroed by k_reset_queue)
+    const int* n_items_dev;     // if set: the item count, read on the device
 };
 hipError_t launch_footprint_batch(hipStream_t s, const BatchArgs& a, int grid, bool sun,
                                   bool keep);
-hipError_t launch_reset_queue(hipStream_t s, int* counter);
+hipError_t launch_reset_queue(hipStream_t s, int* counter, int n = 1);  // n <= 64 ints
 // whether G histograms of R bins plus the pulse taps fit the LDS budget
 bool footprint_group_fits(int G, int R, int J);
 
@@ -200,6 +201,94 @@ hipError_t launch_zero_f32(hipStream_t s, float* p, long n);
 hipError_t launch_adamw(hipStream_t s, float* theta, const float* grad, float* m, float* v,
                         uint16_t* theta_b, long n, const AdamArgs& a);
 hipError_t launch_to_bf16(hipStream_t s, const float* x, uint16_t* y, long n);
+
+// ---- surrogate inputs, gate and fallback ----------------------------------
+constexpr int kSurPatch = 16;           // patch of 16 x 16 coarse cells
+constexpr int kSurTailBins = 64;        // coarse time bins of the tail estimate
+constexpr double kSurCoreFraction = 2e-4;
+
+// Cell sizes: coarse cells (cw x ch pixels) tile the kernel's core box
+// (cells with K >= 2e-4 max K, half extents cm, cn) 16 x 16 times;
+// super-cells (sw x sh) tile the kernel window 16 x 16 times.
+struct SurGeom {
+    int cm, cn, cw, ch, sw, sh, CW, CH, SW, SH;
+};
+
+struct CoarseArgs {
+    const float *depth, *refl, *gain, *nx, *ny, *nz;
+    long pitch;
+    int W, H;
+    const float2* colcs;
+    const float4* rowtab;
+    double to_bin;
+    int R;
+    float sun_x, sun_y, sun_z;
+    SurGeom g;
+    float4* cell;               // [CH][CW] {mean depth, reflectance cover, mean gain, mean cos}
+    float* cell_sun;            // [CH][CW] sum of sun shading
+};
+struct SuperArgs {
+    const int2* pix;            // pre-pass records [W4/4][H][4]
+    const float* sun;           // or null
+    int W, H;
+    SurGeom g;
+    float2* sup;                // [SH][SW] {shade sum, sun sum}
+    int2* range;                // [SH][SW] {first, last} time bin (0, -1: none)
+};
+struct SurAux {
+    int k_ref;
+    float e_tail, a_est;
+    int accepted;
+};
+struct FeatArgs {
+    const lidar_beam_info* beams;
+    const double *az, *el;
+    int B;
+    const float* depth;
+    long pitch;
+    int W, H;
+    double to_bin;
+    int R;
+    const float4* cell;
+    const float* cell_sun;
+    const float2* sup;
+    const int2* range;
+    const double* K64;
+    int M, N, KW;
+    SurGeom g;
+    float ambient, sun_scale, threshold;
+    uint16_t* X;                // [B][1056] BF16
+    SurAux* aux;                // [B]
+};
+struct DecodeArgs {
+    const float* Y;             // [B][16]
+    SurAux* aux;
+    int B, R, E;
+    float threshold;
+    float conf_logit;           // accept when y[12] >= conf_logit
+    float alpha;                // and E_tail < alpha * margin
+    double half_c_dt, bin_ns;
+    lidar_beam_info* beams;
+    lidar_echo* echoes;
+    int32_t* counts;
+};
+struct CompactArgs {
+    const int32_t* groups;      // [n_groups][G]
+    int n_groups, G;
+    const SurAux* aux;
+    int32_t* groups_fb;         // [n_groups][G]: fallback beams, -1 elsewhere
+    int2* items;                // [n_groups] {0, group}
+    int* n_items;               // compacted item count
+    int* n_fallback;            // fallback beams (accumulated)
+};
+hipError_t launch_coarse(hipStream_t s, const CoarseArgs& a);
+hipError_t launch_super(hipStream_t s, const SuperArgs& a);
+hipError_t launch_features(hipStream_t s, const FeatArgs& a);
+hipError_t launch_labels(hipStream_t s, const lidar_echo* echoes, const int32_t* counts,
+                         const SurAux* aux, int B, int E, float threshold, float* lab);
+hipError_t launch_decode(hipStream_t s, const DecodeArgs& a);
+hipError_t launch_compact(hipStream_t s, const CompactArgs& a);
+hipError_t launch_aux_out(hipStream_t s, const SurAux* aux, int B, float* out);
 
 struct SurNet {
     DevBuf<float> theta, m, v, grad;    // FP32 [kSurParams]

@@ -509,12 +509,13 @@ void k_footprint_batch(BatchArgs a)
     __shared__ int item_sh;
     const int tid = threadIdx.x;
     for (int j = tid; j <= 2 * a.p.J; j += kFootprintThreads) taps[j] = a.p.taps[j];
+    const int n_items = a.n_items_dev ? *a.n_items_dev : a.n_items;
     for (;;) {
         if (tid == 0) item_sh = atomicAdd(a.next_item, 1);
         for (int k = tid; k < G * a.p.R; k += kFootprintThreads) hist[k] = 0.0f;
         __syncthreads();
         const int item = item_sh;
-        if (item >= a.n_items) break;                    // uniform: every wave exits
+        if (item >= n_items) break;                      // uniform: every wave exits
         const int2 it = a.items[item];
         const FrameDev f = a.frames[it.x];
         process_group<G, SUN, KEEP>(f, a.p, a.groups + (size_t)it.y * G, hist, taps, red);
@@ -522,9 +523,9 @@ void k_footprint_batch(BatchArgs a)
     }
 }
 
-__global__ void k_reset_queue(int* counter)
+__global__ void k_reset_queue(int* counter, int n)
 {
-    if (threadIdx.x == 0) *counter = 0;
+    if ((int)threadIdx.x < n) counter[threadIdx.x] = 0;
 }
 
 template <int G>
@@ -585,9 +586,9 @@ hipError_t launch_footprint_batch(hipStream_t s, const BatchArgs& a, int grid, b
     }
 }
 
-hipError_t launch_reset_queue(hipStream_t s, int* counter)
+hipError_t launch_reset_queue(hipStream_t s, int* counter, int n)
 {
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, counter);
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, counter, n);
     return hipGetLastError();
 }
 

@@ -65,6 +65,13 @@ struct FrameState {
     std::vector<uint64_t> group_cost;  // samples of the group's beams
     int n_groups = 0;
     int tile = 64;
+    // surrogate inputs
+    SurGeom geom{};
+    bool geom_ok = false;
+    DevBuf<float4> d_cell;
+    DevBuf<float> d_cell_sun;
+    DevBuf<float2> d_sup;
+    DevBuf<int2> d_range;
 };
 
 }  // namespace
@@ -106,13 +113,23 @@ struct lidar_sim {
     hipGraphExec_t graph_exec = nullptr;
     std::map<int, int> tuned_tile;     // kernel-height class -> strip height
 
-    // surrogate network
+    // surrogate network, inputs, gate and fallback
     SurNet net;
     SurWork work;
+    DevBuf<uint16_t> s_X;
+    DevBuf<SurAux> s_aux;
+    DevBuf<int32_t> s_groups_fb;
+    DevBuf<int2> s_items;
+    DevBuf<int> s_cnt;                 // [0] fallback items, [1] queue, [2] fallback beams (running)
+    DevBuf<FrameDev> s_frame;
+    FrameDev s_frame_host{};
+    float gate_conf_logit = 0.0f;      // logit of c_min = 0.5
+    float gate_alpha = 0.5f;
+    bool plain_result = false;
 
     // stats
     lidar_stats st{};
-    std::vector<EventPair> pending_fp, pending_pp, pending_bt, pool;
+    std::vector<EventPair> pending_fp, pending_pp, pending_bt, pending_sur, pool;
 };
 
 namespace {
@@ -177,6 +194,8 @@ lidar_status drain_events(lidar_sim* h)
     HIP_TRY(h, drain(h->pending_fp, h->st.footprint_ms, h->st.footprint_launches), "event timing");
     HIP_TRY(h, drain(h->pending_pp, h->st.prepass_ms, h->st.prepass_launches), "event timing");
     HIP_TRY(h, drain(h->pending_bt, h->st.batch_ms, h->st.batch_launches), "event timing");
+    uint64_t n_sur = 0;
+    HIP_TRY(h, drain(h->pending_sur, h->st.surrogate_ms, n_sur), "event timing");
     return LIDAR_OK;
 }
 
@@ -499,6 +518,7 @@ lidar_status setup_frame(lidar_sim* h, FrameState& fs, lidar_beam_info* beams, c
     uint64_t total = 0;
     for (auto& x : bi) total += x.samples;
     fs.k = k;
+    fs.geom_ok = false;
     fs.kmax = kinfo[0];
     fs.samples = total;
     fs.tile = default_tile(k.KH);
@@ -582,6 +602,116 @@ PathDev path_view(const lidar_sim* h)
     return p;
 }
 
+// ---- surrogate inputs, gate, fallback ---------------------------------------
+
+// Cell sizes of the surrogate's inputs from the frame's kernel grid (host
+// copy; once per pattern and raster).
+lidar_status sur_geometry(lidar_sim* h, FrameState& fs)
+{
+    if (fs.geom_ok) return LIDAR_OK;
+    const KernelDev& k = fs.k;
+    std::vector<double> K((size_t)k.KW * k.KH);
+    HIP_TRY(h, hipMemcpyAsync(K.data(), fs.d_K64.p, K.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              h->stream), "copy kernel grid");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "kernel grid synchronise");
+    int cm = 0, cn = 0;
+    for (int n = 0; n < k.KH; ++n)
+        for (int m = 0; m < k.KW; ++m)
+            if (K[(size_t)n * k.KW + m] >= kSurCoreFraction * fs.kmax) {
+                cm = std::max(cm, std::abs(m - k.M));
+                cn = std::max(cn, std::abs(n - k.N));
+            }
+    SurGeom g;
+    g.cm = cm;
+    g.cn = cn;
+    g.cw = std::max(1, (2 * cm + 1 + kSurPatch - 1) / kSurPatch);
+    g.ch = std::max(1, (2 * cn + 1 + kSurPatch - 1) / kSurPatch);
+    g.sw = std::max(1, (k.KW + kSurPatch - 1) / kSurPatch);
+    g.sh = std::max(1, (k.KH + kSurPatch - 1) / kSurPatch);
+    const int W = (int)fs.gb.width, H = (int)fs.gb.height;
+    g.CW = (W + g.cw - 1) / g.cw;
+    g.CH = (H + g.ch - 1) / g.ch;
+    g.SW = (W + g.sw - 1) / g.sw;
+    g.SH = (H + g.sh - 1) / g.sh;
+    HIP_TRY(h, fs.d_cell.ensure((size_t)g.CW * g.CH), "allocate coarse cells");
+    HIP_TRY(h, fs.d_cell_sun.ensure((size_t)g.CW * g.CH), "allocate coarse cells");
+    HIP_TRY(h, fs.d_sup.ensure((size_t)g.SW * g.SH), "allocate super-cells");
+    HIP_TRY(h, fs.d_range.ensure((size_t)g.SW * g.SH), "allocate super-cells");
+    fs.geom = g;
+    fs.geom_ok = true;
+    return LIDAR_OK;
+}
+
+// Enqueue the pre-pass, the coarse and super-cell maps and the per-beam
+// network inputs (into X) of the single frame.
+lidar_status sur_inputs(lidar_sim* h, FrameState& fs, uint16_t* X)
+{
+    hipStream_t s = h->stream;
+    const lidar_gbuffer_desc& g = fs.gb;
+    const int B = (int)fs.pat.az.size();
+    HIP_TRY(h, h->s_aux.ensure(B), "allocate surrogate beam data");
+    LIDAR_TRY(enqueue_prepass(h, fs, s));
+    const bool sun = h->prm.sun_irradiance != 0.0;
+    const double to_bin = 2.0 / (kLight * (h->prm.bin_ns * 1e-9));
+    CoarseArgs ca;
+    ca.depth = g.depth;
+    ca.refl = g.reflectance;
+    ca.gain = g.retro_gain;
+    ca.nx = g.normal_x;
+    ca.ny = g.normal_y;
+    ca.nz = g.normal_z;
+    ca.pitch = (long)g.pitch;
+    ca.W = (int)g.width;
+    ca.H = (int)g.height;
+    ca.colcs = fs.d_colcs.p;
+    ca.rowtab = fs.d_rowtab.p;
+    ca.to_bin = to_bin;
+    ca.R = (int)h->prm.n_bins;
+    ca.sun_x = (float)h->prm.sun_dir[0];
+    ca.sun_y = (float)h->prm.sun_dir[1];
+    ca.sun_z = (float)h->prm.sun_dir[2];
+    ca.g = fs.geom;
+    ca.cell = fs.d_cell.p;
+    ca.cell_sun = fs.d_cell_sun.p;
+    HIP_TRY(h, launch_coarse(s, ca), "coarse cells launch");
+    SuperArgs sa;
+    sa.pix = fs.d_pix.p;
+    sa.sun = sun ? fs.d_sun.p : nullptr;
+    sa.W = ca.W;
+    sa.H = ca.H;
+    sa.g = fs.geom;
+    sa.sup = fs.d_sup.p;
+    sa.range = fs.d_range.p;
+    HIP_TRY(h, launch_super(s, sa), "super-cells launch");
+    FeatArgs fa;
+    fa.beams = h->d_beams.p;
+    fa.az = fs.d_az.p;
+    fa.el = fs.d_el.p;
+    fa.B = B;
+    fa.depth = g.depth;
+    fa.pitch = (long)g.pitch;
+    fa.W = ca.W;
+    fa.H = ca.H;
+    fa.to_bin = to_bin;
+    fa.R = ca.R;
+    fa.cell = fs.d_cell.p;
+    fa.cell_sun = fs.d_cell_sun.p;
+    fa.sup = fs.d_sup.p;
+    fa.range = fs.d_range.p;
+    fa.K64 = fs.d_K64.p;
+    fa.M = fs.k.M;
+    fa.N = fs.k.N;
+    fa.KW = fs.k.KW;
+    fa.g = fs.geom;
+    fa.ambient = (float)h->prm.ambient_const;
+    fa.sun_scale = sun ? (float)(h->prm.sun_irradiance / fs.kmax) : 0.0f;
+    fa.threshold = (float)h->prm.threshold;
+    fa.X = X;
+    fa.aux = h->s_aux.p;
+    HIP_TRY(h, launch_features(s, fa), "features launch");
+    return LIDAR_OK;
+}
+
 // ---- batches ---------------------------------------------------------------
 
 void free_graph(lidar_sim* h)
@@ -608,6 +738,7 @@ lidar_status enqueue_batch(lidar_sim* h, hipStream_t s, const int2* items, uint6
     ba.n_items = (int)n_items;
     ba.G = h->G;
     ba.next_item = h->b_queue.p;
+    ba.n_items_dev = nullptr;
     const bool sun = h->prm.sun_irradiance != 0.0;
     const bool keep = (h->prm.flags & LIDAR_KEEP_WAVEFORMS) != 0;
     HIP_TRY(h, launch_footprint_batch(s, ba, h->b_grid, sun, keep), "batch footprint launch");
@@ -854,7 +985,7 @@ lidar_status lidar_sim_destroy(lidar_sim* h)
 {
     if (!h) return LIDAR_OK;
     (void)hipStreamSynchronize(h->stream);
-    for (auto* v : {&h->pending_fp, &h->pending_pp, &h->pending_bt, &h->pool})
+    for (auto* v : {&h->pending_fp, &h->pending_pp, &h->pending_bt, &h->pending_sur, &h->pool})
         for (auto& p : *v) {
             (void)hipEventDestroy(p.a);
             (void)hipEventDestroy(p.b);
@@ -886,17 +1017,12 @@ lidar_status lidar_sim_set_gbuffer(lidar_sim* h, const lidar_gbuffer_desc* g)
     return LIDAR_OK;
 }
 
-lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
+static lidar_status ensure_setup(lidar_sim* h, const char* who)
 {
-    if (!h) return LIDAR_E_INVALID;
-    if (mode != LIDAR_MODE_PLAIN) return fail(h, LIDAR_E_UNSUPPORTED, "only LIDAR_MODE_PLAIN is implemented");
-    if (!h->have_pattern) return fail(h, LIDAR_E_STATE, "simulate_frame before set_pattern");
-    if (!h->have_gbuffer) return fail(h, LIDAR_E_STATE, "simulate_frame before set_gbuffer");
+    if (!h->have_pattern) return fail(h, LIDAR_E_STATE, std::string(who) + " before set_pattern");
+    if (!h->have_gbuffer) return fail(h, LIDAR_E_STATE, std::string(who) + " before set_gbuffer");
     FrameState& fs = h->single;
     const size_t B = fs.pat.az.size();
-    const uint32_t R = h->prm.n_bins, E = h->prm.max_echoes;
-    const bool keep = (h->prm.flags & LIDAR_KEEP_WAVEFORMS) != 0;
-    const bool prof = (h->prm.flags & LIDAR_PROFILE) != 0;
     if (!h->setup_ok) {
         HIP_TRY(h, h->d_beams.ensure(B), "allocate beams");
         LIDAR_TRY(setup_frame(h, fs, h->d_beams.p, ""));
@@ -909,6 +1035,23 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
         h->setup_ok = true;
     }
     LIDAR_TRY(alloc_pixels(h, fs));
+    return LIDAR_OK;
+}
+
+static lidar_status simulate_surrogate(lidar_sim* h);
+
+lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (mode != LIDAR_MODE_PLAIN && mode != LIDAR_MODE_SURROGATE)
+        return fail(h, LIDAR_E_UNSUPPORTED, "unknown simulate_frame mode");
+    LIDAR_TRY(ensure_setup(h, "simulate_frame"));
+    if (mode == LIDAR_MODE_SURROGATE) return simulate_surrogate(h);
+    FrameState& fs = h->single;
+    const size_t B = fs.pat.az.size();
+    const uint32_t R = h->prm.n_bins, E = h->prm.max_echoes;
+    const bool keep = (h->prm.flags & LIDAR_KEEP_WAVEFORMS) != 0;
+    const bool prof = (h->prm.flags & LIDAR_PROFILE) != 0;
     HIP_TRY(h, h->d_echoes.ensure(B * E), "allocate echoes");
     HIP_TRY(h, h->d_counts.ensure(B), "allocate counts");
     if (keep) HIP_TRY(h, h->d_waves.ensure(B * (size_t)R), "allocate waveforms");
@@ -943,7 +1086,107 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
         h->pending_fp.push_back(fp);
     }
     h->have_result = true;
+    h->plain_result = true;
     ++h->st.frames;
+    return LIDAR_OK;
+}
+
+// The network on every beam, the gate, and the plain path on the groups of
+// the beams that fall back - all enqueued, no host round trip.
+static lidar_status simulate_surrogate(lidar_sim* h)
+{
+    if (!h->net.ready) return fail(h, LIDAR_E_STATE, "surrogate mode without surrogate weights");
+    FrameState& fs = h->single;
+    const int B = (int)fs.pat.az.size();
+    const uint32_t R = h->prm.n_bins, E = h->prm.max_echoes;
+    const bool keep = (h->prm.flags & LIDAR_KEEP_WAVEFORMS) != 0;
+    const bool prof = (h->prm.flags & LIDAR_PROFILE) != 0;
+    hipStream_t s = h->stream;
+    LIDAR_TRY(sur_geometry(h, fs));
+    HIP_TRY(h, h->d_echoes.ensure((size_t)B * E), "allocate echoes");
+    HIP_TRY(h, h->d_counts.ensure(B), "allocate counts");
+    if (keep) HIP_TRY(h, h->d_waves.ensure((size_t)B * R), "allocate waveforms");
+    HIP_TRY(h, h->s_X.ensure((size_t)B * kSurIn), "allocate surrogate inputs");
+    HIP_TRY(h, h->work.ensure(B), "allocate surrogate workspace");
+    HIP_TRY(h, h->s_groups_fb.ensure((size_t)fs.n_groups * h->G), "allocate fallback groups");
+    HIP_TRY(h, h->s_items.ensure(fs.n_groups), "allocate fallback items");
+    if (!h->s_cnt.p) {
+        HIP_TRY(h, h->s_cnt.ensure(4), "allocate counters");
+        HIP_TRY(h, launch_reset_queue(s, h->s_cnt.p, 4), "counter reset");
+    }
+    HIP_TRY(h, h->s_frame.ensure(1), "allocate frame table");
+    EventPair ev{};
+    if (prof) {
+        hipError_t e;
+        ev = take_pair(h, &e);
+        HIP_TRY(h, e, "create events");
+        HIP_TRY(h, hipEventRecord(ev.a, s), "record event");
+    }
+    LIDAR_TRY(sur_inputs(h, fs, h->s_X.p));
+    HIP_TRY(h, sur_forward(s, h->net, h->s_X.p, B, h->work), "surrogate forward");
+    HIP_TRY(h, launch_reset_queue(s, h->s_cnt.p, 2), "counter reset");
+    DecodeArgs da;
+    da.Y = h->work.Y.p;
+    da.aux = h->s_aux.p;
+    da.B = B;
+    da.R = (int)R;
+    da.E = (int)E;
+    da.threshold = (float)h->prm.threshold;
+    da.conf_logit = h->gate_conf_logit;
+    da.alpha = h->gate_alpha;
+    da.half_c_dt = 0.5 * kLight * (h->prm.bin_ns * 1e-9);
+    da.bin_ns = h->prm.bin_ns;
+    da.beams = h->d_beams.p;
+    da.echoes = h->d_echoes.p;
+    da.counts = h->d_counts.p;
+    HIP_TRY(h, launch_decode(s, da), "gate launch");
+    CompactArgs cp;
+    cp.groups = h->d_groups.p;
+    cp.n_groups = fs.n_groups;
+    cp.G = h->G;
+    cp.aux = h->s_aux.p;
+    cp.groups_fb = h->s_groups_fb.p;
+    cp.items = h->s_items.p;
+    cp.n_items = h->s_cnt.p;
+    cp.n_fallback = h->s_cnt.p + 2;
+    HIP_TRY(h, launch_compact(s, cp), "fallback selection launch");
+    // the plain path over the selected groups (count read on the device)
+    const FrameDev fd = frame_view(h, fs, h->d_beams.p, h->d_echoes.p, h->d_counts.p,
+                                   keep ? h->d_waves.p : nullptr);
+    if (std::memcmp(&fd, &h->s_frame_host, sizeof(FrameDev)) != 0) {
+        h->s_frame_host = fd;
+        HIP_TRY(h, hipMemcpyAsync(h->s_frame.p, &h->s_frame_host, sizeof(FrameDev),
+                                  hipMemcpyHostToDevice, s), "copy frame table");
+        HIP_TRY(h, hipStreamSynchronize(s), "frame table synchronise");
+    }
+    BatchArgs ba;
+    ba.frames = h->s_frame.p;
+    ba.p = path_view(h);
+    ba.groups = h->s_groups_fb.p;
+    ba.items = h->s_items.p;
+    ba.n_items = fs.n_groups;
+    ba.G = h->G;
+    ba.next_item = h->s_cnt.p + 1;
+    ba.n_items_dev = h->s_cnt.p;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    const size_t lds = sizeof(float) * ((size_t)h->G * R + 2 * h->J + 1) + 1024;
+    const size_t per_cu = std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
+    const int grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)cus * per_cu, (size_t)fs.n_groups));
+    HIP_TRY(h, launch_footprint_batch(s, ba, grid, h->prm.sun_irradiance != 0.0, keep),
+            "fallback footprint launch");
+    if (prof) {
+        HIP_TRY(h, hipEventRecord(ev.b, s), "record event");
+        h->pending_sur.push_back(ev);
+    }
+    h->have_result = true;
+    h->plain_result = false;
+    ++h->st.frames;
+    ++h->st.surrogate_frames;
+    h->st.surrogate_beams += (uint64_t)B;
     return LIDAR_OK;
 }
 
@@ -1166,6 +1409,38 @@ lidar_status lidar_sim_surrogate_train_step(lidar_sim* h, const void* x, const f
     return LIDAR_OK;
 }
 
+lidar_status lidar_sim_surrogate_set_gate(lidar_sim* h, double c_min, double alpha)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!(c_min >= 0.0 && c_min <= 1.0) || !(alpha >= 0.0))
+        return fail(h, LIDAR_E_INVALID, "gate needs c_min in [0, 1] and alpha >= 0");
+    h->gate_conf_logit = c_min >= 1.0 ? INFINITY
+                         : c_min <= 0.0 ? -INFINITY
+                                        : (float)std::log(c_min / (1.0 - c_min));
+    h->gate_alpha = alpha >= 1e30 ? INFINITY : (float)alpha;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_surrogate_features(lidar_sim* h, void* x, float* labels, float* aux)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!x) return fail(h, LIDAR_E_INVALID, "surrogate_features needs x");
+    LIDAR_TRY(ensure_setup(h, "surrogate_features"));
+    if (labels && !(h->have_result && h->plain_result))
+        return fail(h, LIDAR_E_STATE, "labels need a plain simulate_frame on these inputs");
+    if (labels && h->prm.max_echoes < 3) return fail(h, LIDAR_E_INVALID, "labels need max_echoes >= 3");
+    FrameState& fs = h->single;
+    const int B = (int)fs.pat.az.size();
+    LIDAR_TRY(sur_geometry(h, fs));
+    LIDAR_TRY(sur_inputs(h, fs, (uint16_t*)x));
+    if (labels)
+        HIP_TRY(h, launch_labels(h->stream, h->d_echoes.p, h->d_counts.p, h->s_aux.p, B,
+                                 (int)h->prm.max_echoes, (float)h->prm.threshold, labels),
+                "labels launch");
+    if (aux) HIP_TRY(h, launch_aux_out(h->stream, h->s_aux.p, B, aux), "aux launch");
+    return LIDAR_OK;
+}
+
 lidar_status lidar_sim_get_stats(lidar_sim* h, lidar_stats* out)
 {
     if (!h) return LIDAR_E_INVALID;
@@ -1175,6 +1450,13 @@ lidar_status lidar_sim_get_stats(lidar_sim* h, lidar_stats* out)
     h->st.samples_per_frame = h->setup_ok ? h->single.samples : 0;
     h->st.kernel_w = h->setup_ok ? (uint32_t)h->single.k.KW : 0;
     h->st.kernel_h = h->setup_ok ? (uint32_t)h->single.k.KH : 0;
+    if (h->s_cnt.p) {
+        int fb = 0;
+        HIP_TRY(h, hipMemcpyAsync(&fb, h->s_cnt.p + 2, sizeof(int), hipMemcpyDeviceToHost, h->stream),
+                "copy fallback count");
+        HIP_TRY(h, hipStreamSynchronize(h->stream), "stats synchronise");
+        h->st.fallback_beams = (uint64_t)fb;
+    }
     *out = h->st;
     return LIDAR_OK;
 }
@@ -1190,6 +1472,11 @@ lidar_status lidar_sim_reset_stats(lidar_sim* h)
     h->st.prepass_launches = 0;
     h->st.batch_ms = 0.0;
     h->st.batch_launches = 0;
+    h->st.surrogate_beams = 0;
+    h->st.fallback_beams = 0;
+    h->st.surrogate_ms = 0.0;
+    h->st.surrogate_frames = 0;
+    if (h->s_cnt.p) HIP_TRY(h, launch_reset_queue(h->stream, h->s_cnt.p + 2, 1), "counter reset");
     return LIDAR_OK;
 }
 

@@ -1,0 +1,198 @@
+"""The surrogate's inputs, gate and fallback on the GPU against the FP64
+oracle, through the C-ABI.
+
+Inputs: every value within one BF16 ulp (at most 2^-7 relative) of the oracle's value
+rounded to BF16, plus 1e-5 absolute (the first channel subtracts nearly equal
+depths; FP32 vs FP64 means); reference bins exact where the beam's pixel is
+valid; the floor estimate and the tail estimate within 1e-4 relative (FP32
+sums of the same terms).  Modes: with c_min = 1 every beam runs the plain
+path and must meet the plain path's parity rules; with every beam accepted
+the echoes are the decoded network outputs."""
+from dataclasses import replace
+import math
+
+import numpy as np
+import pytest
+
+import scenes
+import oracle as O
+from oracle import surrogate as S
+
+from .parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lidar():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_05932_amd as lidar
+    lidar.load()
+    return lidar
+
+
+def _scan():
+    return scenes.config2(0, width=2048, height=128, n_lines=16, n_cols=300)
+
+
+def _oracle_inputs(w):
+    K = O.kernel_grid(w.gbuffer.raster, w.pattern)
+    ref = O.simulate(w.gbuffer, w.pattern, w.params, want_xi=False)
+    X, kref, et, ae, geo = S.features(w.gbuffer, w.pattern, w.params, K, ref.pixel, ref.scale,
+                                      lambda v: O.row_solid_angle(w.gbuffer.raster, v))
+    return ref, X, kref, et, ae, geo
+
+
+def _gpu_inputs(lidar, w, labels=False):
+    import torch
+    planes = lidar.upload_gbuffer(w.gbuffer, "cuda")
+    sim = lidar.LidarSim(w.params, stream=torch.cuda.current_stream())
+    B = w.pattern.n_beams
+    try:
+        sim.set_pattern(w.pattern)
+        sim.set_gbuffer(w.gbuffer.raster, planes)
+        x = torch.zeros((B, S.IN), dtype=torch.int16, device="cuda")
+        aux = torch.zeros((B, 4), dtype=torch.float32, device="cuda")
+        lab = torch.zeros((B, 16), dtype=torch.float32, device="cuda") if labels else None
+        if labels:
+            sim.simulate_frame()
+        sim.surrogate_features(x, lab, aux)
+        out = {"x": scenes.bf16_bits_to_float(x.cpu().numpy().view(np.uint16)).astype(np.float64),
+               "aux": aux.cpu().numpy().astype(np.float64)}
+        if labels:
+            out["labels"] = lab.cpu().numpy().astype(np.float64)
+            out["plain"] = sim.read()
+    finally:
+        sim.close()
+    return out
+
+
+@pytest.mark.parametrize("which", ["scan", "tiny"])
+def test_inputs_match_oracle(lidar, which):
+    if which == "scan":
+        w = _scan()
+    else:
+        rng = np.random.default_rng(3)
+        raster = scenes.Raster(37, 23, -6.0, 6.94, -2.0, 4.0)
+        gb = scenes.random_gbuffer(raster, rng, depth_range=(3.0, 40.0), retro_frac=0.1)
+        d = gb.depth.copy()
+        d[rng.uniform(size=d.shape) < 0.1] = np.inf
+        d[rng.uniform(size=d.shape) < 0.05] = np.nan
+        gb = replace(gb, depth=d)
+        az = np.array([0.1, -5.9, 5.95, 2.0, 6.4, -1.3, -30.0, 0.0])
+        el = np.array([1.0, 3.9, -1.9, 4.2, 0.5, -2.3, 0.0, -0.05])
+        pat = scenes.Pattern(scenes.PATTERN_GAUSS, az, el, sigma_deg=(0.6, 0.45), trunc_sigmas=3.0)
+        p = scenes.SensorParams(n_bins=300, bin_ns=1.0, max_echoes=3, threshold=2e-6,
+                                emit_power=1.0, pulse_fwhm_ns=4.0, pulse_trunc_sigmas=4.0,
+                                ambient_const=1e-7, sun_irradiance=0.5,
+                                sun_dir=(0.3, -0.5, math.sqrt(1 - 0.34)))
+        w = scenes.Workload("tiny", gb, pat, p)
+    ref, X, kref, et, ae, geo = _oracle_inputs(w)
+    got = _gpu_inputs(lidar, w)
+    Xr = S.bf16_round(X)
+    err = np.abs(got["x"] - Xr)
+    tol = np.abs(Xr) * 2.0 ** -7 + 1e-5          # one BF16 ulp
+    bad = np.argwhere(err > tol)
+    print(f"[sur-in] {which}: geo {geo['cw']}x{geo['ch']} / {geo['sw']}x{geo['sh']}, "
+          f"{len(bad)} of {err.size} inputs out of tolerance", flush=True)
+    for b, j in bad[:12]:
+        print(f"[sur-in]   beam {b} input {j}: gpu {got['x'][b, j]:.6g} oracle {X[b, j]:.6g} "
+              f"(bf16 {Xr[b, j]:.6g}) k_ref gpu {got['aux'][b, 0]:.0f} oracle {kref[b]}", flush=True)
+    assert len(bad) == 0, bad[:10]
+    u, v = ref.pixel[:, 0], ref.pixel[:, 1]
+    H, W = w.gbuffer.depth.shape
+    inside = (u >= 0) & (u < W) & (v >= 0) & (v < H)
+    centre = np.zeros(len(u), bool)
+    centre[inside] = np.isfinite(w.gbuffer.depth[v[inside], u[inside]])
+    np.testing.assert_array_equal(got["aux"][centre, 0], kref[centre])
+    assert np.all(np.abs(got["aux"][:, 0] - kref) <= 1)
+    np.testing.assert_allclose(got["aux"][:, 1], et, rtol=1e-4, atol=1e-30)
+    np.testing.assert_allclose(got["aux"][:, 2], ae, rtol=1e-4, atol=1e-30)
+
+
+def test_labels_from_plain_echoes(lidar):
+    w = _scan()
+    ref, X, kref, et, ae, geo = _oracle_inputs(w)
+    got = _gpu_inputs(lidar, w, labels=True)
+    lab = S.labels(kref, ref.echoes, ref.n_echoes, w.params)
+    pe = got["plain"]["echoes"]
+    same = (got["plain"]["n_echoes"] == ref.n_echoes) & (got["aux"][:, 0] == kref)
+    for e in range(3):
+        same &= (ref.n_echoes <= e) | (pe["bin_peak"][:, e] == ref.echoes["bin_peak"][:, e])
+    assert same.mean() > 0.99
+    g, r = got["labels"][same], lab[same]
+    np.testing.assert_array_equal(g[:, :6], r[:, :6])
+    np.testing.assert_allclose(g[:, 6:9], r[:, 6:9], atol=1e-4)
+    np.testing.assert_allclose(g[:, 9:12], r[:, 9:12], atol=1e-3)
+
+
+def _run_mode(lidar, w, weights, c_min, alpha, keep=False):
+    import torch
+    planes = lidar.upload_gbuffer(w.gbuffer, "cuda")
+    sim = lidar.LidarSim(w.params, stream=torch.cuda.current_stream(), keep_waveforms=keep)
+    try:
+        sim.set_pattern(w.pattern)
+        sim.set_gbuffer(w.gbuffer.raster, planes)
+        sim.set_weights(weights)
+        sim.set_gate(c_min, alpha)
+        sim.simulate_frame(lidar.LIDAR_MODE_SURROGATE)
+        out = sim.read(waveforms=keep)
+        st = sim.stats()
+        B = w.pattern.n_beams
+        aux = torch.zeros((B, 4), dtype=torch.float32, device="cuda")
+        x = torch.zeros((B, S.IN), dtype=torch.int16, device="cuda")
+        sim.surrogate_features(x, None, aux)
+        out["aux"] = aux.cpu().numpy()
+        out["x"] = scenes.bf16_bits_to_float(x.cpu().numpy().view(np.uint16))
+    finally:
+        sim.close()
+    return out, st
+
+
+def test_all_fallback_is_the_plain_path(lidar, oracle_mod):
+    w = _scan()
+    out, st = _run_mode(lidar, w, scenes.surrogate_init(1), c_min=1.0, alpha=1e30, keep=True)
+    assert st["fallback_beams"] == w.pattern.n_beams == st["surrogate_beams"]
+    ref = oracle_mod.simulate(w.gbuffer, w.pattern, w.params)
+    rep = compare(out, ref, w.params)
+    print(f"[sur-mode] all fallback: echoes {rep.echoes_compared}", flush=True)
+    assert np.all((out["echoes"]["flags"] & 4) == 0)
+
+
+def test_all_accepted_decodes_the_network(lidar):
+    """Every beam keeps the network's echoes: counts, peak bins, ranges and
+    flags follow from the oracle network on the oracle's inputs, on beams
+    whose pixel is valid (exact reference bin) and whose decisions (existence
+    sign, bin rounding) are clear of their boundaries by 0.01."""
+    w = _scan()
+    flat = scenes.surrogate_init(2)
+    out, st = _run_mode(lidar, w, flat, c_min=0.0, alpha=1e30)
+    assert st["fallback_beams"] == 0
+    ref, X, kref, et, ae, geo = _oracle_inputs(w)
+    Y = S.forward(S.bf16_round(X), flat).Y
+    R = w.params.n_bins
+    u, v = ref.pixel[:, 0], ref.pixel[:, 1]
+    H, W = w.gbuffer.depth.shape
+    inside = (u >= 0) & (u < W) & (v >= 0) & (v < H)
+    clear = np.zeros(len(u), bool)
+    clear[inside] = np.isfinite(w.gbuffer.depth[v[inside], u[inside]])
+    for e in range(3):
+        clear &= np.abs(Y[:, e]) > 0.01
+        frac = np.abs(16 * Y[:, 3 + e] - np.floor(16 * Y[:, 3 + e]) - 0.5)
+        clear &= (Y[:, e] <= 0) | (frac > 0.01)
+    print(f"[sur-mode] all accepted: {clear.sum()} of {len(clear)} beams compared", flush=True)
+    assert clear.mean() > 0.5
+    n_exp = (Y[:, :3] > 0).sum(axis=1)
+    np.testing.assert_array_equal(out["n_echoes"][clear], n_exp[clear])
+    ech = out["echoes"]
+    half_c_dt = 0.5 * 299792458.0 * w.params.bin_ns * 1e-9
+    for b in np.flatnonzero(clear):
+        slots = [e for e in range(3) if Y[b, e] > 0]
+        for i, e in enumerate(slots):
+            k = int(min(R - 1, max(0, kref[b] + np.rint(16 * Y[b, 3 + e]))))
+            assert ech["bin_peak"][b, i] == k
+            assert ech["flags"][b, i] == 4
+            assert ech["range_m"][b, i] == (k + 0.5) * half_c_dt
+    np.testing.assert_allclose(out["beams"]["floor"], ae, rtol=1e-4, atol=1e-30)
