@@ -34,6 +34,7 @@ SHAPES = [("W1", (IN, HID)), ("b1", (HID,)), ("W2", (HID, HID)), ("b2", (HID,)),
           ("W3", (HID, HID)), ("b3", (HID,)), ("W4", (HID, OUT)), ("b4", (OUT,))]
 N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
 BIN_SCALE = 16.0          # y[3..5] are in units of 16 bins
+DK_CLIP = 4.0             # labels of peak offsets are clipped to +-64 bins
 W_BIN, W_INT, W_EPW = 64.0, 1.0, 1.0
 
 
@@ -103,7 +104,8 @@ def _sigmoid(z):
 
 def confidence_target(Y, lab) -> np.ndarray:
     """1 where the prediction has every existence right and every existing
-    echo in the right bin (decided in FP32, as the device does)."""
+    echo in the right bin, its offset label not clipped (decided in FP32, as
+    the device does)."""
     y = np.asarray(Y, dtype=np.float32)
     l = np.asarray(lab, dtype=np.float32)
     ok = np.ones(y.shape[0], dtype=bool)
@@ -111,6 +113,7 @@ def confidence_target(Y, lab) -> np.ndarray:
         te = l[:, e] > np.float32(0.5)
         ok &= (y[:, e] > 0) == te
         ok &= ~(te & (np.abs(y[:, 3 + e] - l[:, 3 + e]) * np.float32(BIN_SCALE) > np.float32(0.5)))
+        ok &= ~(te & (np.abs(l[:, 3 + e]) >= np.float32(DK_CLIP)))
     return ok.astype(np.float64)
 
 
@@ -260,7 +263,7 @@ def _block_bin_range(kbin, bw, bh, nx, ny):
 def coarse_maps(t: dict, geo: dict) -> dict:
     """Coarse cells (cw x ch pixels, clipped at the image edge): mean depth,
     retro gain and cos(theta) over valid pixels, reflectance summed over valid
-    pixels divided by all pixels of the cell, sum of sun shading;
+    pixels divided by all pixels of the cell, sums of shade and sun shading;
     super-cells: sums of shade and sun shading, range of time bins."""
     cw, ch, CW, CH = geo["cw"], geo["ch"], geo["CW"], geo["CH"]
     ones = np.ones_like(t["d"])
@@ -273,9 +276,51 @@ def coarse_maps(t: dict, geo: dict) -> dict:
                 gmean=_block_sum(t["g"], cw, ch, CW, CH) / safe,
                 cmean=_block_sum(t["cos"], cw, ch, CW, CH) / safe,
                 sunc=_block_sum(t["sun"], cw, ch, CW, CH),
+                shadec=_block_sum(t["shade"], cw, ch, CW, CH),
                 shade=_block_sum(t["shade"], geo["sw"], geo["sh"], geo["SW"], geo["SH"]),
                 binrange=_block_bin_range(t["kbin"], geo["sw"], geo["sh"], geo["SW"], geo["SH"]),
                 sun=_block_sum(t["sun"], geo["sw"], geo["sh"], geo["SW"], geo["SH"]))
+
+
+REF_WINDOW = 512          # time bins of the reference-bin histogram
+REF_SMOOTH = (1.0, 2.0, 3.0, 2.0, 1.0)
+
+
+def reference_bin(K, geo, maps, Ib, Jb, u, v, nval, dmean, Ic, Jc, inside, to_bin) -> int:
+    """A coarse estimate of the beam's strongest return: the patch cells
+    whose centre lies in the core box add K(centre) * (shade sum) at the time
+    bin of their mean depth into a histogram of REF_WINDOW bins from the
+    smallest such bin; the first maximum of the histogram smoothed with
+    (1, 2, 3, 2, 1) is the reference bin.  Without such cells: the bin of the
+    nearest cell mean depth in the patch, else 0."""
+    M, N, cm, cn = geo["M"], geo["N"], geo["cm"], geo["cn"]
+    cw, ch = geo["cw"], geo["ch"]
+    ks, ws = [], []
+    for j in range(PATCH):
+        J = Jb - PATCH // 2 + j
+        n = (2 * J * ch + ch - 2 * v) // 2
+        for i in range(PATCH):
+            I = Ib - PATCH // 2 + i
+            m = (2 * I * cw + cw - 2 * u) // 2
+            if not inside[j, i] or nval[j, i] <= 0 or abs(m) > cm or abs(n) > cn:
+                continue
+            w = K[n + N, m + M] * maps["shadec"][Jc[j, 0], Ic[0, i]]
+            if w > 0:
+                ks.append(int(math.floor(dmean[j, i] * to_bin)))
+                ws.append(w)
+    if ks:
+        kmin = min(ks)
+        hist = np.zeros(REF_WINDOW + 4)
+        for k, w in zip(ks, ws):
+            if k - kmin < REF_WINDOW:
+                hist[k - kmin + 2] += w
+        sm = np.zeros(REF_WINDOW)
+        for d, c in enumerate(REF_SMOOTH):
+            sm += c * hist[d:d + REF_WINDOW]
+        return kmin + int(np.argmax(sm))
+    if np.any(nval > 0):
+        return int(math.floor(dmean[nval > 0].min() * to_bin))
+    return 0
 
 
 def beam_features(K, geo, maps, t, u, v, scale, az_deg, el_deg, params):
@@ -291,17 +336,11 @@ def beam_features(K, geo, maps, t, u, v, scale, az_deg, el_deg, params):
     Ic, Jc = np.clip(I, 0, CW - 1), np.clip(J, 0, CH - 1)
     nval = np.where(inside, maps["nval"][Jc, Ic], 0.0)
     dmean = maps["dmean"][Jc, Ic]
-    # reference range: the beam pixel's depth, else the nearest cell mean
-    if 0 <= u < W and 0 <= v < H and t["valid"][v, u]:
-        r_ref = t["d"][v, u]
-    elif np.any(nval > 0):
-        r_ref = dmean[nval > 0].min()
-    else:
-        r_ref = 0.0
     to_bin = t["to_bin"]
-    k_ref = int(math.floor(r_ref * to_bin)) if r_ref > 0 else 0
+    M, N, cm, cn = geo["M"], geo["N"], geo["cm"], geo["cn"]
+    k_ref = reference_bin(K, geo, maps, Ib, Jb, u, v, nval, dmean, Ic, Jc, inside, to_bin)
     x = np.zeros(IN)
-    ch0 = np.where(nval > 0, np.clip((dmean - r_ref) * to_bin / 64.0, -1.0, 1.0), 1.0)
+    ch0 = np.where(nval > 0, np.clip((dmean * to_bin - (k_ref + 0.5)) / 64.0, -1.0, 1.0), 1.0)
     ch1 = np.where(inside, maps["rho"][Jc, Ic], 0.0)
     ch2 = np.where(nval > 0, np.log10(np.where(nval > 0, maps["gmean"][Jc, Ic], 1.0)) / 3.0, 0.0)
     ch3 = np.where(nval > 0, maps["cmean"][Jc, Ic], 0.0)
@@ -310,7 +349,6 @@ def beam_features(K, geo, maps, t, u, v, scale, az_deg, el_deg, params):
     # the kernel is taken at each cell's centre (nearest kernel cell):
     # sun floor of the core box from the coarse cells, tail energy and the
     # tail's sun floor from the super-cells outside the core box
-    M, N, cm, cn = geo["M"], geo["N"], geo["cm"], geo["cn"]
     a_sum = 0.0
     for j in range(PATCH):
         Jc_ = Jb - PATCH // 2 + j
@@ -378,15 +416,16 @@ def features(gbuffer, pattern, params, K, pixels, scales, row_omega):
 
 def labels(kref, echoes, n_echoes, params) -> np.ndarray:
     """Training targets of beams from their plain-path echoes: existence of
-    echoes 1..3, (peak bin - k_ref) / 16, log10(max(intensity, 1e-3 T) / T),
-    pulse width / 4 ns."""
+    echoes 1..3, (peak bin - k_ref) / 16 clipped to +-4, log10(max(intensity,
+    1e-3 T) / T), pulse width / 4 ns."""
     B = len(kref)
     lab = np.zeros((B, 16))
     T = params.threshold
     for e in range(3):
         ex = np.asarray(n_echoes) > e
         lab[:, e] = ex
-        lab[:, 3 + e] = np.where(ex, (echoes["bin_peak"][:, e] - kref) / BIN_SCALE, 0.0)
+        dk = np.clip((echoes["bin_peak"][:, e] - kref) / BIN_SCALE, -DK_CLIP, DK_CLIP)
+        lab[:, 3 + e] = np.where(ex, dk, 0.0)
         inten = np.maximum(echoes["intensity"][:, e].astype(np.float64), 1e-3 * T)
         lab[:, 6 + e] = np.where(ex, np.log10(inten / T), 0.0)
         lab[:, 9 + e] = np.where(ex, echoes["pulse_width_ns"][:, e] / 4.0, 0.0)

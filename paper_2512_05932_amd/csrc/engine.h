@@ -206,6 +206,8 @@ hipError_t launch_to_bf16(hipStream_t s, const float* x, uint16_t* y, long n);
 constexpr int kSurPatch = 16;           // patch of 16 x 16 coarse cells
 constexpr int kSurTailBins = 64;        // coarse time bins of the tail estimate
 constexpr double kSurCoreFraction = 2e-4;
+constexpr int kSurRefWindow = 512;      // time bins of the reference-bin histogram
+constexpr float kSurDkClip = 4.0f;      // offset labels clipped to +-64 bins
 
 // Cell sizes: coarse cells (cw x ch pixels) tile the kernel's core box
 // (cells with K >= 2e-4 max K, half extents cm, cn) 16 x 16 times;
@@ -226,6 +228,7 @@ struct CoarseArgs {
     SurGeom g;
     float4* cell;               // [CH][CW] {mean depth, reflectance cover, mean gain, mean cos}
     float* cell_sun;            // [CH][CW] sum of sun shading
+    float* cell_shade;          // [CH][CW] sum of shade
 };
 struct SuperArgs {
     const int2* pix;            // pre-pass records [W4/4][H][4]
@@ -251,6 +254,7 @@ struct FeatArgs {
     int R;
     const float4* cell;
     const float* cell_sun;
+    const float* cell_shade;
     const float2* sup;
     const int2* range;
     const double* K64;

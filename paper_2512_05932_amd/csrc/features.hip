@@ -61,7 +61,7 @@ __global__ void k_coarse(CoarseArgs a)
     const int u0 = I * a.g.cw, v0 = J * a.g.ch;
     const int u1 = min(a.W, u0 + a.g.cw), v1 = min(a.H, v0 + a.g.ch);
     const float inv_pi = (float)(1.0 / kPi);
-    float sd = 0.0f, sr = 0.0f, sg = 0.0f, sc = 0.0f, ss = 0.0f;
+    float sd = 0.0f, sr = 0.0f, sg = 0.0f, sc = 0.0f, ss = 0.0f, sh = 0.0f;
     int nv = 0;
     for (int v = v0; v < v1; ++v) {
         const float4 rt = a.rowtab[v];
@@ -73,10 +73,13 @@ __global__ void k_coarse(CoarseArgs a)
             const float vx = rt.x * cs.x, vy = rt.x * cs.y, vz = rt.y;
             const float nx = a.nx[px], ny = a.ny[px], nz = a.nz[px];
             const float rho = a.refl[px];
+            const float gain = a.gain[px];
+            const float ct = fmaxf(0.0f, -(nx * vx + ny * vy + nz * vz));
             sd += d;
             sr += rho;
-            sg += a.gain[px];
-            sc += fmaxf(0.0f, -(nx * vx + ny * vy + nz * vz));
+            sg += gain;
+            sc += ct;
+            sh += rt.z * (gain * rho * inv_pi) * ct / (d * d);
             ss += rt.z * (rho * inv_pi) * fmaxf(0.0f, nx * a.sun_x + ny * a.sun_y + nz * a.sun_z);
             ++nv;
         }
@@ -85,6 +88,7 @@ __global__ void k_coarse(CoarseArgs a)
     const float inv = nv > 0 ? 1.0f / (float)nv : 0.0f;
     a.cell[c] = make_float4(sd * inv, sr / nall, sg * inv, sc * inv);
     a.cell_sun[c] = ss;
+    a.cell_shade[c] = sh;
 }
 
 // one wave per super-cell
@@ -125,6 +129,7 @@ __global__ void k_super(SuperArgs a)
 __global__ __launch_bounds__(256) void k_features(FeatArgs a)
 {
     __shared__ float tail[4][kSurTailBins];
+    __shared__ float refh[4][kSurRefWindow + 4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int b = blockIdx.x * 4 + wv;
     if (b >= a.B) return;                                  // whole wave
@@ -138,8 +143,10 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
 
     // the lane's 4 patch cells
     float4 rec[4];
-    float csun[4];
+    float csun[4], cshade[4];
     bool in[4];
+    int kc[4];                                             // candidate bins of the reference
+    float wc[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int q = lane + 64 * s;
@@ -147,32 +154,67 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
         in[s] = I >= 0 && I < g.CW && J >= 0 && J < g.CH;
         rec[s] = in[s] ? a.cell[(long)J * g.CW + I] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         csun[s] = in[s] ? a.cell_sun[(long)J * g.CW + I] : 0.0f;
-    }
-    // reference range: the beam pixel's depth, else the nearest cell mean
-    float r_ref = 0.0f;
-    bool centre = false;
-    if (u >= 0 && u < a.W && v >= 0 && v < a.H) {
-        const float d = a.depth[(long)v * a.pitch + u];
-        if (pixel_valid(d, a.to_bin, a.R)) {
-            r_ref = d;
-            centre = true;
+        cshade[s] = in[s] ? a.cell_shade[(long)J * g.CW + I] : 0.0f;
+        kc[s] = INT_MAX;
+        wc[s] = 0.0f;
+        const int m = floordiv(2 * I * g.cw + g.cw - 2 * u, 2);
+        const int n = floordiv(2 * J * g.ch + g.ch - 2 * v, 2);
+        if (in[s] && rec[s].x > 0.0f && abs(m) <= g.cm && abs(n) <= g.cn) {
+            const float w = (float)a.K64[(long)(n + a.N) * a.KW + (m + a.M)] * cshade[s];
+            if (w > 0.0f) {
+                kc[s] = (int)floor((double)rec[s].x * a.to_bin);
+                wc[s] = w;
+            }
         }
     }
-    if (!centre) {
+    // reference bin: first maximum of the (1, 2, 3, 2, 1)-smoothed histogram
+    // of K * shade over the core cells' time bins, in a window from the
+    // smallest; without core cells, the bin of the nearest cell mean depth
+    int kmin = INT_MAX;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) kmin = min(kmin, kc[s]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) kmin = min(kmin, __shfl_xor(kmin, o));
+    int k_ref = 0;
+    if (kmin != INT_MAX) {
+        float* hh = refh[wv];
+        for (int j = lane; j < kSurRefWindow + 4; j += 64) hh[j] = 0.0f;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (kc[s] != INT_MAX && kc[s] - kmin < kSurRefWindow) atomicAdd(&hh[kc[s] - kmin + 2], wc[s]);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        float best = -1.0f;
+        int bj = INT_MAX;
+        for (int q = 0; q < kSurRefWindow / 64; ++q) {
+            const int j = lane * (kSurRefWindow / 64) + q;
+            const float sm = hh[j] + 2.0f * hh[j + 1] + 3.0f * hh[j + 2] + 2.0f * hh[j + 3] + hh[j + 4];
+            if (sm > best) {
+                best = sm;
+                bj = j;
+            }
+        }
+        const float top = wave_maxf(best);
+        int jj = best == top ? bj : INT_MAX;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) jj = min(jj, __shfl_xor(jj, o));
+        k_ref = kmin + jj;
+    } else {
         float m = INFINITY;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
             if (rec[s].x > 0.0f) m = fminf(m, rec[s].x);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o));
-        r_ref = m < INFINITY ? m : 0.0f;
+        k_ref = m < INFINITY ? (int)floor((double)m * a.to_bin) : 0;
     }
-    const int k_ref = r_ref > 0.0f ? (int)floor((double)r_ref * a.to_bin) : 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int q = lane + 64 * s;
         const bool has = rec[s].x > 0.0f;
-        const float dk = has ? (float)(((double)rec[s].x - (double)r_ref) * a.to_bin / 64.0) : 1.0f;
+        const float dk = has ? (float)(((double)rec[s].x * a.to_bin - ((double)k_ref + 0.5)) / 64.0) : 1.0f;
         x[q] = to_bf16(fminf(1.0f, fmaxf(-1.0f, dk)));
         x[256 + q] = to_bf16(in[s] ? rec[s].y : 0.0f);
         x[512 + q] = to_bf16(has ? log10f(rec[s].z) / 3.0f : 0.0f);
@@ -254,7 +296,7 @@ __global__ void k_labels(const lidar_echo* echoes, const int32_t* counts, const 
         if (n <= e) break;
         const lidar_echo ec = echoes[(size_t)b * E + e];
         l[e] = 1.0f;
-        l[3 + e] = (float)(ec.bin_peak - aux[b].k_ref) / kSurBinScale;
+        l[3 + e] = fminf(kSurDkClip, fmaxf(-kSurDkClip, (float)(ec.bin_peak - aux[b].k_ref) / kSurBinScale));
         l[6 + e] = log10f(fmaxf(ec.intensity, 1e-3f * T) / T);
         l[9 + e] = ec.pulse_width_ns / 4.0f;
     }

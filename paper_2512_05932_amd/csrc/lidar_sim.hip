@@ -69,7 +69,7 @@ struct FrameState {
     SurGeom geom{};
     bool geom_ok = false;
     DevBuf<float4> d_cell;
-    DevBuf<float> d_cell_sun;
+    DevBuf<float> d_cell_sun, d_cell_shade;
     DevBuf<float2> d_sup;
     DevBuf<int2> d_range;
 };
@@ -635,6 +635,7 @@ lidar_status sur_geometry(lidar_sim* h, FrameState& fs)
     g.SH = (H + g.sh - 1) / g.sh;
     HIP_TRY(h, fs.d_cell.ensure((size_t)g.CW * g.CH), "allocate coarse cells");
     HIP_TRY(h, fs.d_cell_sun.ensure((size_t)g.CW * g.CH), "allocate coarse cells");
+    HIP_TRY(h, fs.d_cell_shade.ensure((size_t)g.CW * g.CH), "allocate coarse cells");
     HIP_TRY(h, fs.d_sup.ensure((size_t)g.SW * g.SH), "allocate super-cells");
     HIP_TRY(h, fs.d_range.ensure((size_t)g.SW * g.SH), "allocate super-cells");
     fs.geom = g;
@@ -673,6 +674,7 @@ lidar_status sur_inputs(lidar_sim* h, FrameState& fs, uint16_t* X)
     ca.g = fs.geom;
     ca.cell = fs.d_cell.p;
     ca.cell_sun = fs.d_cell_sun.p;
+    ca.cell_shade = fs.d_cell_shade.p;
     HIP_TRY(h, launch_coarse(s, ca), "coarse cells launch");
     SuperArgs sa;
     sa.pix = fs.d_pix.p;
@@ -696,6 +698,7 @@ lidar_status sur_inputs(lidar_sim* h, FrameState& fs, uint16_t* X)
     fa.R = ca.R;
     fa.cell = fs.d_cell.p;
     fa.cell_sun = fs.d_cell_sun.p;
+    fa.cell_shade = fs.d_cell_shade.p;
     fa.sup = fs.d_sup.p;
     fa.range = fs.d_range.p;
     fa.K64 = fs.d_K64.p;

@@ -143,6 +143,7 @@ __global__ void k_loss(const float* Y, const float* lab, long n, float inv_n, ui
             const bool te = ex > 0.5f;
             ok = ok && ((y[e] > 0.0f) == te);
             ok = ok && !(te && fabsf(y[3 + e] - l[3 + e]) * kSurBinScale > 0.5f);
+            ok = ok && !(te && fabsf(l[3 + e]) >= kSurDkClip);
             L += bce(y[e], ex);
             d[e] = sigm(y[e]) - ex;
             const float dk = y[3 + e] - l[3 + e];
