@@ -294,9 +294,24 @@ hipError_t launch_decode(hipStream_t s, const DecodeArgs& a);
 hipError_t launch_compact(hipStream_t s, const CompactArgs& a);
 hipError_t launch_aux_out(hipStream_t s, const SurAux* aux, int B, float* out);
 
+// fused inference: X [n][1056] BF16 -> Y [n][16] FP32, transposed BF16
+// weights Wt1 [256][1056], Wt2, Wt3 [256][256], Wt4 [16][256]
+struct InferArgs {
+    const uint16_t* X;
+    long n;
+    const uint16_t *Wt1, *Wt2, *Wt3, *Wt4;
+    const float *b1, *b2, *b3, *b4;
+    float* Y;
+};
+constexpr long kSurWtSize = (long)kSurIn * kSurHid + 2L * kSurHid * kSurHid + (long)kSurHid * kSurOut;
+hipError_t launch_transpose_weights(hipStream_t s, const uint16_t* theta_b, uint16_t* wt);
+hipError_t launch_mlp_infer(hipStream_t s, const InferArgs& a);
+
 struct SurNet {
     DevBuf<float> theta, m, v, grad;    // FP32 [kSurParams]
     DevBuf<uint16_t> theta_b;           // BF16 operand copy
+    DevBuf<uint16_t> theta_t;           // transposed BF16 weights [kSurWtSize]
+    bool t_stale = true;
     long step = 0;
     bool ready = false;
 };
@@ -306,8 +321,11 @@ struct SurWork {                        // activations of up to `cap` rows
     DevBuf<uint16_t> H1, H2, H3, dYb, dZb;
     hipError_t ensure(long n);
 };
-// Y (w.Y, [n][16] FP32) of the rows X ([n][1056] BF16)
+// Y (w.Y, [n][16] FP32) of the rows X ([n][1056] BF16), keeping the
+// activations for the backward pass
 hipError_t sur_forward(hipStream_t s, const SurNet& net, const uint16_t* X, long n, SurWork& w);
+// Y ([n][16] FP32) of the rows X by the fused kernel (activations in LDS)
+hipError_t sur_infer(hipStream_t s, SurNet& net, const uint16_t* X, long n, float* Y);
 // loss (added into w.loss[0]) and parameter gradient (net.grad) of rows X
 // with labels lab ([n][16]); runs the forward pass first
 hipError_t sur_gradients(hipStream_t s, SurNet& net, const uint16_t* X, const float* lab, long n,

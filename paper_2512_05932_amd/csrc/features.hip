@@ -236,7 +236,8 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
     const int J0 = max(0, floordiv(v - a.N, g.sh)), J1 = min(g.SH - 1, floordiv(v + a.N, g.sh));
     const int nI = I1 - I0 + 1, nJ = J1 - J0 + 1;
     const int nb = (a.R + kSurTailBins - 1) / kSurTailBins;
-    if (nI > 0 && nJ > 0) {
+    // (no super-cell lies outside a core box that spans the whole window)
+    if (nI > 0 && nJ > 0 && (g.cm < a.M || g.cn < a.N)) {
         for (int q = lane; q < nI * nJ; q += 64) {
             const int Is = I0 + q % nI, Js = J0 + q / nI;
             const int m = floordiv(2 * Is * g.sw + g.sw - 2 * u, 2);

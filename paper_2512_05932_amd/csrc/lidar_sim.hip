@@ -1126,7 +1126,7 @@ static lidar_status simulate_surrogate(lidar_sim* h)
         HIP_TRY(h, hipEventRecord(ev.a, s), "record event");
     }
     LIDAR_TRY(sur_inputs(h, fs, h->s_X.p));
-    HIP_TRY(h, sur_forward(s, h->net, h->s_X.p, B, h->work), "surrogate forward");
+    HIP_TRY(h, sur_infer(s, h->net, h->s_X.p, B, h->work.Y.p), "surrogate forward");
     HIP_TRY(h, launch_reset_queue(s, h->s_cnt.p, 2), "counter reset");
     DecodeArgs da;
     da.Y = h->work.Y.p;
@@ -1328,6 +1328,7 @@ lidar_status lidar_sim_surrogate_set_weights(lidar_sim* h, const float* params, 
     HIP_TRY(h, launch_to_bf16(s, n.theta.p, n.theta_b.p, (long)P), "weight copy");
     HIP_TRY(h, hipStreamSynchronize(s), "weights synchronise");
     n.step = 0;
+    n.t_stale = true;
     n.ready = true;
     return LIDAR_OK;
 }
@@ -1356,9 +1357,7 @@ lidar_status lidar_sim_surrogate_forward(lidar_sim* h, const void* x, float* y, 
 {
     if (!h) return LIDAR_E_INVALID;
     LIDAR_TRY(sur_check(h, x, y, n));
-    HIP_TRY(h, sur_forward(h->stream, h->net, (const uint16_t*)x, (long)n, h->work), "surrogate forward");
-    HIP_TRY(h, hipMemcpyAsync(y, h->work.Y.p, (size_t)n * kSurOut * sizeof(float),
-                              hipMemcpyDeviceToDevice, h->stream), "copy outputs");
+    HIP_TRY(h, sur_infer(h->stream, h->net, (const uint16_t*)x, (long)n, y), "surrogate forward");
     return LIDAR_OK;
 }
 
@@ -1406,6 +1405,7 @@ lidar_status lidar_sim_surrogate_train_step(lidar_sim* h, const void* x, const f
     a.inv_bc2 = (float)(1.0 / (1.0 - std::pow(hp->beta2, (double)t)));
     HIP_TRY(h, launch_adamw(h->stream, net.theta.p, net.grad.p, net.m.p, net.v.p, net.theta_b.p,
                             kSurParams, a), "AdamW launch");
+    net.t_stale = true;
     if (loss)
         HIP_TRY(h, hipMemcpyAsync(loss, h->work.loss.p, sizeof(float), hipMemcpyDeviceToDevice,
                                   h->stream), "copy loss");

@@ -221,9 +221,146 @@ __global__ void k_to_bf16(const float* x, uint16_t* y, long n)
     if (i < n) y[i] = to_bf16(x[i]);
 }
 
+// BF16 operand copies transposed to [out][in] (inputs contiguous) for the
+// fused inference kernel.
+__global__ void k_transpose_bf16(const uint16_t* W, int in, int out, uint16_t* Wt)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)in * out) return;
+    const int k = (int)(i / out), n = (int)(i % out);
+    Wt[(long)n * in + k] = W[i];
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kInfRows = 64;                 // rows (beams) per workgroup
+constexpr int kInfK = 32;                    // K step
+constexpr int kInfLdsK = kInfK + 8;          // staged row stride (elements)
+constexpr int kInfH = kSurHid + 8;           // activation row stride (elements)
+
+__device__ inline bf16x8 ld8(const uint16_t* p) { return *(const bf16x8*)p; }
+
+// One hidden layer for a 64-row tile: out[64][256] = A[64][K] W (W^T given
+// as Wt [256][K]); wave w computes columns 64 w .. 64 w + 63 with 4 x 4
+// blocks of v_mfma_f32_16x16x32_bf16.  A comes from global memory (X,
+// staged through LDS) or from the activation buffer H in LDS.  On return
+// acc holds the FP32 products; every read of A is complete.
+template <bool A_GLOBAL>
+__device__ inline void infer_layer(const uint16_t* Ag, long row0, long n, const uint16_t* H,
+                                   const uint16_t* Wt, int K, uint16_t (*As)[kInfLdsK],
+                                   uint16_t (*Bs)[kInfLdsK], f32x4 (&acc)[4][4])
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int kq = 8 * (lane >> 4);
+    for (int k0 = 0; k0 < K; k0 += kInfK) {
+        // stage: B tile 256 x 32 (4 chunks of 8 per thread), A tile 64 x 32
+#pragma unroll
+        for (int c = 0; c < 4; ++c) *(bf16x8*)&Bs[tid][8 * c] = ld8(Wt + (long)tid * K + k0 + 8 * c);
+        if (A_GLOBAL) {
+            const int r = tid >> 2, c = tid & 3;
+            const long row = row0 + r;
+            bf16x8 v = {};
+            if (row < n) v = ld8(Ag + row * kSurIn + k0 + 8 * c);
+            *(bf16x8*)&As[r][8 * c] = v;
+        }
+        __syncthreads();
+        bf16x8 a[4], b[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int r = t * 16 + (lane & 15);
+            a[t] = A_GLOBAL ? *(const bf16x8*)&As[r][kq] : *(const bf16x8*)&H[r * kInfH + k0 + kq];
+            b[t] = *(const bf16x8*)&Bs[wave * 64 + t * 16 + (lane & 15)][kq];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+}
+
+// bias + GELU of a layer's products into H (BF16), in place
+__device__ inline void infer_store(const f32x4 (&acc)[4][4], const float* bias, uint16_t* H)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = wave * 64 + j * 16 + (lane & 15);
+            const float bc = bias[col];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = i * 16 + 4 * (lane >> 4) + r;
+                H[row * kInfH + col] = to_bf16(gelu(acc[i][j][r] + bc));
+            }
+        }
+}
+
+// The whole network for 64 rows per workgroup; activations stay in LDS.
+__global__ __launch_bounds__(256) void k_mlp_infer(InferArgs a)
+{
+    __shared__ uint16_t H[kInfRows * kInfH];
+    __shared__ uint16_t As[kInfRows][kInfLdsK];
+    __shared__ uint16_t Bs[kSurHid][kInfLdsK];
+    const long row0 = (long)blockIdx.x * kInfRows;
+    f32x4 acc[4][4];
+    infer_layer<true>(a.X, row0, a.n, H, a.Wt1, kSurIn, As, Bs, acc);
+    infer_store(acc, a.b1, H);
+    __syncthreads();
+    infer_layer<false>(nullptr, row0, a.n, H, a.Wt2, kSurHid, As, Bs, acc);
+    infer_store(acc, a.b2, H);
+    __syncthreads();
+    infer_layer<false>(nullptr, row0, a.n, H, a.Wt3, kSurHid, As, Bs, acc);
+    infer_store(acc, a.b3, H);
+    __syncthreads();
+    // output layer: wave w takes rows 16 w .. 16 w + 15, all 16 outputs
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = 8 * (lane >> 4);
+    f32x4 y = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < kSurHid; k0 += kInfK) {
+        const bf16x8 av = *(const bf16x8*)&H[(wave * 16 + (lane & 15)) * kInfH + k0 + kq];
+        const bf16x8 bv = ld8(a.Wt4 + (long)(lane & 15) * kSurHid + k0 + kq);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, y, 0, 0, 0);
+    }
+    const int col = lane & 15;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const long row = row0 + wave * 16 + 4 * (lane >> 4) + r;
+        if (row < a.n) a.Y[row * kSurOut + col] = y[r] + a.b4[col];
+    }
+}
+
 inline unsigned blocks(long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+hipError_t launch_transpose_weights(hipStream_t s, const uint16_t* theta_b, uint16_t* wt)
+{
+    struct L { long off, toff; int in, out; };
+    const L ls[4] = {{kSurOffW1, 0, kSurIn, kSurHid},
+                     {kSurOffW2, (long)kSurIn * kSurHid, kSurHid, kSurHid},
+                     {kSurOffW3, (long)kSurIn * kSurHid + (long)kSurHid * kSurHid, kSurHid, kSurHid},
+                     {kSurOffW4, (long)kSurIn * kSurHid + 2L * kSurHid * kSurHid, kSurHid, kSurOut}};
+    for (const L& l : ls) {
+        const long n = (long)l.in * l.out;
+        hipLaunchKernelGGL(k_transpose_bf16, dim3(blocks(n, 256)), dim3(256), 0, s, theta_b + l.off,
+                           l.in, l.out, wt + l.toff);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(hipStream_t s, const InferArgs& a)
+{
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks(a.n, kInfRows)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g)
 {
@@ -334,6 +471,29 @@ hipError_t sur_forward(hipStream_t s, const SurNet& net, const uint16_t* X, long
     TRY(dense(s, w.H3.p, kSurHid, Wb + kSurOffW4, kSurOut, n, w.Y.p));
     TRY(launch_bias(s, w.Y.p, th + kSurOffB4, n, kSurOut));
     return hipSuccess;
+}
+
+hipError_t sur_infer(hipStream_t s, SurNet& net, const uint16_t* X, long n, float* Y)
+{
+    TRY(net.theta_t.ensure(kSurWtSize));
+    if (net.t_stale) {
+        TRY(launch_transpose_weights(s, net.theta_b.p, net.theta_t.p));
+        net.t_stale = false;
+    }
+    const uint16_t* t = net.theta_t.p;
+    InferArgs a;
+    a.X = X;
+    a.n = n;
+    a.Wt1 = t;
+    a.Wt2 = t + (long)kSurIn * kSurHid;
+    a.Wt3 = a.Wt2 + (long)kSurHid * kSurHid;
+    a.Wt4 = a.Wt3 + (long)kSurHid * kSurHid;
+    a.b1 = net.theta.p + kSurOffB1;
+    a.b2 = net.theta.p + kSurOffB2;
+    a.b3 = net.theta.p + kSurOffB3;
+    a.b4 = net.theta.p + kSurOffB4;
+    a.Y = Y;
+    return launch_mlp_infer(s, a);
 }
 
 // dW = A^T D (A [n][in] BF16 activations, D [n][out] BF16), db = column sums

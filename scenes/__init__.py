@@ -565,3 +565,24 @@ def random_surrogate_labels(seed: int, n: int) -> np.ndarray:
     lab[:, 3:12] = (rng.standard_normal((n, 9)) * 0.5).astype(np.float32)
     lab[:, 3:12] *= np.tile(lab[:, :3], 3)
     return lab
+
+
+# ----------------------------------------------------------------------------
+# Workloads 4 and 5: frames for the surrogate (training data and inference)
+# ----------------------------------------------------------------------------
+
+def surrogate_frame(seed: int, pattern: str = "gauss", n_lines: int = 64,
+                    n_cols: int = 2000) -> Workload:
+    """A scanning-sensor scene (8192x512 px over 145 x 3.2 deg, road + 24
+    boxes, 1 % retroreflective patches) scanned by n_lines x n_cols beams.
+    pattern "gauss": Gaussian beams with the scanning pattern's core (sigma
+    0.0425 x 0.34 deg, cut at 3 sigma) and the batch workload's sensor
+    (constant ambient, no sun); "table": the tabulated pattern with its 1e-4
+    tails and the scanning sensor's parameters (sun floor)."""
+    w = config2(seed, n_lines=n_lines, n_cols=n_cols)
+    if pattern == "table":
+        return replace(w, name=f"surrogate-scan-{n_lines}x{n_cols}-table256")
+    pat = Pattern(PATTERN_GAUSS, w.pattern.beam_az, w.pattern.beam_el,
+                  sigma_deg=(0.0425, 0.34), trunc_sigmas=3.0)
+    return replace(w, pattern=pat, params=config3_params(),
+                   name=f"surrogate-scan-{n_lines}x{n_cols}-gauss")
