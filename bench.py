@@ -50,6 +50,12 @@ def parse():
     ap.add_argument("--batch-only", action="store_true",
                     help="only measure the 64-frame batch (for profiler runs)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate training and inference measurement")
+    ap.add_argument("--surrogate-only", action="store_true")
+    ap.add_argument("--sur-train-frames", type=int, default=16)
+    ap.add_argument("--sur-steps", type=int, default=3000)
+    ap.add_argument("--sur-eval-frames", type=int, default=4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the "
                          "reference for scaling the HBM byte counters")
@@ -218,6 +224,119 @@ def batch_report(args):
             "setup_s": setup_s, "autotune_ms": info["autotune_ms"], "generate_s": gen_s}
 
 
+SUR_FLOPS_PER_BEAM = 2 * (1056 * 256 + 2 * 256 * 256 + 256 * 16)   # the network's products
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def surrogate_report(args, pattern="gauss", train_frames=None, steps=None, eval_frames=None,
+                     oracle_sample=2000):
+    """Surrogate on scanning frames (road + boxes, 8192x512, 64 x 2000 = 128k
+    beams): the network is trained from scratch by the library's kernels on
+    the plain path's echoes of ``train_frames`` frames (AdamW, batch 4096),
+    then held-out frames are simulated in plain and in surrogate mode (gate
+    c_min = 0.95, alpha = 0.5) with the G-buffers resident; reported: both
+    times, speed-up, fallback fraction, agreement within one bin with the
+    plain path (all beams) and with the FP64 oracle (a beam sample)."""
+    import numpy as np
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    import scenes
+    import paper_2512_05932_amd as lidar
+    from paper_2512_05932_amd import surrogate as sur
+    train_frames = train_frames or args.sur_train_frames
+    steps = steps or args.sur_steps
+    eval_frames = eval_frames or args.sur_eval_frames
+    seeds = [1000 + i for i in range(train_frames)] + [args.seed + i for i in range(eval_frames)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(16) as ex:
+        ws = list(ex.map(lambda s: scenes.surrogate_frame(s, pattern), seeds))
+    gen_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    sim = lidar.LidarSim(ws[0].params, stream=stream, profile=True)
+    planes = [lidar.upload_gbuffer(w.gbuffer, "cuda:0") for w in ws]
+    t0 = time.perf_counter()
+    X, L = sur.make_dataset(sim, [(w.gbuffer.raster, p, w.pattern)
+                                  for w, p in zip(ws[:train_frames], planes)])
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    sim.set_weights(scenes.surrogate_init(0))
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    losses = sur.train(sim, X, L, steps, batch=4096, lr=2e-3, log_every=max(1, steps // 5))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    train_ms = ev0.elapsed_time(ev1)
+    n_rows = int(X.shape[0])
+    del X, L
+    sim.set_gate(0.95, 0.5)
+    res = []
+    oracle_agree = None
+    for w, p in zip(ws[train_frames:], planes[train_frames:]):
+        sim.set_pattern(w.pattern)
+        sim.set_gbuffer(w.gbuffer.raster, p)
+        times = {}
+        outs = {}
+        for mode in (lidar.LIDAR_MODE_PLAIN, lidar.LIDAR_MODE_SURROGATE):
+            for _ in range(2):
+                sim.simulate_frame(mode)
+            torch.cuda.synchronize()
+            sim.reset_stats()
+            ev0.record(stream)
+            for _ in range(10):
+                sim.simulate_frame(mode)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            times[mode] = ev0.elapsed_time(ev1) / 10
+            outs[mode] = sim.read()
+            st = sim.stats()
+        ag = sur.echo_agreement(outs[lidar.LIDAR_MODE_PLAIN], outs[lidar.LIDAR_MODE_SURROGATE])
+        res.append({"seed": w.meta["seed"], "plain_ms": times[lidar.LIDAR_MODE_PLAIN],
+                    "surrogate_ms": times[lidar.LIDAR_MODE_SURROGATE],
+                    "fallback": st["fallback_beams"] / max(1, st["surrogate_beams"]),
+                    "within_1_bin_vs_plain": ag["within_1_bin"]})
+        if oracle_agree is None and oracle_sample:
+            import oracle
+            idx = np.sort(np.random.default_rng(3).choice(w.pattern.n_beams, oracle_sample,
+                                                          replace=False))
+            ref = oracle.simulate(w.gbuffer, scenes.subset_beams(w, idx).pattern, w.params,
+                                  want_xi=False, want_xi_hat=False)
+            got = outs[lidar.LIDAR_MODE_SURROGATE]
+            oracle_agree = sur.echo_agreement(
+                {"n_echoes": ref.n_echoes, "echoes": ref.echoes},
+                {"n_echoes": got["n_echoes"][idx], "echoes": got["echoes"][idx]})["within_1_bin"]
+    # the fused network kernel alone, on the last frame's inputs
+    B = ws[-1].pattern.n_beams
+    xin = torch.empty((B, 1056), dtype=torch.int16, device="cuda")
+    yout = torch.empty((B, 16), dtype=torch.float32, device="cuda")
+    sim.surrogate_features(xin)
+    sim.surrogate_forward(xin, yout)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(10):
+        sim.surrogate_forward(xin, yout)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    mlp_ms = ev0.elapsed_time(ev1) / 10
+    sim.close()
+    del planes
+    torch.cuda.empty_cache()
+    tp = float(np.mean([r["plain_ms"] for r in res]))
+    ts = float(np.mean([r["surrogate_ms"] for r in res]))
+    mlp_tflops = SUR_FLOPS_PER_BEAM * B / (mlp_ms * 1e-3) / 1e12
+    return {"workload": ws[-1].name, "beams_per_frame": B, "pattern": pattern,
+            "train_frames": train_frames, "train_rows": n_rows, "train_steps": steps,
+            "batch": 4096, "train_ms": train_ms, "train_rows_per_s": steps * 4096 / (train_ms * 1e-3),
+            "losses": losses, "gate": {"c_min": 0.95, "alpha": 0.5},
+            "eval": res, "plain_ms": tp, "surrogate_ms": ts, "speedup": tp / ts,
+            "beams_per_s_surrogate": B / (ts * 1e-3), "beams_per_s_plain": B / (tp * 1e-3),
+            "fallback": float(np.mean([r["fallback"] for r in res])),
+            "within_1_bin_vs_plain": float(np.min([r["within_1_bin_vs_plain"] for r in res])),
+            "within_1_bin_vs_oracle": oracle_agree, "oracle_sample_beams": oracle_sample,
+            "mlp_ms": mlp_ms, "mlp_tflops": mlp_tflops, "mlp_frac_bf16_peak": mlp_tflops / BF16_PEAK_TFLOPS,
+            "generate_s": gen_s, "dataset_s": data_s}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -238,6 +357,12 @@ def main():
     torch.cuda.set_device(0)
     if args.batch_only:
         print(json.dumps({"batch": batch_report(args)}), flush=True)
+        return
+    if args.surrogate_only:
+        print(json.dumps({"surrogate": surrogate_report(args),
+                          "surrogate_table_pattern": surrogate_report(
+                              args, "table", train_frames=8, steps=1500, eval_frames=1,
+                              oracle_sample=0)}), flush=True)
         return
     w = scenes.config2(args.seed)
     stream = torch.cuda.current_stream()
@@ -293,6 +418,11 @@ def main():
     }
     if not args.no_batch:
         rec["batch"] = batch_report(args)
+    if not args.no_surrogate:
+        rec["surrogate"] = surrogate_report(args)
+        rec["surrogate_table_pattern"] = surrogate_report(args, "table", train_frames=8,
+                                                          steps=1500, eval_frames=1,
+                                                          oracle_sample=0)
     if not args.no_cpu_baseline:
         rec["precision"] = precision_report(w, planes)
         rec["cpu_baseline"] = cpu_baseline(w)

@@ -184,6 +184,7 @@ struct GemmArgs {
     float* C;
     long ldc;
     int M, N, K;
+    int ksplit;                 // > 1: K split over grid.z, added into a zeroed C
 };
 struct AdamArgs {
     float lr, beta1, beta2, eps;

@@ -47,14 +47,17 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
     // load mapping: consecutive threads walk the operand's unit-stride axis
     const bool a_kfast = g.sak == 1;
     const bool b_kfast = g.sbk == 1;
-    for (int k0 = 0; k0 < g.K; k0 += kTileK) {
+    // this workgroup's share of K (whole tiles)
+    const int kchunk = ((g.K + g.ksplit - 1) / g.ksplit + kTileK - 1) / kTileK * kTileK;
+    const int kbeg = blockIdx.z * kchunk, kend = min(g.K, kbeg + kchunk);
+    for (int k0 = kbeg; k0 < kend; k0 += kTileK) {
 #pragma unroll
         for (int q = 0; q < (kTileM * kTileK) / 256; ++q) {
             const int e = tid + 256 * q;
             const int r = a_kfast ? e / kTileK : e % kTileM;
             const int k = a_kfast ? e % kTileK : e / kTileM;
             const int gi = m0 + r, gk = k0 + k;
-            As[r][k] = (gi < g.M && gk < g.K) ? g.A[(long)gi * g.sam + (long)gk * g.sak] : (uint16_t)0;
+            As[r][k] = (gi < g.M && gk < kend) ? g.A[(long)gi * g.sam + (long)gk * g.sak] : (uint16_t)0;
         }
 #pragma unroll
         for (int q = 0; q < (kTileN * kTileK) / 256; ++q) {
@@ -62,7 +65,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
             const int c = b_kfast ? e / kTileK : e % kTileN;
             const int k = b_kfast ? e % kTileK : e / kTileN;
             const int gj = n0 + c, gk = k0 + k;
-            Bs[c][k] = (gj < g.N && gk < g.K) ? g.B[(long)gk * g.sbk + (long)gj * g.sbn] : (uint16_t)0;
+            Bs[c][k] = (gj < g.N && gk < kend) ? g.B[(long)gk * g.sbk + (long)gj * g.sbn] : (uint16_t)0;
         }
         __syncthreads();
 #pragma unroll
@@ -91,7 +94,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
-                if (row < g.M && col < g.N) g.C[(long)row * g.ldc + col] = acc[i][j][r];
+                if (row < g.M && col < g.N) {
+                    if (g.ksplit > 1)
+                        atomicAdd(&g.C[(long)row * g.ldc + col], acc[i][j][r]);
+                    else
+                        g.C[(long)row * g.ldc + col] = acc[i][j][r];
+                }
             }
         }
 }
@@ -179,14 +187,21 @@ __global__ void k_gelu_back(const float* dH, const float* Z, uint16_t* dZb, long
     dZb[i] = to_bf16(dH[i] * gelu_prime(Z[i]));
 }
 
-// db[j] = sum over rows of the BF16 operand dZ[r][j]
-__global__ void k_colsum(const uint16_t* D, long n, int C, float* out)
+// db[j] += sum over rows of the BF16 operand dZ[r][j]: a workgroup takes 64
+// columns x 256 rows (lane = column, wave = every 4th row), sums its waves in
+// LDS and adds into the zeroed output
+__global__ __launch_bounds__(256) void k_colsum(const uint16_t* D, long n, int C, float* out)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= C) return;
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
+    const long r0 = (long)blockIdx.y * 256;
     float s = 0.0f;
-    for (long r = 0; r < n; ++r) s += from_bf16(D[r * C + j]);
-    out[j] = s;
+    if (j < C)
+        for (long r = r0 + wave; r < min(n, r0 + 256); r += 4) s += from_bf16(D[r * C + j]);
+    part[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && j < C) atomicAdd(&out[j], part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
 }
 
 __global__ void k_zero_f32(float* p, long n)
@@ -362,10 +377,20 @@ hipError_t launch_mlp_infer(hipStream_t s, const InferArgs& a)
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g)
+hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g0)
 {
-    if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    dim3 grid((g.N + kTileN - 1) / kTileN, (g.M + kTileM - 1) / kTileM);
+    if (g0.M <= 0 || g0.N <= 0) return hipSuccess;
+    GemmArgs g = g0;
+    const long tiles = (long)((g.N + kTileN - 1) / kTileN) * ((g.M + kTileM - 1) / kTileM);
+    // few output tiles and a long K (weight gradients): split K over the grid
+    g.ksplit = 1;
+    while (tiles * g.ksplit < 512 && g.K / (g.ksplit * 2) >= 4 * kTileK) g.ksplit *= 2;
+    if (g.ksplit > 1) {
+        if (g.ldc != g.N) return hipErrorInvalidValue;   // split K needs a dense C to zero
+        const hipError_t e = launch_zero_f32(s, g.C, (long)g.M * g.N);
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid((g.N + kTileN - 1) / kTileN, (g.M + kTileM - 1) / kTileM, g.ksplit);
     hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
@@ -402,7 +427,9 @@ hipError_t launch_gelu_back(hipStream_t s, const float* dH, const float* Z, uint
 
 hipError_t launch_colsum(hipStream_t s, const uint16_t* D, long n, int C, float* out)
 {
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(C, 64)), dim3(64), 0, s, D, n, C, out);
+    hipError_t e = launch_zero_f32(s, out, C);
+    if (e != hipSuccess || n == 0) return e;
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(C, 64), blocks(n, 256)), dim3(256), 0, s, D, n, C, out);
     return hipGetLastError();
 }
 
@@ -454,7 +481,7 @@ hipError_t SurWork::ensure(long n)
 static hipError_t dense(hipStream_t s, const uint16_t* A, int k, const uint16_t* W, int c, long n,
                         float* Z)
 {
-    GemmArgs g{A, k, 1, W, c, 1, Z, c, (int)n, c, k};
+    GemmArgs g{A, k, 1, W, c, 1, Z, c, (int)n, c, k, 1};
     return launch_gemm_bf16(s, g);
 }
 
@@ -500,7 +527,7 @@ hipError_t sur_infer(hipStream_t s, SurNet& net, const uint16_t* X, long n, floa
 static hipError_t weight_grad(hipStream_t s, const uint16_t* A, int in, const uint16_t* D, int out,
                               long n, float* dW, float* db)
 {
-    GemmArgs g{A, 1, in, D, out, 1, dW, out, in, out, (int)n};
+    GemmArgs g{A, 1, in, D, out, 1, dW, out, in, out, (int)n, 1};
     TRY(launch_gemm_bf16(s, g));
     return launch_colsum(s, D, n, out, db);
 }
@@ -509,7 +536,7 @@ static hipError_t weight_grad(hipStream_t s, const uint16_t* A, int in, const ui
 static hipError_t input_grad(hipStream_t s, const uint16_t* D, int out, const uint16_t* W, int in,
                              long n, float* dH)
 {
-    GemmArgs g{D, out, 1, W, 1, out, dH, in, (int)n, in, out};
+    GemmArgs g{D, out, 1, W, 1, out, dH, in, (int)n, in, out, 1};
     return launch_gemm_bf16(s, g);
 }
 
