@@ -128,3 +128,64 @@ def test_initial_weights_layout():
     p = S.unpack(flat)
     assert np.all(p["W1"][S.IN_USED:] == 0) and np.all(p["W4"][:, S.OUT_USED:] == 0)
     assert abs(p["W1"][:S.IN_USED].std() * math.sqrt(S.IN_USED) - 1.0) < 0.01
+
+
+# ---- the surrogate's inputs (oracle) against closed forms -------------------
+
+def _shell_inputs(depth=40.0, rho=0.6, sun=0.0):
+    import oracle as O
+    r = scenes.Raster(96, 64, -12.0, 12.0, -8.0, 8.0)
+    gb = scenes.shell_gbuffer(r, depth, rho)
+    az = np.array([0.0, 3.3, -5.1])
+    el = np.array([0.0, 1.7, -2.2])
+    pat = scenes.Pattern(scenes.PATTERN_GAUSS, az, el, sigma_deg=(0.5, 0.4), trunc_sigmas=3.0)
+    p = scenes.SensorParams(n_bins=512, bin_ns=1.0, max_echoes=3, threshold=1e-5, emit_power=1.0,
+                            pulse_fwhm_ns=4.0, pulse_trunc_sigmas=4.0, ambient_const=1e-7,
+                            sun_irradiance=sun, sun_dir=(-1.0, 0.0, 0.0))
+    O._load()
+    K = O.kernel_grid(r, pat)
+    ref = O.simulate(gb, pat, p, want_xi=False)
+    out = S.features(gb, pat, p, K, ref.pixel, ref.scale, lambda v: O.row_solid_angle(r, v))
+    return gb, pat, p, ref, out
+
+
+def test_inputs_of_a_constant_range_shell():
+    """Every pixel at 40 m facing the sensor: cell means are the shell's
+    values, the reference bin is the shell's bin, the first channel is the
+    offset of the shell's depth from that bin's centre, there is no tail
+    (the 3-sigma Gaussian's core box spans its window)."""
+    gb, pat, p, ref, (X, kref, et, ae, geo) = _shell_inputs()
+    to_bin = 2.0 / (299792458.0 * 1e-9)
+    k = math.floor(np.float32(40.0) * to_bin)
+    assert np.all(kref == k)
+    np.testing.assert_allclose(X[:, :256], (40.0 * to_bin - (k + 0.5)) / 64.0, rtol=1e-12)
+    np.testing.assert_allclose(X[:, 256:512], np.float32(0.6), rtol=1e-6)     # reflectance cover
+    np.testing.assert_allclose(X[:, 512:768], 0.0, atol=1e-15)                # log10(g = 1)
+    np.testing.assert_allclose(X[:, 768:1024], 1.0, atol=1e-6)                # cos(theta)
+    np.testing.assert_allclose(X[:, 1029], k / 512.0)
+    assert np.all(et == 0.0)
+    np.testing.assert_allclose(ae, 1e-7)                                      # no sun
+
+
+def test_floor_estimate_of_a_sunlit_shell():
+    """With the sun behind the sensor the shell's sun floor is E_sun (rho/pi)
+    sum K Omega (n.s) / max K; the coarse-cell estimate (kernel at cell
+    centres) must agree with the plain oracle's exact floor to 2 %."""
+    gb, pat, p, ref, (X, kref, et, ae, geo) = _shell_inputs(sun=0.5)
+    inside = ref.samples > 0
+    np.testing.assert_allclose(ae[inside], ref.floor[inside], rtol=0.02)
+
+
+def test_labels_closed_form():
+    echoes = np.zeros((2, 3), dtype=[("bin_peak", "i4"), ("intensity", "f8"),
+                                     ("pulse_width_ns", "f8")])
+    echoes["bin_peak"] = [[100, 300, 0], [5, 0, 0]]
+    echoes["intensity"] = [[2e-5, 1e-9, 0], [1e-5, 0, 0]]
+    echoes["pulse_width_ns"] = [[4.0, 8.0, 0], [2.0, 0, 0]]
+    p = scenes.SensorParams(n_bins=512, bin_ns=1.0, max_echoes=3, threshold=1e-5, emit_power=1.0,
+                            pulse_fwhm_ns=4.0)
+    lab = S.labels(np.array([96, 5]), echoes, np.array([2, 5]), p)
+    np.testing.assert_allclose(lab[0], [1, 1, 0, 0.25, 4.0, 0, math.log10(2.0), -3.0, 0,
+                                        1.0, 2.0, 0, 0, 0, 0, 0])
+    # more echoes than stored: existence only for the three slots
+    np.testing.assert_allclose(lab[1, :3], [1, 1, 1])
