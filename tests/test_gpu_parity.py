@@ -245,8 +245,11 @@ def test_error_paths_on_device():
     planes = lidar.upload_gbuffer(w.gbuffer)
     sim.set_gbuffer(w.gbuffer.raster, planes)
     with pytest.raises(lidar.LidarError) as e:
-        sim.simulate_frame(mode=1)
+        sim.simulate_frame(mode=7)
     assert e.value.status == lidar.LIDAR_E_UNSUPPORTED
+    with pytest.raises(lidar.LidarError) as e:
+        sim.simulate_frame(mode=lidar.LIDAR_MODE_SURROGATE)      # no weights yet
+    assert e.value.status == lidar.LIDAR_E_STATE
     sim.simulate_frame()
     with pytest.raises(lidar.LidarError) as e:
         sim.read(waveforms=True)
