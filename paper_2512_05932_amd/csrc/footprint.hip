@@ -40,18 +40,41 @@ namespace {
 
 constexpr int kWaves = kFootprintThreads / 64;
 
+template <int CTRL, int ROW_MASK>
+__device__ inline int dpp_min(int v)
+{
+    return min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, CTRL, ROW_MASK, 0xf, false));
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ inline int dpp_max(int v)
+{
+    return max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, CTRL, ROW_MASK, 0xf, false));
+}
+
+// Minimum / maximum over the 64 lanes (all lanes active) by DPP: within
+// quads, half-rows and rows, then row broadcasts; lane 63 holds the result,
+// returned as a uniform value.
 __device__ inline int wave_min(int x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
-    return x;
+    x = dpp_min<0xb1, 0xf>(x);
+    x = dpp_min<0x4e, 0xf>(x);
+    x = dpp_min<0x141, 0xf>(x);
+    x = dpp_min<0x140, 0xf>(x);
+    x = dpp_min<0x142, 0xa>(x);
+    x = dpp_min<0x143, 0xc>(x);
+    return __builtin_amdgcn_readlane(x, 63);
 }
 
 __device__ inline int wave_max(int x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
-    return x;
+    x = dpp_max<0xb1, 0xf>(x);
+    x = dpp_max<0x4e, 0xf>(x);
+    x = dpp_max<0x141, 0xf>(x);
+    x = dpp_max<0x140, 0xf>(x);
+    x = dpp_max<0x142, 0xa>(x);
+    x = dpp_max<0x143, 0xc>(x);
+    return __builtin_amdgcn_readlane(x, 63);
 }
 
 template <int CTRL, int ROW_MASK>
@@ -180,30 +203,42 @@ __device__ inline void gather_group(const FrameDev& f, const int* ub, const int*
         for (int g = 0; g < G; ++g) acc[g] = 0.0f;
         const char* pb = pbase + (size_t)phase * pstep;
         const char* sb = SUN ? sbase + (size_t)phase * sstep : nullptr;
-        for (int i = 0; i < niter; ++i) {
+        // loads of one batch; the next batch's loads are issued before the
+        // current batch is processed, so their latency overlaps the work
+        struct Loads {
+            int4 ra, rb;
+            float4 sq;
+            float4 kq[G];
+        };
+        auto fetch = [&](int i, Loads& L) {
             // this lane's block; with column phases the last round may run
             // past the span: such lanes re-read the last block with K = 0
             const int bi = i * P + phase;
             const bool act = P == 1 || bi < nblk;
             const size_t back = act ? 0 : (size_t)(bi - (nblk - 1));
-            const int4 ra = ld16<int4>(pb - back * pstep, pvo);
-            const int4 rb = ld16<int4>(pb - back * pstep, pvo + 16u);
-            float4 sq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (SUN) sq = ld16<float4>(sb - back * sstep, svo);
-            const float sv[4] = {sq.x, sq.y, sq.z, sq.w};
-            float kv[4][G];
+            const char* pq = pb + (size_t)i * P * pstep - back * pstep;
+            L.ra = ld16<int4>(pq, pvo);
+            L.rb = ld16<int4>(pq, pvo + 16u);
+            L.sq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (SUN) L.sq = ld16<float4>(sb + (size_t)i * P * sstep - back * sstep, svo);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int b = min(max(kblk[g] + bi, 0), f.NB - 1);
                 const unsigned ko = act ? kvo[g] : (unsigned)f.KH * 16u;
-                const float4 kq = ld16<float4>(kcopy[g] + (unsigned)(b * (int)khp16), ko);
-                kv[0][g] = kq.x;
-                kv[1][g] = kq.y;
-                kv[2][g] = kq.z;
-                kv[3][g] = kq.w;
+                L.kq[g] = ld16<float4>(kcopy[g] + (unsigned)(b * (int)khp16), ko);
             }
-            pb += (size_t)P * pstep;
-            if (SUN) sb += (size_t)P * sstep;
+        };
+        auto process = [&](const Loads& L) {
+            const int4 ra = L.ra, rb = L.rb;
+            const float sv[4] = {L.sq.x, L.sq.y, L.sq.z, L.sq.w};
+            float kv[4][G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                kv[0][g] = L.kq[g].x;
+                kv[1][g] = L.kq[g].y;
+                kv[2][g] = L.kq[g].z;
+                kv[3][g] = L.kq[g].w;
+            }
             const int bin[4] = {ra.x, ra.z, rb.x, rb.z};
             const float sh[4] = {__int_as_float(ra.y), __int_as_float(ra.w),
                                  __int_as_float(rb.y), __int_as_float(rb.w)};
@@ -247,6 +282,16 @@ __device__ inline void gather_group(const FrameDev& f, const int* ub, const int*
 #pragma unroll
                 for (int g = 0; g < G; ++g) acc[g] = r[g];
             }
+        };
+        // two load buffers in turn (no register copies between batches)
+        Loads A, B;
+        if (niter > 0) fetch(0, A);
+        for (int i = 0; i < niter; i += 2) {
+            if (i + 1 < niter) fetch(i + 1, B);
+            process(A);
+            if (i + 1 >= niter) break;
+            if (i + 2 < niter) fetch(i + 2, A);
+            process(B);
         }
         unsigned any = __builtin_bit_cast(unsigned, acc[0]);
 #pragma unroll
