@@ -23,8 +23,9 @@
 // changes (most of them) take a branch-free fast path; otherwise the batch is
 // replayed with the resets and the ended runs are flushed.  Rows that cross
 // the same surface change bin together, so the flushing lanes usually share a
-// bin: they are summed across the wave with DPP (one LDS atomic per bin and
-// beam instead of one per lane, which would serialise on the shared address).
+// bin: their G sums are reduced across the wave together (half and row lane
+// swaps, then DPP), and one LDS atomic per bin and beam replaces one per lane,
+// which would serialise on the shared address.
 //
 // The histograms hold sum K * shade; the beam scale S_b is applied in the
 // pulse convolution (sliding register window, in place).  Echoes are maximal
@@ -97,6 +98,47 @@ __device__ inline float wave_total(float v)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Sum of two registers' 32-lane halves: lanes 0-31 get a(l) + a(l + 32),
+// lanes 32-63 get b(l - 32) + b(l) (one v_permlane32_swap).
+__device__ inline float swap_sum32(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b),
+                                                    false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// The same over 16-lane rows: rows 0 and 2 get a's row pairs (0+1, 2+3),
+// rows 1 and 3 get b's (one v_permlane16_swap).
+__device__ inline float swap_sum16(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b),
+                                                    false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Totals over the 64 lanes of G per-beam values at once (G = 1, 2 or 4; all
+// lanes active).  The half and row swaps fold the G registers into one so
+// that every 16-lane row holds partial sums of a single beam, then a DPP sum
+// within rows finishes: lane i * 64/G holds the total of beam i.
+template <int G>
+__device__ inline float group_totals(const float* v)
+{
+    float x;
+    if constexpr (G == 4) {
+        x = swap_sum16(swap_sum32(v[0], v[2]), swap_sum32(v[1], v[3]));
+    } else if constexpr (G == 2) {
+        const float y = swap_sum32(v[0], v[1]);
+        x = swap_sum16(y, y);
+    } else {
+        const float y = swap_sum32(v[0], v[0]);
+        x = swap_sum16(y, y);
+    }
+    x = dpp_add<0xb1, 0xf>(x);
+    x = dpp_add<0x4e, 0xf>(x);
+    x = dpp_add<0x141, 0xf>(x);
+    return dpp_add<0x140, 0xf>(x);
+}
+
 // Flush the lanes in `fm` (lanes whose run ended) into the histograms.
 template <int G>
 __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const float* acc,
@@ -111,11 +153,12 @@ __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const
         const unsigned long long same = __ballot(fl && cur == key) & m;
         if (__popcll(same) < 3) break;
         const bool in = (same >> lane) & 1ull;
+        float v[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const float s = wave_total(in ? acc[g] : 0.0f);
-            if (lane == 0 && s != 0.0f) atomicAdd(&hist[g * R + key], s);
-        }
+        for (int g = 0; g < G; ++g) v[g] = in ? acc[g] : 0.0f;
+        const float t = group_totals<G>(v);
+        constexpr int span = 64 / G;
+        if (lane % span == 0 && t != 0.0f) atomicAdd(&hist[(lane / span) * R + key], t);
         m &= ~same;
     }
     if ((m >> lane) & 1ull) {
