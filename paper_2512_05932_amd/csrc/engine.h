@@ -12,8 +12,23 @@ namespace lidar {
 constexpr double kLight = 299792458.0;          // m/s
 constexpr double kPi = 3.14159265358979323846;
 
-constexpr int kMaxBins = 8000;                  // 2 waveforms of R floats + taps in 64 KiB LDS
+constexpr int kMaxBins = 8000;                  // one padded waveform + taps fit the LDS of a group
 constexpr int kMaxTaps = 257;
+constexpr int kMaxChunks = (kMaxBins + 63) / 64;  // 64-bin chunks of a waveform
+constexpr int kPassBins = 2048;                 // bins per convolution pass (8 per thread)
+
+// LDS layout of a beam group in the footprint kernels: G waveforms of
+// conv_stride(R, J) floats, each with conv_pad(J) zero bins before its R bins
+// and at least J + 8 after them (the convolution reads 8-bin blocks without
+// bounds checks, 16-byte aligned), then the pulse taps padded with zeros to
+// conv_taps(J) entries (whole blocks of 8).
+__host__ __device__ constexpr int conv_pad(int J) { return J + 8 + ((4 - (2 * J) % 4) % 4); }
+__host__ __device__ constexpr int conv_stride(int R, int J) { return (conv_pad(J) + R + J + 8 + 3) & ~3; }
+__host__ __device__ constexpr int conv_taps(int J) { return (2 * J + 8) & ~7; }
+inline size_t group_lds_bytes(int G, int R, int J)
+{
+    return sizeof(float) * ((size_t)G * conv_stride(R, J) + conv_taps(J));
+}
 constexpr int kFootprintThreads = 256;          // 4 waves of 64
 constexpr int kXcds = 8;                        // MI355X: 8 XCDs, round-robin dispatch
 

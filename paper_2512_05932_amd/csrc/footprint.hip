@@ -40,6 +40,8 @@ namespace lidar {
 namespace {
 
 constexpr int kWaves = kFootprintThreads / 64;
+static_assert(kPassBins == 8 * kFootprintThreads && kPassBins == 32 * 64,
+              "a convolution pass is 8 bins per thread and one 32-bit word of 64-bin chunks");
 
 template <int CTRL, int ROW_MASK>
 __device__ inline int dpp_min(int v)
@@ -140,9 +142,11 @@ __device__ inline float group_totals(const float* v)
 }
 
 // Flush the lanes in `fm` (lanes whose run ended) into the histograms.
+// `stride` is the distance between the beams' histograms; nzc[c] is set for
+// every 64-bin chunk c that receives a sum.
 template <int G>
 __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const float* acc,
-                                  float* hist, int R, int lane)
+                                  float* hist, int stride, unsigned* nzc, int lane)
 {
     unsigned long long m = fm;
     // lanes sharing a bin are reduced across the wave (a few bins per step)
@@ -158,13 +162,15 @@ __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const
         for (int g = 0; g < G; ++g) v[g] = in ? acc[g] : 0.0f;
         const float t = group_totals<G>(v);
         constexpr int span = 64 / G;
-        if (lane % span == 0 && t != 0.0f) atomicAdd(&hist[(lane / span) * R + key], t);
+        if (lane % span == 0 && t != 0.0f) atomicAdd(&hist[(lane / span) * stride + key], t);
+        if (lane == 0) nzc[key >> 6] = 1u;
         m &= ~same;
     }
     if ((m >> lane) & 1ull) {
+        nzc[cur >> 6] = 1u;
 #pragma unroll
         for (int g = 0; g < G; ++g)
-            if (acc[g] != 0.0f) atomicAdd(&hist[g * R + cur], acc[g]);
+            if (acc[g] != 0.0f) atomicAdd(&hist[g * stride + cur], acc[g]);
     }
 }
 
@@ -181,7 +187,8 @@ __device__ inline T ld16(const char* base, unsigned byte_off)
 template <int G, int SH, bool SUN>
 __device__ inline void gather_group(const FrameDev& f, const int* ub, const int* vb,
                                     const bool* have, int r0, int r1, int q0, int q1,
-                                    float* hist, int R, int lane, int wave, float* sacc)
+                                    float* hist, int stride, unsigned* nzc, int lane, int wave,
+                                    float* sacc)
 {
     constexpr int P = 64 / SH;                      // column phases per strip
     const int row_in = lane % SH, phase = lane / SH;
@@ -317,7 +324,7 @@ __device__ inline void gather_group(const FrameDev& f, const int* ub, const int*
                     for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, r[g]);
                     const bool fl = nr && any != 0u;            // sums are >= 0
                     const unsigned long long fm = __ballot(fl);
-                    if (fm) flush_runs<G>(fm, fl, c, r, hist, R, lane);
+                    if (fm) flush_runs<G>(fm, fl, c, r, hist, stride, nzc, lane);
 #pragma unroll
                     for (int g = 0; g < G; ++g) r[g] = (nr ? 0.0f : r[g]) + kv[j][g] * sh[j];
                     c = bin[j];
@@ -341,19 +348,71 @@ __device__ inline void gather_group(const FrameDev& f, const int* ub, const int*
         for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, acc[g]);
         const bool fl = any != 0u;
         const unsigned long long fm = __ballot(fl);
-        if (fm) flush_runs<G>(fm, fl, cur, acc, hist, R, lane);
+        if (fm) flush_runs<G>(fm, fl, cur, acc, hist, stride, nzc, lane);
     }
 }
 
+// Output bins k0 .. k0 + 7 of the pulse convolution, one block of 8 taps:
+// o[q] += w[j] * x[q - j] for the window lo (x[-8 .. -1]) and hi (x[0 .. 7])
+// relative to the block's first tap.
+__device__ inline void conv_block(float* o, const float4& lo0, const float4& lo1,
+                                  const float4& hi0, const float4& hi1, const float* w8)
+{
+    const float4 wa = *(const float4*)w8, wb = *(const float4*)(w8 + 4);
+    const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+    const float X[16] = {lo0.x, lo0.y, lo0.z, lo0.w, lo1.x, lo1.y, lo1.z, lo1.w,
+                         hi0.x, hi0.y, hi0.z, hi0.w, hi1.x, hi1.y, hi1.z, hi1.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o[q] += w[j] * X[q - j + 8];
+}
+
+// o[q] = sum_t taps[t] * x[q - t] for q = 0..7 (x = histogram at k0 + J, so
+// that tap t = J is the centre), over nb blocks of 8 taps.  Every read lies
+// in the zero padding or the histogram; x is 16-byte aligned.
+__device__ inline void conv8(float* o, const float* x, const float* taps, int nb)
+{
+    float4 h0 = *(const float4*)x, h1 = *(const float4*)(x + 4);
+    float4 l0 = *(const float4*)(x - 8), l1 = *(const float4*)(x - 4);
+#pragma unroll 1
+    for (int b = 0; b < nb; b += 2) {
+        conv_block(o, l0, l1, h0, h1, taps + 8 * b);
+        if (b + 1 >= nb) break;
+        // the next block's upper window is this block's lower one
+        h0 = *(const float4*)(x - 8 * b - 16);
+        h1 = *(const float4*)(x - 8 * b - 12);
+        conv_block(o, h0, h1, l0, l1, taps + 8 * b + 8);
+        if (b + 2 >= nb) break;
+        l0 = *(const float4*)(x - 8 * b - 24);
+        l1 = *(const float4*)(x - 8 * b - 20);
+    }
+}
+
+// Bit i of the result is set when byte i of the 64-bit lane mask is non-zero.
+__device__ inline unsigned bytes_any(unsigned long long b)
+{
+    b |= b >> 4;
+    b |= b >> 2;
+    b |= b >> 1;
+    b &= 0x0101010101010101ull;
+    return (unsigned)((b * 0x0102040810204080ull) >> 56);
+}
+
 // The whole group after the histograms were zeroed: gather, floor, pulse,
-// echoes.  All threads of the workgroup call it with the same group.
+// echoes.  All threads of the workgroup call it with the same group.  hist is
+// beam 0's histogram, beam g's starts RS floats further (zero padding around
+// each); nzc[c] flags the 64-bin chunks the gather wrote, amask the chunks of
+// each waveform that hold a bin above the threshold.
 template <int G, bool SUN, bool KEEP>
 __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t* grp,
-                              float* hist, const float* taps, float (*red)[kWaves])
+                              float* hist, const float* taps, float (*red)[kWaves],
+                              unsigned* nzc, unsigned (*amask)[kMaxBins / kPassBins + 1])
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int R = p.R;
+    const int RS = conv_stride(R, p.J);
 
     // group members (uniform over the workgroup: kept in scalar registers)
     int beam[G], ub[G], vb[G];
@@ -387,11 +446,14 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
     for (int g = 0; g < G; ++g) sacc[g] = 0.0f;
     if (r0 <= r1 && q0 <= q1) {
         if (f.tile == 64)
-            gather_group<G, 64, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, R, lane, wave, sacc);
+            gather_group<G, 64, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzc, lane, wave,
+                                     sacc);
         else if (f.tile == 16)
-            gather_group<G, 16, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, R, lane, wave, sacc);
+            gather_group<G, 16, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzc, lane, wave,
+                                     sacc);
         else
-            gather_group<G, 4, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, R, lane, wave, sacc);
+            gather_group<G, 4, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzc, lane, wave,
+                                     sacc);
     }
     if (SUN) {
 #pragma unroll
@@ -416,37 +478,35 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
         }
         floor_b[g] = fl;
     }
-    constexpr int kPass = 8 * kFootprintThreads;        // bins per pass
+    constexpr int kPass = kPassBins;                    // 8 bins per thread and pass
     constexpr int kMaxPass = (kMaxBins + kPass - 1) / kPass;
+    const float T = p.threshold;
+    const int nb = conv_taps(p.J) / 8;
 #pragma unroll 1
     for (int g = 0; g < G; ++g) {
         if (!have[g]) continue;                          // uniform
-        float* h = hist + g * R;
+        float* h = hist + g * RS;
         float o[kMaxPass][8];
 #pragma unroll
         for (int ps = 0; ps < kMaxPass; ++ps) {
             const int k0 = ps * kPass + tid * 8;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) o[ps][q] = 0.0f;
             if (k0 >= R) continue;
-            auto H = [&](int i) -> float { return (i >= 0 && i < R) ? h[i] : 0.0f; };
-            float win[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                win[q] = H(k0 + q + p.J);
-                o[ps][q] = 0.0f;
-            }
-            for (int t = 0; t <= 2 * p.J; ++t) {
-                const float wt = taps[t];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) o[ps][q] += wt * win[q];
-#pragma unroll
-                for (int q = 7; q > 0; --q) win[q] = win[q - 1];
-                win[0] = H(k0 + p.J - t - 1);
-            }
+            // inputs k0 - J .. k0 + 7 + J: skipped when the gather wrote none
+            // of their chunks (the output is then the floor)
+            unsigned nz = 0;
+            const int c1 = min(R - 1, k0 + 7 + p.J) >> 6;
+            for (int c = max(0, k0 - p.J) >> 6; c <= c1; ++c) nz |= nzc[c];
+            if (nz) conv8(o[ps], h + k0 + p.J, taps, nb);
         }
         __syncthreads();                                 // every read of h is done
+        unsigned char* am = (unsigned char*)amask[g];
 #pragma unroll
         for (int ps = 0; ps < kMaxPass; ++ps) {
+            if (ps * kPass >= R) continue;               // uniform
             const int k0 = ps * kPass + tid * 8;
+            unsigned m8 = 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int k = k0 + q;
@@ -454,23 +514,34 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
                     const float val = scale[g] * o[ps][q] + floor_b[g];
                     h[k] = val;
                     if (KEEP) f.waves[(size_t)beam[g] * R + k] = val;
+                    m8 |= (val > T ? 1u : 0u) << q;
                 }
             }
+            // this wave's 512 bins are chunks 8 * wave .. 8 * wave + 7 of the pass
+            const unsigned byte = bytes_any(__ballot(m8 != 0u));
+            if (lane == 0) am[ps * 4 + wave] = (unsigned char)byte;
         }
     }
     __syncthreads();
 
-    // echo detection: wave w takes beams w, w + 4, ...
-    const float T = p.threshold;
+    // echo detection: wave w takes beams w, w + 4, ...; only the chunks with
+    // a bin above the threshold are visited (a run cannot cross another chunk)
     const float dt = (float)p.bin_ns;
 #pragma unroll 1
     for (int g = wave; g < G; g += kWaves) {
         if (!have[g]) continue;
-        const float* xh = hist + g * R;
+        const float* xh = hist + g * RS;
         lidar_echo* out = f.echoes + (size_t)beam[g] * p.E;
         int count = 0;
         int k0 = -1;                                     // first bin of the open run
-        for (int base = 0; base < R; base += 64) {
+        const int nw = (R + kPass - 1) / kPass;         // mask words, one per pass
+        int w = 0;
+        unsigned bits = __builtin_amdgcn_readfirstlane(amask[g][0]);
+        for (;;) {
+            while (bits == 0u && ++w < nw) bits = __builtin_amdgcn_readfirstlane(amask[g][w]);
+            if (bits == 0u) break;
+            const int base = (w * 32 + __builtin_ctz(bits)) * 64;
+            bits &= bits - 1u;
             const int k = base + lane;
             const bool above = k < R && xh[k] > T;
             const unsigned long long mask = __ballot(above);
@@ -559,14 +630,31 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
 
 }  // namespace
 
+// Zero the G padded histograms (float4 stores) and the chunk flags; load the
+// taps with their zero padding.
+__device__ inline void clear_group(float4* lds4, int n4, unsigned* nzc, int tid)
+{
+    const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int k = tid; k < n4; k += kFootprintThreads) lds4[k] = z;
+    for (int c = tid; c < kMaxChunks; c += kFootprintThreads) nzc[c] = 0u;
+}
+
+__device__ inline void load_taps(float* taps, const float* src, int J, int tid)
+{
+    for (int j = tid; j < conv_taps(J); j += kFootprintThreads) taps[j] = j <= 2 * J ? src[j] : 0.0f;
+}
+
 template <int G, bool SUN, bool KEEP>
 __global__ __launch_bounds__(kFootprintThreads)
 void k_footprint(FootprintArgs a)
 {
-    extern __shared__ float lds[];
-    float* hist = lds;                  // [G][R]: sum K * shade, then xi_hat
-    float* taps = lds + G * a.p.R;      // [2J+1]
+    extern __shared__ float4 lds4[];                // group_lds_bytes(G, R, J)
+    const int RS = conv_stride(a.p.R, a.p.J);
+    float* hist = (float*)lds4 + conv_pad(a.p.J);   // [G][RS]: sum K * shade, then xi_hat
+    float* taps = (float*)lds4 + G * RS;            // [conv_taps(J)]
     __shared__ float red[G][kWaves];
+    __shared__ unsigned nzc[kMaxChunks];
+    __shared__ unsigned amask[G][kMaxBins / kPassBins + 1];
 
     // XCD-aware schedule: workgroups go round-robin over the 8 XCDs, so slot
     // s runs on XCD s % 8; each XCD takes one contiguous run of the
@@ -576,10 +664,10 @@ void k_footprint(FootprintArgs a)
     const int gi = (slot % kXcds) * a.chunk + slot / kXcds;
     if (gi >= a.n_groups) return;
     const int tid = threadIdx.x;
-    for (int k = tid; k < G * a.p.R; k += kFootprintThreads) hist[k] = 0.0f;
-    for (int j = tid; j <= 2 * a.p.J; j += kFootprintThreads) taps[j] = a.p.taps[j];
+    clear_group(lds4, G * RS / 4, nzc, tid);
+    load_taps(taps, a.p.taps, a.p.J, tid);
     __syncthreads();
-    process_group<G, SUN, KEEP>(a.f, a.p, a.groups + (size_t)gi * G, hist, taps, red);
+    process_group<G, SUN, KEEP>(a.f, a.p, a.groups + (size_t)gi * G, hist, taps, red, nzc, amask);
 }
 
 // Persistent kernel over the items of a batch: each workgroup repeatedly
@@ -590,23 +678,27 @@ template <int G, bool SUN, bool KEEP>
 __global__ __launch_bounds__(kFootprintThreads)
 void k_footprint_batch(BatchArgs a)
 {
-    extern __shared__ float lds[];
-    float* hist = lds;
-    float* taps = lds + G * a.p.R;
+    extern __shared__ float4 lds4[];
+    const int RS = conv_stride(a.p.R, a.p.J);
+    float* hist = (float*)lds4 + conv_pad(a.p.J);
+    float* taps = (float*)lds4 + G * RS;
     __shared__ float red[G][kWaves];
+    __shared__ unsigned nzc[kMaxChunks];
+    __shared__ unsigned amask[G][kMaxBins / kPassBins + 1];
     __shared__ int item_sh;
     const int tid = threadIdx.x;
-    for (int j = tid; j <= 2 * a.p.J; j += kFootprintThreads) taps[j] = a.p.taps[j];
+    load_taps(taps, a.p.taps, a.p.J, tid);
     const int n_items = a.n_items_dev ? *a.n_items_dev : a.n_items;
     for (;;) {
         if (tid == 0) item_sh = atomicAdd(a.next_item, 1);
-        for (int k = tid; k < G * a.p.R; k += kFootprintThreads) hist[k] = 0.0f;
+        clear_group(lds4, G * RS / 4, nzc, tid);
         __syncthreads();
         const int item = item_sh;
         if (item >= n_items) break;                      // uniform: every wave exits
         const int2 it = a.items[item];
         const FrameDev f = a.frames[it.x];
-        process_group<G, SUN, KEEP>(f, a.p, a.groups + (size_t)it.y * G, hist, taps, red);
+        process_group<G, SUN, KEEP>(f, a.p, a.groups + (size_t)it.y * G, hist, taps, red, nzc,
+                                    amask);
         __syncthreads();                                 // histograms and item_sh reused
     }
 }
@@ -620,7 +712,7 @@ template <int G>
 static hipError_t launch_g(hipStream_t s, const FootprintArgs& a)
 {
     const int grid = kXcds * a.chunk;
-    const size_t lds = sizeof(float) * ((size_t)G * a.p.R + 2 * (size_t)a.p.J + 1);
+    const size_t lds = group_lds_bytes(G, a.p.R, a.p.J);
     const bool sun = a.f.sun != nullptr;
     const bool keep = a.f.waves != nullptr;
     if (sun && keep)
@@ -637,7 +729,7 @@ static hipError_t launch_g(hipStream_t s, const FootprintArgs& a)
 template <int G>
 static hipError_t launch_batch_g(hipStream_t s, const BatchArgs& a, int grid, bool sun, bool keep)
 {
-    const size_t lds = sizeof(float) * ((size_t)G * a.p.R + 2 * (size_t)a.p.J + 1);
+    const size_t lds = group_lds_bytes(G, a.p.R, a.p.J);
     if (sun && keep)
         hipLaunchKernelGGL((k_footprint_batch<G, true, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
     else if (sun)
@@ -651,7 +743,7 @@ static hipError_t launch_batch_g(hipStream_t s, const BatchArgs& a, int grid, bo
 
 bool footprint_group_fits(int G, int R, int J)
 {
-    return sizeof(float) * ((size_t)G * R + 2 * (size_t)J + 1) + 64 * sizeof(float) <= 65536;
+    return group_lds_bytes(G, R, J) + 1024 <= 65536;     // + static LDS of the kernels
 }
 
 hipError_t launch_footprint(hipStream_t s, const FootprintArgs& a)

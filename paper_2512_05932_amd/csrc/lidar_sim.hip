@@ -912,7 +912,7 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     }
-    const size_t lds = sizeof(float) * ((size_t)G * R + 2 * h->J + 1) + 1024;
+    const size_t lds = group_lds_bytes(G, R, h->J) + 2048;   // + static LDS
     const size_t per_cu = std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
     h->b_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * per_cu, total_groups));
     LIDAR_TRY(upload_frame_table(h));
