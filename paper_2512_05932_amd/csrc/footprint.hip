@@ -100,6 +100,20 @@ __device__ inline float wave_total(float v)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Load of a read-only record at a uniform address through the scalar data
+// cache (constant address space): the record lands in scalar registers.
+template <typename T>
+__device__ inline T load_uniform(const T* p)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole dwords");
+    struct Words { unsigned u[sizeof(T) / 4]; } w;
+    const __attribute__((address_space(4))) unsigned* q =
+        (const __attribute__((address_space(4))) unsigned*)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w.u[i] = q[i];
+    return __builtin_bit_cast(T, w);
+}
+
 // Sum of two registers' 32-lane halves: lanes 0-31 get a(l) + a(l + 32),
 // lanes 32-63 get b(l - 32) + b(l) (one v_permlane32_swap).
 __device__ inline float swap_sum32(float a, float b)
@@ -421,12 +435,13 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
     int umin = INT_MAX, umax = INT_MIN, vmin = INT_MAX, vmax = INT_MIN;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        beam[g] = __builtin_amdgcn_readfirstlane(grp[g]);
+        beam[g] = load_uniform(grp + g);
         have[g] = beam[g] >= 0;
         ub[g] = vb[g] = 0;
         scale[g] = 0.0f;
         if (have[g]) {
-            const lidar_beam_info bi = f.beams[beam[g]];
+            // pixel and scale are not written by this kernel (only the floor is)
+            const lidar_beam_info bi = load_uniform(f.beams + beam[g]);
             ub[g] = __builtin_amdgcn_readfirstlane(bi.pixel_u);
             vb[g] = __builtin_amdgcn_readfirstlane(bi.pixel_v);
             scale[g] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
@@ -693,10 +708,10 @@ void k_footprint_batch(BatchArgs a)
         if (tid == 0) item_sh = atomicAdd(a.next_item, 1);
         clear_group(lds4, G * RS / 4, nzc, tid);
         __syncthreads();
-        const int item = item_sh;
+        const int item = __builtin_amdgcn_readfirstlane(item_sh);
         if (item >= n_items) break;                      // uniform: every wave exits
-        const int2 it = a.items[item];
-        const FrameDev f = a.frames[it.x];
+        const int2 it = load_uniform(a.items + item);           // read-only tables
+        const FrameDev f = load_uniform(a.frames + it.x);
         process_group<G, SUN, KEEP>(f, a.p, a.groups + (size_t)it.y * G, hist, taps, red, nzc,
                                     amask);
         __syncthreads();                                 // histograms and item_sh reused
