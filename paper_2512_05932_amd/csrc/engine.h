@@ -19,12 +19,18 @@ constexpr int kPassBins = 2048;                 // bins per convolution pass (8 
 
 // LDS layout of a beam group in the footprint kernels: G waveforms of
 // conv_stride(R, J) floats, each with conv_pad(J) zero bins before its R bins
-// and at least J + 8 after them (the convolution reads 8-bin blocks without
-// bounds checks, 16-byte aligned), then the pulse taps padded with zeros to
-// conv_taps(J) entries (whole blocks of 8).
-__host__ __device__ constexpr int conv_pad(int J) { return J + 8 + ((4 - (2 * J) % 4) % 4); }
-__host__ __device__ constexpr int conv_stride(int R, int J) { return (conv_pad(J) + R + J + 8 + 3) & ~3; }
-__host__ __device__ constexpr int conv_taps(int J) { return (2 * J + 8) & ~7; }
+// and at least J + 8 after them, every waveform 16-byte aligned; then the
+// pulse taps, preceded by conv_shift(J) zeros (so that the tap centre falls on
+// a multiple of 4) and padded with zeros to conv_taps(J) entries (whole
+// blocks of 8).  The convolution reads and the output pass writes aligned
+// 4-bin vectors without bounds checks.
+__host__ __device__ constexpr int conv_shift(int J) { return ((J + 3) & ~3) - J; }
+__host__ __device__ constexpr int conv_pad(int J) { return (J + 8 + 3) & ~3; }
+__host__ __device__ constexpr int conv_stride(int R, int J)
+{
+    return conv_pad(J) + ((R + J + conv_shift(J) + 8 + 3) & ~3);
+}
+__host__ __device__ constexpr int conv_taps(int J) { return (2 * J + 1 + conv_shift(J) + 7) & ~7; }
 inline size_t group_lds_bytes(int G, int R, int J)
 {
     return sizeof(float) * ((size_t)G * conv_stride(R, J) + conv_taps(J));

@@ -382,9 +382,9 @@ __device__ inline void conv_block(float* o, const float4& lo0, const float4& lo1
         for (int q = 0; q < 8; ++q) o[q] += w[j] * X[q - j + 8];
 }
 
-// o[q] = sum_t taps[t] * x[q - t] for q = 0..7 (x = histogram at k0 + J, so
-// that tap t = J is the centre), over nb blocks of 8 taps.  Every read lies
-// in the zero padding or the histogram; x is 16-byte aligned.
+// o[q] = sum_t taps[t] * x[q - t] for q = 0..7 (x = histogram at k0 + J +
+// conv_shift(J), the centre of the shifted taps), over nb blocks of 8 taps.
+// Every read lies in the zero padding or the histogram; x is 16-byte aligned.
 __device__ inline void conv8(float* o, const float* x, const float* taps, int nb)
 {
     float4 h0 = *(const float4*)x, h1 = *(const float4*)(x + 4);
@@ -513,7 +513,7 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
             unsigned nz = 0;
             const int c1 = min(R - 1, k0 + 7 + p.J) >> 6;
             for (int c = max(0, k0 - p.J) >> 6; c <= c1; ++c) nz |= nzc[c];
-            if (nz) conv8(o[ps], h + k0 + p.J, taps, nb);
+            if (nz) conv8(o[ps], h + k0 + p.J + conv_shift(p.J), taps, nb);
         }
         __syncthreads();                                 // every read of h is done
         unsigned char* am = (unsigned char*)amask[g];
@@ -521,16 +521,25 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
         for (int ps = 0; ps < kMaxPass; ++ps) {
             if (ps * kPass >= R) continue;               // uniform
             const int k0 = ps * kPass + tid * 8;
+            float val[8];
             unsigned m8 = 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int k = k0 + q;
-                if (k < R) {
-                    const float val = scale[g] * o[ps][q] + floor_b[g];
-                    h[k] = val;
-                    if (KEEP) f.waves[(size_t)beam[g] * R + k] = val;
-                    m8 |= (val > T ? 1u : 0u) << q;
-                }
+                val[q] = scale[g] * o[ps][q] + floor_b[g];
+                m8 |= (k0 + q < R && val[q] > T ? 1u : 0u) << q;
+            }
+            if (k0 + 8 <= R) {
+                *(float4*)(h + k0) = make_float4(val[0], val[1], val[2], val[3]);
+                *(float4*)(h + k0 + 4) = make_float4(val[4], val[5], val[6], val[7]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (k0 + q < R) h[k0 + q] = val[q];
+            }
+            if (KEEP) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (k0 + q < R) f.waves[(size_t)beam[g] * R + k0 + q] = val[q];
             }
             // this wave's 512 bins are chunks 8 * wave .. 8 * wave + 7 of the pass
             const unsigned byte = bytes_any(__ballot(m8 != 0u));
@@ -656,7 +665,9 @@ __device__ inline void clear_group(float4* lds4, int n4, unsigned* nzc, int tid)
 
 __device__ inline void load_taps(float* taps, const float* src, int J, int tid)
 {
-    for (int j = tid; j < conv_taps(J); j += kFootprintThreads) taps[j] = j <= 2 * J ? src[j] : 0.0f;
+    const int d = conv_shift(J);
+    for (int j = tid; j < conv_taps(J); j += kFootprintThreads)
+        taps[j] = (j >= d && j - d <= 2 * J) ? src[j - d] : 0.0f;
 }
 
 template <int G, bool SUN, bool KEEP>
