@@ -140,6 +140,10 @@ struct BatchArgs {
     int n_items, G;
     int* next_item;             // work-queue counter (zeroed by k_reset_queue)
     const int* n_items_dev;     // if set: the item count, read on the device
+    // if set: the queue hands out tickets, ticket t = items [tickets[t],
+    // tickets[t + 1]) (non-empty); else one item per queue step
+    const int* tickets;         // [n_tickets + 1]
+    int n_tickets;
 };
 hipError_t launch_footprint_batch(hipStream_t s, const BatchArgs& a, int grid, bool sun,
                                   bool keep);

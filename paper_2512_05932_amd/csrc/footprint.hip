@@ -697,9 +697,10 @@ void k_footprint(FootprintArgs a)
 }
 
 // Persistent kernel over the items of a batch: each workgroup repeatedly
-// takes the next item from the queue (costliest items first), so frames of
-// very different sizes share the GPU without a tail of idle CUs.  Every
-// workgroup exits once the queue is exhausted.
+// takes the next ticket (a run of items, costliest first) from the queue, so
+// frames of very different sizes share the GPU without a tail of idle CUs,
+// and cheap items cost a fraction of a queue atomic each.  Every workgroup
+// exits once the queue is exhausted.
 template <int G, bool SUN, bool KEEP>
 __global__ __launch_bounds__(kFootprintThreads)
 void k_footprint_batch(BatchArgs a)
@@ -714,18 +715,30 @@ void k_footprint_batch(BatchArgs a)
     __shared__ int item_sh;
     const int tid = threadIdx.x;
     load_taps(taps, a.p.taps, a.p.J, tid);
-    const int n_items = a.n_items_dev ? *a.n_items_dev : a.n_items;
+    const int n_tickets = a.tickets ? a.n_tickets : (a.n_items_dev ? *a.n_items_dev : a.n_items);
     for (;;) {
         if (tid == 0) item_sh = atomicAdd(a.next_item, 1);
         clear_group(lds4, G * RS / 4, nzc, tid);
         __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(item_sh);
-        if (item >= n_items) break;                      // uniform: every wave exits
-        const int2 it = load_uniform(a.items + item);           // read-only tables
-        const FrameDev f = load_uniform(a.frames + it.x);
-        process_group<G, SUN, KEEP>(f, a.p, a.groups + (size_t)it.y * G, hist, taps, red, nzc,
-                                    amask);
-        __syncthreads();                                 // histograms and item_sh reused
+        const int t = __builtin_amdgcn_readfirstlane(item_sh);
+        if (t >= n_tickets) break;                       // uniform: every wave exits
+        int i0 = t, i1 = t + 1;
+        if (a.tickets) {
+            i0 = load_uniform(a.tickets + t);
+            i1 = load_uniform(a.tickets + t + 1);
+        }
+        // item_sh is rewritten only after the barrier that ends the first item
+        for (int item = i0; item < i1; ++item) {
+            if (item > i0) {
+                clear_group(lds4, G * RS / 4, nzc, tid);
+                __syncthreads();
+            }
+            const int2 it = load_uniform(a.items + item);       // read-only tables
+            const FrameDev f = load_uniform(a.frames + it.x);
+            process_group<G, SUN, KEEP>(f, a.p, a.groups + (size_t)it.y * G, hist, taps, red,
+                                        nzc, amask);
+            __syncthreads();                             // histograms and item_sh reused
+        }
     }
 }
 

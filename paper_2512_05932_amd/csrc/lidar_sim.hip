@@ -105,6 +105,8 @@ struct lidar_sim {
     DevBuf<FrameDev> b_frames;
     DevBuf<int2> b_items;
     uint64_t b_items_n = 0, b_samples = 0;
+    DevBuf<int32_t> b_tickets;         // [b_tickets_n + 1] item runs handed out by the queue
+    int b_tickets_n = 0;
     int b_grid = 0;
     bool b_autotuned = false;
     double b_autotune_ms = 0.0;
@@ -726,9 +728,10 @@ void free_graph(lidar_sim* h)
 }
 
 // Enqueue the batch on s: the pre-pass of every frame (optional), the queue
-// reset and the persistent footprint launch over `items`.
+// reset and the persistent footprint launch over `items` (handed out in the
+// runs `tickets` if given, else one by one).
 lidar_status enqueue_batch(lidar_sim* h, hipStream_t s, const int2* items, uint64_t n_items,
-                           bool with_prepass)
+                           bool with_prepass, const int32_t* tickets = nullptr, int n_tickets = 0)
 {
     if (with_prepass)
         for (auto& fs : h->frames) LIDAR_TRY(enqueue_prepass(h, *fs, s));
@@ -742,6 +745,8 @@ lidar_status enqueue_batch(lidar_sim* h, hipStream_t s, const int2* items, uint6
     ba.G = h->G;
     ba.next_item = h->b_queue.p;
     ba.n_items_dev = nullptr;
+    ba.tickets = tickets;
+    ba.n_tickets = n_tickets;
     const bool sun = h->prm.sun_irradiance != 0.0;
     const bool keep = (h->prm.flags & LIDAR_KEEP_WAVEFORMS) != 0;
     HIP_TRY(h, launch_footprint_batch(s, ba, h->b_grid, sun, keep), "batch footprint launch");
@@ -915,6 +920,29 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
     const size_t lds = group_lds_bytes(G, R, h->J) + 2048;   // + static LDS
     const size_t per_cu = std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
     h->b_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * per_cu, total_groups));
+    // tickets: runs of consecutive items whose cost reaches a target that
+    // shrinks with the work left (guided self-scheduling: a quarter of an
+    // even share per workgroup), at most kMaxTicket items; the costly head
+    // goes one item per ticket, the cheap tail in runs, and the last tickets
+    // are small again so that the workgroups finish together
+    constexpr size_t kMaxTicket = 256;
+    std::vector<int32_t> tickets(1, 0);
+    uint64_t remaining = 0;
+    for (uint64_t c : cost) remaining += c;
+    for (size_t j = 0; j < total_groups;) {
+        const uint64_t target = remaining / (4 * (uint64_t)h->b_grid);
+        uint64_t acc = 0;
+        size_t k = j;
+        do acc += cost[order[k++]];
+        while (k < total_groups && k - j < kMaxTicket && acc < target);
+        tickets.push_back((int32_t)k);
+        remaining -= acc;
+        j = k;
+    }
+    h->b_tickets_n = (int)tickets.size() - 1;
+    HIP_TRY(h, h->b_tickets.ensure(tickets.size()), "allocate batch tickets");
+    HIP_TRY(h, hipMemcpyAsync(h->b_tickets.p, tickets.data(), tickets.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, h->stream), "copy batch tickets");
     LIDAR_TRY(upload_frame_table(h));
     h->b_autotuned = false;
     h->b_autotune_ms = 0.0;
@@ -926,7 +954,8 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
                 "create capture stream");
     HIP_TRY(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal),
             "begin graph capture");
-    lidar_status st = enqueue_batch(h, h->capture_stream, h->b_items.p, h->b_items_n, true);
+    lidar_status st = enqueue_batch(h, h->capture_stream, h->b_items.p, h->b_items_n, true,
+                                    h->b_tickets.p, h->b_tickets_n);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(h->capture_stream, &graph);
     if (st != LIDAR_OK) {
@@ -1171,12 +1200,14 @@ static lidar_status simulate_surrogate(lidar_sim* h)
     ba.G = h->G;
     ba.next_item = h->s_cnt.p + 1;
     ba.n_items_dev = h->s_cnt.p;
+    ba.tickets = nullptr;
+    ba.n_tickets = 0;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     }
-    const size_t lds = sizeof(float) * ((size_t)h->G * R + 2 * h->J + 1) + 1024;
+    const size_t lds = group_lds_bytes(h->G, (int)R, h->J) + 2048;   // + static LDS
     const size_t per_cu = std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
     const int grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)cus * per_cu, (size_t)fs.n_groups));
     HIP_TRY(h, launch_footprint_batch(s, ba, grid, h->prm.sun_irradiance != 0.0, keep),
