@@ -88,6 +88,10 @@ struct PrepassArgs {
     int W4;                     // W rounded up to a multiple of 4 (padding: sky)
 };
 hipError_t launch_prepass(hipStream_t s, const PrepassArgs& a, bool with_sun);
+// all frames of a batch in one launch (tile_off: [n + 1] prefix of prepass_tiles)
+int prepass_tiles(const PrepassArgs& a);
+hipError_t launch_prepass_batch(hipStream_t s, const PrepassArgs* frames, const int* tile_off,
+                                int n, int total_tiles, bool with_sun);
 
 // Kernel table in 4-column blocks, in four copies shifted by one column:
 // copy s, block b, row n holds K(c, n) for the kernel columns

@@ -28,9 +28,14 @@
 // which would serialise on the shared address.
 //
 // The histograms hold sum K * shade; the beam scale S_b is applied in the
-// pulse convolution (sliding register window, in place).  Echoes are maximal
-// runs of xi_hat > T found with 64-bin ballots, one wave per beam
-// (section II-C, EPW paragraph).
+// pulse convolution (in place; 8 output bins per thread and blocks of 8 taps
+// over zero-padded histograms, so the window lives in registers and no read
+// needs a bounds check).  The gather flags the 64-bin chunks it writes:
+// outputs whose inputs lie only in unflagged chunks are the floor without
+// convolving, and the output pass flags the chunks holding a bin above the
+// threshold.  Echoes are maximal runs of xi_hat > T found with 64-bin
+// ballots over the flagged chunks, one wave per beam (section II-C, EPW
+// paragraph).
 #include <climits>
 
 #include "engine.h"

@@ -107,6 +107,9 @@ struct lidar_sim {
     uint64_t b_items_n = 0, b_samples = 0;
     DevBuf<int32_t> b_tickets;         // [b_tickets_n + 1] item runs handed out by the queue
     int b_tickets_n = 0;
+    DevBuf<PrepassArgs> b_prep;        // [n_frames] pre-pass arguments of the batch's frames
+    DevBuf<int32_t> b_prep_off;        // [n_frames + 1] first pre-pass tile of each frame
+    int b_prep_tiles = 0;
     int b_grid = 0;
     bool b_autotuned = false;
     double b_autotune_ms = 0.0;
@@ -537,7 +540,7 @@ lidar_status alloc_pixels(lidar_sim* h, FrameState& fs)
     return LIDAR_OK;
 }
 
-lidar_status enqueue_prepass(lidar_sim* h, FrameState& fs, hipStream_t s)
+PrepassArgs prepass_args(const lidar_sim* h, FrameState& fs)
 {
     const lidar_gbuffer_desc& g = fs.gb;
     const bool sun = h->prm.sun_irradiance != 0.0;
@@ -561,7 +564,23 @@ lidar_status enqueue_prepass(lidar_sim* h, FrameState& fs, hipStream_t s)
     pa.sun_z = (float)h->prm.sun_dir[2];
     pa.pix = fs.d_pix.p;
     pa.sun = sun ? fs.d_sun.p : nullptr;
-    HIP_TRY(h, launch_prepass(s, pa, sun), "pre-pass launch");
+    return pa;
+}
+
+lidar_status enqueue_prepass(lidar_sim* h, FrameState& fs, hipStream_t s)
+{
+    HIP_TRY(h, launch_prepass(s, prepass_args(h, fs), h->prm.sun_irradiance != 0.0),
+            "pre-pass launch");
+    return LIDAR_OK;
+}
+
+// The pre-pass of every frame of the batch in one launch (tables built by
+// setup_batch).
+lidar_status enqueue_batch_prepass(lidar_sim* h, hipStream_t s)
+{
+    HIP_TRY(h, launch_prepass_batch(s, h->b_prep.p, h->b_prep_off.p, (int)h->frames.size(),
+                                    h->b_prep_tiles, h->prm.sun_irradiance != 0.0),
+            "batch pre-pass launch");
     return LIDAR_OK;
 }
 
@@ -733,8 +752,7 @@ void free_graph(lidar_sim* h)
 lidar_status enqueue_batch(lidar_sim* h, hipStream_t s, const int2* items, uint64_t n_items,
                            bool with_prepass, const int32_t* tickets = nullptr, int n_tickets = 0)
 {
-    if (with_prepass)
-        for (auto& fs : h->frames) LIDAR_TRY(enqueue_prepass(h, *fs, s));
+    if (with_prepass) LIDAR_TRY(enqueue_batch_prepass(h, s));
     HIP_TRY(h, launch_reset_queue(s, h->b_queue.p), "queue reset launch");
     BatchArgs ba;
     ba.frames = h->b_frames.p;
@@ -779,7 +797,7 @@ lidar_status autotune_batch(lidar_sim* h, const std::vector<int2>& items)
 {
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = h->stream;
-    for (auto& fs : h->frames) LIDAR_TRY(enqueue_prepass(h, *fs, s));
+    LIDAR_TRY(enqueue_batch_prepass(h, s));
     std::map<int, std::vector<int2>> by_class;
     for (const int2& it : items) by_class[height_class(h->frames[it.x]->k.KH)].push_back(it);
     DevBuf<int2> d_trial;
@@ -880,6 +898,27 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
     }
     const uint64_t total_groups = group_off[n];
     if (total_groups >= (1ull << 31)) return fail(h, LIDAR_E_INVALID, "batch has more than 2^31 beam groups");
+    // pre-pass tables: every frame's arguments and tile offsets (the host
+    // vectors outlive the copies: the frame-table upload below synchronises)
+    std::vector<PrepassArgs> pa(n);
+    std::vector<int32_t> off(n + 1, 0);
+    {
+        uint64_t tiles = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            pa[i] = prepass_args(h, *h->frames[i]);
+            off[i] = (int32_t)tiles;
+            tiles += (uint64_t)prepass_tiles(pa[i]);
+        }
+        if (tiles >= (1ull << 31)) return fail(h, LIDAR_E_INVALID, "batch has more than 2^31 pre-pass tiles");
+        off[n] = (int32_t)tiles;
+        h->b_prep_tiles = (int)tiles;
+        HIP_TRY(h, h->b_prep.ensure(n), "allocate pre-pass table");
+        HIP_TRY(h, h->b_prep_off.ensure(n + 1), "allocate pre-pass offsets");
+        HIP_TRY(h, hipMemcpyAsync(h->b_prep.p, pa.data(), n * sizeof(PrepassArgs),
+                                  hipMemcpyHostToDevice, h->stream), "copy pre-pass table");
+        HIP_TRY(h, hipMemcpyAsync(h->b_prep_off.p, off.data(), (n + 1) * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, h->stream), "copy pre-pass offsets");
+    }
     // every frame's groups in one table; work items ordered by estimated
     // cost, costliest first (gather samples plus the convolution and
     // detection work of the group's R bins)

@@ -20,14 +20,13 @@ constexpr int kTile = 32;
 constexpr int kRowsPerPass = 8;     // 32 x 8 threads, 4 passes per tile
 }
 
+// One 32 x 32 tile of a frame, columns u0.., rows v0...
 template <bool SUN>
-__global__ __launch_bounds__(kTile * kRowsPerPass)
-void k_prepass(PrepassArgs a)
+__device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0)
 {
     __shared__ int2 trec[kTile][kTile + 1];
     __shared__ float tsun[kTile][kTile + 1];
     const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
-    const int u0 = blockIdx.x * kTile, v0 = blockIdx.y * kTile;
     const float inv_pi = (float)(1.0 / kPi);
     // read rows (coalesced along u), shade, stage in LDS
 #pragma unroll
@@ -76,6 +75,49 @@ void k_prepass(PrepassArgs a)
             if (SUN) a.sun[o] = tsun[r][bi * 4 + j];
         }
     }
+}
+
+template <bool SUN>
+__global__ __launch_bounds__(kTile * kRowsPerPass)
+void k_prepass(PrepassArgs a)
+{
+    prepass_tile<SUN>(a, blockIdx.x * kTile, blockIdx.y * kTile);
+}
+
+// All frames of a batch in one launch: block t is tile t of the frames' tiles
+// laid end to end (tile_off[f] = first tile of frame f, tile_off[n] = total).
+template <bool SUN>
+__global__ __launch_bounds__(kTile * kRowsPerPass)
+void k_prepass_batch(const PrepassArgs* frames, const int* tile_off, int n)
+{
+    const int t = blockIdx.x;
+    int lo = 0, hi = n - 1;                 // last frame with tile_off[f] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (tile_off[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const PrepassArgs a = frames[lo];
+    const int lt = t - tile_off[lo];
+    const int tiles_x = (a.W4 + kTile - 1) / kTile;
+    prepass_tile<SUN>(a, (lt % tiles_x) * kTile, (lt / tiles_x) * kTile);
+}
+
+int prepass_tiles(const PrepassArgs& a)
+{
+    return ((a.W4 + kTile - 1) / kTile) * ((a.H + kTile - 1) / kTile);
+}
+
+hipError_t launch_prepass_batch(hipStream_t s, const PrepassArgs* frames, const int* tile_off,
+                                int n, int total_tiles, bool with_sun)
+{
+    if (total_tiles <= 0) return hipSuccess;
+    dim3 block(kTile * kRowsPerPass);
+    if (with_sun)
+        hipLaunchKernelGGL(k_prepass_batch<true>, dim3(total_tiles), block, 0, s, frames, tile_off, n);
+    else
+        hipLaunchKernelGGL(k_prepass_batch<false>, dim3(total_tiles), block, 0, s, frames, tile_off, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_prepass(hipStream_t s, const PrepassArgs& a, bool with_sun)

@@ -147,6 +147,24 @@ def test_extreme_bin_counts(oracle_mod, R, dt):
     compare(got, ref, p)
 
 
+@pytest.mark.parametrize("R,dt,fwhm", [(8000, 0.06, 4.0), (2000, 0.0531, 4.0), (500, 1.0, 0.5),
+                                        (333, 0.3, 1.2), (1000, 0.2, 2.0)])
+def test_pulse_tap_counts(oracle_mod, R, dt, fwhm):
+    """Pulse lengths from 1 to 128 taps each side (odd and even J), with the
+    longest waveform: the convolution's zero padding, tap shift and block
+    count, and the group size the LDS budget allows."""
+    gb, pat = _tiny(PATTERN_TABLE, W=64, H=64)
+    gb = replace(gb, depth=np.where(np.isfinite(gb.depth), gb.depth * 0.1, gb.depth).astype(np.float32))
+    p = _tiny_params(n_bins=R, bin_ns=dt, pulse_fwhm_ns=fwhm, threshold=1e-5)
+    sigma = fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    J = math.ceil(p.pulse_trunc_sigmas * sigma / dt)
+    assert 1 <= J <= 128
+    ref = oracle_mod.simulate(gb, pat, p)
+    got = run_gpu(gb, pat, p)
+    rep = compare(got, ref, p)
+    _report(f"taps-J{J}-R{R}", rep)
+
+
 def test_single_pixel_image_and_single_beam(oracle_mod):
     raster = Raster(1, 1, -0.5, 0.5, -0.5, 0.5)
     gb = scenes.shell_gbuffer(raster, 12.0, 0.7)
