@@ -104,12 +104,26 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
         }
 }
 
-__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf by the rational approximation of Abramowitz & Stegun, formula 7.1.26
+// (absolute error <= 1.5e-7): for x >= 0, erf(x) = 1 - t (a1 + t (a2 + t (a3
+// + t (a4 + t a5)))) exp(-x^2) with t = 1 / (1 + p x); odd in x.  The
+// hardware reciprocal and exponential add a few ulp; the result feeds BF16
+// activations (relative step 2^-8), far coarser than either error.
+__device__ inline float erf_as(float x)
+{
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
+    const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f +
+                       t * (-1.453152027f + t * 1.061405429f))));
+    return copysignf(1.0f - poly * __expf(-ax * ax), x);
+}
+
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
 
 __device__ inline float gelu_prime(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-           z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) +
+           z * __expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
 // Z += bias (in place); H = bf16(gelu(Z)).
@@ -248,107 +262,151 @@ __global__ void k_transpose_bf16(const uint16_t* W, int in, int out, uint16_t* W
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kInfRows = 64;                 // rows (beams) per workgroup
+// Fused inference: 128 rows (beams) per workgroup of 4 waves; wave w computes
+// rows 64 (w / 2) .. + 63 and output columns 128 (w % 2) .. + 127 of every
+// hidden layer as 4 x 8 tiles of v_mfma_f32_16x16x32_bf16.  Per K step of 32
+// the weight tile (256 x 32) and, in the first layer, the input tile
+// (128 x 32) are staged in LDS, double buffered: the next step's tiles are
+// loaded into registers while the current step's MFMAs run, so one barrier
+// per step remains.  Activations stay in LDS between layers.
+constexpr int kInfRows = 128;                // rows (beams) per workgroup
 constexpr int kInfK = 32;                    // K step
 constexpr int kInfLdsK = kInfK + 8;          // staged row stride (elements)
 constexpr int kInfH = kSurHid + 8;           // activation row stride (elements)
 
 __device__ inline bf16x8 ld8(const uint16_t* p) { return *(const bf16x8*)p; }
 
-// One hidden layer for a 64-row tile: out[64][256] = A[64][K] W (W^T given
-// as Wt [256][K]); wave w computes columns 64 w .. 64 w + 63 with 4 x 4
-// blocks of v_mfma_f32_16x16x32_bf16.  A comes from global memory (X,
-// staged through LDS) or from the activation buffer H in LDS.  On return
-// acc holds the FP32 products; every read of A is complete.
+struct InferLds {
+    uint16_t H[kInfRows * kInfH];            // activations (BF16)
+    uint16_t Bs[2][kSurHid][kInfLdsK];       // weight tiles [out][k]
+    uint16_t As[2][kInfRows][kInfLdsK];      // input tiles of the first layer
+};
+
+// One hidden layer: acc = A W for the wave's 64 x 128 block, A = X (global,
+// staged) or H (LDS), W^T given as Wt [256][K].  Ends with a barrier: every
+// read of H is complete on return.
 template <bool A_GLOBAL>
-__device__ inline void infer_layer(const uint16_t* Ag, long row0, long n, const uint16_t* H,
-                                   const uint16_t* Wt, int K, uint16_t (*As)[kInfLdsK],
-                                   uint16_t (*Bs)[kInfLdsK], f32x4 (&acc)[4][4])
+__device__ inline void infer_layer(const uint16_t* Ag, long row0, long n, InferLds& L,
+                                   const uint16_t* Wt, int K, f32x4 (&acc)[4][8])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1, l16 = lane & 15, kq = 8 * (lane >> 4);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int kq = 8 * (lane >> 4);
-    for (int k0 = 0; k0 < K; k0 += kInfK) {
-        // stage: B tile 256 x 32 (4 chunks of 8 per thread), A tile 64 x 32
+        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int S = K / kInfK;
+    bf16x8 rb[4], ra[2];
+    // 16-byte chunk q of a tile: row q / 4, elements 8 (q % 4) .. + 7
+    auto load = [&](int st) {
+        const int k0 = st * kInfK;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) *(bf16x8*)&Bs[tid][8 * c] = ld8(Wt + (long)tid * K + k0 + 8 * c);
+        for (int c = 0; c < 4; ++c) {
+            const int q = tid + 256 * c;
+            rb[c] = ld8(Wt + (long)(q >> 2) * K + k0 + 8 * (q & 3));
+        }
         if (A_GLOBAL) {
-            const int r = tid >> 2, c = tid & 3;
-            const long row = row0 + r;
-            bf16x8 v = {};
-            if (row < n) v = ld8(Ag + row * kSurIn + k0 + 8 * c);
-            *(bf16x8*)&As[r][8 * c] = v;
-        }
-        __syncthreads();
-        bf16x8 a[4], b[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int r = t * 16 + (lane & 15);
-            a[t] = A_GLOBAL ? *(const bf16x8*)&As[r][kq] : *(const bf16x8*)&H[r * kInfH + k0 + kq];
-            b[t] = *(const bf16x8*)&Bs[wave * 64 + t * 16 + (lane & 15)][kq];
+            for (int c = 0; c < 2; ++c) {
+                const int q = tid + 256 * c;
+                const long row = row0 + (q >> 2);
+                ra[c] = bf16x8{};
+                if (row < n) ra[c] = ld8(Ag + row * kSurIn + k0 + 8 * (q & 3));
+            }
         }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int q = tid + 256 * c;
+            *(bf16x8*)&L.Bs[buf][q >> 2][8 * (q & 3)] = rb[c];
+        }
+        if (A_GLOBAL) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int q = tid + 256 * c;
+                *(bf16x8*)&L.As[buf][q >> 2][8 * (q & 3)] = ra[c];
+            }
+        }
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int st = 0; st < S; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < S) load(st + 1);
+        bf16x8 a[4], b[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 64 * wr + 16 * i + l16;
+            a[i] = A_GLOBAL ? *(const bf16x8*)&L.As[buf][r][kq]
+                            : *(const bf16x8*)&L.H[r * kInfH + st * kInfK + kq];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b[j] = *(const bf16x8*)&L.Bs[buf][128 * wc + 16 * j + l16][kq];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 8; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (st + 1 < S) store(buf ^ 1);
         __syncthreads();
     }
 }
 
-// bias + GELU of a layer's products into H (BF16), in place
-__device__ inline void infer_store(const f32x4 (&acc)[4][4], const float* bias, uint16_t* H)
+// bias + GELU of the wave's block into H (BF16)
+__device__ inline void infer_store(const f32x4 (&acc)[4][8], const float* bias, uint16_t* H)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 8; ++j) {
+        const int col = 128 * wc + 16 * j + (lane & 15);
+        const float bc = bias[col];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = wave * 64 + j * 16 + (lane & 15);
-            const float bc = bias[col];
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = i * 16 + 4 * (lane >> 4) + r;
+                const int row = 64 * wr + 16 * i + 4 * (lane >> 4) + r;
                 H[row * kInfH + col] = to_bf16(gelu(acc[i][j][r] + bc));
             }
-        }
+    }
 }
 
-// The whole network for 64 rows per workgroup; activations stay in LDS.
+// The whole network for 128 rows per workgroup.
 __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs a)
 {
-    __shared__ uint16_t H[kInfRows * kInfH];
-    __shared__ uint16_t As[kInfRows][kInfLdsK];
-    __shared__ uint16_t Bs[kSurHid][kInfLdsK];
+    extern __shared__ float4 lds_v4[];
+    InferLds& L = *(InferLds*)lds_v4;
     const long row0 = (long)blockIdx.x * kInfRows;
-    f32x4 acc[4][4];
-    infer_layer<true>(a.X, row0, a.n, H, a.Wt1, kSurIn, As, Bs, acc);
-    infer_store(acc, a.b1, H);
+    f32x4 acc[4][8];
+    infer_layer<true>(a.X, row0, a.n, L, a.Wt1, kSurIn, acc);
+    infer_store(acc, a.b1, L.H);
+    infer_layer<false>(nullptr, row0, a.n, L, a.Wt2, kSurHid, acc);
+    infer_store(acc, a.b2, L.H);
+    infer_layer<false>(nullptr, row0, a.n, L, a.Wt3, kSurHid, acc);
+    infer_store(acc, a.b3, L.H);
     __syncthreads();
-    infer_layer<false>(nullptr, row0, a.n, H, a.Wt2, kSurHid, As, Bs, acc);
-    infer_store(acc, a.b2, H);
-    __syncthreads();
-    infer_layer<false>(nullptr, row0, a.n, H, a.Wt3, kSurHid, As, Bs, acc);
-    infer_store(acc, a.b3, H);
-    __syncthreads();
-    // output layer: wave w takes rows 16 w .. 16 w + 15, all 16 outputs
+    // output layer: wave w takes rows 32 w .. 32 w + 31, all 16 outputs
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = 8 * (lane >> 4);
-    f32x4 y = {0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4 y[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
     for (int k0 = 0; k0 < kSurHid; k0 += kInfK) {
-        const bf16x8 av = *(const bf16x8*)&H[(wave * 16 + (lane & 15)) * kInfH + k0 + kq];
         const bf16x8 bv = ld8(a.Wt4 + (long)(lane & 15) * kSurHid + k0 + kq);
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, y, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bf16x8 av = *(const bf16x8*)&L.H[(wave * 32 + 16 * i + (lane & 15)) * kInfH + k0 + kq];
+            y[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, y[i], 0, 0, 0);
+        }
     }
     const int col = lane & 15;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const long row = row0 + wave * 16 + 4 * (lane >> 4) + r;
-        if (row < a.n) a.Y[row * kSurOut + col] = y[r] + a.b4[col];
-    }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long row = row0 + wave * 32 + 16 * i + 4 * (lane >> 4) + r;
+            if (row < a.n) a.Y[row * kSurOut + col] = y[i][r] + a.b4[col];
+        }
 }
 
 inline unsigned blocks(long n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -373,7 +431,16 @@ hipError_t launch_transpose_weights(hipStream_t s, const uint16_t* theta_b, uint
 hipError_t launch_mlp_infer(hipStream_t s, const InferArgs& a)
 {
     if (a.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks(a.n, kInfRows)), dim3(256), 0, s, a);
+    // more than 64 KiB of dynamic LDS: allowed up to the device's per-block limit
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_mlp_infer,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)sizeof(InferLds));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks(a.n, kInfRows)), dim3(256), sizeof(InferLds), s, a);
     return hipGetLastError();
 }
 
