@@ -13,6 +13,7 @@
 // the plain path.  Validity, time bins and cos(theta) follow the pre-pass
 // (Eqs. 3-4); the kernel is taken at each cell's centre.
 #include <climits>
+#include <type_traits>
 
 #include "engine.h"
 
@@ -33,18 +34,51 @@ __device__ inline uint16_t to_bf16(float f)
     return (uint16_t)(u >> 16);
 }
 
+// Wave-wide reductions (all 64 lanes active) by DPP within quads, half-rows
+// and rows, then row broadcasts; lane 63 holds the result, returned to every
+// lane as a uniform value.
+template <typename T, typename Op>
+__device__ inline T wave_reduce(T v, T identity, Op op)
+{
+    auto step = [&](auto ctrl, auto row_mask) {
+        const int o = __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, identity),
+                                                  __builtin_bit_cast(int, v), decltype(ctrl)::value,
+                                                  decltype(row_mask)::value, 0xf, false);
+        v = op(v, __builtin_bit_cast(T, o));
+    };
+    using std::integral_constant;
+    step(integral_constant<int, 0xb1>{}, integral_constant<int, 0xf>{});    // quad_perm [1,0,3,2]
+    step(integral_constant<int, 0x4e>{}, integral_constant<int, 0xf>{});    // quad_perm [2,3,0,1]
+    step(integral_constant<int, 0x141>{}, integral_constant<int, 0xf>{});   // row_half_mirror
+    step(integral_constant<int, 0x140>{}, integral_constant<int, 0xf>{});   // row_mirror
+    step(integral_constant<int, 0x142>{}, integral_constant<int, 0xa>{});   // row_bcast:15
+    step(integral_constant<int, 0x143>{}, integral_constant<int, 0xc>{});   // row_bcast:31
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
 __device__ inline float wave_sum(float v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return wave_reduce(v, 0.0f, [](float x, float y) { return x + y; });
 }
 
 __device__ inline float wave_maxf(float v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return v;
+    return wave_reduce(v, -INFINITY, [](float x, float y) { return fmaxf(x, y); });
+}
+
+__device__ inline float wave_minf(float v)
+{
+    return wave_reduce(v, INFINITY, [](float x, float y) { return fminf(x, y); });
+}
+
+__device__ inline int wave_mini(int v)
+{
+    return wave_reduce(v, INT_MAX, [](int x, int y) { return min(x, y); });
+}
+
+__device__ inline int wave_maxi(int v)
+{
+    return wave_reduce(v, INT_MIN, [](int x, int y) { return max(x, y); });
 }
 
 __device__ inline bool pixel_valid(float d, double to_bin, int R)
@@ -114,11 +148,8 @@ __global__ void k_super(SuperArgs a)
     }
     shade = wave_sum(shade);
     sun = wave_sum(sun);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        lo = min(lo, __shfl_xor(lo, o));
-        hi = max(hi, __shfl_xor(hi, o));
-    }
+    lo = wave_mini(lo);
+    hi = wave_maxi(hi);
     if (lane == 0) {
         a.sup[c] = make_float2(shade, sun);
         a.range[c] = lo <= hi ? make_int2(lo, hi) : make_int2(0, -1);
@@ -173,8 +204,7 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
     int kmin = INT_MAX;
 #pragma unroll
     for (int s = 0; s < 4; ++s) kmin = min(kmin, kc[s]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) kmin = min(kmin, __shfl_xor(kmin, o));
+    kmin = wave_mini(kmin);
     int k_ref = 0;
     if (kmin != INT_MAX) {
         float* hh = refh[wv];
@@ -197,17 +227,14 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
             }
         }
         const float top = wave_maxf(best);
-        int jj = best == top ? bj : INT_MAX;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) jj = min(jj, __shfl_xor(jj, o));
+        const int jj = wave_mini(best == top ? bj : INT_MAX);
         k_ref = kmin + jj;
     } else {
         float m = INFINITY;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
             if (rec[s].x > 0.0f) m = fminf(m, rec[s].x);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o));
+        m = wave_minf(m);
         k_ref = m < INFINITY ? (int)floor((double)m * a.to_bin) : 0;
     }
 #pragma unroll
