@@ -272,6 +272,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kInfRows = 128;                // rows (beams) per workgroup
 constexpr int kInfK = 32;                    // K step
 constexpr int kInfLdsK = kInfK + 8;          // staged row stride (elements)
+constexpr int kInfAhead = 3;                 // K steps loaded ahead of their use
 constexpr int kInfH = kSurHid + 8;           // activation row stride (elements)
 
 __device__ inline bf16x8 ld8(const uint16_t* p) { return *(const bf16x8*)p; }
@@ -296,61 +297,73 @@ __device__ inline void infer_layer(const uint16_t* Ag, long row0, long n, InferL
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const int S = K / kInfK;
-    bf16x8 rb[4], ra[2];
+    // register ring of kInfAhead steps: step k is loaded kInfAhead steps
+    // before its tiles are consumed and one step before they are stored
+    bf16x8 rb[kInfAhead][4], ra[kInfAhead][2];
     // 16-byte chunk q of a tile: row q / 4, elements 8 (q % 4) .. + 7
-    auto load = [&](int st) {
+    auto load = [&](int st, bf16x8 (&b4)[4], bf16x8 (&a2)[2]) {
         const int k0 = st * kInfK;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int q = tid + 256 * c;
-            rb[c] = ld8(Wt + (long)(q >> 2) * K + k0 + 8 * (q & 3));
+            b4[c] = ld8(Wt + (long)(q >> 2) * K + k0 + 8 * (q & 3));
         }
         if (A_GLOBAL) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const int q = tid + 256 * c;
                 const long row = row0 + (q >> 2);
-                ra[c] = bf16x8{};
-                if (row < n) ra[c] = ld8(Ag + row * kSurIn + k0 + 8 * (q & 3));
+                a2[c] = bf16x8{};
+                if (row < n) a2[c] = ld8(Ag + row * kSurIn + k0 + 8 * (q & 3));
             }
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](int buf, const bf16x8 (&b4)[4], const bf16x8 (&a2)[2]) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int q = tid + 256 * c;
-            *(bf16x8*)&L.Bs[buf][q >> 2][8 * (q & 3)] = rb[c];
+            *(bf16x8*)&L.Bs[buf][q >> 2][8 * (q & 3)] = b4[c];
         }
         if (A_GLOBAL) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const int q = tid + 256 * c;
-                *(bf16x8*)&L.As[buf][q >> 2][8 * (q & 3)] = ra[c];
+                *(bf16x8*)&L.As[buf][q >> 2][8 * (q & 3)] = a2[c];
             }
         }
     };
-    load(0);
-    store(0);
+#pragma unroll
+    for (int u = 0; u < kInfAhead; ++u)
+        if (u < S) load(u, rb[u], ra[u]);
+    store(0, rb[0], ra[0]);
     __syncthreads();
-    for (int st = 0; st < S; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < S) load(st + 1);
-        bf16x8 a[4], b[8];
+    for (int st0 = 0; st0 < S; st0 += kInfAhead) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = 64 * wr + 16 * i + l16;
-            a[i] = A_GLOBAL ? *(const bf16x8*)&L.As[buf][r][kq]
-                            : *(const bf16x8*)&L.H[r * kInfH + st * kInfK + kq];
+        for (int u = 0; u < kInfAhead; ++u) {
+            const int st = st0 + u;                          // ring slot u
+            if (st >= S) break;
+            const int buf = st & 1;
+            bf16x8 a[4], b[8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 64 * wr + 16 * i + l16;
+                a[i] = A_GLOBAL ? *(const bf16x8*)&L.As[buf][r][kq]
+                                : *(const bf16x8*)&L.H[r * kInfH + st * kInfK + kq];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) b[j] = *(const bf16x8*)&L.Bs[buf][128 * wc + 16 * j + l16][kq];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            // the next step's tiles (slot u + 1) into the other buffer; slot u
+            // is free again and takes step st + kInfAhead
+            const int un = (u + 1) % kInfAhead;
+            if (st + 1 < S) store(buf ^ 1, rb[un], ra[un]);
+            if (st + kInfAhead < S) load(st + kInfAhead, rb[u], ra[u]);
+            __syncthreads();
         }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) b[j] = *(const bf16x8*)&L.Bs[buf][128 * wc + 16 * j + l16][kq];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        if (st + 1 < S) store(buf ^ 1);
-        __syncthreads();
     }
 }
 
