@@ -172,10 +172,12 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
     const int Ib = floordiv(u, g.cw), Jb = floordiv(v, g.ch);
     uint16_t* x = a.X + (size_t)b * kSurIn;
 
-    // the lane's 4 patch cells
+    // the lane's 4 patch cells (lane + 64 s: 16 consecutive cells of a patch
+    // row per quarter-wave, so that the loads coalesce)
     float4 rec[4];
-    float csun[4], cshade[4];
+    float csun[4];
     bool in[4];
+    float kcore[4];                                        // K at the cell centre inside the core box
     int kc[4];                                             // candidate bins of the reference
     float wc[4];
 #pragma unroll
@@ -185,17 +187,17 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
         in[s] = I >= 0 && I < g.CW && J >= 0 && J < g.CH;
         rec[s] = in[s] ? a.cell[(long)J * g.CW + I] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         csun[s] = in[s] ? a.cell_sun[(long)J * g.CW + I] : 0.0f;
-        cshade[s] = in[s] ? a.cell_shade[(long)J * g.CW + I] : 0.0f;
-        kc[s] = INT_MAX;
-        wc[s] = 0.0f;
+        const float cshade = in[s] ? a.cell_shade[(long)J * g.CW + I] : 0.0f;
         const int m = floordiv(2 * I * g.cw + g.cw - 2 * u, 2);
         const int n = floordiv(2 * J * g.ch + g.ch - 2 * v, 2);
-        if (in[s] && rec[s].x > 0.0f && abs(m) <= g.cm && abs(n) <= g.cn) {
-            const float w = (float)a.K64[(long)(n + a.N) * a.KW + (m + a.M)] * cshade[s];
-            if (w > 0.0f) {
-                kc[s] = (int)floor((double)rec[s].x * a.to_bin);
-                wc[s] = w;
-            }
+        kcore[s] = (in[s] && abs(m) <= g.cm && abs(n) <= g.cn)
+                       ? (float)a.K64[(long)(n + a.N) * a.KW + (m + a.M)] : 0.0f;
+        kc[s] = INT_MAX;
+        wc[s] = 0.0f;
+        const float w = kcore[s] * cshade;
+        if (rec[s].x > 0.0f && w > 0.0f) {
+            kc[s] = (int)floor((double)rec[s].x * a.to_bin);
+            wc[s] = w;
         }
     }
     // reference bin: first maximum of the (1, 2, 3, 2, 1)-smoothed histogram
@@ -250,14 +252,7 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
     // sun floor of the core box from the coarse cells
     float asum = 0.0f;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int q = lane + 64 * s;
-        const int I = Ib - kSurPatch / 2 + (q & 15), J = Jb - kSurPatch / 2 + (q >> 4);
-        const int m = floordiv(2 * I * g.cw + g.cw - 2 * u, 2);
-        const int n = floordiv(2 * J * g.ch + g.ch - 2 * v, 2);
-        if (in[s] && abs(m) <= g.cm && abs(n) <= g.cn)
-            asum += (float)a.K64[(long)(n + a.N) * a.KW + (m + a.M)] * csun[s];
-    }
+    for (int s = 0; s < 4; ++s) asum += kcore[s] * csun[s];
     // super-cells outside the core box: sun floor and tail energy per bin
     const int I0 = max(0, floordiv(u - a.M, g.sw)), I1 = min(g.SW - 1, floordiv(u + a.M, g.sw));
     const int J0 = max(0, floordiv(v - a.N, g.sh)), J1 = min(g.SH - 1, floordiv(v + a.N, g.sh));
