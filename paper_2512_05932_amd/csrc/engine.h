@@ -14,8 +14,14 @@ constexpr double kPi = 3.14159265358979323846;
 
 constexpr int kMaxBins = 8000;                  // one padded waveform + taps fit the LDS of a group
 constexpr int kMaxTaps = 257;
-constexpr int kMaxChunks = (kMaxBins + 63) / 64;  // 64-bin chunks of a waveform
 constexpr int kPassBins = 2048;                 // bins per convolution pass (8 per thread)
+// chunks of 1 << chunk_shift(R) bins (at least 64) cover R bins with at most 32
+__host__ __device__ constexpr int chunk_shift(int R)
+{
+    int s = 6;
+    while (((R + (1 << s) - 1) >> s) > 32) ++s;
+    return s;
+}
 
 // LDS layout of a beam group in the footprint kernels: G waveforms of
 // conv_stride(R, J) floats, each with conv_pad(J) zero bins before its R bins

@@ -30,10 +30,11 @@
 // The histograms hold sum K * shade; the beam scale S_b is applied in the
 // pulse convolution (in place; 8 output bins per thread and blocks of 8 taps
 // over zero-padded histograms, so the window lives in registers and no read
-// needs a bounds check).  The gather flags the 64-bin chunks it writes:
+// needs a bounds check).  The gather flags the chunks it writes (32 chunks of
+// 64 or more bins, a register bit mask per lane, OR-reduced per wave):
 // outputs whose inputs lie only in unflagged chunks are the floor without
-// convolving, and the output pass flags the chunks holding a bin above the
-// threshold.  Echoes are maximal runs of xi_hat > T found with 64-bin
+// convolving, and the output pass flags the 64-bin chunks holding a bin above
+// the threshold.  Echoes are maximal runs of xi_hat > T found with 64-bin
 // ballots over the flagged chunks, one wave per beam (section II-C, EPW
 // paragraph).
 #include <climits>
@@ -83,6 +84,24 @@ __device__ inline int wave_max(int x)
     x = dpp_max<0x142, 0xa>(x);
     x = dpp_max<0x143, 0xc>(x);
     return __builtin_amdgcn_readlane(x, 63);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ inline unsigned dpp_or(unsigned v)
+{
+    return v | (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
+}
+
+// Bitwise OR over the 64 lanes (all active), returned as a uniform value.
+__device__ inline unsigned wave_or(unsigned x)
+{
+    x = dpp_or<0xb1, 0xf>(x);
+    x = dpp_or<0x4e, 0xf>(x);
+    x = dpp_or<0x141, 0xf>(x);
+    x = dpp_or<0x140, 0xf>(x);
+    x = dpp_or<0x142, 0xa>(x);
+    x = dpp_or<0x143, 0xc>(x);
+    return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
 }
 
 template <int CTRL, int ROW_MASK>
@@ -161,11 +180,11 @@ __device__ inline float group_totals(const float* v)
 }
 
 // Flush the lanes in `fm` (lanes whose run ended) into the histograms.
-// `stride` is the distance between the beams' histograms; nzc[c] is set for
-// every 64-bin chunk c that receives a sum.
+// `stride` is the distance between the beams' histograms; bit c of the
+// lane's nzb is set for every chunk c (bins c << nzs ..) that receives a sum.
 template <int G>
 __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const float* acc,
-                                  float* hist, int stride, unsigned* nzc, int lane)
+                                  float* hist, int stride, unsigned& nzb, int nzs, int lane)
 {
     unsigned long long m = fm;
     // lanes sharing a bin are reduced across the wave (a few bins per step)
@@ -182,11 +201,11 @@ __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const
         const float t = group_totals<G>(v);
         constexpr int span = 64 / G;
         if (lane % span == 0 && t != 0.0f) atomicAdd(&hist[(lane / span) * stride + key], t);
-        if (lane == 0) nzc[key >> 6] = 1u;
+        nzb |= 1u << (key >> nzs);
         m &= ~same;
     }
     if ((m >> lane) & 1ull) {
-        nzc[cur >> 6] = 1u;
+        nzb |= 1u << (cur >> nzs);
 #pragma unroll
         for (int g = 0; g < G; ++g)
             if (acc[g] != 0.0f) atomicAdd(&hist[g * stride + cur], acc[g]);
@@ -206,7 +225,8 @@ __device__ inline T ld16(const char* base, unsigned byte_off)
 template <int G, int SH, bool SUN>
 __device__ inline void gather_group(const FrameDev& f, const int* ub, const int* vb,
                                     const bool* have, int r0, int r1, int q0, int q1,
-                                    float* hist, int stride, unsigned* nzc, int lane, int wave,
+                                    float* hist, int stride, unsigned* nzmask, int nzs, int lane,
+                                    int wave,
                                     float* sacc)
 {
     constexpr int P = 64 / SH;                      // column phases per strip
@@ -224,6 +244,7 @@ __device__ inline void gather_group(const FrameDev& f, const int* ub, const int*
     const size_t khp16 = (size_t)(f.KH + 1) * 16u;          // block stride in a copy
     const size_t copy_bytes = (size_t)f.NB * khp16;
     const size_t pstep = (size_t)f.H * 32u, sstep = (size_t)f.H * 16u;
+    unsigned nzb = 0u;                                  // chunks this lane wrote
     for (int it = wave; it < items; it += kWaves) {
         const int s = it / nchunk, ch = it - s * nchunk;
         const int v = r0 + s * SH + row_in;
@@ -343,7 +364,7 @@ __device__ inline void gather_group(const FrameDev& f, const int* ub, const int*
                     for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, r[g]);
                     const bool fl = nr && any != 0u;            // sums are >= 0
                     const unsigned long long fm = __ballot(fl);
-                    if (fm) flush_runs<G>(fm, fl, c, r, hist, stride, nzc, lane);
+                    if (fm) flush_runs<G>(fm, fl, c, r, hist, stride, nzb, nzs, lane);
 #pragma unroll
                     for (int g = 0; g < G; ++g) r[g] = (nr ? 0.0f : r[g]) + kv[j][g] * sh[j];
                     c = bin[j];
@@ -367,8 +388,11 @@ __device__ inline void gather_group(const FrameDev& f, const int* ub, const int*
         for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, acc[g]);
         const bool fl = any != 0u;
         const unsigned long long fm = __ballot(fl);
-        if (fm) flush_runs<G>(fm, fl, cur, acc, hist, stride, nzc, lane);
+        if (fm) flush_runs<G>(fm, fl, cur, acc, hist, stride, nzb, nzs, lane);
     }
+    // the wave's chunk flags, one LDS atomic per wave
+    nzb = wave_or(nzb);
+    if (lane == 0 && nzb) atomicOr(nzmask, nzb);
 }
 
 // Output bins k0 .. k0 + 7 of the pulse convolution, one block of 8 taps:
@@ -421,17 +445,19 @@ __device__ inline unsigned bytes_any(unsigned long long b)
 // The whole group after the histograms were zeroed: gather, floor, pulse,
 // echoes.  All threads of the workgroup call it with the same group.  hist is
 // beam 0's histogram, beam g's starts RS floats further (zero padding around
-// each); nzc[c] flags the 64-bin chunks the gather wrote, amask the chunks of
+// each); bit c of *nzmask flags the chunks of 1 << nzs bins (chunk_shift) that
+// the gather wrote, amask the 64-bin chunks of
 // each waveform that hold a bin above the threshold.
 template <int G, bool SUN, bool KEEP>
 __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t* grp,
                               float* hist, const float* taps, float (*red)[kWaves],
-                              unsigned* nzc, unsigned (*amask)[kMaxBins / kPassBins + 1])
+                              unsigned* nzmask, unsigned (*amask)[kMaxBins / kPassBins + 1])
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int R = p.R;
     const int RS = conv_stride(R, p.J);
+    const int nzs = chunk_shift(R);
 
     // group members (uniform over the workgroup: kept in scalar registers)
     int beam[G], ub[G], vb[G];
@@ -466,13 +492,13 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
     for (int g = 0; g < G; ++g) sacc[g] = 0.0f;
     if (r0 <= r1 && q0 <= q1) {
         if (f.tile == 64)
-            gather_group<G, 64, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzc, lane, wave,
+            gather_group<G, 64, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane, wave,
                                      sacc);
         else if (f.tile == 16)
-            gather_group<G, 16, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzc, lane, wave,
+            gather_group<G, 16, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane, wave,
                                      sacc);
         else
-            gather_group<G, 4, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzc, lane, wave,
+            gather_group<G, 4, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane, wave,
                                      sacc);
     }
     if (SUN) {
@@ -502,6 +528,7 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
     constexpr int kMaxPass = (kMaxBins + kPass - 1) / kPass;
     const float T = p.threshold;
     const int nb = conv_taps(p.J) / 8;
+    const unsigned nzm = __builtin_amdgcn_readfirstlane(*nzmask);
 #pragma unroll 1
     for (int g = 0; g < G; ++g) {
         if (!have[g]) continue;                          // uniform
@@ -515,10 +542,9 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
             if (k0 >= R) continue;
             // inputs k0 - J .. k0 + 7 + J: skipped when the gather wrote none
             // of their chunks (the output is then the floor)
-            unsigned nz = 0;
-            const int c1 = min(R - 1, k0 + 7 + p.J) >> 6;
-            for (int c = max(0, k0 - p.J) >> 6; c <= c1; ++c) nz |= nzc[c];
-            if (nz) conv8(o[ps], h + k0 + p.J + conv_shift(p.J), taps, nb);
+            const int c0 = max(0, k0 - p.J) >> nzs, c1 = min(R - 1, k0 + 7 + p.J) >> nzs;
+            const unsigned span = c1 - c0 >= 31 ? ~0u : (2u << (c1 - c0)) - 1u;
+            if ((nzm >> c0) & span) conv8(o[ps], h + k0 + p.J + conv_shift(p.J), taps, nb);
         }
         __syncthreads();                                 // every read of h is done
         unsigned char* am = (unsigned char*)amask[g];
@@ -661,11 +687,11 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
 
 // Zero the G padded histograms (float4 stores) and the chunk flags; load the
 // taps with their zero padding.
-__device__ inline void clear_group(float4* lds4, int n4, unsigned* nzc, int tid)
+__device__ inline void clear_group(float4* lds4, int n4, unsigned* nzmask, int tid)
 {
     const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     for (int k = tid; k < n4; k += kFootprintThreads) lds4[k] = z;
-    for (int c = tid; c < kMaxChunks; c += kFootprintThreads) nzc[c] = 0u;
+    if (tid == 0) *nzmask = 0u;
 }
 
 __device__ inline void load_taps(float* taps, const float* src, int J, int tid)
@@ -684,7 +710,7 @@ void k_footprint(FootprintArgs a)
     float* hist = (float*)lds4 + conv_pad(a.p.J);   // [G][RS]: sum K * shade, then xi_hat
     float* taps = (float*)lds4 + G * RS;            // [conv_taps(J)]
     __shared__ float red[G][kWaves];
-    __shared__ unsigned nzc[kMaxChunks];
+    __shared__ unsigned nzmask;
     __shared__ unsigned amask[G][kMaxBins / kPassBins + 1];
 
     // XCD-aware schedule: workgroups go round-robin over the 8 XCDs, so slot
@@ -695,10 +721,11 @@ void k_footprint(FootprintArgs a)
     const int gi = (slot % kXcds) * a.chunk + slot / kXcds;
     if (gi >= a.n_groups) return;
     const int tid = threadIdx.x;
-    clear_group(lds4, G * RS / 4, nzc, tid);
+    clear_group(lds4, G * RS / 4, &nzmask, tid);
     load_taps(taps, a.p.taps, a.p.J, tid);
     __syncthreads();
-    process_group<G, SUN, KEEP>(a.f, a.p, a.groups + (size_t)gi * G, hist, taps, red, nzc, amask);
+    process_group<G, SUN, KEEP>(a.f, a.p, a.groups + (size_t)gi * G, hist, taps, red, &nzmask,
+                                amask);
 }
 
 // Persistent kernel over the items of a batch: each workgroup repeatedly
@@ -715,7 +742,7 @@ void k_footprint_batch(BatchArgs a)
     float* hist = (float*)lds4 + conv_pad(a.p.J);
     float* taps = (float*)lds4 + G * RS;
     __shared__ float red[G][kWaves];
-    __shared__ unsigned nzc[kMaxChunks];
+    __shared__ unsigned nzmask;
     __shared__ unsigned amask[G][kMaxBins / kPassBins + 1];
     __shared__ int item_sh;
     const int tid = threadIdx.x;
@@ -723,7 +750,7 @@ void k_footprint_batch(BatchArgs a)
     const int n_tickets = a.tickets ? a.n_tickets : (a.n_items_dev ? *a.n_items_dev : a.n_items);
     for (;;) {
         if (tid == 0) item_sh = atomicAdd(a.next_item, 1);
-        clear_group(lds4, G * RS / 4, nzc, tid);
+        clear_group(lds4, G * RS / 4, &nzmask, tid);
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(item_sh);
         if (t >= n_tickets) break;                       // uniform: every wave exits
@@ -735,13 +762,13 @@ void k_footprint_batch(BatchArgs a)
         // item_sh is rewritten only after the barrier that ends the first item
         for (int item = i0; item < i1; ++item) {
             if (item > i0) {
-                clear_group(lds4, G * RS / 4, nzc, tid);
+                clear_group(lds4, G * RS / 4, &nzmask, tid);
                 __syncthreads();
             }
             const int2 it = load_uniform(a.items + item);       // read-only tables
             const FrameDev f = load_uniform(a.frames + it.x);
             process_group<G, SUN, KEEP>(f, a.p, a.groups + (size_t)it.y * G, hist, taps, red,
-                                        nzc, amask);
+                                        &nzmask, amask);
             __syncthreads();                             // histograms and item_sh reused
         }
     }
