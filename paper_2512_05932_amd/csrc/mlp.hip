@@ -261,165 +261,170 @@ __global__ void k_transpose_bf16(const uint16_t* W, int in, int out, uint16_t* W
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v4 __attribute__((ext_vector_type(4)));
 
-// Fused inference: 128 rows (beams) per workgroup of 4 waves; wave w computes
-// rows 64 (w / 2) .. + 63 and output columns 128 (w % 2) .. + 127 of every
-// hidden layer as 4 x 8 tiles of v_mfma_f32_16x16x32_bf16.  Per K step of 32
-// the weight tile (256 x 32) and, in the first layer, the input tile
-// (128 x 32) are staged in LDS, double buffered: the next step's tiles are
-// loaded into registers while the current step's MFMAs run, so one barrier
-// per step remains.  Activations stay in LDS between layers.
-constexpr int kInfRows = 128;                // rows (beams) per workgroup
+// Fused inference with the activations in registers.  The weights are the
+// MFMA's A operand (a tile of 16 output features) and the beams its B operand
+// (16 rows), so a wave holds all 256 features of its 16 beams.  The output of
+// v_mfma_f32_16x16x32_bf16 (lane l: features 4 (l / 16) .. + 3 of row l % 16)
+// is the next layer's B operand as it stands once both operands of a K step
+// of 32 take the features in the same order: lane quad q and element e stand
+// for feature 32 s + 4 q + e (e < 4) or 32 s + 16 + 4 q + (e - 4).  The first
+// layer reads its inputs in natural order (8 q + e).  Weight tiles (256 x 32)
+// are staged in double-buffered LDS, shared by the workgroup's 8 waves (128
+// beams); the tiles of step k + 2 are loaded while step k's MFMAs run.
+constexpr int kInfWaves = 8;
+constexpr int kInfRows = 16 * kInfWaves;     // rows (beams) per workgroup
+constexpr int kInfThreads = 64 * kInfWaves;
 constexpr int kInfK = 32;                    // K step
 constexpr int kInfLdsK = kInfK + 8;          // staged row stride (elements)
-constexpr int kInfAhead = 3;                 // K steps loaded ahead of their use
-constexpr int kInfH = kSurHid + 8;           // activation row stride (elements)
+constexpr int kInfAhead = 2;                 // K steps loaded ahead of their use
+
+struct InferLds {
+    uint16_t Bs[2][kSurHid][kInfLdsK];       // weight tiles [out][k]
+};
 
 __device__ inline bf16x8 ld8(const uint16_t* p) { return *(const bf16x8*)p; }
 
-struct InferLds {
-    uint16_t H[kInfRows * kInfH];            // activations (BF16)
-    uint16_t Bs[2][kSurHid][kInfLdsK];       // weight tiles [out][k]
-    uint16_t As[2][kInfRows][kInfLdsK];      // input tiles of the first layer
-};
-
-// One hidden layer: acc = A W for the wave's 64 x 128 block, A = X (global,
-// staged) or H (LDS), W^T given as Wt [256][K].  Ends with a barrier: every
-// read of H is complete on return.
-template <bool A_GLOBAL>
-__device__ inline void infer_layer(const uint16_t* Ag, long row0, long n, InferLds& L,
-                                   const uint16_t* Wt, int K, f32x4 (&acc)[4][8])
+// the workgroup's share of one weight tile: 1024 chunks of 8 elements,
+// kStage per thread (chunk c: row c / 4, elements 8 (c % 4) .. + 7)
+constexpr int kStage = 4 * kSurHid / kInfThreads;
+__device__ inline void stage_load(const uint16_t* Wt, int K, int k0, int tid, bf16x8 (&r)[kStage])
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1, l16 = lane & 15, kq = 8 * (lane >> 4);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < kStage; ++c) {
+        const int q = tid + kInfThreads * c;
+        r[c] = ld8(Wt + (long)(q >> 2) * K + k0 + 8 * (q & 3));
+    }
+}
+
+__device__ inline void stage_store(InferLds& L, int buf, int tid, const bf16x8 (&r)[kStage])
+{
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int S = K / kInfK;
-    // register ring of kInfAhead steps: step k is loaded kInfAhead steps
-    // before its tiles are consumed and one step before they are stored
-    bf16x8 rb[kInfAhead][4], ra[kInfAhead][2];
-    // 16-byte chunk q of a tile: row q / 4, elements 8 (q % 4) .. + 7
-    auto load = [&](int st, bf16x8 (&b4)[4], bf16x8 (&a2)[2]) {
-        const int k0 = st * kInfK;
+    for (int c = 0; c < kStage; ++c) {
+        const int q = tid + kInfThreads * c;
+        *(bf16x8*)&L.Bs[buf][q >> 2][8 * (q & 3)] = r[c];
+    }
+}
+
+// A fragment of tile t in the permuted order (hidden layers)
+__device__ inline bf16x8 frag_perm(const InferLds& L, int buf, int t, int l16, int q)
+{
+    const bf16v4 lo = *(const bf16v4*)&L.Bs[buf][16 * t + l16][4 * q];
+    const bf16v4 hi = *(const bf16v4*)&L.Bs[buf][16 * t + l16][16 + 4 * q];
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+__device__ inline __bf16 bf(float x) { return __builtin_bit_cast(__bf16, to_bf16(x)); }
+
+// bias + GELU of the wave's 16 x 256 block into B fragments of the next layer
+__device__ inline void to_frags(const f32x4 (&acc)[16], const float* bias, int q, bf16x8 (&h)[8])
+{
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int q = tid + 256 * c;
-            b4[c] = ld8(Wt + (long)(q >> 2) * K + k0 + 8 * (q & 3));
-        }
-        if (A_GLOBAL) {
+    for (int s = 0; s < 8; ++s) {
+        const float4 b0 = *(const float4*)(bias + 32 * s + 4 * q);
+        const float4 b1 = *(const float4*)(bias + 32 * s + 16 + 4 * q);
+        const f32x4 x0 = acc[2 * s], x1 = acc[2 * s + 1];
+        h[s] = bf16x8{bf(gelu(x0[0] + b0.x)), bf(gelu(x0[1] + b0.y)), bf(gelu(x0[2] + b0.z)),
+                      bf(gelu(x0[3] + b0.w)), bf(gelu(x1[0] + b1.x)), bf(gelu(x1[1] + b1.y)),
+                      bf(gelu(x1[2] + b1.z)), bf(gelu(x1[3] + b1.w))};
+    }
+}
+
+// First layer: acc = W1 x over the 1056 inputs (B fragments straight from X).
+__device__ inline void layer_first(const uint16_t* X, long row, long n, InferLds& L,
+                                   const uint16_t* Wt, f32x4 (&acc)[16])
+{
+    const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
+    constexpr int S = kSurIn / kInfK;
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int q = tid + 256 * c;
-                const long row = row0 + (q >> 2);
-                a2[c] = bf16x8{};
-                if (row < n) a2[c] = ld8(Ag + row * kSurIn + k0 + 8 * (q & 3));
-            }
-        }
-    };
-    auto store = [&](int buf, const bf16x8 (&b4)[4], const bf16x8 (&a2)[2]) {
+    for (int t = 0; t < 16; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 rb[kInfAhead][kStage], xb[kInfAhead];
+    auto xload = [&](int st) { return row < n ? ld8(X + row * kSurIn + st * kInfK + 8 * q) : bf16x8{}; };
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int q = tid + 256 * c;
-            *(bf16x8*)&L.Bs[buf][q >> 2][8 * (q & 3)] = b4[c];
-        }
-        if (A_GLOBAL) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int q = tid + 256 * c;
-                *(bf16x8*)&L.As[buf][q >> 2][8 * (q & 3)] = a2[c];
-            }
-        }
-    };
-#pragma unroll
-    for (int u = 0; u < kInfAhead; ++u)
-        if (u < S) load(u, rb[u], ra[u]);
-    store(0, rb[0], ra[0]);
+    for (int u = 0; u < kInfAhead; ++u) {
+        stage_load(Wt, kSurIn, u * kInfK, tid, rb[u]);
+        xb[u] = xload(u);
+    }
+    stage_store(L, 0, tid, rb[0]);
     __syncthreads();
     for (int st0 = 0; st0 < S; st0 += kInfAhead) {
 #pragma unroll
         for (int u = 0; u < kInfAhead; ++u) {
-            const int st = st0 + u;                          // ring slot u
+            const int st = st0 + u;                      // ring slot u
             if (st >= S) break;
             const int buf = st & 1;
-            bf16x8 a[4], b[8];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = 64 * wr + 16 * i + l16;
-                a[i] = A_GLOBAL ? *(const bf16x8*)&L.As[buf][r][kq]
-                                : *(const bf16x8*)&L.H[r * kInfH + st * kInfK + kq];
+            for (int t = 0; t < 16; ++t) {
+                const bf16x8 a = *(const bf16x8*)&L.Bs[buf][16 * t + l16][8 * q];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xb[u], acc[t], 0, 0, 0);
             }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) b[j] = *(const bf16x8*)&L.Bs[buf][128 * wc + 16 * j + l16][kq];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-            // the next step's tiles (slot u + 1) into the other buffer; slot u
-            // is free again and takes step st + kInfAhead
             const int un = (u + 1) % kInfAhead;
-            if (st + 1 < S) store(buf ^ 1, rb[un], ra[un]);
-            if (st + kInfAhead < S) load(st + kInfAhead, rb[u], ra[u]);
+            if (st + 1 < S) stage_store(L, buf ^ 1, tid, rb[un]);
+            if (st + kInfAhead < S) {
+                stage_load(Wt, kSurIn, (st + kInfAhead) * kInfK, tid, rb[u]);
+                xb[u] = xload(st + kInfAhead);
+            }
             __syncthreads();
         }
     }
 }
 
-// bias + GELU of the wave's block into H (BF16)
-__device__ inline void infer_store(const f32x4 (&acc)[4][8], const float* bias, uint16_t* H)
+// Hidden layer: acc = W h over 256 inputs held as B fragments.
+__device__ inline void layer_hidden(const bf16x8 (&h)[8], InferLds& L, const uint16_t* Wt,
+                                    f32x4 (&acc)[16])
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
+    constexpr int S = kSurHid / kInfK;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int col = 128 * wc + 16 * j + (lane & 15);
-        const float bc = bias[col];
+    for (int t = 0; t < 16; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 rb[kInfAhead][kStage];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+    for (int u = 0; u < kInfAhead; ++u) stage_load(Wt, kSurHid, u * kInfK, tid, rb[u]);
+    stage_store(L, 0, tid, rb[0]);
+    __syncthreads();
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 64 * wr + 16 * i + 4 * (lane >> 4) + r;
-                H[row * kInfH + col] = to_bf16(gelu(acc[i][j][r] + bc));
-            }
+    for (int st = 0; st < S; ++st) {
+        const int buf = st & 1, u = st % kInfAhead;
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_perm(L, buf, t, l16, q), h[st],
+                                                             acc[t], 0, 0, 0);
+        if (st + 1 < S) stage_store(L, buf ^ 1, tid, rb[(u + 1) % kInfAhead]);
+        if (st + kInfAhead < S) stage_load(Wt, kSurHid, (st + kInfAhead) * kInfK, tid, rb[u]);
+        __syncthreads();
     }
 }
 
-// The whole network for 128 rows per workgroup.
-__global__ __launch_bounds__(256) void k_mlp_infer(InferArgs a)
+// The whole network for 128 rows per workgroup, 16 per wave.
+__global__ __launch_bounds__(kInfThreads) void k_mlp_infer(InferArgs a)
 {
     extern __shared__ float4 lds_v4[];
     InferLds& L = *(InferLds*)lds_v4;
-    const long row0 = (long)blockIdx.x * kInfRows;
-    f32x4 acc[4][8];
-    infer_layer<true>(a.X, row0, a.n, L, a.Wt1, kSurIn, acc);
-    infer_store(acc, a.b1, L.H);
-    infer_layer<false>(nullptr, row0, a.n, L, a.Wt2, kSurHid, acc);
-    infer_store(acc, a.b2, L.H);
-    infer_layer<false>(nullptr, row0, a.n, L, a.Wt3, kSurHid, acc);
-    infer_store(acc, a.b3, L.H);
-    __syncthreads();
-    // output layer: wave w takes rows 32 w .. 32 w + 31, all 16 outputs
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int kq = 8 * (lane >> 4);
-    f32x4 y[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
-    for (int k0 = 0; k0 < kSurHid; k0 += kInfK) {
-        const bf16x8 bv = ld8(a.Wt4 + (long)(lane & 15) * kSurHid + k0 + kq);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, q = lane >> 4;
+    const long row = (long)blockIdx.x * kInfRows + 16 * wave + l16;
+    f32x4 acc[16];
+    bf16x8 h[8];
+    layer_first(a.X, row, a.n, L, a.Wt1, acc);
+    to_frags(acc, a.b1, q, h);
+    layer_hidden(h, L, a.Wt2, acc);
+    to_frags(acc, a.b2, q, h);
+    layer_hidden(h, L, a.Wt3, acc);
+    to_frags(acc, a.b3, q, h);
+    // output layer: one tile of 16 outputs, weights read directly (8 KB)
+    f32x4 y = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const bf16x8 av = *(const bf16x8*)&L.H[(wave * 32 + 16 * i + (lane & 15)) * kInfH + k0 + kq];
-            y[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, y[i], 0, 0, 0);
-        }
+    for (int s = 0; s < 8; ++s) {
+        const uint16_t* w = a.Wt4 + (long)l16 * kSurHid + 32 * s;
+        const bf16v4 lo = *(const bf16v4*)(w + 4 * q), hi = *(const bf16v4*)(w + 16 + 4 * q);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7),
+                                                    h[s], y, 0, 0, 0);
     }
-    const int col = lane & 15;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const long row = row0 + wave * 32 + 16 * i + 4 * (lane >> 4) + r;
-            if (row < a.n) a.Y[row * kSurOut + col] = y[i][r] + a.b4[col];
-        }
+    if (row < a.n) {
+        const float4 b4 = *(const float4*)(a.b4 + 4 * q);
+        *(float4*)(a.Y + row * kSurOut + 4 * q) = make_float4(y[0] + b4.x, y[1] + b4.y, y[2] + b4.z,
+                                                              y[3] + b4.w);
+    }
 }
 
 inline unsigned blocks(long n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -444,16 +449,8 @@ hipError_t launch_transpose_weights(hipStream_t s, const uint16_t* theta_b, uint
 hipError_t launch_mlp_infer(hipStream_t s, const InferArgs& a)
 {
     if (a.n <= 0) return hipSuccess;
-    // more than 64 KiB of dynamic LDS: allowed up to the device's per-block limit
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_mlp_infer,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)sizeof(InferLds));
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks(a.n, kInfRows)), dim3(256), sizeof(InferLds), s, a);
+    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks(a.n, kInfRows)), dim3(kInfThreads), sizeof(InferLds), s,
+                       a);
     return hipGetLastError();
 }
 
