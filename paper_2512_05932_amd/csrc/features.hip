@@ -243,7 +243,8 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
     for (int s = 0; s < 4; ++s) {
         const int q = lane + 64 * s;
         const bool has = rec[s].x > 0.0f;
-        const float dk = has ? (float)(((double)rec[s].x * a.to_bin - ((double)k_ref + 0.5)) / 64.0) : 1.0f;
+        // an input feature (stored as BF16): FP32 suffices
+        const float dk = has ? (rec[s].x * (float)a.to_bin - ((float)k_ref + 0.5f)) * (1.0f / 64.0f) : 1.0f;
         x[q] = to_bf16(fminf(1.0f, fmaxf(-1.0f, dk)));
         x[256 + q] = to_bf16(in[s] ? rec[s].y : 0.0f);
         x[512 + q] = to_bf16(has ? log10f(rec[s].z) / 3.0f : 0.0f);
@@ -279,21 +280,19 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
     asum = wave_sum(asum);
     const float e_tail = bi.scale * wave_maxf(th[lane]);
     const float a_est = a.ambient + a.sun_scale * asum;
+    // the six beam parameters: uniform values, computed once per wave in
+    // FP32 (they are stored as BF16) and picked by lanes 0..5
     if (lane < kSurIn - 1024) {
-        float p = 0.0f;
-        switch (lane) {
-        case 0: p = (float)(((double)(u - Ib * g.cw) + 0.5) / g.cw - 0.5); break;
-        case 1: p = (float)(((double)(v - Jb * g.ch) + 0.5) / g.ch - 0.5); break;
-        case 2: p = (float)(a.el[b] / 90.0); break;
-        case 3: p = (float)(a.az[b] / 180.0); break;
-        case 4:
-            p = a.threshold > 0.0f
-                    ? fminf(2.0f, fmaxf(-4.0f, log10f(fmaxf(a_est, 1e-30f) / a.threshold))) / 4.0f
-                    : 0.0f;
-            break;
-        case 5: p = (float)k_ref / (float)a.R; break;
-        default: p = 0.0f;
-        }
+        const float p0 = ((float)(u - Ib * g.cw) + 0.5f) / (float)g.cw - 0.5f;
+        const float p1 = ((float)(v - Jb * g.ch) + 0.5f) / (float)g.ch - 0.5f;
+        const float p2 = (float)a.el[b] * (1.0f / 90.0f);
+        const float p3 = (float)a.az[b] * (1.0f / 180.0f);
+        const float p4 = a.threshold > 0.0f
+                             ? fminf(2.0f, fmaxf(-4.0f, log10f(fmaxf(a_est, 1e-30f) / a.threshold))) / 4.0f
+                             : 0.0f;
+        const float p5 = (float)k_ref / (float)a.R;
+        const float p = lane == 0 ? p0 : lane == 1 ? p1 : lane == 2 ? p2 : lane == 3 ? p3
+                      : lane == 4 ? p4 : lane == 5 ? p5 : 0.0f;
         x[1024 + lane] = to_bf16(p);
     }
     if (lane == 0) {
