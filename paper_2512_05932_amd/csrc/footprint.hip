@@ -529,52 +529,68 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
     const float T = p.threshold;
     const int nb = conv_taps(p.J) / 8;
     const unsigned nzm = __builtin_amdgcn_readfirstlane(*nzmask);
-#pragma unroll 1
-    for (int g = 0; g < G; ++g) {
-        if (!have[g]) continue;                          // uniform
+    // outputs k0 .. k0 + 7 of pass ps for beam g into o8 (inputs k0 - J ..
+    // k0 + 7 + J: skipped when the gather wrote none of their chunks, the
+    // output is then the floor)
+    auto conv_pass = [&](int g, int ps, float* o8) {
+        const int k0 = ps * kPass + tid * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o8[q] = 0.0f;
+        if (k0 >= R) return;
+        const int c0 = max(0, k0 - p.J) >> nzs, c1 = min(R - 1, k0 + 7 + p.J) >> nzs;
+        const unsigned span = c1 - c0 >= 31 ? ~0u : (2u << (c1 - c0)) - 1u;
+        if ((nzm >> c0) & span) conv8(o8, hist + g * RS + k0 + p.J + conv_shift(p.J), taps, nb);
+    };
+    // xi_hat of pass ps for beam g in place (after every read of it), the
+    // kept waveform and the chunks above the threshold
+    auto write_pass = [&](int g, int ps, const float* o8) {
+        if (ps * kPass >= R) return;                     // uniform
         float* h = hist + g * RS;
-        float o[kMaxPass][8];
+        const int k0 = ps * kPass + tid * 8;
+        float val[8];
+        unsigned m8 = 0;
 #pragma unroll
-        for (int ps = 0; ps < kMaxPass; ++ps) {
-            const int k0 = ps * kPass + tid * 8;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) o[ps][q] = 0.0f;
-            if (k0 >= R) continue;
-            // inputs k0 - J .. k0 + 7 + J: skipped when the gather wrote none
-            // of their chunks (the output is then the floor)
-            const int c0 = max(0, k0 - p.J) >> nzs, c1 = min(R - 1, k0 + 7 + p.J) >> nzs;
-            const unsigned span = c1 - c0 >= 31 ? ~0u : (2u << (c1 - c0)) - 1u;
-            if ((nzm >> c0) & span) conv8(o[ps], h + k0 + p.J + conv_shift(p.J), taps, nb);
+        for (int q = 0; q < 8; ++q) {
+            val[q] = scale[g] * o8[q] + floor_b[g];
+            m8 |= (k0 + q < R && val[q] > T ? 1u : 0u) << q;
         }
-        __syncthreads();                                 // every read of h is done
-        unsigned char* am = (unsigned char*)amask[g];
+        if (k0 + 8 <= R) {
+            *(float4*)(h + k0) = make_float4(val[0], val[1], val[2], val[3]);
+            *(float4*)(h + k0 + 4) = make_float4(val[4], val[5], val[6], val[7]);
+        } else {
 #pragma unroll
-        for (int ps = 0; ps < kMaxPass; ++ps) {
-            if (ps * kPass >= R) continue;               // uniform
-            const int k0 = ps * kPass + tid * 8;
-            float val[8];
-            unsigned m8 = 0;
+            for (int q = 0; q < 8; ++q)
+                if (k0 + q < R) h[k0 + q] = val[q];
+        }
+        if (KEEP) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                val[q] = scale[g] * o[ps][q] + floor_b[g];
-                m8 |= (k0 + q < R && val[q] > T ? 1u : 0u) << q;
-            }
-            if (k0 + 8 <= R) {
-                *(float4*)(h + k0) = make_float4(val[0], val[1], val[2], val[3]);
-                *(float4*)(h + k0 + 4) = make_float4(val[4], val[5], val[6], val[7]);
-            } else {
+            for (int q = 0; q < 8; ++q)
+                if (k0 + q < R) f.waves[(size_t)beam[g] * R + k0 + q] = val[q];
+        }
+        // this wave's 512 bins are chunks 8 * wave .. 8 * wave + 7 of the pass
+        const unsigned byte = bytes_any(__ballot(m8 != 0u));
+        if (lane == 0) ((unsigned char*)amask[g])[ps * 4 + wave] = (unsigned char)byte;
+    };
+    if (R <= kPass) {
+        // one pass: every beam's outputs stay in registers, one barrier
+        float o[G][8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (k0 + q < R) h[k0 + q] = val[q];
-            }
-            if (KEEP) {
+        for (int g = 0; g < G; ++g)
+            if (have[g]) conv_pass(g, 0, o[g]);          // uniform
+        __syncthreads();                                 // every read of the histograms is done
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (k0 + q < R) f.waves[(size_t)beam[g] * R + k0 + q] = val[q];
-            }
-            // this wave's 512 bins are chunks 8 * wave .. 8 * wave + 7 of the pass
-            const unsigned byte = bytes_any(__ballot(m8 != 0u));
-            if (lane == 0) am[ps * 4 + wave] = (unsigned char)byte;
+        for (int g = 0; g < G; ++g)
+            if (have[g]) write_pass(g, 0, o[g]);
+    } else {
+#pragma unroll 1
+        for (int g = 0; g < G; ++g) {
+            if (!have[g]) continue;                      // uniform
+            float o[kMaxPass][8];
+#pragma unroll
+            for (int ps = 0; ps < kMaxPass; ++ps) conv_pass(g, ps, o[ps]);
+            __syncthreads();                             // every read of h is done
+#pragma unroll
+            for (int ps = 0; ps < kMaxPass; ++ps) write_pass(g, ps, o[ps]);
         }
     }
     __syncthreads();
@@ -734,7 +750,7 @@ void k_footprint(FootprintArgs a)
 // and cheap items cost a fraction of a queue atomic each.  Every workgroup
 // exits once the queue is exhausted.
 template <int G, bool SUN, bool KEEP>
-__global__ __launch_bounds__(kFootprintThreads)
+__global__ __launch_bounds__(kFootprintThreads) __attribute__((amdgpu_waves_per_eu(KEEP || SUN ? 1 : 4)))
 void k_footprint_batch(BatchArgs a)
 {
     extern __shared__ float4 lds4[];
