@@ -2,8 +2,8 @@
 // time-bin histograms in LDS -> ambient floor -> pulse convolution ->
 // wavefront-ballot echo detection.  Two kernels share the group body: one
 // workgroup per group of one frame (`k_footprint`), and a persistent kernel
-// that takes (frame, group) items of a whole batch from a work queue
-// (`k_footprint_batch`).
+// that takes tickets of (frame, group) items of a whole batch from a work
+// queue (`k_footprint_batch`).
 //
 // Work decomposition.  A workgroup (4 waves of 64) takes a group of up to G
 // beams formed by the host scheduler from beams close on the raster.  The
@@ -30,7 +30,8 @@
 // The histograms hold sum K * shade; the beam scale S_b is applied in the
 // pulse convolution (in place; 8 output bins per thread and blocks of 8 taps
 // over zero-padded histograms, so the window lives in registers and no read
-// needs a bounds check).  The gather flags the chunks it writes (32 chunks of
+// needs a bounds check; with one pass per waveform all beams' outputs wait in
+// registers for a single barrier).  The gather flags the chunks it writes (32 chunks of
 // 64 or more bins, a register bit mask per lane, OR-reduced per wave):
 // outputs whose inputs lie only in unflagged chunks are the floor without
 // convolving, and the output pass flags the 64-bin chunks holding a bin above
