@@ -183,7 +183,7 @@ def batch_report(args):
     import scenes
     import paper_2512_05932_amd as lidar
     t0 = time.perf_counter()
-    bw = scenes.config3(args.seed)
+    bw = scenes.frame_batch(args.seed)
     gen_s = time.perf_counter() - t0
     planes = [lidar.upload_gbuffer(f.gbuffer, "cuda:0") for f in bw.frames]
     stream = torch.cuda.current_stream()
@@ -222,6 +222,61 @@ def batch_report(args):
             "frames_per_s": info["n_frames"] / (ms * 1e-3),
             "echoes": echoes, "steps": args.batch_steps,
             "setup_s": setup_s, "autotune_ms": info["autotune_ms"], "generate_s": gen_s}
+
+
+def prepass_bytes(w):
+    """Algorithmic HBM bytes of one pre-pass launch: the depth plane for every
+    pixel, the other five planes (reflectance, gain, normal) for pixels with a
+    valid in-range depth, and the 4-column pixel records (8 B, plus 4 B of sun
+    shading with the sun term) for every pixel of the padded width."""
+    import numpy as np
+    d = w.gbuffer.depth.astype(np.float64)
+    H, W = d.shape
+    to_bin = 2.0 / (299792458.0 * w.params.bin_ns * 1e-9)
+    with np.errstate(invalid="ignore"):
+        valid = np.isfinite(d) & (d > 0) & (np.floor(d * to_bin) < w.params.n_bins)
+    W4 = (W + 3) // 4 * 4
+    out = 8 + (4 if w.params.sun_irradiance != 0.0 else 0)
+    return 4 * d.size + 20 * int(valid.sum()) + out * W4 * H
+
+
+def replayed_small_report(args, n_frames=32, steps=20):
+    """HBM-bound case: n_frames 1024x512 frames of i.i.d. surfaces, each
+    with 1000 Gaussian beams of 89 cells, as one replayed graph.  Each frame's
+    compulsory traffic is its G-buffer read once (24 B per pixel) and its
+    echoes and counts written; the fraction is against 8 TB/s."""
+    import torch
+    import scenes
+    import paper_2512_05932_amd as lidar
+    frames = [scenes.iid_frame(args.seed + i) for i in range(n_frames)]
+    planes = [lidar.upload_gbuffer(f.gbuffer, "cuda:0") for f in frames]
+    stream = torch.cuda.current_stream()
+    sim = lidar.LidarSim(frames[0].params, stream=stream)
+    batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(frames, planes)],
+                        [f.pattern for f in frames])
+    sim.simulate_batch(batch)
+    sim.simulate_batch(batch)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        sim.simulate_batch(batch)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    info = sim.batch_info()
+    sim.close()
+    del planes
+    torch.cuda.empty_cache()
+    E = frames[0].params.max_echoes
+    compulsory = sum(24 * f.gbuffer.depth.size + f.pattern.n_beams * (40 * E + 4) for f in frames)
+    gbs = compulsory / (ms * 1e-3) / 1e9
+    return {"workload": f"{n_frames} x 1024x512 i.i.d. frames (40x25 beams), one graph replay",
+            "ms_per_batch": ms, "compulsory_bytes": compulsory, "achieved_GBs": gbs,
+            "peak_GBs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
+            "samples_per_s": info["samples"] / (ms * 1e-3),
+            "beams_per_s": info["n_beams"] / (ms * 1e-3), "steps": steps}
 
 
 SUR_FLOPS_PER_BEAM = 2 * (1056 * 256 + 2 * 256 * 256 + 256 * 16)   # the network's products
@@ -364,7 +419,7 @@ def main():
                               args, "table", train_frames=8, steps=1500, eval_frames=1,
                               oracle_sample=0)}), flush=True)
         return
-    w = scenes.config2(args.seed)
+    w = scenes.road_scan(args.seed)
     stream = torch.cuda.current_stream()
     planes = lidar.upload_gbuffer(w.gbuffer, "cuda:0")
     sim = lidar.LidarSim(w.params, stream=stream, profile=True)
@@ -415,6 +470,18 @@ def main():
                      "avg_launch_ms": fp_ms,
                      "flops_per_launch": flops},
         "prepass_ms": st["prepass_ms"] / max(1, st["prepass_launches"]),
+    }
+    # the HBM-bound parts: the pre-pass streams the G-buffer once per frame,
+    # and small frames replayed in a batch are bound by their compulsory bytes
+    pp_ms = rec["prepass_ms"]
+    pp_bytes = prepass_bytes(w)
+    rec["hbm_roofline"] = {
+        "prepass": {"kernel": "k_prepass", "bound": "hbm", "bytes_per_launch": pp_bytes,
+                    "avg_launch_ms": pp_ms,
+                    "achieved": pp_bytes / (pp_ms * 1e-3) / 1e9 if pp_ms > 0 else None,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": pp_bytes / (pp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if pp_ms > 0 else None},
+        "replayed_iid_frames": replayed_small_report(args) if not args.no_batch else None,
     }
     if not args.no_batch:
         rec["batch"] = batch_report(args)

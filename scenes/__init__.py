@@ -166,7 +166,7 @@ def grid_beams(raster: Raster, n_az: int, n_el: int, az_range=None, el_range=Non
     return aa.ravel().astype(np.float64), ee.ravel().astype(np.float64)
 
 
-def config1(seed: int = 0) -> Workload:
+def iid_frame(seed: int = 0) -> Workload:
     """1024x512 px over 60x30 deg, i.i.d. surfaces, 40x25 grid of Gaussian
     beams (sigma 0.1 deg, cut at 3 sigma), 512 bins of 1 ns, 4 ns FWHM pulse,
     constant ambient, fixed threshold."""
@@ -195,8 +195,8 @@ SENSOR_HEIGHT = 0.5
 # that fills the beam at normal incidence; E_sun puts the median per-beam sun
 # floor near 0.2 T.  Both literals were derived with the FP64 oracle and are
 # re-derived by the test suite (tests/test_workloads.py).
-CONFIG2_THRESHOLD = 9.345e-08
-CONFIG2_SUN_IRRADIANCE = 1.335
+ROAD_THRESHOLD = 9.345e-08
+ROAD_SUN_IRRADIANCE = 1.335
 
 
 def elliptic_table(nx=256, ny=256, half_deg=(2.0, 2.0), fwhm_deg=(0.1, 0.8),
@@ -361,7 +361,7 @@ def road_scene(raster: Raster, rng: np.random.Generator, n_boxes=24,
     return gb, boxes, obj
 
 
-def config2(seed: int = 0, width: int = 8192, height: int = 512,
+def road_scan(seed: int = 0, width: int = 8192, height: int = 512,
             n_lines: int = 16, n_cols: int = 1800) -> Workload:
     """Scanning sensor: 8192x512 px over 145 x 3.2 deg, road + 24 boxes, 1 %
     retroreflective patches with gain 500, 16 x 1800 beams, tabulated 256x256
@@ -377,10 +377,10 @@ def config2(seed: int = 0, width: int = 8192, height: int = 512,
     se, ce = math.sin(math.radians(30.0)), math.cos(math.radians(30.0))
     sun = (ce * math.cos(math.radians(45.0)), ce * math.sin(math.radians(45.0)), se)
     params = SensorParams(n_bins=2048, bin_ns=0.5, max_echoes=3,
-                          threshold=CONFIG2_THRESHOLD, emit_power=1.0,
+                          threshold=ROAD_THRESHOLD, emit_power=1.0,
                           pulse_fwhm_ns=4.0, pulse_trunc_sigmas=4.0,
                           ambient_const=0.0,
-                          sun_irradiance=CONFIG2_SUN_IRRADIANCE, sun_dir=sun)
+                          sun_irradiance=ROAD_SUN_IRRADIANCE, sun_dir=sun)
     name = f"plain-scan-{width}x{height}-{n_lines}x{n_cols}beams-table256"
     return Workload(name, gb, pat, params, {"seed": seed, "boxes": boxes,
                                             "object_id": obj})
@@ -442,21 +442,21 @@ def jitter_beams(raster: Raster, n_az: int, n_el: int, rng: np.random.Generator)
     return az, el
 
 
-CONFIG3_SIZES = ((512, 256), (1024, 512), (2048, 1024), (4096, 2048))
+BATCH_SIZES = ((512, 256), (1024, 512), (2048, 1024), (4096, 2048))
 
 
-def config3_params() -> SensorParams:
+def batch_params() -> SensorParams:
     """Sensor of the batch workload: the scanning sensor's waveform (2048 bins
     of 0.5 ns, 4 ns pulse, threshold) with a constant ambient term instead of
     the sun (the sun floor grows with the footprint's solid angle, which here
     spans three decades)."""
     return SensorParams(n_bins=2048, bin_ns=0.5, max_echoes=3,
-                        threshold=CONFIG2_THRESHOLD, emit_power=1.0,
+                        threshold=ROAD_THRESHOLD, emit_power=1.0,
                         pulse_fwhm_ns=4.0, pulse_trunc_sigmas=4.0,
                         ambient_const=1e-8, sun_irradiance=0.0)
 
 
-def config3(seed: int = 0, n_frames: int = 64, sizes=CONFIG3_SIZES,
+def frame_batch(seed: int = 0, n_frames: int = 64, sizes=BATCH_SIZES,
             beams=(5000, 100000), footprint_px=(20.0, 20000.0),
             fov=(60.0, 30.0), threads: int = 8) -> BatchWorkload:
     """Batch of ``n_frames`` frames: sizes cycled through ``sizes`` (equal
@@ -468,7 +468,7 @@ def config3(seed: int = 0, n_frames: int = 64, sizes=CONFIG3_SIZES,
     sqrt(F / pi) px = 3 sigma).  Smaller ``sizes``/``beams``/``footprint_px``
     give the same recipe at test scale."""
     rng = np.random.default_rng(seed)
-    params = config3_params()
+    params = batch_params()
     size_idx = np.repeat(np.arange(len(sizes)), int(math.ceil(n_frames / len(sizes))))[:n_frames]
     rng.shuffle(size_idx)
 
@@ -579,10 +579,10 @@ def surrogate_frame(seed: int, pattern: str = "gauss", n_lines: int = 64,
     0.0425 x 0.34 deg, cut at 3 sigma) and the batch workload's sensor
     (constant ambient, no sun); "table": the tabulated pattern with its 1e-4
     tails and the scanning sensor's parameters (sun floor)."""
-    w = config2(seed, n_lines=n_lines, n_cols=n_cols)
+    w = road_scan(seed, n_lines=n_lines, n_cols=n_cols)
     if pattern == "table":
         return replace(w, name=f"surrogate-scan-{n_lines}x{n_cols}-table256")
     pat = Pattern(PATTERN_GAUSS, w.pattern.beam_az, w.pattern.beam_el,
                   sigma_deg=(0.0425, 0.34), trunc_sigmas=3.0)
-    return replace(w, pattern=pat, params=config3_params(),
+    return replace(w, pattern=pat, params=batch_params(),
                    name=f"surrogate-scan-{n_lines}x{n_cols}-gauss")

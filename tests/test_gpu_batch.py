@@ -27,7 +27,7 @@ def _gpu():
 def _small_batch(seed=0, n_frames=12):
     """The batch recipe at test scale: 4 raster sizes (ragged, not multiples
     of 4 or 64), 150-1500 beams, footprints of 20-4000 pixels."""
-    return scenes.config3(seed, n_frames=n_frames,
+    return scenes.frame_batch(seed, n_frames=n_frames,
                           sizes=((130, 66), (258, 129), (517, 250), (301, 301)),
                           beams=(150, 1500), footprint_px=(20.0, 4000.0))
 
@@ -150,7 +150,7 @@ def test_batch_full_size_sampled_beams(oracle_mod):
     every frame are checked against the oracle one by one."""
     import torch
     import paper_2512_05932_amd as lidar
-    bw = scenes.config3(0)
+    bw = scenes.frame_batch(0)
     print(f"[batch] full: generated {len(bw.frames)} frames", flush=True)
     planes = _upload(bw)
     sim = lidar.LidarSim(bw.params, stream=torch.cuda.current_stream(), keep_waveforms=False)

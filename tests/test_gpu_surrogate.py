@@ -34,7 +34,7 @@ def lidar():
 
 
 def _scan():
-    return scenes.config2(0, width=2048, height=128, n_lines=16, n_cols=300)
+    return scenes.road_scan(0, width=2048, height=128, n_lines=16, n_cols=300)
 
 
 def _oracle_inputs(w):

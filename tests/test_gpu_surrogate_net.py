@@ -30,7 +30,7 @@ def lidar():
 
 def _sim(lidar):
     import torch
-    w = scenes.config1(0)
+    w = scenes.iid_frame(0)
     return lidar.LidarSim(w.params, stream=torch.cuda.current_stream())
 
 

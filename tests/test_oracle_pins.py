@@ -46,7 +46,7 @@ def test_gaussian_lattice_sum_is_2pi_sigma2(oracle_mod, sig, h):
 def test_gaussian_3sigma_support_has_89_cells(oracle_mod):
     """Workload 1 grid: the 3-sigma disc of sigma = 0.1 deg at 60/1024 deg per
     pixel holds the lattice points m^2 + n^2 <= (0.3 / (60/1024))^2: 89 cells."""
-    w = scenes.config1()
+    w = scenes.iid_frame()
     K = oracle_mod.kernel_grid(w.gbuffer.raster, w.pattern)
     assert K.shape == (11, 11)
     r2 = (0.3 / (60 / 1024)) ** 2
@@ -232,7 +232,7 @@ def test_epw_monotone_intensity_linear_in_power(oracle_mod):
 
 @pytest.fixture(scope="module")
 def w1():
-    return scenes.config1(0)
+    return scenes.iid_frame(0)
 
 
 @pytest.fixture(scope="module")

@@ -15,11 +15,11 @@ import scenes
 
 @pytest.fixture(scope="module")
 def w2():
-    return scenes.config2(0)
+    return scenes.road_scan(0)
 
 
-def test_config1_recipe_and_echo_statistics(oracle_mod):
-    w = scenes.config1(0)
+def test_iid_frame_recipe_and_echo_statistics(oracle_mod):
+    w = scenes.iid_frame(0)
     gb = w.gbuffer
     assert gb.depth.shape == (512, 1024)
     assert 5.0 <= gb.depth.min() and gb.depth.max() <= 60.0
@@ -32,7 +32,7 @@ def test_config1_recipe_and_echo_statistics(oracle_mod):
     assert (res.n_echoes == 0).mean() < 0.5
 
 
-def test_config2_threshold_literal(oracle_mod, w2):
+def test_road_scan_threshold_literal(oracle_mod, w2):
     """T = 5 % of the pulse-convolved peak of a rho = 0.5 face at 100 m filling
     the beam: that face gives xi = P_e rho / (pi d^2) in one bin."""
     taps = oracle_mod.pulse_taps(w2.params)
@@ -40,7 +40,7 @@ def test_config2_threshold_literal(oracle_mod, w2):
     assert w2.params.threshold == pytest.approx(0.05 * peak, rel=1e-3)
 
 
-def test_config2_recipe_sun_floor_and_blooming(oracle_mod, w2):
+def test_road_scan_recipe_sun_floor_and_blooming(oracle_mod, w2):
     gb = w2.gbuffer
     assert gb.depth.shape == (512, 8192)
     assert 0.01 <= (gb.retro_gain > 1).mean() < 0.013
