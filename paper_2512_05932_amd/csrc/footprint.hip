@@ -76,6 +76,24 @@ __device__ inline int wave_min(int x)
     return __builtin_amdgcn_readlane(x, 63);
 }
 
+template <int CTRL, int ROW_MASK>
+__device__ inline float dpp_maxf(float v)
+{
+    return fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(
+                        __float_as_int(-INFINITY), __float_as_int(v), CTRL, ROW_MASK, 0xf, false)));
+}
+
+__device__ inline float wave_maxf(float x)
+{
+    x = dpp_maxf<0xb1, 0xf>(x);
+    x = dpp_maxf<0x4e, 0xf>(x);
+    x = dpp_maxf<0x141, 0xf>(x);
+    x = dpp_maxf<0x140, 0xf>(x);
+    x = dpp_maxf<0x142, 0xa>(x);
+    x = dpp_maxf<0x143, 0xc>(x);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
 __device__ inline int wave_max(int x)
 {
     x = dpp_max<0xb1, 0xf>(x);
@@ -634,27 +652,21 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
                 const int k1 = base + pe;
                 if (count < p.E) {
                     // first maximum of the run
-                    float best = -INFINITY;
-                    int bk = INT_MAX;
+                    float lbest = -INFINITY;                 // this lane's first maximum
+                    int lbk = INT_MAX;
                     for (int s = k0; s <= k1; s += 64) {
                         const int kk = s + lane;
                         if (kk <= k1) {
                             const float x = xh[kk];
-                            if (x > best) {
-                                best = x;
-                                bk = kk;
+                            if (x > lbest) {
+                                lbest = x;
+                                lbk = kk;
                             }
                         }
                     }
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) {
-                        const float ob = __shfl_xor(best, o);
-                        const int oi = __shfl_xor(bk, o);
-                        if (ob > best || (ob == best && oi < bk)) {
-                            best = ob;
-                            bk = oi;
-                        }
-                    }
+                    // the largest value, then the smallest bin holding it
+                    const float best = wave_maxf(lbest);
+                    const int bk = wave_min(lbest == best ? lbk : INT_MAX);
                     if (lane == 0) {
                         // threshold crossings between bin centres, as
                         // fractions of a bin from the centre of the bin before
@@ -694,9 +706,9 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
         if (lane == 0) {
             f.counts[beam[g]] = count;
             f.beams[beam[g]].floor = floor_b[g];
-            lidar_echo z = {};
-            for (int i = count; i < p.E; ++i) out[i] = z;
         }
+        const lidar_echo z = {};
+        for (int i = count + lane; i < p.E; i += 64) out[i] = z;
     }
 }
 
