@@ -28,8 +28,8 @@ def _small_batch(seed=0, n_frames=12):
     """The batch recipe at test scale: 4 raster sizes (ragged, not multiples
     of 4 or 64), 150-1500 beams, footprints of 20-4000 pixels."""
     return scenes.frame_batch(seed, n_frames=n_frames,
-                          sizes=((130, 66), (258, 129), (517, 250), (301, 301)),
-                          beams=(150, 1500), footprint_px=(20.0, 4000.0))
+                              sizes=((130, 66), (258, 129), (517, 250), (301, 301)),
+                              beams=(150, 1500), footprint_px=(20.0, 4000.0))
 
 
 def _upload(bw):
