@@ -155,7 +155,9 @@ typedef struct {
     uint32_t grid;             /* workgroups of the persistent launch */
     uint32_t graph;            /* 1 when the batch replays a captured HIP graph */
     uint32_t autotuned;        /* 1 when the tiles came from timed trials */
-    uint32_t reserved;
+    uint32_t wave_items;       /* items of frames on the wave schedule (one wave per
+                                  item instead of one workgroup; see the frames'
+                                  schedule in lidar_sim_simulate_batch) */
     double autotune_ms;        /* time spent in the trials */
 } lidar_batch_info;
 
@@ -234,10 +236,13 @@ lidar_status lidar_sim_read_echoes(lidar_sim* h, lidar_echo* echoes, int32_t* n_
  * frame uses the handle's sensor parameters.  The first call with a set of
  * descriptors copies the patterns, resamples every frame's kernel, forms the
  * beam groups of all frames into one work list ordered by estimated cost
- * (costliest first), optionally autotunes the strip height of each
- * kernel-size class (LIDAR_AUTOTUNE), and captures the whole batch - per-frame
- * pre-passes plus one persistent footprint launch that takes work items from
- * a queue - into a HIP graph.  Later calls with identical descriptors (same
+ * (costliest first), picks each frame's schedule - the group schedule (a
+ * workgroup per beam group) or, for frames whose groups mostly hold one beam,
+ * the wave schedule (each wave of a workgroup takes its own groups; only with
+ * 4-beam groups and n_bins <= 2048) - optionally autotunes the strip height
+ * and the schedule of each kernel-size class (LIDAR_AUTOTUNE), and captures
+ * the whole batch - per-frame pre-passes plus one persistent footprint launch
+ * per schedule, each taking work items from a queue - into a HIP graph.  Later calls with identical descriptors (same
  * pointers, sizes and values) only replay the graph; the caller may change the
  * contents of the G-buffer planes between calls, but not the host pattern or
  * beam arrays (call lidar_sim_reset_batch after changing those in place).

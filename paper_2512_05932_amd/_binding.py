@@ -84,7 +84,7 @@ class lidar_train_hparams(C.Structure):
 class lidar_batch_info(C.Structure):
     _fields_ = [("n_frames", C.c_uint32), ("group_size", C.c_uint32), ("n_beams", C.c_uint64),
                 ("n_items", C.c_uint64), ("samples", C.c_uint64), ("grid", C.c_uint32),
-                ("graph", C.c_uint32), ("autotuned", C.c_uint32), ("reserved", C.c_uint32),
+                ("graph", C.c_uint32), ("autotuned", C.c_uint32), ("wave_items", C.c_uint32),
                 ("autotune_ms", C.c_double)]
 
 

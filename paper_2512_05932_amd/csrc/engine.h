@@ -15,6 +15,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxBins = 8000;                  // one padded waveform + taps fit the LDS of a group
 constexpr int kMaxTaps = 257;
 constexpr int kPassBins = 2048;                 // bins per convolution pass (8 per thread)
+constexpr int kWaveMaxBins = 2048;              // longest waveform of the wave schedule (in registers)
 // chunks of 1 << chunk_shift(R) bins (at least 64) cover R bins with at most 32
 __host__ __device__ constexpr int chunk_shift(int R)
 {
@@ -42,7 +43,10 @@ inline size_t group_lds_bytes(int G, int R, int J)
     return sizeof(float) * ((size_t)G * conv_stride(R, J) + conv_taps(J));
 }
 constexpr int kFootprintThreads = 256;          // 4 waves of 64
+constexpr int kWavesPerGroup = kFootprintThreads / 64;
 constexpr int kXcds = 8;                        // MI355X: 8 XCDs, round-robin dispatch
+constexpr int kQueueStride = 32;                // ints between ticket counters (128 bytes)
+constexpr int kQueueInts = kXcds * kQueueStride;  // one ticket dispenser
 
 // Pattern as the set-up kernels see it (device copy of the table).
 struct PatternDev {
@@ -117,6 +121,7 @@ struct FrameDev {
     int M, N, KW, KH, NB;
     int tile;                   // strip height: 64, 16 or 4 rows (64/tile column phases)
     float sun_scale;            // E_sun / max K (0: no sun term)
+    int wave;                   // batches: 1 = the frame's items go to the wave schedule
     lidar_beam_info* beams;     // [B] in: pixel, scale; out: floor
     lidar_echo* echoes;         // [B][E]
     int32_t* counts;            // [B]
@@ -148,7 +153,8 @@ struct BatchArgs {
     const int32_t* groups;      // [total groups][G]: each frame's groups, concatenated
     const int2* items;          // [n_items] {frame, global group index}, costliest first
     int n_items, G;
-    int* next_item;             // work-queue counter (zeroed by k_reset_queue)
+    int* next_item;             // work-queue counter(s), zeroed by k_reset_queue: with tickets
+                                // kXcds counters kQueueStride ints apart, else one
     const int* n_items_dev;     // if set: the item count, read on the device
     // if set: the queue hands out tickets, ticket t = items [tickets[t],
     // tickets[t + 1]) (non-empty); else one item per queue step
@@ -157,7 +163,11 @@ struct BatchArgs {
 };
 hipError_t launch_footprint_batch(hipStream_t s, const BatchArgs& a, int grid, bool sun,
                                   bool keep);
-hipError_t launch_reset_queue(hipStream_t s, int* counter, int n = 1);  // n <= 64 ints
+// the wave schedule over the tickets of a (kWavesPerGroup beams per group,
+// R <= kWaveMaxBins); each wave takes tickets from *next_item
+hipError_t launch_footprint_batch_wave(hipStream_t s, const BatchArgs& a, int grid, bool sun,
+                                       bool keep);
+hipError_t launch_reset_queue(hipStream_t s, int* counter, int n = 1);
 // whether G histograms of R bins plus the pulse taps fit the LDS budget
 bool footprint_group_fits(int G, int R, int J);
 

@@ -239,14 +239,13 @@ __device__ inline T ld16(const char* base, unsigned byte_off)
     return *(const T*)(base + byte_off);
 }
 
-// Gather of one group's union footprint into the G histograms (strips of
-// SH rows, 64/SH column phases); adds this lane's per-beam sun sums to sacc.
+// Gather of the union footprint of G beams into their histograms (strips of
+// SH rows, 64/SH column phases) by nw waves, this one taking items it0,
+// it0 + nw, ...; adds this lane's per-beam sun sums to sacc.
 template <int G, int SH, bool SUN>
-__device__ inline void gather_group(const FrameDev& f, const int* ub, const int* vb,
-                                    const bool* have, int r0, int r1, int q0, int q1,
-                                    float* hist, int stride, unsigned* nzmask, int nzs, int lane,
-                                    int wave,
-                                    float* sacc)
+__device__ __attribute__((always_inline)) inline void gather_group(
+    const FrameDev& f, const int* ub, const int* vb, const bool* have, int r0, int r1, int q0, int q1,
+    float* hist, int stride, unsigned* nzmask, int nzs, int lane, int it0, int nw, float* sacc)
 {
     constexpr int P = 64 / SH;                      // column phases per strip
     const int row_in = lane % SH, phase = lane / SH;
@@ -256,7 +255,7 @@ __device__ inline void gather_group(const FrameDev& f, const int* ub, const int*
     const int ncols = q1 - q0a + 1;
     // column chunks give every wave work when a group has few strips (a
     // chunk spans at least 32 columns and two rounds of the column phases)
-    int nchunk = (2 * kWaves + nstrips - 1) / nstrips;
+    int nchunk = nw > 1 ? (2 * nw + nstrips - 1) / nstrips : 1;
     nchunk = min(nchunk, max(1, ncols / max(32, 8 * P)));
     const int cw = (((ncols + nchunk - 1) / nchunk) + 3) & ~3;
     const int items = nstrips * nchunk;
@@ -264,7 +263,7 @@ __device__ inline void gather_group(const FrameDev& f, const int* ub, const int*
     const size_t copy_bytes = (size_t)f.NB * khp16;
     const size_t pstep = (size_t)f.H * 32u, sstep = (size_t)f.H * 16u;
     unsigned nzb = 0u;                                  // chunks this lane wrote
-    for (int it = wave; it < items; it += kWaves) {
+    for (int it = it0; it < items; it += nw) {
         const int s = it / nchunk, ch = it - s * nchunk;
         const int v = r0 + s * SH + row_in;
         const bool rowok = v <= r1;
@@ -461,6 +460,158 @@ __device__ inline unsigned bytes_any(unsigned long long b)
     return (unsigned)((b * 0x0102040810204080ull) >> 56);
 }
 
+// Pulse convolution outputs k0 .. k0 + 7 of histogram h (before the scale
+// and the floor; zero from bin R on), skipped when the gather wrote none of
+// the chunks holding their inputs (nzm, chunks of 1 << nzs bins).
+__device__ inline void conv_out8(const float* h, const float* taps, const PathDev& p, int nb, int k0,
+                                 unsigned nzm, int nzs, float* o8)
+{
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o8[q] = 0.0f;
+    if (k0 >= p.R) return;
+    const int c0 = max(0, k0 - p.J) >> nzs, c1 = min(p.R - 1, k0 + 7 + p.J) >> nzs;
+    const unsigned span = c1 - c0 >= 31 ? ~0u : (2u << (c1 - c0)) - 1u;
+    if ((nzm >> c0) & span) conv8(o8, h + k0 + p.J + conv_shift(p.J), taps, nb);
+}
+
+// xi_hat = scale * o8 + floor into bins k0 .. k0 + 7 (below R) of h, in place,
+// and of the kept waveform; bit q of the result: bin k0 + q is above T.
+template <bool KEEP>
+__device__ inline unsigned write_out8(float* h, float* kept, int k0, int R, float scale, float floor_b,
+                                      float T, const float* o8)
+{
+    float val[8];
+    unsigned m8 = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        val[q] = scale * o8[q] + floor_b;
+        m8 |= (k0 + q < R && val[q] > T ? 1u : 0u) << q;
+    }
+    if (k0 + 8 <= R) {
+        *(float4*)(h + k0) = make_float4(val[0], val[1], val[2], val[3]);
+        *(float4*)(h + k0 + 4) = make_float4(val[4], val[5], val[6], val[7]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k0 + q < R) h[k0 + q] = val[q];
+    }
+    if (KEEP) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k0 + q < R) kept[k0 + q] = val[q];
+    }
+    return m8;
+}
+
+// Echoes of one waveform xh (xi_hat in LDS) by one wave: maximal runs above
+// the threshold found with 64-bin ballots over the chunks flagged in am (bit
+// c of word w: chunk 32 w + c of 64 bins holds a bin above T; a run cannot
+// cross another chunk), their first maximum, crossings and pulse width
+// (section II-C, EPW paragraph); writes the first E echoes, the count of all
+// runs and the floor.
+__device__ inline void detect_echoes(const FrameDev& f, const PathDev& p, int beam, const float* xh,
+                                     const unsigned* am, float floor_b, int lane)
+{
+    const int R = p.R;
+    const float T = p.threshold;
+    const float dt = (float)p.bin_ns;
+    lidar_echo* out = f.echoes + (size_t)beam * p.E;
+    int count = 0;
+    int k0 = -1;                                         // first bin of the open run
+    const int nw = (R + kPassBins - 1) / kPassBins;      // mask words of 32 chunks
+    int w = 0;
+    unsigned bits = __builtin_amdgcn_readfirstlane(am[0]);
+    for (;;) {
+        while (bits == 0u && ++w < nw) bits = __builtin_amdgcn_readfirstlane(am[w]);
+        if (bits == 0u) break;
+        const int base = (w * 32 + __builtin_ctz(bits)) * 64;
+        bits &= bits - 1u;
+        const int k = base + lane;
+        const bool above = k < R && xh[k] > T;
+        const unsigned long long mask = __ballot(above);
+        const bool next_above = base + 64 < R && xh[base + 64] > T;
+        const unsigned long long prev = (mask << 1) | (k0 >= 0 ? 1ull : 0ull);
+        const unsigned long long nxt = (mask >> 1) | (next_above ? (1ull << 63) : 0ull);
+        unsigned long long starts = mask & ~prev;
+        unsigned long long ends = mask & ~nxt;
+        while (starts | ends) {
+            const int ps = starts ? __builtin_ctzll(starts) : 64;
+            const int pe = ends ? __builtin_ctzll(ends) : 64;
+            if (ps <= pe) {
+                k0 = base + ps;
+                starts &= starts - 1;
+                continue;
+            }
+            ends &= ends - 1;
+            const int k1 = base + pe;
+            if (count < p.E) {
+                // first maximum of the run
+                float lbest = -INFINITY;                 // this lane's first maximum
+                int lbk = INT_MAX;
+                for (int s = k0; s <= k1; s += 64) {
+                    const int kk = s + lane;
+                    if (kk <= k1) {
+                        const float x = xh[kk];
+                        if (x > lbest) {
+                            lbest = x;
+                            lbk = kk;
+                        }
+                    }
+                }
+                // the largest value, then the smallest bin holding it
+                const float best = wave_maxf(lbest);
+                const int bk = wave_min(lbest == best ? lbk : INT_MAX);
+                if (lane == 0) {
+                    // threshold crossings between bin centres, as fractions of
+                    // a bin from the centre of the bin before the run and from
+                    // the centre of its last bin
+                    float f_up, f_dn;
+                    uint32_t flags = 0;
+                    if (k0 == 0) {
+                        f_up = 0.5f;
+                        flags |= LIDAR_ECHO_AT_FIRST_BIN;
+                    } else {
+                        const float xa = xh[k0 - 1], xb = xh[k0];
+                        f_up = (T - xa) / (xb - xa);
+                    }
+                    if (k1 == R - 1) {
+                        f_dn = 0.5f;
+                        flags |= LIDAR_ECHO_AT_LAST_BIN;
+                    } else {
+                        const float xa = xh[k1], xb = xh[k1 + 1];
+                        f_dn = (xa - T) / (xa - xb);
+                    }
+                    lidar_echo e;
+                    e.range_m = ((double)bk + 0.5) * p.half_c_dt;
+                    e.time_ns = ((double)bk + 0.5) * p.bin_ns;
+                    e.intensity = best - floor_b;
+                    e.pulse_width_ns = ((float)(k1 - k0 + 1) + f_dn - f_up) * dt;
+                    e.bin_peak = bk;
+                    e.bin_first = k0;
+                    e.bin_last = k1;
+                    e.flags = flags;
+                    out[count] = e;
+                }
+            }
+            ++count;
+            k0 = -1;
+        }
+    }
+    if (lane == 0) {
+        f.counts[beam] = count;
+        f.beams[beam].floor = floor_b;
+    }
+    const lidar_echo z = {};
+    for (int i = count + lane; i < p.E; i += 64) out[i] = z;
+}
+
+// LDS written by some lanes of this wave is read by others after this point.
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // The whole group after the histograms were zeroed: gather, floor, pulse,
 // echoes.  All threads of the workgroup call it with the same group.  hist is
 // beam 0's histogram, beam g's starts RS floats further (zero padding around
@@ -468,7 +619,7 @@ __device__ inline unsigned bytes_any(unsigned long long b)
 // the gather wrote, amask the 64-bin chunks of
 // each waveform that hold a bin above the threshold.
 template <int G, bool SUN, bool KEEP>
-__device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t* grp,
+__device__ __attribute__((always_inline)) inline void process_group(const FrameDev& f, const PathDev& p, const int32_t* grp,
                               float* hist, const float* taps, float (*red)[kWaves],
                               unsigned* nzmask, unsigned (*amask)[kMaxBins / kPassBins + 1])
 {
@@ -512,13 +663,13 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
     if (r0 <= r1 && q0 <= q1) {
         if (f.tile == 64)
             gather_group<G, 64, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane, wave,
-                                     sacc);
+                                     kWaves, sacc);
         else if (f.tile == 16)
             gather_group<G, 16, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane, wave,
-                                     sacc);
+                                     kWaves, sacc);
         else
             gather_group<G, 4, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane, wave,
-                                     sacc);
+                                    kWaves, sacc);
     }
     if (SUN) {
 #pragma unroll
@@ -548,45 +699,17 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
     const float T = p.threshold;
     const int nb = conv_taps(p.J) / 8;
     const unsigned nzm = __builtin_amdgcn_readfirstlane(*nzmask);
-    // outputs k0 .. k0 + 7 of pass ps for beam g into o8 (inputs k0 - J ..
-    // k0 + 7 + J: skipped when the gather wrote none of their chunks, the
-    // output is then the floor)
+    // outputs k0 .. k0 + 7 of pass ps for beam g into o8
     auto conv_pass = [&](int g, int ps, float* o8) {
-        const int k0 = ps * kPass + tid * 8;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) o8[q] = 0.0f;
-        if (k0 >= R) return;
-        const int c0 = max(0, k0 - p.J) >> nzs, c1 = min(R - 1, k0 + 7 + p.J) >> nzs;
-        const unsigned span = c1 - c0 >= 31 ? ~0u : (2u << (c1 - c0)) - 1u;
-        if ((nzm >> c0) & span) conv8(o8, hist + g * RS + k0 + p.J + conv_shift(p.J), taps, nb);
+        conv_out8(hist + g * RS, taps, p, nb, ps * kPass + tid * 8, nzm, nzs, o8);
     };
     // xi_hat of pass ps for beam g in place (after every read of it), the
-    // kept waveform and the chunks above the threshold
+    // kept waveform and the chunks above the threshold (this wave's 512 bins
+    // are chunks 8 * wave .. 8 * wave + 7 of the pass)
     auto write_pass = [&](int g, int ps, const float* o8) {
         if (ps * kPass >= R) return;                     // uniform
-        float* h = hist + g * RS;
-        const int k0 = ps * kPass + tid * 8;
-        float val[8];
-        unsigned m8 = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            val[q] = scale[g] * o8[q] + floor_b[g];
-            m8 |= (k0 + q < R && val[q] > T ? 1u : 0u) << q;
-        }
-        if (k0 + 8 <= R) {
-            *(float4*)(h + k0) = make_float4(val[0], val[1], val[2], val[3]);
-            *(float4*)(h + k0 + 4) = make_float4(val[4], val[5], val[6], val[7]);
-        } else {
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (k0 + q < R) h[k0 + q] = val[q];
-        }
-        if (KEEP) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (k0 + q < R) f.waves[(size_t)beam[g] * R + k0 + q] = val[q];
-        }
-        // this wave's 512 bins are chunks 8 * wave .. 8 * wave + 7 of the pass
+        const unsigned m8 = write_out8<KEEP>(hist + g * RS, KEEP ? f.waves + (size_t)beam[g] * R : nullptr,
+                                             ps * kPass + tid * 8, R, scale[g], floor_b[g], T, o8);
         const unsigned byte = bytes_any(__ballot(m8 != 0u));
         if (lane == 0) ((unsigned char*)amask[g])[ps * 4 + wave] = (unsigned char)byte;
     };
@@ -614,102 +737,65 @@ __device__ void process_group(const FrameDev& f, const PathDev& p, const int32_t
     }
     __syncthreads();
 
-    // echo detection: wave w takes beams w, w + 4, ...; only the chunks with
-    // a bin above the threshold are visited (a run cannot cross another chunk)
-    const float dt = (float)p.bin_ns;
+    // echo detection: wave w takes beams w, w + 4, ...
 #pragma unroll 1
-    for (int g = wave; g < G; g += kWaves) {
-        if (!have[g]) continue;
-        const float* xh = hist + g * RS;
-        lidar_echo* out = f.echoes + (size_t)beam[g] * p.E;
-        int count = 0;
-        int k0 = -1;                                     // first bin of the open run
-        const int nw = (R + kPass - 1) / kPass;         // mask words, one per pass
-        int w = 0;
-        unsigned bits = __builtin_amdgcn_readfirstlane(amask[g][0]);
-        for (;;) {
-            while (bits == 0u && ++w < nw) bits = __builtin_amdgcn_readfirstlane(amask[g][w]);
-            if (bits == 0u) break;
-            const int base = (w * 32 + __builtin_ctz(bits)) * 64;
-            bits &= bits - 1u;
-            const int k = base + lane;
-            const bool above = k < R && xh[k] > T;
-            const unsigned long long mask = __ballot(above);
-            const bool next_above = base + 64 < R && xh[base + 64] > T;
-            const unsigned long long prev = (mask << 1) | (k0 >= 0 ? 1ull : 0ull);
-            const unsigned long long nxt = (mask >> 1) | (next_above ? (1ull << 63) : 0ull);
-            unsigned long long starts = mask & ~prev;
-            unsigned long long ends = mask & ~nxt;
-            while (starts | ends) {
-                const int ps = starts ? __builtin_ctzll(starts) : 64;
-                const int pe = ends ? __builtin_ctzll(ends) : 64;
-                if (ps <= pe) {
-                    k0 = base + ps;
-                    starts &= starts - 1;
-                    continue;
-                }
-                ends &= ends - 1;
-                const int k1 = base + pe;
-                if (count < p.E) {
-                    // first maximum of the run
-                    float lbest = -INFINITY;                 // this lane's first maximum
-                    int lbk = INT_MAX;
-                    for (int s = k0; s <= k1; s += 64) {
-                        const int kk = s + lane;
-                        if (kk <= k1) {
-                            const float x = xh[kk];
-                            if (x > lbest) {
-                                lbest = x;
-                                lbk = kk;
-                            }
-                        }
-                    }
-                    // the largest value, then the smallest bin holding it
-                    const float best = wave_maxf(lbest);
-                    const int bk = wave_min(lbest == best ? lbk : INT_MAX);
-                    if (lane == 0) {
-                        // threshold crossings between bin centres, as
-                        // fractions of a bin from the centre of the bin before
-                        // the run and from the centre of its last bin
-                        float f_up, f_dn;
-                        uint32_t flags = 0;
-                        if (k0 == 0) {
-                            f_up = 0.5f;
-                            flags |= LIDAR_ECHO_AT_FIRST_BIN;
-                        } else {
-                            const float xa = xh[k0 - 1], xb = xh[k0];
-                            f_up = (T - xa) / (xb - xa);
-                        }
-                        if (k1 == R - 1) {
-                            f_dn = 0.5f;
-                            flags |= LIDAR_ECHO_AT_LAST_BIN;
-                        } else {
-                            const float xa = xh[k1], xb = xh[k1 + 1];
-                            f_dn = (xa - T) / (xa - xb);
-                        }
-                        lidar_echo e;
-                        e.range_m = ((double)bk + 0.5) * p.half_c_dt;
-                        e.time_ns = ((double)bk + 0.5) * p.bin_ns;
-                        e.intensity = best - floor_b[g];
-                        e.pulse_width_ns = ((float)(k1 - k0 + 1) + f_dn - f_up) * dt;
-                        e.bin_peak = bk;
-                        e.bin_first = k0;
-                        e.bin_last = k1;
-                        e.flags = flags;
-                        out[count] = e;
-                    }
-                }
-                ++count;
-                k0 = -1;
-            }
-        }
-        if (lane == 0) {
-            f.counts[beam[g]] = count;
-            f.beams[beam[g]].floor = floor_b[g];
-        }
-        const lidar_echo z = {};
-        for (int i = count + lane; i < p.E; i += 64) out[i] = z;
+    for (int g = wave; g < G; g += kWaves)
+        if (have[g]) detect_echoes(f, p, beam[g], hist + g * RS, amask[g], floor_b[g], lane);
+}
+
+// One beam by one wave (the wave schedule of a batch), after the wave zeroed
+// its histogram slot hist (zero padding around it) and its chunk flags nzw:
+// the steps of process_group with wave-local ordering only, the convolution in
+// passes of 512 bins (8 per lane; R <= kWavePassBins * kWavePasses).
+constexpr int kWavePassBins = 512;
+constexpr int kWavePasses = kWaveMaxBins / kWavePassBins;
+
+template <bool SUN, bool KEEP>
+__device__ __attribute__((always_inline)) inline void process_beam_wave(
+    const FrameDev& f, const PathDev& p, int beam, float* hist, int RS, const float* taps, unsigned* nzw,
+    unsigned* am, int lane)
+{
+    const int R = p.R;
+    const int nzs = chunk_shift(R);
+    const lidar_beam_info bi = load_uniform(f.beams + beam);
+    const int u = __builtin_amdgcn_readfirstlane(bi.pixel_u);
+    const int v = __builtin_amdgcn_readfirstlane(bi.pixel_v);
+    const float scale = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+        __builtin_bit_cast(int, bi.scale)));
+    const int r0 = (int)max(0L, (long)v - f.N), r1 = (int)min((long)f.H - 1, (long)v + f.N);
+    const int q0 = (int)max(0L, (long)u - f.M), q1 = (int)min((long)f.W - 1, (long)u + f.M);
+    const bool one = true;
+    float sacc = 0.0f;
+    if (r0 <= r1 && q0 <= q1) {
+        if (f.tile == 64)
+            gather_group<1, 64, SUN>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
+        else if (f.tile == 16)
+            gather_group<1, 16, SUN>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
+        else
+            gather_group<1, 4, SUN>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
     }
+    float floor_b = p.ambient;
+    if (SUN) floor_b += f.sun_scale * wave_total(sacc);
+    wave_sync();                                         // the histogram is complete
+    const unsigned nzm = __builtin_amdgcn_readfirstlane(*nzw);
+    const int nb = conv_taps(p.J) / 8;
+    float o[kWavePasses][8];
+#pragma unroll
+    for (int ps = 0; ps < kWavePasses; ++ps)
+        conv_out8(hist, taps, p, nb, ps * kWavePassBins + lane * 8, nzm, nzs, o[ps]);
+    wave_sync();                                         // every read of the histogram is done
+    unsigned word = 0;                                   // chunks above the threshold
+#pragma unroll
+    for (int ps = 0; ps < kWavePasses; ++ps) {
+        if (ps * kWavePassBins >= R) break;              // uniform
+        const unsigned m8 = write_out8<KEEP>(hist, KEEP ? f.waves + (size_t)beam * R : nullptr,
+                                             ps * kWavePassBins + lane * 8, R, scale, floor_b,
+                                             p.threshold, o[ps]);
+        word |= bytes_any(__ballot(m8 != 0u)) << (8 * ps);
+    }
+    if (lane == 0) am[0] = word;
+    wave_sync();
+    detect_echoes(f, p, beam, hist, am, floor_b, lane);
 }
 
 }  // namespace
@@ -757,6 +843,22 @@ void k_footprint(FootprintArgs a)
                                 amask);
 }
 
+// Next ticket from the dispenser of a batch: kXcds counters kQueueStride ints
+// apart, counter c handing out tickets c, c + kXcds, ... (so the costliest
+// tickets still go first).  A worker starts at its XCD's counter and moves to
+// the next one when it runs dry; the atomics of the workers are spread over
+// eight addresses instead of serialising on one.  Returns n when every
+// counter is exhausted.
+__device__ inline int next_ticket(int* q, int& c, int n)
+{
+    for (int tried = 0; tried < kXcds; ++tried) {
+        const int t = atomicAdd(q + c * kQueueStride, 1) * kXcds + c;
+        if (t < n) return t;
+        c = c + 1 == kXcds ? 0 : c + 1;
+    }
+    return n;
+}
+
 // Persistent kernel over the items of a batch: each workgroup repeatedly
 // takes the next ticket (a run of items, costliest first) from the queue, so
 // frames of very different sizes share the GPU without a tail of idle CUs,
@@ -777,8 +879,9 @@ void k_footprint_batch(BatchArgs a)
     const int tid = threadIdx.x;
     load_taps(taps, a.p.taps, a.p.J, tid);
     const int n_tickets = a.tickets ? a.n_tickets : (a.n_items_dev ? *a.n_items_dev : a.n_items);
+    int qc = blockIdx.x % kXcds;                         // this workgroup's XCD (round-robin dispatch)
     for (;;) {
-        if (tid == 0) item_sh = atomicAdd(a.next_item, 1);
+        if (tid == 0) item_sh = a.tickets ? next_ticket(a.next_item, qc, n_tickets) : atomicAdd(a.next_item, 1);
         clear_group(lds4, G * RS / 4, &nzmask, tid);
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(item_sh);
@@ -803,9 +906,57 @@ void k_footprint_batch(BatchArgs a)
     }
 }
 
+// Wave schedule of a batch (frames whose groups are mostly single beams with
+// small footprints, where three of the four waves of a group would idle):
+// every wave of the persistent workgroups takes tickets from its own queue
+// counter and processes the items' beams one by one in its own histogram slot,
+// with no workgroup barrier after the taps are loaded; the workgroup's LDS is
+// that of a group of kWaves beams.  Every wave exits once its queue is empty.
+template <bool SUN, bool KEEP>
+__global__ __launch_bounds__(kFootprintThreads) __attribute__((amdgpu_waves_per_eu(KEEP || SUN ? 1 : 4)))
+void k_footprint_batch_wave(BatchArgs a)
+{
+    constexpr int G = kWaves;
+    extern __shared__ float4 lds4[];
+    const int RS = conv_stride(a.p.R, a.p.J);
+    float* taps = (float*)lds4 + G * RS;
+    __shared__ unsigned nzw[kWaves];
+    __shared__ unsigned amask[kWaves][kMaxBins / kPassBins + 1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    load_taps(taps, a.p.taps, a.p.J, tid);
+    clear_group(lds4, G * RS / 4, &nzw[0], tid);        // the zero paddings stay zero
+    __syncthreads();
+    float4* slot4 = lds4 + wave * (RS / 4);             // RS is a multiple of 4
+    float* hist = (float*)slot4 + conv_pad(a.p.J);
+    int qc = blockIdx.x % kXcds;                         // this workgroup's XCD (round-robin dispatch)
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = next_ticket(a.next_item, qc, a.n_tickets);
+        t = __builtin_amdgcn_readlane(t, 0);
+        if (t >= a.n_tickets) break;                     // uniform over the wave
+        const int i0 = load_uniform(a.tickets + t), i1 = load_uniform(a.tickets + t + 1);
+        for (int item = i0; item < i1; ++item) {
+            const int2 it = load_uniform(a.items + item);
+            const FrameDev f = load_uniform(a.frames + it.x);
+#pragma unroll 1
+            for (int m = 0; m < G; ++m) {
+                const int beam = load_uniform(a.groups + (size_t)it.y * G + m);
+                if (beam < 0) continue;                  // uniform
+                const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                for (int k = lane; k < RS / 4; k += 64) slot4[k] = z;
+                if (lane == 0) nzw[wave] = 0u;
+                wave_sync();
+                process_beam_wave<SUN, KEEP>(f, a.p, beam, hist, RS, taps, &nzw[wave], amask[wave], lane);
+                wave_sync();                             // the slot is reused
+            }
+        }
+    }
+}
+
 __global__ void k_reset_queue(int* counter, int n)
 {
-    if ((int)threadIdx.x < n) counter[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) counter[i] = 0;
 }
 
 template <int G>
@@ -866,9 +1017,25 @@ hipError_t launch_footprint_batch(hipStream_t s, const BatchArgs& a, int grid, b
     }
 }
 
+hipError_t launch_footprint_batch_wave(hipStream_t s, const BatchArgs& a, int grid, bool sun, bool keep)
+{
+    if (a.G != kWaves || a.p.R > kWaveMaxBins || !a.tickets) return hipErrorInvalidValue;
+    const size_t lds = group_lds_bytes(kWaves, a.p.R, a.p.J);
+    const dim3 b(kFootprintThreads);
+    if (sun && keep)
+        hipLaunchKernelGGL((k_footprint_batch_wave<true, true>), dim3(grid), b, lds, s, a);
+    else if (sun)
+        hipLaunchKernelGGL((k_footprint_batch_wave<true, false>), dim3(grid), b, lds, s, a);
+    else if (keep)
+        hipLaunchKernelGGL((k_footprint_batch_wave<false, true>), dim3(grid), b, lds, s, a);
+    else
+        hipLaunchKernelGGL((k_footprint_batch_wave<false, false>), dim3(grid), b, lds, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset_queue(hipStream_t s, int* counter, int n)
 {
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, counter, n);
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(256), 0, s, counter, n);
     return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "engine.h"
@@ -65,6 +67,7 @@ struct FrameState {
     std::vector<uint64_t> group_cost;  // samples of the group's beams
     int n_groups = 0;
     int tile = 64;
+    int wave = 0;                      // batches: wave schedule (one wave per group, see footprint.hip)
     // surrogate inputs
     SurGeom geom{};
     bool geom_ok = false;
@@ -105,8 +108,10 @@ struct lidar_sim {
     DevBuf<FrameDev> b_frames;
     DevBuf<int2> b_items;
     uint64_t b_items_n = 0, b_samples = 0;
-    DevBuf<int32_t> b_tickets;         // [b_tickets_n + 1] item runs handed out by the queue
+    DevBuf<int32_t> b_tickets;         // [b_tickets_n + 1] item runs handed out by the queues
     int b_tickets_n = 0;
+    int b_tickets_g = 0;               // tickets 0 .. b_tickets_g - 1: group schedule; the rest: wave
+    uint64_t b_wave_items = 0;
     DevBuf<PrepassArgs> b_prep;        // [n_frames] pre-pass arguments of the batch's frames
     DevBuf<int32_t> b_prep_off;        // [n_frames + 1] first pre-pass tile of each frame
     int b_prep_tiles = 0;
@@ -116,7 +121,7 @@ struct lidar_sim {
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    std::map<int, int> tuned_tile;     // kernel-height class -> strip height
+    std::map<int, std::pair<int, int>> tuned;  // kernel-height class -> strip height, wave schedule
 
     // surrogate network, inputs, gate and fallback
     SurNet net;
@@ -588,7 +593,7 @@ FrameDev frame_view(const lidar_sim* h, const FrameState& fs, lidar_beam_info* b
                     lidar_echo* echoes, int32_t* counts, float* waves)
 {
     const bool sun = h->prm.sun_irradiance != 0.0;
-    FrameDev f;
+    FrameDev f{};
     f.pix = fs.d_pix.p;
     f.sun = sun ? fs.d_sun.p : nullptr;
     f.W = (int)fs.gb.width;
@@ -747,13 +752,16 @@ void free_graph(lidar_sim* h)
 }
 
 // Enqueue the batch on s: the pre-pass of every frame (optional), the queue
-// reset and the persistent footprint launch over `items` (handed out in the
-// runs `tickets` if given, else one by one).
+// reset and the persistent footprint launches over `items`: handed out in the
+// runs `tickets` if given (the first n_group of them to the group schedule,
+// the rest to the wave schedule), else one by one to the group schedule.
 lidar_status enqueue_batch(lidar_sim* h, hipStream_t s, const int2* items, uint64_t n_items,
-                           bool with_prepass, const int32_t* tickets = nullptr, int n_tickets = 0)
+                           bool with_prepass, const int32_t* tickets = nullptr, int n_tickets = 0,
+                           int n_group = -1)
 {
+    if (n_group < 0) n_group = n_tickets;
     if (with_prepass) LIDAR_TRY(enqueue_batch_prepass(h, s));
-    HIP_TRY(h, launch_reset_queue(s, h->b_queue.p), "queue reset launch");
+    HIP_TRY(h, launch_reset_queue(s, h->b_queue.p, 2 * kQueueInts), "queue reset launch");
     BatchArgs ba;
     ba.frames = h->b_frames.p;
     ba.p = path_view(h);
@@ -764,10 +772,17 @@ lidar_status enqueue_batch(lidar_sim* h, hipStream_t s, const int2* items, uint6
     ba.next_item = h->b_queue.p;
     ba.n_items_dev = nullptr;
     ba.tickets = tickets;
-    ba.n_tickets = n_tickets;
+    ba.n_tickets = n_group;
     const bool sun = h->prm.sun_irradiance != 0.0;
     const bool keep = (h->prm.flags & LIDAR_KEEP_WAVEFORMS) != 0;
-    HIP_TRY(h, launch_footprint_batch(s, ba, h->b_grid, sun, keep), "batch footprint launch");
+    if (!tickets || n_group > 0)
+        HIP_TRY(h, launch_footprint_batch(s, ba, h->b_grid, sun, keep), "batch footprint launch");
+    if (tickets && n_tickets > n_group) {
+        ba.tickets = tickets + n_group;
+        ba.n_tickets = n_tickets - n_group;
+        ba.next_item = h->b_queue.p + kQueueInts;
+        HIP_TRY(h, launch_footprint_batch_wave(s, ba, h->b_grid, sun, keep), "batch wave-schedule launch");
+    }
     return LIDAR_OK;
 }
 
@@ -781,6 +796,7 @@ lidar_status upload_frame_table(lidar_sim* h)
         const uint64_t o = h->beam_off[i];
         fd[i] = frame_view(h, *h->frames[i], h->b_beams.p + o, h->b_echoes.p + o * E,
                            h->b_counts.p + o, keep ? h->b_waves.p + o * R : nullptr);
+        fd[i].wave = h->frames[i]->wave;
     }
     HIP_TRY(h, h->b_frames.ensure(fd.size()), "allocate frame table");
     HIP_TRY(h, hipMemcpyAsync(h->b_frames.p, fd.data(), fd.size() * sizeof(FrameDev),
@@ -789,26 +805,66 @@ lidar_status upload_frame_table(lidar_sim* h)
     return LIDAR_OK;
 }
 
+// Tickets over items in queue order: runs of consecutive items whose cost
+// reaches a target that shrinks with the work left (guided self-scheduling: a
+// quarter of an even share per worker), at most kMaxTicket items; the costly
+// head goes one item per ticket, the cheap tail in runs, and the last tickets
+// are small again so that the workers finish together.  The workers are the
+// workgroups of the group schedule or the waves of the wave schedule.
+std::vector<int32_t> build_tickets(const uint64_t* cost, size_t n, uint64_t workers, int32_t first)
+{
+    constexpr size_t kMaxTicket = 256;
+    std::vector<int32_t> tickets;
+    uint64_t remaining = 0;
+    for (size_t j = 0; j < n; ++j) remaining += cost[j];
+    for (size_t j = 0; j < n;) {
+        const uint64_t target = remaining / (4 * workers);
+        uint64_t acc = 0;
+        size_t k = j;
+        do acc += cost[k++];
+        while (k < n && k - j < kMaxTicket && acc < target);
+        tickets.push_back(first + (int32_t)k);
+        remaining -= acc;
+        j = k;
+    }
+    return tickets;
+}
+
+// Whether the batch may use the wave schedule: one histogram slot per wave
+// (groups of kWavesPerGroup) and waveforms short enough for registers.
+bool wave_schedule_ok(const lidar_sim* h)
+{
+    return h->G == kWavesPerGroup && (int)h->prm.n_bins <= kWaveMaxBins;
+}
+
 // Autotuner: for every kernel-height class of the batch, time the persistent
-// launch over that class's items alone with each candidate strip height and
-// keep the fastest.  The pixel records are computed once first; the results
-// are remembered by the handle for later batches.
-lidar_status autotune_batch(lidar_sim* h, const std::vector<int2>& items)
+// launch over that class's items alone (in tickets, as the batch runs them)
+// with each candidate strip height, in the group and in the wave schedule,
+// and keep the fastest.  The pixel records are computed once first; the
+// results are remembered by the handle for later batches.
+lidar_status autotune_batch(lidar_sim* h, const std::vector<int2>& items, const std::vector<uint64_t>& cost)
 {
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = h->stream;
     LIDAR_TRY(enqueue_batch_prepass(h, s));
-    std::map<int, std::vector<int2>> by_class;
-    for (const int2& it : items) by_class[height_class(h->frames[it.x]->k.KH)].push_back(it);
+    std::map<int, std::vector<size_t>> by_class;
+    for (size_t j = 0; j < items.size(); ++j) by_class[height_class(h->frames[items[j].x]->k.KH)].push_back(j);
     DevBuf<int2> d_trial;
+    DevBuf<int32_t> d_tickets;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     lidar_status st = he == hipSuccess ? LIDAR_OK : hip_fail(h, he, "autotune events");
+    const int n_modes = wave_schedule_ok(h) ? 2 : 1;
     for (auto& kv : by_class) {
         if (st != LIDAR_OK) break;
         const int cls = kv.first;
-        const std::vector<int2>& its = kv.second;
+        std::vector<int2> its;
+        std::vector<uint64_t> cs;
+        for (size_t j : kv.second) {
+            its.push_back(items[j]);
+            cs.push_back(cost[j]);
+        }
         he = d_trial.ensure(its.size());
         if (he == hipSuccess)
             he = hipMemcpyAsync(d_trial.p, its.data(), its.size() * sizeof(int2),
@@ -818,32 +874,56 @@ lidar_status autotune_batch(lidar_sim* h, const std::vector<int2>& items)
             break;
         }
         float best = 1e30f;
-        int best_tile = default_tile(cls);
-        for (int tile : {64, 16, 4}) {
-            if (tile == 64 && cls < 16) continue;   // strips 4x taller than the kernel
-            for (auto& fs : h->frames)
-                if (height_class(fs->k.KH) == cls) fs->tile = tile;
-            if ((st = upload_frame_table(h)) != LIDAR_OK) break;
-            float ms = 0.0f;
-            for (int rep = 0; rep < 2 && st == LIDAR_OK; ++rep) {
-                he = hipEventRecord(e0, s);
-                if (he != hipSuccess) { st = hip_fail(h, he, "autotune event"); break; }
-                if ((st = enqueue_batch(h, s, d_trial.p, its.size(), false)) != LIDAR_OK) break;
-                he = hipEventRecord(e1, s);
-                if (he == hipSuccess) he = hipEventSynchronize(e1);
-                if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-                if (he != hipSuccess) { st = hip_fail(h, he, "autotune timing"); break; }
+        int best_tile = default_tile(cls), best_wave = 0;
+        for (int mode = 0; mode < n_modes && st == LIDAR_OK; ++mode) {
+            std::vector<int32_t> tk(1, 0);
+            const std::vector<int32_t> runs =
+                build_tickets(cs.data(), cs.size(), (uint64_t)h->b_grid * (mode ? kWavesPerGroup : 1), 0);
+            tk.insert(tk.end(), runs.begin(), runs.end());
+            he = d_tickets.ensure(tk.size());
+            if (he == hipSuccess)
+                he = hipMemcpyAsync(d_tickets.p, tk.data(), tk.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, s);
+            if (he != hipSuccess) {
+                st = hip_fail(h, he, "autotune tickets");
+                break;
             }
-            if (st != LIDAR_OK) break;
-            if (ms < best) {
-                best = ms;
-                best_tile = tile;
+            for (int tile : {64, 16, 4}) {
+                if (tile == 64 && cls < 16) continue;   // strips 4x taller than the kernel
+                for (auto& fs : h->frames)
+                    if (height_class(fs->k.KH) == cls) {
+                        fs->tile = tile;
+                        fs->wave = mode;
+                    }
+                if ((st = upload_frame_table(h)) != LIDAR_OK) break;
+                float ms = 0.0f;
+                for (int rep = 0; rep < 2 && st == LIDAR_OK; ++rep) {
+                    he = hipEventRecord(e0, s);
+                    if (he != hipSuccess) { st = hip_fail(h, he, "autotune event"); break; }
+                    const int nt = (int)tk.size() - 1;
+                    if ((st = enqueue_batch(h, s, d_trial.p, its.size(), false, d_tickets.p, nt,
+                                            mode ? 0 : nt)) != LIDAR_OK)
+                        break;
+                    he = hipEventRecord(e1, s);
+                    if (he == hipSuccess) he = hipEventSynchronize(e1);
+                    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                    if (he != hipSuccess) { st = hip_fail(h, he, "autotune timing"); break; }
+                }
+                if (st != LIDAR_OK) break;
+                if (ms < best) {
+                    best = ms;
+                    best_tile = tile;
+                    best_wave = mode;
+                }
             }
         }
         if (st != LIDAR_OK) break;
-        h->tuned_tile[cls] = best_tile;
+        h->tuned[cls] = {best_tile, best_wave};
         for (auto& fs : h->frames)
-            if (height_class(fs->k.KH) == cls) fs->tile = best_tile;
+            if (height_class(fs->k.KH) == cls) {
+                fs->tile = best_tile;
+                fs->wave = best_wave;
+            }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -881,7 +961,7 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
     HIP_TRY(h, h->b_echoes.ensure(B * E), "allocate batch echoes");
     HIP_TRY(h, h->b_counts.ensure(B), "allocate batch counts");
     if (h->prm.flags & LIDAR_KEEP_WAVEFORMS) HIP_TRY(h, h->b_waves.ensure(B * R), "allocate batch waveforms");
-    HIP_TRY(h, h->b_queue.ensure(1), "allocate work queue");
+    HIP_TRY(h, h->b_queue.ensure(2 * kQueueInts), "allocate work queues");
     std::vector<uint64_t> group_off(n + 1, 0);
     uint64_t samples = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -890,8 +970,8 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
         fs.gb = gbs[i];
         LIDAR_TRY(copy_pattern(h, fs, &pds[i]));
         LIDAR_TRY(setup_frame(h, fs, h->b_beams.p + h->beam_off[i], who));
-        auto it = h->tuned_tile.find(height_class(fs.k.KH));
-        if (it != h->tuned_tile.end()) fs.tile = it->second;
+        auto it = h->tuned.find(height_class(fs.k.KH));
+        if (it != h->tuned.end()) std::tie(fs.tile, fs.wave) = it->second;
         LIDAR_TRY(alloc_pixels(h, fs));
         group_off[i + 1] = group_off[i] + fs.n_groups;
         samples += fs.samples;
@@ -936,17 +1016,9 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
             cost[gidx] = fs.group_cost[gi] + bin_cost;
         }
     }
-    std::vector<size_t> order(total_groups);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-    std::vector<int2> sorted(total_groups);
-    for (size_t j = 0; j < total_groups; ++j) sorted[j] = items[order[j]];
     HIP_TRY(h, h->b_groups.ensure(groups.size()), "allocate batch groups");
-    HIP_TRY(h, h->b_items.ensure(sorted.size()), "allocate batch items");
     HIP_TRY(h, hipMemcpyAsync(h->b_groups.p, groups.data(), groups.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, h->stream), "copy batch groups");
-    HIP_TRY(h, hipMemcpyAsync(h->b_items.p, sorted.data(), sorted.size() * sizeof(int2),
-                              hipMemcpyHostToDevice, h->stream), "copy batch items");
     h->b_items_n = total_groups;
     h->b_samples = samples;
     // persistent grid: as many workgroups as the CUs hold at the LDS-bound
@@ -959,33 +1031,70 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
     const size_t lds = group_lds_bytes(G, R, h->J) + 2048;   // + static LDS
     const size_t per_cu = std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
     h->b_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * per_cu, total_groups));
-    // tickets: runs of consecutive items whose cost reaches a target that
-    // shrinks with the work left (guided self-scheduling: a quarter of an
-    // even share per workgroup), at most kMaxTicket items; the costly head
-    // goes one item per ticket, the cheap tail in runs, and the last tickets
-    // are small again so that the workgroups finish together
-    constexpr size_t kMaxTicket = 256;
-    std::vector<int32_t> tickets(1, 0);
-    uint64_t remaining = 0;
-    for (uint64_t c : cost) remaining += c;
-    for (size_t j = 0; j < total_groups;) {
-        const uint64_t target = remaining / (4 * (uint64_t)h->b_grid);
-        uint64_t acc = 0;
-        size_t k = j;
-        do acc += cost[order[k++]];
-        while (k < total_groups && k - j < kMaxTicket && acc < target);
-        tickets.push_back((int32_t)k);
-        remaining -= acc;
-        j = k;
+    // schedule per frame: remembered from an earlier autotuning of the class,
+    // else the wave schedule where most groups hold a single beam (three of
+    // the four waves of a group would idle), then the autotuner if asked
+    for (uint32_t i = 0; i < n; ++i) {
+        FrameState& fs = *h->frames[i];
+        auto it = h->tuned.find(height_class(fs.k.KH));
+        if (it != h->tuned.end()) continue;
+        uint64_t members = 0;
+        for (int32_t b : fs.groups) members += b >= 0 ? 1 : 0;
+        fs.wave = wave_schedule_ok(h) && members < 2 * (uint64_t)fs.n_groups ? 1 : 0;
     }
-    h->b_tickets_n = (int)tickets.size() - 1;
-    HIP_TRY(h, h->b_tickets.ensure(tickets.size()), "allocate batch tickets");
-    HIP_TRY(h, hipMemcpyAsync(h->b_tickets.p, tickets.data(), tickets.size() * sizeof(int32_t),
-                              hipMemcpyHostToDevice, h->stream), "copy batch tickets");
+    if (!wave_schedule_ok(h))
+        for (auto& fs : h->frames) fs->wave = 0;
     LIDAR_TRY(upload_frame_table(h));
     h->b_autotuned = false;
     h->b_autotune_ms = 0.0;
-    if (h->prm.flags & LIDAR_AUTOTUNE) LIDAR_TRY(autotune_batch(h, sorted));
+    if (h->prm.flags & LIDAR_AUTOTUNE) {
+        std::vector<size_t> order(total_groups);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+        std::vector<int2> by_cost(total_groups);
+        std::vector<uint64_t> c_by_cost(total_groups);
+        for (size_t j = 0; j < total_groups; ++j) {
+            by_cost[j] = items[order[j]];
+            c_by_cost[j] = cost[order[j]];
+        }
+        LIDAR_TRY(autotune_batch(h, by_cost, c_by_cost));
+    }
+    // queue order: the group schedule's items, then the wave schedule's, each
+    // costliest first; tickets never mix the two
+    std::vector<size_t> order(total_groups);
+    std::iota(order.begin(), order.end(), 0);
+    auto wave_of = [&](size_t j) { return h->frames[items[j].x]->wave; };
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+        const int wx = wave_of(x), wy = wave_of(y);
+        return wx != wy ? wx < wy : cost[x] > cost[y];
+    });
+    std::vector<int2> sorted(total_groups);
+    std::vector<uint64_t> sorted_cost(total_groups);
+    std::vector<char> sorted_wave(total_groups);
+    for (size_t j = 0; j < total_groups; ++j) {
+        sorted[j] = items[order[j]];
+        sorted_cost[j] = cost[order[j]];
+        sorted_wave[j] = (char)wave_of(order[j]);
+    }
+    HIP_TRY(h, h->b_items.ensure(sorted.size()), "allocate batch items");
+    HIP_TRY(h, hipMemcpyAsync(h->b_items.p, sorted.data(), sorted.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, h->stream), "copy batch items");
+    size_t n_group_items = 0;
+    while (n_group_items < total_groups && !sorted_wave[n_group_items]) ++n_group_items;
+    std::vector<int32_t> tickets(1, 0);
+    const std::vector<int32_t> tg = build_tickets(sorted_cost.data(), n_group_items, h->b_grid, 0);
+    const std::vector<int32_t> tw =
+        build_tickets(sorted_cost.data() + n_group_items, total_groups - n_group_items,
+                      (uint64_t)h->b_grid * kWavesPerGroup, (int32_t)n_group_items);
+    tickets.insert(tickets.end(), tg.begin(), tg.end());
+    tickets.insert(tickets.end(), tw.begin(), tw.end());
+    h->b_tickets_n = (int)tickets.size() - 1;
+    h->b_tickets_g = (int)tg.size();
+    h->b_wave_items = total_groups - n_group_items;
+    HIP_TRY(h, h->b_tickets.ensure(tickets.size()), "allocate batch tickets");
+    HIP_TRY(h, hipMemcpyAsync(h->b_tickets.p, tickets.data(), tickets.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, h->stream), "copy batch tickets");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "batch tables synchronise");
     // capture the batch into a graph on a private stream; it is launched on
     // the handle's stream
     if (!h->capture_stream)
@@ -994,7 +1103,7 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
     HIP_TRY(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal),
             "begin graph capture");
     lidar_status st = enqueue_batch(h, h->capture_stream, h->b_items.p, h->b_items_n, true,
-                                    h->b_tickets.p, h->b_tickets_n);
+                                    h->b_tickets.p, h->b_tickets_n, h->b_tickets_g);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(h->capture_stream, &graph);
     if (st != LIDAR_OK) {
@@ -1101,8 +1210,8 @@ static lidar_status ensure_setup(lidar_sim* h, const char* who)
         HIP_TRY(h, hipMemcpyAsync(h->d_groups.p, fs.groups.data(), fs.groups.size() * sizeof(int32_t),
                                   hipMemcpyHostToDevice, h->stream), "copy beam groups");
         HIP_TRY(h, hipStreamSynchronize(h->stream), "set-up synchronise");
-        auto it = h->tuned_tile.find(height_class(fs.k.KH));
-        if (it != h->tuned_tile.end()) fs.tile = it->second;
+        auto it = h->tuned.find(height_class(fs.k.KH));
+        if (it != h->tuned.end()) fs.tile = it->second.first;
         h->setup_ok = true;
     }
     LIDAR_TRY(alloc_pixels(h, fs));
@@ -1359,6 +1468,7 @@ lidar_status lidar_sim_batch_info(lidar_sim* h, lidar_batch_info* out)
     bi.grid = (uint32_t)h->b_grid;
     bi.graph = h->graph_exec ? 1u : 0u;
     bi.autotuned = h->b_autotuned ? 1u : 0u;
+    bi.wave_items = (uint32_t)h->b_wave_items;
     bi.autotune_ms = h->b_autotune_ms;
     *out = bi;
     return LIDAR_OK;

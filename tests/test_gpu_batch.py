@@ -72,6 +72,54 @@ def test_batch_every_beam_matches_oracle(oracle_mod):
         sim.close()
 
 
+def test_batch_wave_schedule_single_beam_groups(oracle_mod):
+    """Frames whose beam groups all hold a single beam (three 1024x512
+    i.i.d. frames, 1000 beams each, footprints far apart) go to the wave
+    schedule; every beam is compared with the oracle, on two replays."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    frames = [scenes.iid_frame(s) for s in range(3)]
+    bw = scenes.BatchWorkload("iid-3", frames, frames[0].params)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(bw.params, stream=torch.cuda.current_stream(), keep_waveforms=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        for rep in range(2):
+            sim.simulate_batch(batch)
+            info = sim.batch_info()
+            assert info["wave_items"] == info["n_items"] == 3000
+            reps = _check_all(sim, bw, bw.params, oracle_mod, f"wave-iid-3 replay {rep}")
+            assert sum(r.echoes_compared for r in reps) > 8000
+    finally:
+        sim.close()
+
+
+def test_batch_mixed_schedules(oracle_mod):
+    """One batch whose sparse frames (150 beams, 20-pixel footprints) take the
+    wave schedule and whose dense frames (1500 beams, 4000-pixel footprints)
+    take the group schedule: two persistent launches in one graph."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    sparse = scenes.frame_batch(6, n_frames=3, sizes=((517, 250), (301, 301)), beams=(150, 150),
+                                footprint_px=(20.0, 20.0))
+    dense = scenes.frame_batch(7, n_frames=3, sizes=((517, 250), (301, 301)), beams=(1500, 1500),
+                               footprint_px=(4000.0, 4000.0))
+    bw = scenes.BatchWorkload("mixed", sparse.frames + dense.frames, sparse.params)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(bw.params, stream=torch.cuda.current_stream(), keep_waveforms=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        sim.simulate_batch(batch)
+        info = sim.batch_info()
+        assert 0 < info["wave_items"] < info["n_items"]
+        reps = _check_all(sim, bw, bw.params, oracle_mod, "mixed-schedules")
+        assert sum(r.echoes_compared for r in reps) > 2000
+    finally:
+        sim.close()
+
+
 def test_batch_graph_replays_follow_changed_gbuffers(oracle_mod):
     """The captured graph is replayed three times; between replays the
     G-buffer contents change in place (eager torch work and a synchronise):
