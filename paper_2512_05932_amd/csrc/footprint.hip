@@ -847,13 +847,18 @@ void k_footprint(FootprintArgs a)
 // apart, counter c handing out tickets c, c + kXcds, ... (so the costliest
 // tickets still go first).  A worker starts at its XCD's counter and moves to
 // the next one when it runs dry; the atomics of the workers are spread over
-// eight addresses instead of serialising on one.  Returns n when every
-// counter is exhausted.
+// eight addresses instead of serialising on one, and a counter seen dry by a
+// plain load is passed over without an atomic.  Returns n when every counter
+// is exhausted.
 __device__ inline int next_ticket(int* q, int& c, int n)
 {
     for (int tried = 0; tried < kXcds; ++tried) {
-        const int t = atomicAdd(q + c * kQueueStride, 1) * kXcds + c;
-        if (t < n) return t;
+        int* qc = q + c * kQueueStride;
+        if (tried == 0 ||
+            __hip_atomic_load(qc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * kXcds + c < n) {
+            const int t = atomicAdd(qc, 1) * kXcds + c;
+            if (t < n) return t;
+        }
         c = c + 1 == kXcds ? 0 : c + 1;
     }
     return n;

@@ -810,8 +810,11 @@ lidar_status upload_frame_table(lidar_sim* h)
 // quarter of an even share per worker), at most kMaxTicket items; the costly
 // head goes one item per ticket, the cheap tail in runs, and the last tickets
 // are small again so that the workers finish together.  The workers are the
-// workgroups of the group schedule or the waves of the wave schedule.
-std::vector<int32_t> build_tickets(const uint64_t* cost, size_t n, uint64_t workers, int32_t first)
+// workgroups of the group schedule or the waves of the wave schedule; a
+// ticket costs at least min_cost where items allow (each ticket is a queue
+// atomic, which matters when the items are tiny).
+std::vector<int32_t> build_tickets(const uint64_t* cost, size_t n, uint64_t workers, int32_t first,
+                                   uint64_t min_cost = 0)
 {
     constexpr size_t kMaxTicket = 256;
     std::vector<int32_t> tickets;
@@ -822,12 +825,19 @@ std::vector<int32_t> build_tickets(const uint64_t* cost, size_t n, uint64_t work
         uint64_t acc = 0;
         size_t k = j;
         do acc += cost[k++];
-        while (k < n && k - j < kMaxTicket && acc < target);
+        while (k < n && k - j < kMaxTicket && (acc < target || acc < min_cost));
         tickets.push_back(first + (int32_t)k);
         remaining -= acc;
         j = k;
     }
     return tickets;
+}
+
+// Smallest ticket of the wave schedule: the convolution and detection cost
+// of four single-beam items (see the item cost in setup_batch).
+uint64_t wave_ticket_cost(const lidar_sim* h)
+{
+    return 4 * (uint64_t)h->G * h->prm.n_bins * (2 * h->J + 1) / 8;
 }
 
 // Whether the batch may use the wave schedule: one histogram slot per wave
@@ -878,7 +888,8 @@ lidar_status autotune_batch(lidar_sim* h, const std::vector<int2>& items, const 
         for (int mode = 0; mode < n_modes && st == LIDAR_OK; ++mode) {
             std::vector<int32_t> tk(1, 0);
             const std::vector<int32_t> runs =
-                build_tickets(cs.data(), cs.size(), (uint64_t)h->b_grid * (mode ? kWavesPerGroup : 1), 0);
+                build_tickets(cs.data(), cs.size(), (uint64_t)h->b_grid * (mode ? kWavesPerGroup : 1), 0,
+                              mode ? wave_ticket_cost(h) : 0);
             tk.insert(tk.end(), runs.begin(), runs.end());
             he = d_tickets.ensure(tk.size());
             if (he == hipSuccess)
@@ -1085,7 +1096,7 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
     const std::vector<int32_t> tg = build_tickets(sorted_cost.data(), n_group_items, h->b_grid, 0);
     const std::vector<int32_t> tw =
         build_tickets(sorted_cost.data() + n_group_items, total_groups - n_group_items,
-                      (uint64_t)h->b_grid * kWavesPerGroup, (int32_t)n_group_items);
+                      (uint64_t)h->b_grid * kWavesPerGroup, (int32_t)n_group_items, wave_ticket_cost(h));
     tickets.insert(tickets.end(), tg.begin(), tg.end());
     tickets.insert(tickets.end(), tw.begin(), tw.end());
     h->b_tickets_n = (int)tickets.size() - 1;
