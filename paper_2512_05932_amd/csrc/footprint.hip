@@ -746,11 +746,11 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
 // One beam by one wave (the wave schedule of a batch), after the wave zeroed
 // its histogram slot hist (zero padding around it) and its chunk flags nzw:
 // the steps of process_group with wave-local ordering only, the convolution in
-// passes of 512 bins (8 per lane; R <= kWavePassBins * kWavePasses).
+// NP passes of 512 bins (8 per lane; R <= kWavePassBins * NP).
 constexpr int kWavePassBins = 512;
 constexpr int kWavePasses = kWaveMaxBins / kWavePassBins;
 
-template <bool SUN, bool KEEP>
+template <int NP, bool SUN, bool KEEP>
 __device__ __attribute__((always_inline)) inline void process_beam_wave(
     const FrameDev& f, const PathDev& p, int beam, float* hist, int RS, const float* taps, unsigned* nzw,
     unsigned* am, int lane)
@@ -779,14 +779,14 @@ __device__ __attribute__((always_inline)) inline void process_beam_wave(
     wave_sync();                                         // the histogram is complete
     const unsigned nzm = __builtin_amdgcn_readfirstlane(*nzw);
     const int nb = conv_taps(p.J) / 8;
-    float o[kWavePasses][8];
+    float o[NP][8];
 #pragma unroll
-    for (int ps = 0; ps < kWavePasses; ++ps)
+    for (int ps = 0; ps < NP; ++ps)
         conv_out8(hist, taps, p, nb, ps * kWavePassBins + lane * 8, nzm, nzs, o[ps]);
     wave_sync();                                         // every read of the histogram is done
     unsigned word = 0;                                   // chunks above the threshold
 #pragma unroll
-    for (int ps = 0; ps < kWavePasses; ++ps) {
+    for (int ps = 0; ps < NP; ++ps) {
         if (ps * kWavePassBins >= R) break;              // uniform
         const unsigned m8 = write_out8<KEEP>(hist, KEEP ? f.waves + (size_t)beam * R : nullptr,
                                              ps * kWavePassBins + lane * 8, R, scale, floor_b,
@@ -917,8 +917,8 @@ void k_footprint_batch(BatchArgs a)
 // counter and processes the items' beams one by one in its own histogram slot,
 // with no workgroup barrier after the taps are loaded; the workgroup's LDS is
 // that of a group of kWaves beams.  Every wave exits once its queue is empty.
-template <bool SUN, bool KEEP>
-__global__ __launch_bounds__(kFootprintThreads) __attribute__((amdgpu_waves_per_eu(KEEP || SUN ? 1 : 4)))
+template <int NP, bool SUN, bool KEEP>
+__global__ __launch_bounds__(kFootprintThreads) __attribute__((amdgpu_waves_per_eu(KEEP || SUN ? 1 : (NP == 1 ? 8 : 4))))
 void k_footprint_batch_wave(BatchArgs a)
 {
     constexpr int G = kWaves;
@@ -952,7 +952,7 @@ void k_footprint_batch_wave(BatchArgs a)
                 for (int k = lane; k < RS / 4; k += 64) slot4[k] = z;
                 if (lane == 0) nzw[wave] = 0u;
                 wave_sync();
-                process_beam_wave<SUN, KEEP>(f, a.p, beam, hist, RS, taps, &nzw[wave], amask[wave], lane);
+                process_beam_wave<NP, SUN, KEEP>(f, a.p, beam, hist, RS, taps, &nzw[wave], amask[wave], lane);
                 wave_sync();                             // the slot is reused
             }
         }
@@ -1027,14 +1027,26 @@ hipError_t launch_footprint_batch_wave(hipStream_t s, const BatchArgs& a, int gr
     if (a.G != kWaves || a.p.R > kWaveMaxBins || !a.tickets) return hipErrorInvalidValue;
     const size_t lds = group_lds_bytes(kWaves, a.p.R, a.p.J);
     const dim3 b(kFootprintThreads);
-    if (sun && keep)
-        hipLaunchKernelGGL((k_footprint_batch_wave<true, true>), dim3(grid), b, lds, s, a);
-    else if (sun)
-        hipLaunchKernelGGL((k_footprint_batch_wave<true, false>), dim3(grid), b, lds, s, a);
-    else if (keep)
-        hipLaunchKernelGGL((k_footprint_batch_wave<false, true>), dim3(grid), b, lds, s, a);
-    else
-        hipLaunchKernelGGL((k_footprint_batch_wave<false, false>), dim3(grid), b, lds, s, a);
+    // one output pass (fewer registers, more waves per SIMD) for short waveforms
+    if (a.p.R <= kWavePassBins) {
+        if (sun && keep)
+            hipLaunchKernelGGL((k_footprint_batch_wave<1, true, true>), dim3(grid), b, lds, s, a);
+        else if (sun)
+            hipLaunchKernelGGL((k_footprint_batch_wave<1, true, false>), dim3(grid), b, lds, s, a);
+        else if (keep)
+            hipLaunchKernelGGL((k_footprint_batch_wave<1, false, true>), dim3(grid), b, lds, s, a);
+        else
+            hipLaunchKernelGGL((k_footprint_batch_wave<1, false, false>), dim3(grid), b, lds, s, a);
+    } else {
+        if (sun && keep)
+            hipLaunchKernelGGL((k_footprint_batch_wave<kWavePasses, true, true>), dim3(grid), b, lds, s, a);
+        else if (sun)
+            hipLaunchKernelGGL((k_footprint_batch_wave<kWavePasses, true, false>), dim3(grid), b, lds, s, a);
+        else if (keep)
+            hipLaunchKernelGGL((k_footprint_batch_wave<kWavePasses, false, true>), dim3(grid), b, lds, s, a);
+        else
+            hipLaunchKernelGGL((k_footprint_batch_wave<kWavePasses, false, false>), dim3(grid), b, lds, s, a);
+    }
     return hipGetLastError();
 }
 
