@@ -72,14 +72,21 @@ def test_batch_every_beam_matches_oracle(oracle_mod):
         sim.close()
 
 
-def test_batch_wave_schedule_single_beam_groups(oracle_mod):
+@pytest.mark.parametrize("sun", [False, True])
+def test_batch_wave_schedule_single_beam_groups(oracle_mod, sun):
     """Frames whose beam groups all hold a single beam (three 1024x512
     i.i.d. frames, 1000 beams each, footprints far apart) go to the wave
-    schedule; every beam is compared with the oracle, on two replays."""
+    schedule; every beam is compared with the oracle, on two replays; with
+    and without the sun term."""
     import torch
     import paper_2512_05932_amd as lidar
     frames = [scenes.iid_frame(s) for s in range(3)]
-    bw = scenes.BatchWorkload("iid-3", frames, frames[0].params)
+    params = frames[0].params
+    if sun:
+        se = math.sin(math.radians(35.0))
+        params = replace(params, sun_irradiance=30.0,
+                         sun_dir=(math.sqrt(1 - se * se) * 0.8, math.sqrt(1 - se * se) * 0.6, se))
+    bw = scenes.BatchWorkload("iid-3", frames, params)
     planes = _upload(bw)
     sim = lidar.LidarSim(bw.params, stream=torch.cuda.current_stream(), keep_waveforms=True)
     try:
@@ -89,8 +96,11 @@ def test_batch_wave_schedule_single_beam_groups(oracle_mod):
             sim.simulate_batch(batch)
             info = sim.batch_info()
             assert info["wave_items"] == info["n_items"] == 3000
-            reps = _check_all(sim, bw, bw.params, oracle_mod, f"wave-iid-3 replay {rep}")
-            assert sum(r.echoes_compared for r in reps) > 8000
+            reps = _check_all(sim, bw, bw.params, oracle_mod, f"wave-iid-3 sun={sun} replay {rep}")
+            assert sum(r.echoes_compared for r in reps) > 6000
+        if sun:
+            floors = np.concatenate([sim.read_batch(i)["beams"]["floor"] for i in range(3)])
+            assert np.count_nonzero(floors > params.ambient_const) > 0.8 * floors.size
     finally:
         sim.close()
 
