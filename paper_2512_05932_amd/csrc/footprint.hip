@@ -3,7 +3,10 @@
 // wavefront-ballot echo detection.  Two kernels share the group body: one
 // workgroup per group of one frame (`k_footprint`), and a persistent kernel
 // that takes tickets of (frame, group) items of a whole batch from a work
-// queue (`k_footprint_batch`).
+// queue (`k_footprint_batch`).  A third, `k_footprint_batch_wave`, runs the
+// same steps for one beam per wave (frames whose groups mostly hold a single
+// beam), every wave taking its own tickets.  Tickets come from eight counters,
+// one per XCD (next_ticket).
 //
 // Work decomposition.  A workgroup (4 waves of 64) takes a group of up to G
 // beams formed by the host scheduler from beams close on the raster.  The
