@@ -710,7 +710,10 @@ lidar_status sur_inputs(lidar_sim* h, FrameState& fs, uint16_t* X)
     sa.g = fs.geom;
     sa.sup = fs.d_sup.p;
     sa.range = fs.d_range.p;
-    HIP_TRY(h, launch_super(s, sa), "super-cells launch");
+    // super-cells feed only the sun floor and tail energy outside the core box:
+    // none when the core box spans the kernel window (as for truncated Gaussians)
+    if (fs.geom.cm < fs.k.M || fs.geom.cn < fs.k.N)
+        HIP_TRY(h, launch_super(s, sa), "super-cells launch");
     FeatArgs fa;
     fa.beams = h->d_beams.p;
     fa.az = fs.d_az.p;
