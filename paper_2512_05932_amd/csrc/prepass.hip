@@ -10,27 +10,29 @@
 // that a footprint-kernel lane, which owns one row, reads 4 consecutive
 // columns of its row with one 16-byte access, and the 64 lanes of a wave
 // (64 consecutive rows) read one contiguous span; the transpose goes through
-// a 32x32 LDS tile.  Columns between W and the next multiple of 4 are sky.
+// a 64x16 LDS tile.  Columns between W and the next multiple of 4 are sky.
 #include "engine.h"
 
 namespace lidar {
 
 namespace {
-constexpr int kTile = 32;
-constexpr int kRowsPerPass = 8;     // 32 x 8 threads, 4 passes per tile
+constexpr int kTileW = 64, kTileH = 16;   // tile of kTileW columns x kTileH rows (256-byte row reads)
+constexpr int kThreads = 256;
+constexpr int kRowsPerPass = kThreads / kTileW;
+static_assert(kTileW % 4 == 0 && kTileH % kRowsPerPass == 0, "whole 4-column blocks and passes");
 }
 
-// One 32 x 32 tile of a frame, columns u0.., rows v0...
+// One kTileW x kTileH tile of a frame, columns u0.., rows v0...
 template <bool SUN>
 __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0)
 {
-    __shared__ int2 trec[kTile][kTile + 1];
-    __shared__ float tsun[kTile][kTile + 1];
-    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
+    __shared__ int2 trec[kTileH][kTileW + 1];
+    __shared__ float tsun[kTileH][kTileW + 1];
+    const int tx = threadIdx.x % kTileW, ty = threadIdx.x / kTileW;
     const float inv_pi = (float)(1.0 / kPi);
     // read rows (coalesced along u), shade, stage in LDS
 #pragma unroll
-    for (int p = 0; p < kTile / kRowsPerPass; ++p) {
+    for (int p = 0; p < kTileH / kRowsPerPass; ++p) {
         int vl = ty + p * kRowsPerPass;
         int u = u0 + tx, v = v0 + vl;
         int bin = -1;
@@ -61,12 +63,12 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0)
         if (SUN) tsun[vl][tx] = sunv;
     }
     __syncthreads();
-    // write 8 blocks of 4 columns x 32 rows, each contiguous in memory
+    // write kTileW / 4 blocks of 4 columns x kTileH rows, each contiguous in memory
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int p = 0; p < (kTile * kTile) / (kTile * kRowsPerPass); ++p) {
-        const int e = p * kTile * kRowsPerPass + tid;     // 0 .. 1023
-        const int bi = e / (4 * kTile), r = (e / 4) % kTile, j = e % 4;
+    for (int p = 0; p < (kTileW * kTileH) / kThreads; ++p) {
+        const int e = p * kThreads + tid;
+        const int bi = e / (4 * kTileH), r = (e / 4) % kTileH, j = e % 4;
         const int u = u0 + bi * 4 + j, v = v0 + r;
         if (u < a.W4 && v < a.H) {
             const long o = (((long)(u >> 2) * a.H + v) << 2) + (u & 3);
@@ -78,16 +80,16 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0)
 }
 
 template <bool SUN>
-__global__ __launch_bounds__(kTile * kRowsPerPass)
+__global__ __launch_bounds__(kThreads)
 void k_prepass(PrepassArgs a)
 {
-    prepass_tile<SUN>(a, blockIdx.x * kTile, blockIdx.y * kTile);
+    prepass_tile<SUN>(a, blockIdx.x * kTileW, blockIdx.y * kTileH);
 }
 
 // All frames of a batch in one launch: block t is tile t of the frames' tiles
 // laid end to end (tile_off[f] = first tile of frame f, tile_off[n] = total).
 template <bool SUN>
-__global__ __launch_bounds__(kTile * kRowsPerPass)
+__global__ __launch_bounds__(kThreads)
 void k_prepass_batch(const PrepassArgs* frames, const int* tile_off, int n)
 {
     const int t = blockIdx.x;
@@ -99,20 +101,20 @@ void k_prepass_batch(const PrepassArgs* frames, const int* tile_off, int n)
     }
     const PrepassArgs a = frames[lo];
     const int lt = t - tile_off[lo];
-    const int tiles_x = (a.W4 + kTile - 1) / kTile;
-    prepass_tile<SUN>(a, (lt % tiles_x) * kTile, (lt / tiles_x) * kTile);
+    const int tiles_x = (a.W4 + kTileW - 1) / kTileW;
+    prepass_tile<SUN>(a, (lt % tiles_x) * kTileW, (lt / tiles_x) * kTileH);
 }
 
 int prepass_tiles(const PrepassArgs& a)
 {
-    return ((a.W4 + kTile - 1) / kTile) * ((a.H + kTile - 1) / kTile);
+    return ((a.W4 + kTileW - 1) / kTileW) * ((a.H + kTileH - 1) / kTileH);
 }
 
 hipError_t launch_prepass_batch(hipStream_t s, const PrepassArgs* frames, const int* tile_off,
                                 int n, int total_tiles, bool with_sun)
 {
     if (total_tiles <= 0) return hipSuccess;
-    dim3 block(kTile * kRowsPerPass);
+    dim3 block(kThreads);
     if (with_sun)
         hipLaunchKernelGGL(k_prepass_batch<true>, dim3(total_tiles), block, 0, s, frames, tile_off, n);
     else
@@ -122,8 +124,8 @@ hipError_t launch_prepass_batch(hipStream_t s, const PrepassArgs* frames, const 
 
 hipError_t launch_prepass(hipStream_t s, const PrepassArgs& a, bool with_sun)
 {
-    dim3 grid((a.W4 + kTile - 1) / kTile, (a.H + kTile - 1) / kTile);
-    dim3 block(kTile * kRowsPerPass);
+    dim3 grid((a.W4 + kTileW - 1) / kTileW, (a.H + kTileH - 1) / kTileH);
+    dim3 block(kThreads);
     if (with_sun)
         hipLaunchKernelGGL(k_prepass<true>, grid, block, 0, s, a);
     else
