@@ -105,6 +105,30 @@ def test_batch_wave_schedule_single_beam_groups(oracle_mod, sun):
         sim.close()
 
 
+@pytest.mark.parametrize("n_bins,bin_ns", [(700, 0.55), (1100, 0.35)])
+def test_batch_wave_schedule_ragged_waveforms(oracle_mod, n_bins, bin_ns):
+    """The wave schedule with waveform lengths that end inside a 512-bin
+    output pass (and inside a 64-bin chunk), the last bin near the farthest
+    depths so that echoes reach it: two i.i.d. frames."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    frames = [scenes.iid_frame(s) for s in (4, 5)]
+    params = replace(frames[0].params, n_bins=n_bins, bin_ns=bin_ns)
+    bw = scenes.BatchWorkload(f"iid-2-R{n_bins}", frames, params)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(bw.params, stream=torch.cuda.current_stream(), keep_waveforms=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        sim.simulate_batch(batch)
+        info = sim.batch_info()
+        assert info["wave_items"] == info["n_items"] == 2000
+        reps = _check_all(sim, bw, bw.params, oracle_mod, f"wave-iid-2 R={n_bins}")
+        assert sum(r.echoes_compared for r in reps) > 3000
+    finally:
+        sim.close()
+
+
 def test_batch_mixed_schedules(oracle_mod):
     """One batch whose sparse frames (150 beams, 20-pixel footprints) take the
     wave schedule and whose dense frames (1500 beams, 4000-pixel footprints)
