@@ -1,7 +1,9 @@
 """FP64 CPU oracle of the single-bounce beam-iteration LiDAR model.
 
 TEST INFRASTRUCTURE ONLY: imported by the test suite, by the smoke check and
-by the CPU-baseline leg of the benchmark, never by the product path.  It is
+by the benchmark's measuring legs (the CPU baseline, and the reference for the
+per-field error of the precision report and the surrogate's range error),
+never by the product path: no result the library returns comes from here.  It is
 independent of the HIP library (no shared code, headers or constants); the
 only thing both consume is the seeded input arrays from ``scenes``.
 
