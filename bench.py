@@ -213,9 +213,17 @@ def batch_report(args):
     sim.close()
     del planes
     torch.cuda.empty_cache()
+    # compulsory HBM bytes: every G-buffer read once (24 B per pixel), echoes
+    # and counts written
+    E = bw.params.max_echoes
+    compulsory = sum(24 * f.gbuffer.depth.size + f.pattern.n_beams * (40 * E + 4) for f in bw.frames)
+    gbs = compulsory / (ms * 1e-3) / 1e9
     return {"workload": bw.name, "frames": info["n_frames"], "beams": info["n_beams"],
             "samples": info["samples"], "work_items": info["n_items"],
+            "wave_schedule_items": info["wave_items"],
             "grid": info["grid"], "ms_per_batch": ms,
+            "compulsory_bytes": compulsory, "achieved_GBs": gbs, "peak_GBs": HBM_PEAK_GBS,
+            "hbm_frac": gbs / HBM_PEAK_GBS,
             "graph_ms_profiled": st["batch_ms"] / max(1, st["batch_launches"]),
             "samples_per_s": info["samples"] / (ms * 1e-3),
             "beams_per_s": info["n_beams"] / (ms * 1e-3),
