@@ -168,7 +168,8 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
     th[lane] = 0.0f;                                       // kSurTailBins == 64
     const SurGeom g = a.g;
     const lidar_beam_info bi = a.beams[b];
-    const int u = bi.pixel_u, v = bi.pixel_v;
+    // the wave's beam: uniform, so the divisions below run on scalar registers
+    const int u = __builtin_amdgcn_readfirstlane(bi.pixel_u), v = __builtin_amdgcn_readfirstlane(bi.pixel_v);
     const int Ib = floordiv(u, g.cw), Jb = floordiv(v, g.ch);
     uint16_t* x = a.X + (size_t)b * kSurIn;
 
