@@ -192,11 +192,15 @@ SENSOR_HEIGHT = 0.5
 
 # Threshold and sun irradiance of the scanning-sensor workload.  T is 5 % of
 # the pulse-convolved peak return of a rho = 0.5 Lambertian face at 100 m
-# that fills the beam at normal incidence; E_sun puts the median per-beam sun
-# floor near 0.2 T.  Both literals were derived with the FP64 oracle and are
+# that fills the beam at normal incidence.  The per-beam sun floor is
+# bimodal (a quarter of the beams see only sky through their core, the
+# beams whose core sees the sunlit road collect 20-50 times more than the
+# median), so E_sun is set by its upper end: the 95th percentile of the
+# floor is 0.75 T, which keeps every beam's floor below T (the median floor
+# is then 0.004 T).  Both literals were derived with the FP64 oracle and are
 # re-derived by the test suite (tests/test_workloads.py).
 ROAD_THRESHOLD = 9.345e-08
-ROAD_SUN_IRRADIANCE = 1.335
+ROAD_SUN_IRRADIANCE = 0.02841
 
 
 def elliptic_table(nx=256, ny=256, half_deg=(2.0, 2.0), fwhm_deg=(0.1, 0.8),

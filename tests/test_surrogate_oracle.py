@@ -189,3 +189,143 @@ def test_labels_closed_form():
                                         1.0, 2.0, 0, 0, 0, 0, 0])
     # more echoes than stored: existence only for the three slots
     np.testing.assert_allclose(lab[1, :3], [1, 1, 1])
+
+
+# ---- tail energy and reference bin against hand-computed values -------------
+#
+# A 256 x 128 raster of 0.125-deg pixels and a 33 x 33 table whose cell
+# centres fall on the kernel's pixel offsets (half extent 2.0625 deg, so that
+# K[n][m] is exactly table[n + 16][m + 16]): a core of 1 at the centre and 0.5
+# on the 5 x 3 cells around it, and a flat tail of 1e-4 elsewhere (below the
+# 2e-4 core fraction).  The core box is then m in [-2, 2], n in [-1, 1];
+# coarse cells are single pixels and super-cells 3 x 3 pixels.  One beam sits
+# at pixel (128, 64).  Every other pixel is sky unless a test places a
+# surface, always facing the sensor (cos(theta) = 1) with gain 1.
+
+_HALF = 2.0625
+_TAIL = float(np.float32(1e-4))     # the table's float32 tail level
+_C = 299792458.0
+
+
+def _tail_table():
+    t = np.full((33, 33), _TAIL, np.float32)
+    t[15:18, 14:19] = 0.5
+    t[16, 16] = 1.0
+    return t
+
+
+def _sky_scene():
+    r = scenes.Raster(256, 128, -16.0, 16.0, -8.0, 8.0)
+    n = -scenes.pixel_directions(r)
+    gb = scenes.GBuffer(r, np.full((128, 256), np.inf, np.float32),
+                        np.zeros((128, 256), np.float32), np.ones((128, 256), np.float32),
+                        n.astype(np.float32))
+    pat = scenes.Pattern(scenes.PATTERN_TABLE, np.array([0.0625]), np.array([-0.0625]),
+                         table=_tail_table(), half_deg=(_HALF, _HALF))
+    p = scenes.SensorParams(n_bins=512, bin_ns=1.0, max_echoes=3, threshold=1e-9, emit_power=1.0,
+                            pulse_fwhm_ns=4.0, pulse_trunc_sigmas=4.0, ambient_const=1e-12)
+    return r, gb, pat, p
+
+
+def _depth_of_bin(k):
+    """A radial range whose time bin (1 ns bins) is k: the bin centre."""
+    return np.float32((k + 0.5) * _C * 1e-9 / 2.0)
+
+
+def _shade(r, v, d, rho):
+    """Omega(v) (rho / pi) / d^2 of a pixel facing the sensor, Omega the
+    exact pixel solid angle dphi (sin e_top - sin e_bot)."""
+    d2r = math.pi / 180.0
+    e_top = r.el_max - v * 0.125
+    e_bot = e_top - 0.125
+    om = 0.125 * d2r * (math.sin(e_top * d2r) - math.sin(e_bot * d2r))
+    return om * (rho / math.pi) / (float(d) ** 2)
+
+
+def _features(r, gb, pat, p):
+    import oracle as O
+    O._load()
+    K = O.kernel_grid(r, pat)
+    assert K.shape == (33, 33) and K[16, 16] == 1.0 and K[16, 18] == 0.5 and K[16, 19] == _TAIL
+    ref = O.simulate(gb, pat, p, want_xi=False)
+    assert tuple(ref.pixel[0]) == (128, 64)
+    out = S.features(gb, pat, p, K, ref.pixel, ref.scale, lambda v: O.row_solid_angle(r, v))
+    return ref, out
+
+
+def test_tail_energy_of_two_tail_super_cells():
+    """Super-cell A (columns 138-140, rows 63-65; centre offset m = 11, n = 0)
+    holds pixels in bins 14..17, super-cell B (columns 141-143; m = 14) pixels
+    in bins 16..21.  Each spreads K (1e-4) times its shade sum evenly over its
+    bin range; with 8 bins per coarse tail bin, A covers coarse bins 1 and 2,
+    B coarse bin 2 only, so E_tail = S_b 1e-4 (shade_A / 4 + shade_B / 6)."""
+    r, gb, pat, p = _sky_scene()
+    bins_a, bins_b = [14, 15, 16, 17], [16, 17, 18, 19, 20, 21]
+    shade = {"A": 0.0, "B": 0.0}
+    i = 0
+    for name, cols, bins in (("A", range(138, 141), bins_a), ("B", range(141, 144), bins_b)):
+        for v in range(63, 66):
+            for u in cols:
+                k = bins[i % len(bins)]
+                i += 1
+                rho = 0.3 + 0.05 * (i % 5)
+                gb.depth[v, u] = _depth_of_bin(k)
+                gb.reflectance[v, u] = rho
+                shade[name] += _shade(r, v, gb.depth[v, u], float(np.float32(rho)))
+    ref, (X, kref, et, ae, geo) = _features(r, gb, pat, p)
+    assert (geo["cm"], geo["cn"], geo["cw"], geo["ch"], geo["sw"], geo["sh"]) == (2, 1, 1, 1, 3, 3)
+    expect = ref.scale[0] * _TAIL * (shade["A"] / 4.0 + shade["B"] / 6.0)
+    assert et[0] == pytest.approx(expect, rel=1e-6)
+    # the patches lie outside the 16 x 16 coarse patch and the core box: no
+    # reference-bin contribution, no floor
+    assert ae[0] == pytest.approx(1e-12)
+
+
+def test_reference_bin_smoothed_first_maximum():
+    """Core-box cells put K x shade into bins k = 300 (centre pixel, K = 1),
+    k + 1 (the two pixels at m = +-1, K = 0.5) and k + 3 (the pixel at m = 2,
+    n = 0, K = 0.5).  Smoothing with (1, 2, 3, 2, 1) gives, at bin j,
+    h(j-2) + 2 h(j-1) + 3 h(j) + 2 h(j+1) + h(j+2); with h = (1, 1.1, 0, 1.5)
+    x w0 the smoothed values at k .. k+3 are 5.2, 7.1, 6.2, 5.6 (times w0),
+    so k_ref = k + 1, while the unsmoothed maximum sits at k + 3."""
+    r, gb, pat, p = _sky_scene()
+    k = 300
+    w0 = 1e-3
+    cells = {(128, 64): (k, 1.0, 1.0), (127, 64): (k + 1, 0.5, 0.55), (129, 64): (k + 1, 0.5, 0.55),
+             (130, 64): (k + 3, 0.5, 1.5)}
+    h = {}
+    for (u, v), (kb, kv, rel) in cells.items():
+        gb.depth[v, u] = _depth_of_bin(kb)
+        # reflectance chosen so that K x shade = rel x w0
+        rho = rel * w0 / (kv * _shade(r, v, gb.depth[v, u], 1.0))
+        gb.reflectance[v, u] = rho
+        h[kb] = h.get(kb, 0.0) + kv * _shade(r, v, gb.depth[v, u], float(np.float32(rho)))
+    assert h[k] == pytest.approx(w0, rel=1e-6) and h[k + 1] == pytest.approx(1.1 * w0, rel=1e-6)
+    assert h[k + 3] == pytest.approx(1.5 * w0, rel=1e-6)
+    ref, (X, kref, et, ae, geo) = _features(r, gb, pat, p)
+    assert kref[0] == k + 1
+    # the first channel is each cell's mean-depth offset from k_ref's centre
+    d = float(gb.depth[64, 128])
+    assert X[0, 8 * 16 + 8] == pytest.approx((d * 2.0 / (_C * 1e-9) - (k + 1.5)) / 64.0, rel=1e-9)
+
+
+def test_reference_bin_first_of_equal_maxima_and_fallback():
+    """Two equal weights w two bins apart (k and k + 2) smooth to 3w + w at k,
+    2w + 2w at k + 1 and w + 3w at k + 2: three equal maxima, of which the
+    first (bin k) is taken.  Without a core-box cell the reference bin is
+    the bin of the nearest cell mean depth in the patch."""
+    r, gb, pat, p = _sky_scene()
+    k = 200
+    for (u, v), kb in (((128, 64), k), ((130, 64), k + 2)):
+        gb.depth[v, u] = _depth_of_bin(kb)
+        kv = 1.0 if u == 128 else 0.5
+        gb.reflectance[v, u] = 1e-3 / (kv * _shade(r, v, gb.depth[v, u], 1.0))
+    ref, (X, kref, et, ae, geo) = _features(r, gb, pat, p)
+    assert kref[0] == k
+    # no core cell: only a pixel outside the core box but inside the patch
+    r, gb, pat, p = _sky_scene()
+    gb.depth[64, 133] = _depth_of_bin(77)
+    gb.depth[60, 124] = _depth_of_bin(90)
+    gb.reflectance[64, 133] = gb.reflectance[60, 124] = 0.5
+    ref, (X, kref, et, ae, geo) = _features(r, gb, pat, p)
+    assert kref[0] == 77

@@ -48,9 +48,13 @@ def test_road_scan_recipe_sun_floor_and_blooming(oracle_mod, w2):
     idx = np.arange(0, w2.pattern.n_beams, 11)
     sub = scenes.subset_beams(w2, idx)
     res = oracle_mod.simulate(gb, sub.pattern, sub.params, want_xi=False, want_xi_hat=False)
-    # median sun floor near 0.2 T
-    assert 0.15 < np.median(res.floor) / w2.params.threshold < 0.25
+    # sun floor: its 95th percentile at 0.75 T, so that the echo stage sees
+    # real returns (a floor above T would make the whole waveform one run)
+    r = res.floor / w2.params.threshold
+    assert 0.70 < np.quantile(r, 0.95) < 0.80
+    assert (r >= 1.0).mean() < 0.05
     assert (res.n_echoes > 0).mean() > 0.6
+    assert not np.any((res.echoes["flags"][:, 0] == 3) & (res.n_echoes > 0))
     # blooming: an echo whose bin matches a retroreflective pixel of the
     # footprint while the beam's own pixel is neither retroreflective nor at
     # that range
