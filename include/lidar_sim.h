@@ -222,7 +222,10 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode);
 /* Copy the last frame's results out.  echoes: [n_beams][max_echoes] (unused
  * slots zeroed), n_echoes: [n_beams] runs found (may exceed max_echoes),
  * waveforms: [n_beams][n_bins] xi_hat (needs LIDAR_KEEP_WAVEFORMS), beams:
- * [n_beams].  Any output may be NULL.  dst_is_device != 0: the destinations
+ * [n_beams].  After a LIDAR_MODE_SURROGATE frame the waveform rows of the
+ * beams whose echoes the network predicted (flag LIDAR_ECHO_SURROGATE) are
+ * NaN: no waveform is computed for them.  Any output may be NULL.
+ * dst_is_device != 0: the destinations
  * are device pointers and the copies are enqueued on the stream; else they are
  * host pointers and the call synchronises the stream.
  * Errors: LIDAR_E_STATE (no frame simulated), LIDAR_E_INVALID (waveforms
@@ -339,8 +342,9 @@ lidar_status lidar_sim_surrogate_set_gate(lidar_sim* h, double c_min, double alp
 
 /* Network inputs of the current frame (pattern and G-buffer as set): x,
  * device [n_beams][1056] bfloat16; aux (nullable), device [n_beams][4] FP32
- * {reference bin, E_tail, estimated floor A_b, accepted by the last
- * surrogate frame}; labels (nullable), device [n_beams][16] FP32 training
+ * {reference bin, E_tail, estimated floor A_b, 1 if the last surrogate
+ * frame on the current pattern kept the network's echoes, else 0 (0 before
+ * any surrogate frame)}; labels (nullable), device [n_beams][16] FP32 training
  * targets from the echoes of the last simulate_frame, which must have run
  * in LIDAR_MODE_PLAIN on the same inputs (existence, (peak bin - reference
  * bin) / 16, log10(max(intensity, 1e-3 T) / T), pulse width / 4 ns).

@@ -37,7 +37,8 @@ EXPORTED = ["lidar_sim_create", "lidar_sim_destroy", "lidar_sim_set_pattern",
             "lidar_sim_reset_batch", "lidar_sim_surrogate_set_weights",
             "lidar_sim_surrogate_get_weights", "lidar_sim_surrogate_forward",
             "lidar_sim_surrogate_gradients", "lidar_sim_surrogate_train_step",
-            "lidar_sim_surrogate_set_gate", "lidar_sim_surrogate_features", "lidar_sim_get_stats", "lidar_sim_reset_stats", "lidar_sim_last_error"]
+            "lidar_sim_surrogate_set_gate", "lidar_sim_surrogate_features", "lidar_sim_get_stats",
+            "lidar_sim_reset_stats", "lidar_sim_last_error"]
 
 SUR_IN, SUR_OUT, SUR_PARAMS = 1056, 16, 406288
 

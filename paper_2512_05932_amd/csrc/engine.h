@@ -78,9 +78,11 @@ hipError_t launch_kernel_rows(hipStream_t s, KernelDev k, const double* K64, dou
 hipError_t launch_kernel_peak(hipStream_t s, KernelDev k, const double* rowsum,
                               const double* rowmax, double* kinfo);
 hipError_t launch_raster_tables(hipStream_t s, RasterDev r, float2* colcs, float4* rowtab);
+// omega: scratch of H + 2 KH doubles (per-row solid angles)
 hipError_t launch_beam_setup(hipStream_t s, RasterDev r, KernelDev k, const double* az,
                              const double* el, int B, const double* rowsum,
-                             const int32_t* prefix, double emit_power, lidar_beam_info* beams);
+                             const int32_t* prefix, double* omega, double emit_power,
+                             lidar_beam_info* beams);
 hipError_t launch_pulse_taps(hipStream_t s, float sigma_ns, float bin_ns, int J, float* taps);
 
 // ---- per frame ----
@@ -339,6 +341,8 @@ hipError_t launch_labels(hipStream_t s, const lidar_echo* echoes, const int32_t*
 hipError_t launch_decode(hipStream_t s, const DecodeArgs& a);
 hipError_t launch_compact(hipStream_t s, const CompactArgs& a);
 hipError_t launch_aux_out(hipStream_t s, const SurAux* aux, int B, float* out);
+// NaN rows of the kept waveforms [B][R] of accepted beams
+hipError_t launch_fill_accepted(hipStream_t s, const SurAux* aux, int B, int R, float* waves);
 
 // fused inference: X [n][1056] BF16 -> Y [n][16] FP32, transposed BF16
 // weights Wt1 [256][1056], Wt2, Wt3 [256][256], Wt4 [16][256]

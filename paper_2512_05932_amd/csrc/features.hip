@@ -297,12 +297,12 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a)
         x[1024 + lane] = to_bf16(p);
     }
     if (lane == 0) {
-        SurAux o;
-        o.k_ref = k_ref;
-        o.e_tail = e_tail;
-        o.a_est = a_est;
-        o.accepted = 0;
-        a.aux[b] = o;
+        // the gate decision of the last surrogate frame (accepted) is left
+        // as it is: only k_decode writes it
+        SurAux* o = a.aux + b;
+        o->k_ref = k_ref;
+        o->e_tail = e_tail;
+        o->a_est = a_est;
     }
 }
 
@@ -389,6 +389,17 @@ __global__ void k_compact(CompactArgs a)
     }
 }
 
+// Kept waveforms of the beams whose echoes the network predicted: no
+// waveform is computed for them, so their rows are NaN (one workgroup per
+// beam; the others' rows are written by the plain-path fallback).
+__global__ void k_fill_accepted(const SurAux* aux, int B, int R, float* waves)
+{
+    const int b = blockIdx.x;
+    if (b >= B || !aux[b].accepted) return;
+    float* row = waves + (size_t)b * R;
+    for (int k = threadIdx.x; k < R; k += blockDim.x) row[k] = __builtin_nanf("");
+}
+
 __global__ void k_aux_out(const SurAux* aux, int B, float* out)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -440,6 +451,12 @@ hipError_t launch_decode(hipStream_t s, const DecodeArgs& a)
 hipError_t launch_compact(hipStream_t s, const CompactArgs& a)
 {
     hipLaunchKernelGGL(k_compact, dim3(blocks(a.n_groups, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_accepted(hipStream_t s, const SurAux* aux, int B, int R, float* waves)
+{
+    hipLaunchKernelGGL(k_fill_accepted, dim3(B), dim3(256), 0, s, aux, B, R, waves);
     return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ struct FrameState {
     KernelDev k{};
     double kmax = 0.0;
     uint64_t samples = 0;
-    DevBuf<double> d_K64, d_rowsum, d_rowmax, d_kinfo;
+    DevBuf<double> d_K64, d_rowsum, d_rowmax, d_kinfo, d_omega;
     DevBuf<float> d_Kb;
     DevBuf<int2> d_rowrange;
     DevBuf<int32_t> d_prefix;
@@ -87,8 +87,11 @@ struct lidar_sim {
     int G = 4;                         // beams per group (LDS budget)
     DevBuf<float> d_taps;
 
+    int cus = 256;                     // compute units of the device (queried at create)
+
     // single-frame mode
     bool have_pattern = false, have_gbuffer = false, setup_ok = false, have_result = false;
+    uint64_t pattern_gen = 0;          // incremented by every set_pattern
     FrameState single;
     DevBuf<lidar_beam_info> d_beams;
     DevBuf<lidar_echo> d_echoes;
@@ -133,6 +136,8 @@ struct lidar_sim {
     DevBuf<int> s_cnt;                 // [0] fallback items, [1] queue, [2] fallback beams (running)
     DevBuf<FrameDev> s_frame;
     FrameDev s_frame_host{};
+    uint64_t s_aux_gen = ~0ull;        // pattern generation whose gate decisions s_aux holds
+    const SurAux* s_aux_ptr = nullptr; // allocation those decisions were written to
     float gate_conf_logit = 0.0f;      // logit of c_min = 0.5
     float gate_alpha = 0.5f;
     bool plain_result = false;
@@ -492,6 +497,7 @@ lidar_status setup_frame(lidar_sim* h, FrameState& fs, lidar_beam_info* beams, c
     HIP_TRY(h, fs.d_kinfo.ensure(2), "allocate kernel info");
     HIP_TRY(h, fs.d_colcs.ensure(g.width), "allocate raster tables");
     HIP_TRY(h, fs.d_rowtab.ensure(g.height), "allocate raster tables");
+    HIP_TRY(h, fs.d_omega.ensure((size_t)g.height + 2 * (size_t)k.KH), "allocate raster tables");
 
     PatternDev p;
     p.kind = (int)fs.pat.kind;
@@ -512,7 +518,8 @@ lidar_status setup_frame(lidar_sim* h, FrameState& fs, lidar_beam_info* beams, c
             "kernel peak launch");
     HIP_TRY(h, launch_raster_tables(s, r, fs.d_colcs.p, fs.d_rowtab.p), "raster tables launch");
     HIP_TRY(h, launch_beam_setup(s, r, k, fs.d_az.p, fs.d_el.p, (int)B, fs.d_rowsum.p,
-                                 fs.d_prefix.p, h->prm.emit_power, beams), "beam setup launch");
+                                 fs.d_prefix.p, fs.d_omega.p, h->prm.emit_power, beams),
+            "beam setup launch");
     // the pattern's integral over the grid must be positive: checked once per
     // (pattern, raster), which synchronises the stream
     double kinfo[2];
@@ -677,6 +684,13 @@ lidar_status sur_inputs(lidar_sim* h, FrameState& fs, uint16_t* X)
     const lidar_gbuffer_desc& g = fs.gb;
     const int B = (int)fs.pat.az.size();
     HIP_TRY(h, h->s_aux.ensure(B), "allocate surrogate beam data");
+    if (h->s_aux_gen != h->pattern_gen || h->s_aux_ptr != h->s_aux.p) {
+        // no gate decision yet for these beams
+        HIP_TRY(h, launch_zero_f32(s, (float*)h->s_aux.p, (long)B * (long)(sizeof(SurAux) / 4)),
+                "clear surrogate beam data");
+        h->s_aux_gen = h->pattern_gen;
+        h->s_aux_ptr = h->s_aux.p;
+    }
     LIDAR_TRY(enqueue_prepass(h, fs, s));
     const bool sun = h->prm.sun_irradiance != 0.0;
     const double to_bin = 2.0 / (kLight * (h->prm.bin_ns * 1e-9));
@@ -1037,14 +1051,9 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
     h->b_samples = samples;
     // persistent grid: as many workgroups as the CUs hold at the LDS-bound
     // occupancy (extra workgroups would find the queue empty and exit)
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-    }
     const size_t lds = group_lds_bytes(G, R, h->J) + 2048;   // + static LDS
     const size_t per_cu = std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
-    h->b_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * per_cu, total_groups));
+    h->b_grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)h->cus * per_cu, total_groups));
     // schedule per frame: remembered from an earlier autotuning of the class,
     // else the wave schedule where most groups hold a single beam (three of
     // the four waves of a group would idle), then the autotuner if asked
@@ -1158,6 +1167,12 @@ lidar_status lidar_sim_create(const lidar_sim_params* params, void* hip_stream, 
     }
     h->prm = *params;
     h->stream = (hipStream_t)hip_stream;
+    {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            h->cus = n;
+    }
     double sigma = params->pulse_fwhm_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
     h->J = (int)std::ceil(params->pulse_trunc_sigmas * sigma / params->bin_ns);
     h->G = 4;
@@ -1195,6 +1210,7 @@ lidar_status lidar_sim_set_pattern(lidar_sim* h, const lidar_pattern_desc* pd)
     if (!h) return LIDAR_E_INVALID;
     LIDAR_TRY(check_pattern(h, pd, ""));
     LIDAR_TRY(copy_pattern(h, h->single, pd));
+    ++h->pattern_gen;
     h->have_pattern = true;
     h->setup_ok = false;
     h->have_result = false;
@@ -1364,16 +1380,13 @@ static lidar_status simulate_surrogate(lidar_sim* h)
     ba.n_items_dev = h->s_cnt.p;
     ba.tickets = nullptr;
     ba.n_tickets = 0;
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-    }
     const size_t lds = group_lds_bytes(h->G, (int)R, h->J) + 2048;   // + static LDS
     const size_t per_cu = std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
-    const int grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)cus * per_cu, (size_t)fs.n_groups));
+    const int grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)h->cus * per_cu, (size_t)fs.n_groups));
     HIP_TRY(h, launch_footprint_batch(s, ba, grid, h->prm.sun_irradiance != 0.0, keep),
             "fallback footprint launch");
+    // no waveform is computed for the beams the network answered
+    if (keep) HIP_TRY(h, launch_fill_accepted(s, h->s_aux.p, B, (int)R, h->d_waves.p), "waveform fill launch");
     if (prof) {
         HIP_TRY(h, hipEventRecord(ev.b, s), "record event");
         h->pending_sur.push_back(ev);

@@ -162,11 +162,22 @@ __global__ void k_raster_tables(RasterDev r, float2* colcs, float4* rowtab)
     }
 }
 
+// omega[i] = Omega(v0 + i), the FP64 solid angle of a pixel of row v0 + i
+// (rows above and below the image included).
+__global__ void k_row_omega(RasterDev r, long v0, int n, double* omega)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) omega[i] = row_omega(r, v0 + i);
+}
+
 // Per beam: containing pixel (floor rounding), FP64 normalisation over every
 // kernel cell (on- and off-image rows), scale S_b = P_e / N_b, and the number
-// of non-zero kernel cells inside the image.
+// of non-zero kernel cells inside the image.  Row solid angles come from the
+// table omega (rows om_v0 .. om_v0 + om_n - 1, the same FP64 values) and are
+// computed directly for beams beyond it.
 __global__ void k_beam_setup(RasterDev r, KernelDev k, const double* az, const double* el,
                              int B, const double* rowsum, const int32_t* prefix,
+                             const double* omega, long om_v0, int om_n,
                              double emit_power, lidar_beam_info* beams)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -179,7 +190,12 @@ __global__ void k_beam_setup(RasterDev r, KernelDev k, const double* az, const d
     fv = fmin(fmax(fv, -lim), lim);
     long ub = (long)fu, vb = (long)fv;
     double nb = 0.0;
-    for (int n = -k.N; n <= k.N; ++n) nb += rowsum[n + k.N] * row_omega(r, vb + n);
+    if (vb - k.N >= om_v0 && vb + k.N < om_v0 + om_n) {
+        const double* om = omega + (vb - k.N - om_v0);
+        for (int n = 0; n < k.KH; ++n) nb += rowsum[n] * om[n];
+    } else {
+        for (int n = -k.N; n <= k.N; ++n) nb += rowsum[n + k.N] * row_omega(r, vb + n);
+    }
     uint32_t samples = 0;
     long c_lo = (long)-k.M > -ub ? (long)-k.M : -ub;
     long c_hi = (long)k.M < (long)r.W - 1 - ub ? (long)k.M : (long)r.W - 1 - ub;
@@ -259,10 +275,15 @@ hipError_t launch_raster_tables(hipStream_t s, RasterDev r, float2* colcs, float
 
 hipError_t launch_beam_setup(hipStream_t s, RasterDev r, KernelDev k, const double* az,
                              const double* el, int B, const double* rowsum,
-                             const int32_t* prefix, double emit_power, lidar_beam_info* beams)
+                             const int32_t* prefix, double* omega, double emit_power,
+                             lidar_beam_info* beams)
 {
+    // rows -KH .. H + KH - 1: every beam whose footprint meets the image
+    const long v0 = -(long)k.KH;
+    const int n = r.H + 2 * k.KH;
+    hipLaunchKernelGGL(k_row_omega, dim3((n + 255) / 256), dim3(256), 0, s, r, v0, n, omega);
     hipLaunchKernelGGL(k_beam_setup, dim3((B + 127) / 128), dim3(128), 0, s, r, k, az, el, B,
-                       rowsum, prefix, emit_power, beams);
+                       rowsum, prefix, (const double*)omega, v0, n, emit_power, beams);
     return hipGetLastError();
 }
 

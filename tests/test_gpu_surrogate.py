@@ -194,3 +194,36 @@ def test_all_accepted_decodes_the_network(lidar):
             assert ech["flags"][b, i] == 4
             assert ech["range_m"][b, i] == (k + 0.5) * half_c_dt
     np.testing.assert_allclose(out["beams"]["floor"], ae, rtol=1e-4, atol=1e-30)
+
+
+def test_gate_decisions_reported_in_aux(lidar):
+    """Column 3 of surrogate_features' aux is the last surrogate frame's gate
+    decision: all ones when every beam is kept, all zeros when every beam
+    falls back (the input kernel does not overwrite it)."""
+    w = _scan()
+    out, st = _run_mode(lidar, w, scenes.surrogate_init(2), c_min=0.0, alpha=1e30)
+    assert st["fallback_beams"] == 0
+    assert np.all(out["aux"][:, 3] == 1.0)
+    out, st = _run_mode(lidar, w, scenes.surrogate_init(2), c_min=1.0, alpha=1e30)
+    assert st["fallback_beams"] == w.pattern.n_beams
+    assert np.all(out["aux"][:, 3] == 0.0)
+
+
+def test_partial_accept_waveforms(lidar, oracle_mod):
+    """With some beams kept and some falling back, kept waveforms are NaN
+    for the beams the network answered (no waveform is computed for them)
+    and the fallback beams' waveforms match the FP64 oracle."""
+    w = _scan()
+    out, st = _run_mode(lidar, w, scenes.surrogate_init(2), c_min=0.5, alpha=1e30, keep=True)
+    acc = out["aux"][:, 3] == 1.0
+    print(f"[sur-mode] partial accept: {acc.sum()} of {len(acc)} kept", flush=True)
+    assert 0 < acc.sum() < len(acc)
+    assert st["fallback_beams"] == int((~acc).sum())
+    wav = out["waveforms"]
+    assert np.all(np.isnan(wav[acc]))
+    assert np.all((out["echoes"]["flags"][acc][out["n_echoes"][acc] > 0][:, 0] & 4) == 4)
+    ref = oracle_mod.simulate(w.gbuffer, scenes.subset_beams(w, np.flatnonzero(~acc)).pattern,
+                              w.params)
+    peak = ref.xi_hat.max(axis=1, keepdims=True)
+    err = (np.abs(wav[~acc] - ref.xi_hat) / peak).max()
+    assert err <= 1e-5
