@@ -359,8 +359,39 @@ lidar_status lidar_sim_get_stats(lidar_sim* h, lidar_stats* out);
 /* Zero the frame and timing counters.  Errors: LIDAR_E_INVALID (null). */
 lidar_status lidar_sim_reset_stats(lidar_sim* h);
 
+/* ---- Allocation-free frame ------------------------------------------------
+ * For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc): set_pattern + set_gbuffer +
+ * simulate_frame(LIDAR_MODE_PLAIN) + read_echoes(dst_is_device = 1) in one
+ * stateless call that allocates nothing.  Every device buffer of the frame
+ * (pulse taps, pattern and beam copies, kernel tables, beam groups, pixel
+ * records) is carved from a static device array of LIDAR_STATIC_SCRATCH_BYTES
+ * that each GPU holds from the library's first use on it until the process
+ * ends; frames whose buffers do not fit (about 8 bytes per pixel of the
+ * width rounded up to 4, 12 with the sun term, 16 per beam, plus the kernel
+ * tables: 55 MB for an 8192x512 frame with a 225x641 kernel) are rejected
+ * with LIDAR_E_INVALID.  params->flags must be 0 (no kept waveforms,
+ * profiling or autotuning).  Outputs, all device pointers owned by the
+ * caller: echoes [n_beams][max_echoes], n_echoes [n_beams], beams
+ * [n_beams] (laid out as in lidar_sim_read_echoes).  Host inputs are copied;
+ * the G-buffer planes are read on the stream.  The call synchronises the
+ * stream once, after the kernel set-up (the pattern-integral check), and
+ * returns with the frame's pre-pass and footprint kernel enqueued.  Every
+ * call on a GPU uses that GPU's one array: calls whose work overlaps on one
+ * GPU (different streams or threads) race; calls one after another on the
+ * same stream do not.  Errors: as create, set_pattern, set_gbuffer and
+ * simulate_frame, LIDAR_E_INVALID for null outputs or a frame too large
+ * for the array; lidar_sim_last_error(NULL) describes them. */
+#define LIDAR_STATIC_SCRATCH_BYTES (64u << 20)
+lidar_status lidar_sim_simulate_static(const lidar_sim_params* params,
+                                       const lidar_pattern_desc* pattern,
+                                       const lidar_gbuffer_desc* gbuffer, void* hip_stream,
+                                       lidar_echo* echoes, int32_t* n_echoes,
+                                       lidar_beam_info* beams);
+
 /* Text of the last error of the handle (handle-owned; "" if none).  With a
- * NULL handle: the last error of a failed lidar_sim_create in this thread. */
+ * NULL handle: the last error of a failed lidar_sim_create or
+ * lidar_sim_simulate_static in this thread. */
 const char* lidar_sim_last_error(const lidar_sim* h);
 
 #ifdef __cplusplus

@@ -38,7 +38,7 @@ EXPORTED = ["lidar_sim_create", "lidar_sim_destroy", "lidar_sim_set_pattern",
             "lidar_sim_surrogate_get_weights", "lidar_sim_surrogate_forward",
             "lidar_sim_surrogate_gradients", "lidar_sim_surrogate_train_step",
             "lidar_sim_surrogate_set_gate", "lidar_sim_surrogate_features", "lidar_sim_get_stats",
-            "lidar_sim_reset_stats", "lidar_sim_last_error"]
+            "lidar_sim_reset_stats", "lidar_sim_simulate_static", "lidar_sim_last_error"]
 
 SUR_IN, SUR_OUT, SUR_PARAMS = 1056, 16, 406288
 
@@ -134,6 +134,8 @@ def load():
     lib.lidar_sim_surrogate_features.argtypes = [V, V, V, V]
     lib.lidar_sim_get_stats.argtypes = [V, P(lidar_stats)]
     lib.lidar_sim_reset_stats.argtypes = [V]
+    lib.lidar_sim_simulate_static.argtypes = [P(lidar_sim_params), P(lidar_pattern_desc),
+                                              P(lidar_gbuffer_desc), V, V, V, V]
     lib.lidar_sim_last_error.argtypes = [V]
     lib.lidar_sim_last_error.restype = C.c_char_p
     for name in EXPORTED[:-1]:
@@ -206,6 +208,27 @@ class Batch:
                 cache[id(pat)] = pattern_desc(pat, self._keep)
             self.pd[i] = cache[id(pat)]
         self.n_beams = [int(self.pd[i].n_beams) for i in range(n)]
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def simulate_static(params, pattern, raster, planes, echoes, n_echoes, beams, stream=None,
+                    pitch: int | None = None):
+    """lidar_sim_simulate_static: one plain frame with no device allocation.
+    echoes / n_echoes / beams: device tensors of [B][E] lidar_echo bytes
+    (uint8 [B][E*40]), int32 [B] and lidar_beam_info bytes (uint8 [B][24])."""
+    lib = load()
+    keep: list = []
+    prm = make_params(params, 0)
+    pd = pattern_desc(pattern, keep)
+    gd = gbuffer_desc(raster, planes, pitch)
+    s = C.c_void_p(stream.cuda_stream if stream is not None else 0)
+    rc = lib.lidar_sim_simulate_static(C.byref(prm), C.byref(pd), C.byref(gd), s,
+                                       C.c_void_p(echoes.data_ptr()), C.c_void_p(n_echoes.data_ptr()),
+                                       C.c_void_p(beams.data_ptr()))
+    if rc != LIDAR_OK:
+        raise LidarError(rc, lib.lidar_sim_last_error(None).decode())
 
 
 class LidarSim:

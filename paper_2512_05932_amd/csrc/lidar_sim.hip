@@ -16,6 +16,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -147,11 +148,53 @@ struct lidar_sim {
     std::vector<EventPair> pending_fp, pending_pp, pending_bt, pending_sur, pool;
 };
 
+// ---- scratch of the allocation-free entry point -----------------------------
+// lidar_sim_simulate_static works entirely in this file-scope device array:
+// every GPU the library runs on holds its own copy at its own address (taken
+// once per device with hipGetSymbolAddress), kept until the process ends.  In
+// host code the name is not a device address; host code uses only the
+// address recorded per device.
+namespace lidar {
+constexpr size_t kStaticScratchBytes = LIDAR_STATIC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+}  // namespace lidar
+
 namespace {
 
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxStaticDevices] = {};
+
+// Device address of the current device's scratch array, recorded at the first
+// call on that device (with the device current).
+hipError_t static_scratch_addr(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxStaticDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(lidar::scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+namespace {
+
+// Record an error on the handle (or, without one, as the thread's last
+// handle-less error: failed create or simulate_static).
 lidar_status fail(lidar_sim* h, lidar_status code, const std::string& msg)
 {
     if (h) h->err = msg;
+    else g_create_error = msg;
     return code;
 }
 
@@ -1142,6 +1185,216 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
     return LIDAR_OK;
 }
 
+
+// ---- allocation-free frame ---------------------------------------------------
+
+// Byte offsets of the static path's buffers in the scratch array (256-byte
+// aligned), in the order they are taken.
+struct ScratchPlan {
+    size_t off = 0;
+    template <typename T>
+    size_t take(size_t count)
+    {
+        const size_t o = off;
+        off = (off + count * sizeof(T) + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+// The plain path of one frame (set-up, pre-pass, fused footprint kernel) with
+// every device buffer carved from the static scratch array; errors go to the
+// thread's handle-less error text.
+lidar_status simulate_static(const lidar_sim_params* prm, const lidar_pattern_desc* pd,
+                             const lidar_gbuffer_desc* gb, hipStream_t s, lidar_echo* echoes,
+                             int32_t* counts, lidar_beam_info* beams)
+{
+    lidar_sim* const h = nullptr;          // errors: g_create_error
+    std::string why;
+    if (check_params(prm, why) != LIDAR_OK) return fail(h, LIDAR_E_INVALID, why);
+    if (prm->flags != 0)
+        return fail(h, LIDAR_E_INVALID, "simulate_static takes no flags (no kept waveforms, "
+                                        "profiling or autotuning)");
+    LIDAR_TRY(check_pattern(h, pd, ""));
+    LIDAR_TRY(check_gbuffer(h, gb, ""));
+    if (!echoes || !counts || !beams)
+        return fail(h, LIDAR_E_INVALID, "simulate_static needs the device outputs echoes, "
+                                        "n_echoes and beams");
+    // host copy of the pattern (as copy_pattern, without device buffers)
+    FrameState fs;
+    PatternHost& pat = fs.pat;
+    const size_t B = pd->n_beams;
+    pat.kind = pd->kind;
+    pat.az.assign(pd->beam_az_deg, pd->beam_az_deg + B);
+    pat.el.assign(pd->beam_el_deg, pd->beam_el_deg + B);
+    if (pd->kind == LIDAR_PATTERN_GAUSS) {
+        pat.sigma[0] = pd->sigma_deg[0];
+        pat.sigma[1] = pd->sigma_deg[1];
+        pat.trunc = pd->trunc_sigmas;
+    } else {
+        pat.nx = pd->nx;
+        pat.ny = pd->ny;
+        pat.half[0] = pd->half_deg[0];
+        pat.half[1] = pd->half_deg[1];
+        pat.table.assign(pd->table, pd->table + (size_t)pd->nx * pd->ny);
+    }
+    fs.gb = *gb;
+    const RasterDev r = raster_of(*gb);
+    double Mf, Nf;
+    kernel_extent(pat, r, &Mf, &Nf);
+    if (!(Mf >= 0 && Nf >= 0) || Mf > 4096 || Nf > 4096 || (2 * Mf + 1) * (2 * Nf + 1) > 16.0e6)
+        return fail(h, LIDAR_E_INVALID, "kernel grid too large for this raster (more than 16M "
+                                        "cells or 8193 columns/rows)");
+    if ((4.0 * Mf + 8.0) * (double)gb->height * 8.0 >= 2147483648.0)
+        return fail(h, LIDAR_E_INVALID, "kernel window times image height too large "
+                                        "(4*M+8)*height*8 must stay below 2^31 bytes");
+    KernelDev k;
+    k.M = (int)Mf;
+    k.N = (int)Nf;
+    k.KW = 2 * k.M + 1;
+    k.KH = 2 * k.N + 1;
+    fs.k = k;
+    const double sigma = prm->pulse_fwhm_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    const int J = (int)std::ceil(prm->pulse_trunc_sigmas * sigma / prm->bin_ns);
+    int G = 4;
+    while (G > 1 && !footprint_group_fits(G, (int)prm->n_bins, J)) G /= 2;
+    const bool sun = prm->sun_irradiance != 0.0;
+    const size_t W = gb->width, H = gb->height, W4 = (W + 3) & ~(size_t)3;
+    const size_t NB = (size_t)kernel_blocks(k.KW), KW = (size_t)k.KW, KH = (size_t)k.KH;
+    // the beam groups (host scheduling from the beams' pixels; costs unused)
+    build_groups(fs, r, G, std::vector<lidar_beam_info>(B));
+    // scratch layout; checked against the array's size before any device call
+    ScratchPlan plan;
+    const size_t o_taps = plan.take<float>(2 * (size_t)J + 1);
+    const size_t o_table = plan.take<float>(pat.table.size());
+    const size_t o_az = plan.take<double>(B), o_el = plan.take<double>(B);
+    const size_t o_K64 = plan.take<double>(KW * KH);
+    const size_t o_Kb = plan.take<float>(4 * NB * (KH + 1) * 4);
+    const size_t o_rowsum = plan.take<double>(KH), o_rowmax = plan.take<double>(KH);
+    const size_t o_rowrange = plan.take<int2>(KH);
+    const size_t o_prefix = plan.take<int32_t>(KH * (KW + 1));
+    const size_t o_kinfo = plan.take<double>(2);
+    const size_t o_omega = plan.take<double>(H + 2 * KH);
+    const size_t o_colcs = plan.take<float2>(W), o_rowtab = plan.take<float4>(H);
+    const size_t o_pix = plan.take<int2>(W4 * H);
+    const size_t o_sun = plan.take<float>(sun ? W4 * H : 0);
+    const size_t o_groups = plan.take<int32_t>(fs.groups.size());
+    if (plan.off > kStaticScratchBytes)
+        return fail(h, LIDAR_E_INVALID,
+                    "simulate_static: this frame needs " + std::to_string(plan.off) +
+                        " bytes of scratch, the static area holds " +
+                        std::to_string(kStaticScratchBytes) + " (about 8 bytes per pixel, 12 with "
+                        "the sun term, 16 per beam, and the kernel tables)");
+    char* base = nullptr;
+    HIP_TRY(h, static_scratch_addr((void**)&base), "static scratch address");
+    float* taps = (float*)(base + o_taps);
+    float* table = (float*)(base + o_table);
+    double* az = (double*)(base + o_az);
+    double* el = (double*)(base + o_el);
+    double* K64 = (double*)(base + o_K64);
+    float* Kb = (float*)(base + o_Kb);
+    double* rowsum = (double*)(base + o_rowsum);
+    double* rowmax = (double*)(base + o_rowmax);
+    int2* rowrange = (int2*)(base + o_rowrange);
+    int32_t* prefix = (int32_t*)(base + o_prefix);
+    double* kinfo_d = (double*)(base + o_kinfo);
+    double* omega = (double*)(base + o_omega);
+    float2* colcs = (float2*)(base + o_colcs);
+    float4* rowtab = (float4*)(base + o_rowtab);
+    int2* pix = (int2*)(base + o_pix);
+    float* sunb = sun ? (float*)(base + o_sun) : nullptr;
+    int32_t* groups = (int32_t*)(base + o_groups);
+    // host inputs into the scratch (the host copies stay alive until the
+    // synchronisation below)
+    HIP_TRY(h, hipMemcpyAsync(az, pat.az.data(), B * sizeof(double), hipMemcpyHostToDevice, s), "copy beams");
+    HIP_TRY(h, hipMemcpyAsync(el, pat.el.data(), B * sizeof(double), hipMemcpyHostToDevice, s), "copy beams");
+    if (!pat.table.empty())
+        HIP_TRY(h, hipMemcpyAsync(table, pat.table.data(), pat.table.size() * sizeof(float),
+                                  hipMemcpyHostToDevice, s), "copy table");
+    HIP_TRY(h, hipMemcpyAsync(groups, fs.groups.data(), fs.groups.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s), "copy beam groups");
+    HIP_TRY(h, launch_pulse_taps(s, (float)sigma, (float)prm->bin_ns, J, taps), "pulse taps launch");
+    PatternDev pdev;
+    pdev.kind = (int)pat.kind;
+    pdev.sx = pat.sigma[0];
+    pdev.sy = pat.sigma[1];
+    pdev.trunc = pat.trunc;
+    pdev.table = pat.table.empty() ? nullptr : table;
+    pdev.nx = (int)pat.nx;
+    pdev.ny = (int)pat.ny;
+    pdev.hx = pat.half[0];
+    pdev.hy = pat.half[1];
+    HIP_TRY(h, launch_kernel_grid(s, pdev, r, k, K64), "kernel grid launch");
+    HIP_TRY(h, launch_kernel_blocks(s, k, K64, Kb), "kernel blocks launch");
+    HIP_TRY(h, launch_kernel_rows(s, k, K64, rowsum, rowmax, rowrange, prefix), "kernel rows launch");
+    HIP_TRY(h, launch_kernel_peak(s, k, rowsum, rowmax, kinfo_d), "kernel peak launch");
+    HIP_TRY(h, launch_raster_tables(s, r, colcs, rowtab), "raster tables launch");
+    HIP_TRY(h, launch_beam_setup(s, r, k, az, el, (int)B, rowsum, prefix, omega, prm->emit_power, beams),
+            "beam setup launch");
+    double kinfo[2];
+    HIP_TRY(h, hipMemcpyAsync(kinfo, kinfo_d, sizeof(kinfo), hipMemcpyDeviceToHost, s), "copy kernel info");
+    HIP_TRY(h, hipStreamSynchronize(s), "set-up synchronise");
+    if (!(kinfo[1] > 0.0) || !is_fin(kinfo[1]) || !(kinfo[0] > 0.0))
+        return fail(h, LIDAR_E_INVALID, "pattern integral over the kernel grid is not positive "
+                                        "(kernel narrower than one pixel or all-zero table)");
+    // the frame: pre-pass, then the fused footprint kernel (asynchronous)
+    PrepassArgs pa;
+    pa.depth = gb->depth;
+    pa.refl = gb->reflectance;
+    pa.gain = gb->retro_gain;
+    pa.nx = gb->normal_x;
+    pa.ny = gb->normal_y;
+    pa.nz = gb->normal_z;
+    pa.pitch = (long)gb->pitch;
+    pa.W = (int)W;
+    pa.H = (int)H;
+    pa.W4 = (int)W4;
+    pa.colcs = colcs;
+    pa.rowtab = rowtab;
+    pa.to_bin = 2.0 / (kLight * (prm->bin_ns * 1e-9));
+    pa.R = (int)prm->n_bins;
+    pa.sun_x = (float)prm->sun_dir[0];
+    pa.sun_y = (float)prm->sun_dir[1];
+    pa.sun_z = (float)prm->sun_dir[2];
+    pa.pix = pix;
+    pa.sun = sunb;
+    HIP_TRY(h, launch_prepass(s, pa, sun), "pre-pass launch");
+    FootprintArgs fa;
+    FrameDev& f = fa.f;
+    f = FrameDev{};
+    f.pix = pix;
+    f.sun = sunb;
+    f.W = (int)W;
+    f.H = (int)H;
+    f.Kb = Kb;
+    f.rowrange = rowrange;
+    f.M = k.M;
+    f.N = k.N;
+    f.KW = k.KW;
+    f.KH = k.KH;
+    f.NB = (int)NB;
+    f.tile = default_tile(k.KH);
+    f.sun_scale = sun ? (float)(prm->sun_irradiance / kinfo[0]) : 0.0f;
+    f.beams = beams;
+    f.echoes = echoes;
+    f.counts = counts;
+    f.waves = nullptr;
+    PathDev& pp = fa.p;
+    pp.taps = taps;
+    pp.J = J;
+    pp.R = (int)prm->n_bins;
+    pp.E = (int)prm->max_echoes;
+    pp.threshold = (float)prm->threshold;
+    pp.ambient = (float)prm->ambient_const;
+    pp.half_c_dt = 0.5 * kLight * (prm->bin_ns * 1e-9);
+    pp.bin_ns = prm->bin_ns;
+    fa.groups = groups;
+    fa.n_groups = fs.n_groups;
+    fa.G = G;
+    fa.chunk = (fs.n_groups + kXcds - 1) / kXcds;
+    HIP_TRY(h, launch_footprint(s, fa), "footprint launch");
+    return LIDAR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1688,6 +1941,14 @@ lidar_status lidar_sim_reset_stats(lidar_sim* h)
     h->st.surrogate_frames = 0;
     if (h->s_cnt.p) HIP_TRY(h, launch_reset_queue(h->stream, h->s_cnt.p + 2, 1), "counter reset");
     return LIDAR_OK;
+}
+
+lidar_status lidar_sim_simulate_static(const lidar_sim_params* params, const lidar_pattern_desc* pattern,
+                                       const lidar_gbuffer_desc* gbuffer, void* hip_stream,
+                                       lidar_echo* echoes, int32_t* n_echoes, lidar_beam_info* beams)
+{
+    g_create_error.clear();
+    return simulate_static(params, pattern, gbuffer, (hipStream_t)hip_stream, echoes, n_echoes, beams);
 }
 
 const char* lidar_sim_last_error(const lidar_sim* h)

@@ -116,3 +116,46 @@ def test_null_arguments_are_rejected(binding):
     assert lib.lidar_sim_read_batch(None, 0, None, None, None, None, 0) == binding.LIDAR_E_INVALID
     assert lib.lidar_sim_batch_info(None, None) == binding.LIDAR_E_INVALID
     assert lib.lidar_sim_reset_batch(None) == binding.LIDAR_E_INVALID
+
+
+def _static_args(binding, width, height, flags=0):
+    """Descriptors of a frame for lidar_sim_simulate_static whose device
+    pointers are placeholders: every call here is rejected before any of
+    them is read."""
+    import numpy as np
+    import scenes
+    keep: list = []
+    prm = binding.make_params(_P(), flags=flags)
+    r = scenes.Raster(width, height, -60.0, 60.0, -20.0, 20.0)
+    pat = scenes.Pattern(scenes.PATTERN_GAUSS, np.array([0.0, 1.0]), np.array([0.0, -1.0]),
+                         sigma_deg=(0.1, 0.1), trunc_sigmas=3.0)
+    pd = binding.pattern_desc(pat, keep)
+    fake = 0x1000
+    gd = binding.lidar_gbuffer_desc(width, height, width, r.az_min, r.az_max, r.el_min, r.el_max,
+                                    *([fake] * 6))
+    return prm, pd, gd, keep
+
+
+def test_static_frame_rejects_frames_beyond_its_scratch(binding):
+    """16384 x 2048 pixels need 256 MiB of pixel records: more than the
+    static array holds; the call says how much it needed."""
+    lib = binding.load()
+    prm, pd, gd, keep = _static_args(binding, 16384, 2048)
+    fake = C.c_void_p(0x1000)
+    rc = lib.lidar_sim_simulate_static(C.byref(prm), C.byref(pd), C.byref(gd), None, fake, fake, fake)
+    assert rc == binding.LIDAR_E_INVALID
+    msg = lib.lidar_sim_last_error(None).decode()
+    assert "bytes of scratch" in msg and str(binding.STATIC_SCRATCH_BYTES) in msg
+
+
+def test_static_frame_rejects_flags_and_null_outputs(binding):
+    lib = binding.load()
+    fake = C.c_void_p(0x1000)
+    prm, pd, gd, keep = _static_args(binding, 64, 32, flags=binding.LIDAR_KEEP_WAVEFORMS)
+    rc = lib.lidar_sim_simulate_static(C.byref(prm), C.byref(pd), C.byref(gd), None, fake, fake, fake)
+    assert rc == binding.LIDAR_E_INVALID and "flags" in lib.lidar_sim_last_error(None).decode()
+    prm, pd, gd, keep = _static_args(binding, 64, 32)
+    rc = lib.lidar_sim_simulate_static(C.byref(prm), C.byref(pd), C.byref(gd), None, None, fake, fake)
+    assert rc == binding.LIDAR_E_INVALID and "outputs" in lib.lidar_sim_last_error(None).decode()
+    rc = lib.lidar_sim_simulate_static(None, C.byref(pd), C.byref(gd), None, fake, fake, fake)
+    assert rc == binding.LIDAR_E_INVALID
