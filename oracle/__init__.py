@@ -33,7 +33,8 @@ class _Pattern(C.Structure):
     _fields_ = [("kind", C.c_int32), ("sigma_az", C.c_double), ("sigma_el", C.c_double),
                 ("trunc_sigmas", C.c_double), ("table", C.POINTER(C.c_float)),
                 ("nx", C.c_int32), ("ny", C.c_int32),
-                ("half_az", C.c_double), ("half_el", C.c_double)]
+                ("half_az", C.c_double), ("half_el", C.c_double),
+                ("rx_table", C.POINTER(C.c_float))]
 
 
 class _Params(C.Structure):
@@ -41,7 +42,9 @@ class _Params(C.Structure):
                 ("bin_ns", C.c_double), ("threshold", C.c_double),
                 ("emit_power", C.c_double), ("pulse_fwhm_ns", C.c_double),
                 ("pulse_trunc_sigmas", C.c_double), ("ambient_const", C.c_double),
-                ("sun_irradiance", C.c_double), ("sun_dir", C.c_double * 3)]
+                ("sun_irradiance", C.c_double), ("sun_dir", C.c_double * 3),
+                ("pulse_taps", C.POINTER(C.c_double)), ("n_pulse_taps", C.c_int32),
+                ("echo_select", C.c_int32), ("range_mode", C.c_int32)]
 
 
 ECHO_DTYPE = np.dtype([("range_m", "f8"), ("time_ns", "f8"), ("intensity", "f8"),
@@ -84,6 +87,13 @@ def _load():
         lib.orc_detect.restype = C.c_int32
         lib.orc_detect.argtypes = [P(C.c_double), C.c_int32, C.c_double, C.c_double,
                                    C.c_double, C.c_int32, C.c_void_p]
+        lib.orc_select.restype = C.c_int32
+        lib.orc_select.argtypes = [P(C.c_double), P(C.c_double), C.c_int32, C.c_double,
+                                   C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_void_p]
+        lib.orc_plane_range.restype = C.c_double
+        lib.orc_plane_range.argtypes = [C.c_double, P(C.c_double), P(C.c_double), P(C.c_double)]
+        lib.orc_pixel_interval.argtypes = [P(_Raster), C.c_int64, C.c_int64, C.c_double,
+                                           P(C.c_double), P(C.c_double), P(C.c_double)]
         _lib = lib
     return _lib
 
@@ -104,16 +114,31 @@ def _pattern(p, keep):
     if p.table is not None:
         t = np.ascontiguousarray(p.table, dtype=np.float32)
         keep.append(t)
+        rx = None
+        if getattr(p, "rx_table", None) is not None:
+            rxa = np.ascontiguousarray(p.rx_table, dtype=np.float32)
+            assert rxa.shape == t.shape
+            keep.append(rxa)
+            rx = _fptr(rxa)
         return _Pattern(p.kind, 0.0, 0.0, 0.0, _fptr(t), t.shape[1], t.shape[0],
-                        float(p.half_deg[0]), float(p.half_deg[1]))
+                        float(p.half_deg[0]), float(p.half_deg[1]), rx)
     return _Pattern(p.kind, float(p.sigma_deg[0]), float(p.sigma_deg[1]),
-                    float(p.trunc_sigmas), None, 0, 0, 0.0, 0.0)
+                    float(p.trunc_sigmas), None, 0, 0, 0.0, 0.0, None)
 
 
-def _params(q) -> _Params:
+def _params(q, keep=None) -> _Params:
+    taps = getattr(q, "pulse_taps", None)
+    tp, nt = None, 0
+    if taps is not None:
+        ta = np.ascontiguousarray(taps, dtype=np.float64)
+        if keep is None:
+            raise ValueError("a tabulated pulse needs a keep list")
+        keep.append(ta)
+        tp, nt = _dptr(ta), int(ta.shape[0])
     return _Params(q.n_bins, q.max_echoes, q.bin_ns, q.threshold, q.emit_power,
                    q.pulse_fwhm_ns, q.pulse_trunc_sigmas, q.ambient_const,
-                   q.sun_irradiance, (C.c_double * 3)(*q.sun_dir))
+                   q.sun_irradiance, (C.c_double * 3)(*q.sun_dir), tp, nt,
+                   int(getattr(q, "echo_select", 0)), int(getattr(q, "range_mode", 0)))
 
 
 @dataclass
@@ -136,7 +161,7 @@ def simulate(gbuffer, pattern, params, want_xi=True, want_xi_hat=True,
     planes = [np.ascontiguousarray(a, dtype=np.float32) for a in gbuffer.planes()]
     r = _raster(gbuffer.raster)
     pat = _pattern(pattern, keep)
-    prm = _params(params)
+    prm = _params(params, keep)
     B, R, E = pattern.n_beams, params.n_bins, params.max_echoes
     az = np.ascontiguousarray(pattern.beam_az, dtype=np.float64)
     el = np.ascontiguousarray(pattern.beam_el, dtype=np.float64)
@@ -196,7 +221,8 @@ def beam_pixel(raster, az: float, el: float):
 
 def pulse_taps(params) -> np.ndarray:
     lib = _load()
-    q = _params(params)
+    keep = []
+    q = _params(params, keep)
     J = lib.orc_pulse_half_taps(C.byref(q))
     taps = np.zeros(2 * J + 1)
     lib.orc_pulse_taps(C.byref(q), _dptr(taps))
@@ -212,3 +238,33 @@ def detect(xi_hat: np.ndarray, threshold: float, floor: float, bin_ns: float,
     n = lib.orc_detect(_dptr(xh), xh.shape[0], threshold, floor, bin_ns, max_echoes,
                        out.ctypes.data_as(C.c_void_p))
     return n, out[:min(n, max_echoes)]
+
+
+def select(xi: np.ndarray, xi_hat: np.ndarray, threshold: float, floor: float, bin_ns: float,
+           max_echoes: int, mode: int):
+    """Echoes of one beam under an echo-selection mode; returns (count,
+    echoes[max_echoes])."""
+    lib = _load()
+    a = np.ascontiguousarray(xi, dtype=np.float64)
+    b = np.ascontiguousarray(xi_hat, dtype=np.float64)
+    out = np.zeros(max(1, max_echoes), dtype=ECHO_DTYPE)
+    n = lib.orc_select(_dptr(a), _dptr(b), a.shape[0], threshold, floor, bin_ns, max_echoes,
+                       int(mode), out.ctypes.data_as(C.c_void_p))
+    return n, out[:max_echoes]
+
+
+def plane_range(d: float, p, w, n) -> float:
+    """d (p.n)/(w.n) with the ratio limited to [1/2, 2]."""
+    lib = _load()
+    arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (p, w, n)]
+    return lib.orc_plane_range(float(d), *[_dptr(x) for x in arr])
+
+
+def pixel_interval(raster, u: int, v: int, d: float, normal):
+    """(r0, r1): the range interval of pixel (u, v) of range d and normal n."""
+    lib = _load()
+    r = _raster(raster)
+    nn = np.ascontiguousarray(normal, dtype=np.float64)
+    r0, r1 = C.c_double(), C.c_double()
+    lib.orc_pixel_interval(C.byref(r), int(u), int(v), float(d), _dptr(nn), C.byref(r0), C.byref(r1))
+    return r0.value, r1.value

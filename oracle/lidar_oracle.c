@@ -32,6 +32,22 @@
  *      peak bin centre and the echo pulse width from linearly interpolated
  *      threshold crossings (section II-C, EPW paragraph).
  *
+ * Options of the same path:
+ *   - a tabulated pulse varpi (samples at the bin pitch, centred), used
+ *     normalised to unit sum like the Gaussian (section II-C, EPW paragraph);
+ *   - a collector sensitivity table kappa for the sun term, measured apart
+ *     from the combined pattern (section III-B); without it kappa = K/max K;
+ *   - range modes (section II-D, rasterization; Alg. 1, pixelRangeInterval):
+ *     the pixel's centre range (default); the range corrected to the true
+ *     direction v of each kernel cell, r = d (p.n) / (v.n) with p the pixel
+ *     centre direction; or the pixel's range interval, the plane through
+ *     the pixel's centre point with normal n met by the four corner rays,
+ *     the pixel's weight shared evenly by the bins of that interval;
+ *   - echo selection (section II-C, after Alg. 1): the strongest, nearest or
+ *     longest (widest EPW) run of xi_hat, or, without the pulse
+ *     post-processing, the strongest or nearest bin of the raw signal at or
+ *     above T (the single echo comparable to range stacking, Alg. 2).
+ *
  * Readings where the paper is silent (each one is listed in the design doc):
  * accumulate rather than assign in Alg. 1; a single bin per pixel;
  * floor rounding to the containing pixel; correlation orientation
@@ -67,7 +83,12 @@ typedef struct {
     const float* table;     /* [ny][nx], row 0 = +elevation */
     int32_t nx, ny;
     double half_az, half_el;
+    const float* rx_table;  /* optional kappa [ny][nx] on the table's grid (kind 2) */
 } orc_pattern;
+
+enum { ORC_ALL = 0, ORC_STRONGEST = 1, ORC_NEAREST = 2, ORC_LONGEST = 3,
+       ORC_RAW_STRONGEST = 4, ORC_RAW_NEAREST = 5 };
+enum { ORC_RANGE_CENTRE = 0, ORC_RANGE_CORRECTED = 1, ORC_RANGE_INTERVAL = 2 };
 
 typedef struct {
     int32_t n_bins, max_echoes;
@@ -75,6 +96,10 @@ typedef struct {
     double pulse_fwhm_ns, pulse_trunc_sigmas;
     double ambient_const, sun_irradiance;
     double sun_dir[3];
+    const double* pulse_taps;   /* optional tabulated pulse, n_pulse_taps samples */
+    int32_t n_pulse_taps;
+    int32_t echo_select;        /* ORC_ALL .. ORC_RAW_NEAREST */
+    int32_t range_mode;         /* ORC_RANGE_* */
 } orc_params;
 
 typedef struct {
@@ -173,21 +198,29 @@ void orc_kernel_grid(const orc_raster* r, const orc_pattern* p, double* K)
 
 int32_t orc_pulse_half_taps(const orc_params* q)
 {
+    if (q->pulse_taps) return (q->n_pulse_taps - 1) / 2;
     double sigma = q->pulse_fwhm_ns / (2.0 * sqrt(2.0 * log(2.0)));
     return (int32_t)ceil(q->pulse_trunc_sigmas * sigma / q->bin_ns);
 }
 
-/* Centred Gaussian pulse sampled at the bin pitch, normalised to unit sum;
- * taps[j + J] for j in [-J, J]. */
+/* Centred pulse sampled at the bin pitch, normalised to unit sum; taps[j + J]
+ * for j in [-J, J]: the given table, or a Gaussian of the given FWHM. */
 void orc_pulse_taps(const orc_params* q, double* taps)
 {
-    double sigma = q->pulse_fwhm_ns / (2.0 * sqrt(2.0 * log(2.0)));
     int32_t J = orc_pulse_half_taps(q);
     double s = 0.0;
-    for (int32_t j = -J; j <= J; ++j) {
-        double t = (double)j * q->bin_ns;
-        taps[j + J] = exp(-(t * t) / (2.0 * sigma * sigma));
-        s += taps[j + J];
+    if (q->pulse_taps) {
+        for (int32_t j = -J; j <= J; ++j) {
+            taps[j + J] = q->pulse_taps[j + J];
+            s += taps[j + J];
+        }
+    } else {
+        double sigma = q->pulse_fwhm_ns / (2.0 * sqrt(2.0 * log(2.0)));
+        for (int32_t j = -J; j <= J; ++j) {
+            double t = (double)j * q->bin_ns;
+            taps[j + J] = exp(-(t * t) / (2.0 * sigma * sigma));
+            s += taps[j + J];
+        }
     }
     for (int32_t j = -J; j <= J; ++j) taps[j + J] /= s;
 }
@@ -235,6 +268,102 @@ int32_t orc_detect(const double* xh, int32_t R, double T, double floor_b, double
     return count;
 }
 
+/* Pick one of the runs of xi_hat (echo selection): the strongest (largest
+ * peak), the nearest (first) or the longest (widest pulse width); the first
+ * such run wins a tie.  runs[0..n) hold every run in time order. */
+static int32_t orc_pick(const orc_echo* runs, int32_t n, int32_t mode)
+{
+    int32_t best = 0;
+    for (int32_t i = 1; i < n; ++i) {
+        if (mode == ORC_STRONGEST) {
+            double a = runs[i].intensity, b = runs[best].intensity;
+            if (a > b) best = i;
+        } else if (mode == ORC_LONGEST) {
+            if (runs[i].pulse_width_ns > runs[best].pulse_width_ns) best = i;
+        }
+    }
+    return best;
+}
+
+/* Echoes of one beam under the selection mode: xh is xi_hat, xi the raw
+ * binned signal (scaled by S_b); writes max_echoes slots (zeroed beyond the
+ * echoes kept) and returns the count (all runs, or 0/1 for the raw modes). */
+int32_t orc_select(const double* xi, const double* xh, int32_t R, double T, double floor_b,
+                   double bin_ns, int32_t max_echoes, int32_t mode, orc_echo* out)
+{
+    memset(out, 0, sizeof(orc_echo) * (size_t)max_echoes);
+    if (mode == ORC_ALL) return orc_detect(xh, R, T, floor_b, bin_ns, max_echoes, out);
+    if (mode == ORC_RAW_STRONGEST || mode == ORC_RAW_NEAREST) {
+        int32_t k = -1;
+        for (int32_t i = 0; i < R; ++i) {
+            if (!(xi[i] >= T)) continue;
+            if (k < 0) k = i;
+            if (mode == ORC_RAW_NEAREST) break;
+            if (xi[i] > xi[k]) k = i;
+        }
+        if (k < 0) return 0;
+        double half_c_dt = 0.5 * ORC_C_LIGHT * (bin_ns * 1e-9);
+        out[0].bin_peak = out[0].bin_first = out[0].bin_last = k;
+        out[0].time_ns = ((double)k + 0.5) * bin_ns;
+        out[0].range_m = ((double)k + 0.5) * half_c_dt;
+        out[0].intensity = xi[k];
+        out[0].pulse_width_ns = 0.0;
+        out[0].flags = 0;
+        return 1;
+    }
+    orc_echo* runs = (orc_echo*)malloc(sizeof(orc_echo) * (size_t)(R / 2 + 1));
+    int32_t n = orc_detect(xh, R, T, floor_b, bin_ns, R / 2 + 1, runs);
+    if (n > 0) out[0] = runs[mode == ORC_NEAREST ? 0 : orc_pick(runs, n, mode)];
+    free(runs);
+    return n;
+}
+
+/* ---- range of a sample ----------------------------------------------------- */
+
+static void orc_dir(double az_deg, double el_deg, double* d)
+{
+    double a = deg2rad(az_deg), e = deg2rad(el_deg);
+    d[0] = cos(e) * cos(a);
+    d[1] = cos(e) * sin(a);
+    d[2] = sin(e);
+}
+
+/* Range at which the plane through the point d*p (p: unit pixel-centre
+ * direction) with normal n meets the ray along w: d (p.n) / (w.n), the
+ * ratio (p.n)/(w.n) limited to [1/2, 2] (and 2 when the ray misses the
+ * plane's side facing the sensor). */
+double orc_plane_range(double d, const double* p, const double* w, const double* n)
+{
+    double pn = p[0] * n[0] + p[1] * n[1] + p[2] * n[2];
+    double wn = w[0] * n[0] + w[1] * n[1] + w[2] * n[2];
+    double q = pn / wn;
+    if (!(q > 0.0)) q = 2.0;
+    if (q < 0.5) q = 0.5;
+    if (q > 2.0) q = 2.0;
+    return d * q;
+}
+
+/* The pixel's range interval (Alg. 1, pixelRangeInterval): the centre range
+ * and the ranges of the four corner rays on the pixel's plane; *r0, *r1 are
+ * their minimum and maximum. */
+void orc_pixel_interval(const orc_raster* r, int64_t u, int64_t v, double d, const double* n,
+                        double* r0, double* r1)
+{
+    double dphi = orc_dphi(r), de = orc_de(r), p[3], w[3];
+    orc_dir(r->az_min + ((double)u + 0.5) * dphi, r->el_max - ((double)v + 0.5) * de, p);
+    double lo = d, hi = d;
+    for (int c = 0; c < 4; ++c) {
+        double az = r->az_min + (double)(u + (c & 1)) * dphi;
+        double el = r->el_max - (double)(v + (c >> 1)) * de;
+        orc_dir(az, el, w);
+        double rc = orc_plane_range(d, p, w, n);
+        if (rc < lo) lo = rc;
+        if (rc > hi) hi = rc;
+    }
+    *r0 = lo;
+    *r1 = hi;
+}
+
 /* ---- the whole per-beam path -------------------------------------------- */
 
 /*
@@ -261,6 +390,17 @@ int orc_simulate(const orc_raster* r, const float* depth, const float* refl,
     orc_kernel_grid(r, p, K);
     double kmax = 0.0;
     for (int64_t i = 0; i < KW * KH; ++i) if (K[i] > kmax) kmax = K[i];
+    /* collector sensitivity of the sun term: the kappa table resampled like
+     * K, or K / max K */
+    double* kap = (double*)malloc(sizeof(double) * KW * KH);
+    if (!kap) { free(K); return -1; }
+    if (p->kind == 2 && p->rx_table) {
+        orc_pattern rx = *p;
+        rx.table = p->rx_table;
+        orc_kernel_grid(r, &rx, kap);
+    } else {
+        for (int64_t i = 0; i < KW * KH; ++i) kap[i] = K[i] / kmax;
+    }
 
     int32_t J = orc_pulse_half_taps(q);
     double* taps = (double*)malloc(sizeof(double) * (2 * J + 1));
@@ -291,6 +431,7 @@ int orc_simulate(const orc_raster* r, const float* depth, const float* refl,
         double* xh = (double*)malloc(sizeof(double) * R);
         int64_t ub, vb;
         orc_beam_pixel(r, beam_az[b], beam_el[b], &ub, &vb);
+        double true_dir[3];
 
         /* normalisation over the whole kernel, on- and off-image rows */
         double nb = 0.0;
@@ -307,28 +448,54 @@ int orc_simulate(const orc_raster* r, const float* depth, const float* refl,
             if (v < 0 || v >= H) continue;
             double om = orc_row_solid_angle(r, v);
             for (int64_t m = -M; m <= M; ++m) {
+                /* the laser term covers the cells with K > 0, the sun term
+                 * the cells with kappa > 0 (the same cells without a kappa
+                 * table) */
                 double kv = K[(n + N) * KW + (m + M)];
-                if (!(kv > 0.0)) continue;
+                double ka = kap[(n + N) * KW + (m + M)];
+                if (!(kv > 0.0) && !(ka > 0.0)) continue;
                 int64_t u = ub + m;
                 if (u < 0 || u >= W) continue;
-                ++nsamp;
+                if (kv > 0.0) ++nsamp;
                 int64_t px = v * W + u;
                 double d = (double)depth[px];
                 if (!(isfinite(d) && d > 0.0)) continue;
-                double kb = floor(d * to_bin);
-                if (!(kb >= 0.0 && kb < (double)R)) continue;
+                double nrm[3] = {(double)nxp[px], (double)nyp[px], (double)nzp[px]};
+                /* the pixel's bins: its centre bin, the bin of the range
+                 * corrected to this kernel cell's true direction, or the bins
+                 * of its range interval */
+                double kb = floor(d * to_bin), k0 = kb, k1 = kb;
+                int pixel_ok = kb >= 0.0 && kb < (double)R;
+                if (q->range_mode == ORC_RANGE_INTERVAL) {
+                    double r0, r1;
+                    orc_pixel_interval(r, u, v, d, nrm, &r0, &r1);
+                    k0 = floor(r0 * to_bin);
+                    k1 = floor(r1 * to_bin);
+                    pixel_ok = k0 < (double)R;
+                }
+                if (!pixel_ok) continue;
                 double vx = cel[v] * cphi[u], vy = cel[v] * sphi[u], vz = sel[v];
-                double nx = (double)nxp[px], ny = (double)nyp[px], nz = (double)nzp[px];
+                double nx = nrm[0], ny = nrm[1], nz = nrm[2];
                 double cos_t = -(nx * vx + ny * vy + nz * vz);
                 if (cos_t < 0.0) cos_t = 0.0;
                 double rho = (double)refl[px];
                 double beta = (double)gain[px] * rho / ORC_PI;
                 double w = Sb * kv * om * beta * cos_t / (d * d);
-                xi[(int64_t)kb] += w;
+                if (q->range_mode == ORC_RANGE_CORRECTED) {
+                    double pd[3] = {vx, vy, vz};
+                    orc_dir(beam_az[b] + (double)m * dphi, beam_el[b] - (double)n * de, true_dir);
+                    double kc = floor(orc_plane_range(d, pd, true_dir, nrm) * to_bin);
+                    if (kc >= 0.0 && kc < (double)R) xi[(int64_t)kc] += w;
+                } else if (q->range_mode == ORC_RANGE_INTERVAL) {
+                    double share = w / (k1 - k0 + 1.0);
+                    for (double k = k0; k <= k1 && k < (double)R; k += 1.0) xi[(int64_t)k] += share;
+                } else {
+                    xi[(int64_t)kb] += w;
+                }
                 if (q->sun_irradiance != 0.0) {
                     double ns = nx * q->sun_dir[0] + ny * q->sun_dir[1] + nz * q->sun_dir[2];
                     if (ns < 0.0) ns = 0.0;
-                    sun_acc += (kv / kmax) * om * (rho / ORC_PI) * ns;
+                    sun_acc += ka * om * (rho / ORC_PI) * ns;
                 }
             }
         }
@@ -343,10 +510,10 @@ int orc_simulate(const orc_raster* r, const float* depth, const float* refl,
             }
             xh[k] = s + fl;
         }
-        orc_echo tmp[64];
+        orc_echo tmp[8];
         orc_echo* eo = echoes ? &echoes[(int64_t)b * q->max_echoes] : tmp;
-        int32_t ne = orc_detect(xh, R, q->threshold, fl, q->bin_ns,
-                                echoes ? q->max_echoes : 0, eo);
+        int32_t ne = orc_select(xi, xh, R, q->threshold, fl, q->bin_ns, q->max_echoes,
+                                q->echo_select, eo);
         if (n_echoes) n_echoes[b] = ne;
         if (xi_out) memcpy(&xi_out[(int64_t)b * R], xi, sizeof(double) * R);
         if (xh_out) memcpy(&xh_out[(int64_t)b * R], xh, sizeof(double) * R);
@@ -357,6 +524,6 @@ int orc_simulate(const orc_raster* r, const float* depth, const float* refl,
         free(xi);
         free(xh);
     }
-    free(K); free(taps); free(cphi); free(sphi); free(cel); free(sel);
+    free(K); free(kap); free(taps); free(cphi); free(sphi); free(cel); free(sel);
     return 0;
 }

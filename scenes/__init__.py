@@ -72,6 +72,7 @@ class Pattern:
     trunc_sigmas: float = 3.0            # GAUSS: elliptical cut radius in sigmas
     table: np.ndarray | None = None      # TABLE: [ny][nx] float32, row 0 = +el
     half_deg: tuple = (0.0, 0.0)         # TABLE: half extent along az, el
+    rx_table: np.ndarray | None = None   # TABLE: collector sensitivity kappa on the same grid
 
     @property
     def n_beams(self) -> int:
@@ -90,6 +91,15 @@ class SensorParams:
     ambient_const: float = 0.0
     sun_irradiance: float = 0.0
     sun_dir: tuple = (0.0, 0.0, 1.0)
+    pulse_taps: np.ndarray | None = None  # tabulated pulse: 2J+1 samples at the bin pitch
+    echo_select: int = 0                  # ECHO_SELECT_* (0: the first max_echoes runs)
+    range_mode: int = 0                   # RANGE_* (0: each pixel at its centre range)
+
+
+# echo selection and range modes (values of the C-ABI's enums)
+ECHO_SELECT_ALL, ECHO_SELECT_STRONGEST, ECHO_SELECT_NEAREST, ECHO_SELECT_LONGEST = 0, 1, 2, 3
+ECHO_SELECT_RAW_STRONGEST, ECHO_SELECT_RAW_NEAREST = 4, 5
+RANGE_CENTRE, RANGE_CORRECTED, RANGE_INTERVAL = 0, 1, 2
 
 
 @dataclass
