@@ -63,6 +63,36 @@ enum {
 /* lidar_pattern_desc.kind */
 enum { LIDAR_PATTERN_GAUSS = 1, LIDAR_PATTERN_TABLE = 2 };
 
+/* lidar_sim_params.echo_select: which echoes a beam reports (section II-C,
+ * after Alg. 1: a single echo per beam, searched for the strongest, nearest
+ * or longest one).  ALL: the first max_echoes runs of xi_hat > T in time
+ * order.  STRONGEST / NEAREST / LONGEST: the one run with the largest peak,
+ * the first run, or the run with the largest pulse width (the first such run
+ * on a tie) in slot 0; n_echoes still counts every run.  RAW_STRONGEST /
+ * RAW_NEAREST: without the pulse post-processing, the bin of the raw binned
+ * signal S_b xi[k] with the largest value, or the first bin, at or above T
+ * (the single echo comparable to range stacking, Alg. 2): slot 0 holds it
+ * as a one-bin echo (bin_first = bin_peak = bin_last, pulse width 0,
+ * intensity S_b xi[k], no floor) and n_echoes is 1 or 0; kept waveforms are
+ * then the raw S_b xi. */
+enum { LIDAR_ECHO_ALL = 0, LIDAR_ECHO_STRONGEST = 1, LIDAR_ECHO_NEAREST = 2,
+       LIDAR_ECHO_LONGEST = 3, LIDAR_ECHO_RAW_STRONGEST = 4, LIDAR_ECHO_RAW_NEAREST = 5 };
+
+/* lidar_sim_params.range_mode: the range a pixel contributes at (section
+ * II-D, rasterization; Alg. 1, pixelRangeInterval).  CENTRE: its depth, one
+ * time bin.  CORRECTED: for every beam and kernel cell, the range on the
+ * pixel's plane (centre point d p, normal n) along the cell's true direction
+ * v = dir(az_b + m dphi, el_b - n de): d (p.n) / (v.n), the ratio limited to
+ * [1/2, 2] (2 where v misses the plane's facing side); one bin per sample.
+ * INTERVAL: the range interval [r0, r1] of the pixel's plane over its
+ * centre and four corner rays (same ratio limit); the pixel's weight is
+ * shared evenly by the bins of that interval (bins past the last one are
+ * dropped), and the pixel counts (also for the sun term) when its depth is
+ * valid and r0 is inside the bin window.  CORRECTED runs one beam per
+ * workgroup and only in lidar_sim_simulate_frame (LIDAR_MODE_PLAIN);
+ * INTERVAL also in batches. */
+enum { LIDAR_RANGE_CENTRE = 0, LIDAR_RANGE_CORRECTED = 1, LIDAR_RANGE_INTERVAL = 2 };
+
 /* lidar_sim_simulate_frame mode: the plain method, or the learned surrogate
  * with the plain method as fallback (extension) */
 enum { LIDAR_MODE_PLAIN = 0, LIDAR_MODE_SURROGATE = 1 };
@@ -81,13 +111,23 @@ typedef struct {
                                   is a maximal run of bins with xi_hat > T */
     double emit_power;         /* P_e: the footprint weights of a beam sum to P_e
                                   times the shading over its whole kernel */
-    double pulse_fwhm_ns;      /* FWHM of the Gaussian pulse varpi (ns), > 0 */
+    double pulse_fwhm_ns;      /* FWHM of the Gaussian pulse varpi (ns), > 0; unused
+                                  with pulse_taps */
     double pulse_trunc_sigmas; /* pulse taps j with |j| <= ceil(this*sigma/dt) */
     double ambient_const;      /* constant floor added to every bin */
     double sun_irradiance;     /* E_sun, 0 = no sun term */
     double sun_dir[3];         /* unit vector towards the sun, sensor frame */
     uint32_t flags;            /* LIDAR_KEEP_WAVEFORMS | LIDAR_PROFILE | LIDAR_AUTOTUNE */
-    uint32_t reserved;         /* must be 0 */
+    uint32_t echo_select;      /* LIDAR_ECHO_ALL .. LIDAR_ECHO_RAW_NEAREST */
+    uint32_t range_mode;       /* LIDAR_RANGE_CENTRE | _CORRECTED | _INTERVAL */
+    uint32_t n_pulse_taps;     /* with pulse_taps: odd, 1..257 */
+    const float* pulse_taps;   /* optional tabulated pulse varpi (host, copied at
+                                  create): n_pulse_taps samples at the bin pitch,
+                                  centred on the middle one, finite, >= 0, positive
+                                  sum; used normalised to unit sum like the Gaussian
+                                  (section II-C, EPW paragraph: varpi is the emitted
+                                  pulse, in general a measured shape); NULL: the
+                                  Gaussian of pulse_fwhm_ns */
 } lidar_sim_params;
 
 /* Combined emitter x collector pattern (kappa*eta, Eq. 5) and the beams. */
@@ -104,6 +144,14 @@ typedef struct {
     double half_deg[2];        /* TABLE: half extent along azimuth, elevation */
     const double* beam_az_deg; /* host [n_beams] beam-centre azimuths */
     const double* beam_el_deg; /* host [n_beams] beam-centre elevations */
+    const float* rx_table;     /* TABLE, optional: collector sensitivity kappa (section
+                                  III-B: measured apart from the emitter) on the
+                                  table's grid, finite, >= 0, copied; the sun term
+                                  sums kappa Omega (rho/pi) max(0, n.s) over the
+                                  kernel-window cells with kappa > 0.  NULL: kappa =
+                                  K / max K over the cells with K > 0.  Not with
+                                  LIDAR_MODE_SURROGATE (its floor estimate uses
+                                  K / max K) */
 } lidar_pattern_desc;
 
 /* One rendered frame: six float32 device planes [height][pitch] (borrowed). */
@@ -371,7 +419,8 @@ lidar_status lidar_sim_reset_stats(lidar_sim* h);
  * width rounded up to 4, 12 with the sun term, 16 per beam, plus the kernel
  * tables: 55 MB for an 8192x512 frame with a 225x641 kernel) are rejected
  * with LIDAR_E_INVALID.  params->flags must be 0 (no kept waveforms,
- * profiling or autotuning).  Outputs, all device pointers owned by the
+ * profiling or autotuning); range modes other than LIDAR_RANGE_CENTRE and
+ * an rx_table give LIDAR_E_UNSUPPORTED.  Outputs, all device pointers owned by the
  * caller: echoes [n_beams][max_echoes], n_echoes [n_beams], beams
  * [n_beams] (laid out as in lidar_sim_read_echoes).  Host inputs are copied;
  * the G-buffer planes are read on the stream.  The call synchronises the

@@ -29,6 +29,9 @@ LIDAR_PATTERN_TABLE = 2
 LIDAR_MODE_PLAIN = 0
 LIDAR_MODE_SURROGATE = 1
 LIDAR_ECHO_SURROGATE = 4
+LIDAR_ECHO_ALL, LIDAR_ECHO_STRONGEST, LIDAR_ECHO_NEAREST, LIDAR_ECHO_LONGEST = 0, 1, 2, 3
+LIDAR_ECHO_RAW_STRONGEST, LIDAR_ECHO_RAW_NEAREST = 4, 5
+LIDAR_RANGE_CENTRE, LIDAR_RANGE_CORRECTED, LIDAR_RANGE_INTERVAL = 0, 1, 2
 
 # every function the header declares
 EXPORTED = ["lidar_sim_create", "lidar_sim_destroy", "lidar_sim_set_pattern",
@@ -48,14 +51,17 @@ class lidar_sim_params(C.Structure):
                 ("threshold", C.c_double), ("emit_power", C.c_double),
                 ("pulse_fwhm_ns", C.c_double), ("pulse_trunc_sigmas", C.c_double),
                 ("ambient_const", C.c_double), ("sun_irradiance", C.c_double),
-                ("sun_dir", C.c_double * 3), ("flags", C.c_uint32), ("reserved", C.c_uint32)]
+                ("sun_dir", C.c_double * 3), ("flags", C.c_uint32), ("echo_select", C.c_uint32),
+                ("range_mode", C.c_uint32), ("n_pulse_taps", C.c_uint32),
+                ("pulse_taps", C.POINTER(C.c_float))]
 
 
 class lidar_pattern_desc(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("n_beams", C.c_uint32), ("sigma_deg", C.c_double * 2),
                 ("trunc_sigmas", C.c_double), ("table", C.POINTER(C.c_float)),
                 ("nx", C.c_uint32), ("ny", C.c_uint32), ("half_deg", C.c_double * 2),
-                ("beam_az_deg", C.POINTER(C.c_double)), ("beam_el_deg", C.POINTER(C.c_double))]
+                ("beam_az_deg", C.POINTER(C.c_double)), ("beam_el_deg", C.POINTER(C.c_double)),
+                ("rx_table", C.POINTER(C.c_float))]
 
 
 class lidar_gbuffer_desc(C.Structure):
@@ -144,13 +150,24 @@ def load():
     return lib
 
 
-def make_params(p, flags: int = 0) -> lidar_sim_params:
-    """lidar_sim_params from any object with the fields of the C struct."""
+def make_params(p, flags: int = 0, keep: list | None = None) -> lidar_sim_params:
+    """lidar_sim_params from any object with the fields of the C struct
+    (optional: pulse_taps, echo_select, range_mode); a tabulated pulse array
+    goes into `keep`, which must outlive the call that reads it."""
+    taps = getattr(p, "pulse_taps", None)
+    tp, nt = None, 0
+    if taps is not None:
+        t = np.ascontiguousarray(taps, dtype=np.float32)
+        if keep is None:
+            raise ValueError("a tabulated pulse needs a keep list")
+        keep.append(t)
+        tp, nt = t.ctypes.data_as(C.POINTER(C.c_float)), int(t.shape[0])
     return lidar_sim_params(int(p.n_bins), int(p.max_echoes), float(p.bin_ns),
                             float(p.threshold), float(p.emit_power), float(p.pulse_fwhm_ns),
                             float(p.pulse_trunc_sigmas), float(p.ambient_const),
                             float(p.sun_irradiance), (C.c_double * 3)(*map(float, p.sun_dir)),
-                            int(flags), 0)
+                            int(flags), int(getattr(p, "echo_select", 0)),
+                            int(getattr(p, "range_mode", 0)), nt, tp)
 
 
 def pattern_desc(pattern, keep: list) -> lidar_pattern_desc:
@@ -172,6 +189,13 @@ def pattern_desc(pattern, keep: list) -> lidar_pattern_desc:
         d.ny, d.nx = table.shape
         d.half_deg = (C.c_double * 2)(*map(float, pattern.half_deg))
         keep.append(table)
+        rx = getattr(pattern, "rx_table", None)
+        if rx is not None:
+            rxa = np.ascontiguousarray(rx, dtype=np.float32)
+            if rxa.shape != table.shape:
+                raise ValueError("rx_table must have the table's shape")
+            d.rx_table = rxa.ctypes.data_as(C.POINTER(C.c_float))
+            keep.append(rxa)
     return d
 
 
@@ -220,7 +244,7 @@ def simulate_static(params, pattern, raster, planes, echoes, n_echoes, beams, st
     (uint8 [B][E*40]), int32 [B] and lidar_beam_info bytes (uint8 [B][24])."""
     lib = load()
     keep: list = []
-    prm = make_params(params, 0)
+    prm = make_params(params, 0, keep)
     pd = pattern_desc(pattern, keep)
     gd = gbuffer_desc(raster, planes, pitch)
     s = C.c_void_p(stream.cuda_stream if stream is not None else 0)
@@ -240,7 +264,8 @@ class LidarSim:
         self.params = params
         flags = (LIDAR_KEEP_WAVEFORMS if keep_waveforms else 0) | \
             (LIDAR_PROFILE if profile else 0) | (LIDAR_AUTOTUNE if autotune else 0)
-        self._prm = make_params(params, flags)
+        keep: list = []
+        self._prm = make_params(params, flags, keep)
         self._h = C.c_void_p()
         s = C.c_void_p(stream.cuda_stream if stream is not None else 0)
         rc = self._lib.lidar_sim_create(C.byref(self._prm), s, C.byref(self._h))

@@ -85,6 +85,19 @@ hipError_t launch_beam_setup(hipStream_t s, RasterDev r, KernelDev k, const doub
                              lidar_beam_info* beams);
 hipError_t launch_pulse_taps(hipStream_t s, float sigma_ns, float bin_ns, int J, float* taps);
 
+// FP64 direction tables of a raster for the range modes: cos and sin of the
+// pixel-centre azimuth of every column / elevation of every row, and of the
+// column and row edges (W + 1 and H + 1 entries; edge u is az_min + u dphi,
+// edge v is el_max - v de).
+struct RangeTables {
+    const double2* col;         // [W]
+    const double2* row;         // [H]
+    const double2* col_edge;    // [W + 1]
+    const double2* row_edge;    // [H + 1]
+};
+hipError_t launch_range_tables(hipStream_t s, RasterDev r, double2* col, double2* row,
+                               double2* col_edge, double2* row_edge);
+
 // ---- per frame ----
 struct PrepassArgs {
     const float *depth, *refl, *gain, *nx, *ny, *nz;
@@ -98,12 +111,16 @@ struct PrepassArgs {
     int2* pix;                  // [W4/4][H][4] {bin, shade bits}, 4-column blocks
     float* sun;                 // [W4/4][H][4] sun shading, 4-column blocks (or null)
     int W4;                     // W rounded up to a multiple of 4 (padding: sky)
+    int range_mode;             // LIDAR_RANGE_*: INTERVAL packs {first | last << 16} bins
+                                // and the shade per bin; CORRECTED also writes rec4
+    RangeTables rt;             // range modes: FP64 direction tables
+    float4* rec4;               // CORRECTED: [W4/4][H][4] {depth, nx, ny, nz} (or null)
 };
 hipError_t launch_prepass(hipStream_t s, const PrepassArgs& a, bool with_sun);
 // all frames of a batch in one launch (tile_off: [n + 1] prefix of prepass_tiles)
 int prepass_tiles(const PrepassArgs& a);
 hipError_t launch_prepass_batch(hipStream_t s, const PrepassArgs* frames, const int* tile_off,
-                                int n, int total_tiles, bool with_sun);
+                                int n, int total_tiles, bool with_sun, int range_mode);
 
 // Kernel table in 4-column blocks, in four copies shifted by one column:
 // copy s, block b, row n holds K(c, n) for the kernel columns
@@ -124,6 +141,16 @@ struct FrameDev {
     int tile;                   // strip height: 64, 16 or 4 rows (64/tile column phases)
     float sun_scale;            // E_sun / max K (0: no sun term)
     int wave;                   // batches: 1 = the frame's items go to the wave schedule
+    int span;                   // 1: pixel keys are {first | last << 16} bin ranges
+    int floor_given;            // 1: the floor A_b is in beams[].floor (kappa table)
+    // LIDAR_RANGE_CORRECTED (one beam per group): records, FP64 tables, and
+    // per beam (cos, sin) of the beam's azimuth and elevation offsets from its
+    // pixel centre (radians)
+    const float4* rec4;         // [W4/4][H][4] {depth, nx, ny, nz}
+    const double2* col64;       // [W] pixel-centre azimuth cos, sin
+    const double2* row64;       // [H] pixel-centre elevation cos, sin
+    const double4* bcorr;       // [B] {cos daz, sin daz, cos del, sin del}
+    double to_bin;              // 2 / (c dt)
     lidar_beam_info* beams;     // [B] in: pixel, scale; out: floor
     lidar_echo* echoes;         // [B][E]
     int32_t* counts;            // [B]
@@ -134,6 +161,7 @@ struct FrameDev {
 struct PathDev {
     const float* taps;          // [2J+1]
     int J, R, E;
+    int select;                 // LIDAR_ECHO_*
     float threshold;
     float ambient;
     double half_c_dt;           // (c/2) dt in metres, FP64
@@ -170,6 +198,23 @@ hipError_t launch_footprint_batch(hipStream_t s, const BatchArgs& a, int grid, b
 hipError_t launch_footprint_batch_wave(hipStream_t s, const BatchArgs& a, int grid, bool sun,
                                        bool keep);
 hipError_t launch_reset_queue(hipStream_t s, int* counter, int n = 1);
+// LIDAR_RANGE_CORRECTED single frame: groups of one beam
+hipError_t launch_footprint_corr(hipStream_t s, const FootprintArgs& a);
+// per-beam offsets of the beams from their pixel centres (corrected range)
+hipError_t launch_beam_corr(hipStream_t s, RasterDev r, const double* az, const double* el, int B,
+                            const lidar_beam_info* beams, double4* bcorr);
+// sun floor from a kappa table: beams[b].floor = ambient + E_sun sum over the
+// kernel window of kappa * sun shading (kappa in the blocked layout of Kb)
+struct SunFloorArgs {
+    const float* sun;           // [W4/4][H][4]
+    int W, H;
+    const float* Kr;            // [4][NB][KH+1][4] kappa blocks
+    int M, N, KW, KH, NB;
+    float ambient, e_sun;
+    lidar_beam_info* beams;
+    int B;
+};
+hipError_t launch_sun_floor(hipStream_t s, const SunFloorArgs& a);
 // whether G histograms of R bins plus the pulse taps fit the LDS budget
 bool footprint_group_fits(int G, int R, int J);
 

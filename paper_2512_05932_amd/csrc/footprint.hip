@@ -201,12 +201,33 @@ __device__ inline float group_totals(const float* v)
     return dpp_add<0x140, 0xf>(x);
 }
 
+// Add t into the bins of a pixel key: the bin itself, or with range keys
+// (pixel range intervals) every bin first .. last of key = first | last << 16.
+__device__ inline void add_key(float* h, int key, float t, bool rng)
+{
+    if (!rng) {
+        atomicAdd(h + key, t);
+        return;
+    }
+    const int k1 = key >> 16;
+    for (int k = key & 0xffff; k <= k1; ++k) atomicAdd(h + k, t);
+}
+
+// Chunk flags (chunks of 1 << nzs bins) of the bins of a key.
+__device__ inline unsigned key_chunks(int key, int nzs, bool rng)
+{
+    if (!rng) return 1u << (key >> nzs);
+    const int c0 = (key & 0xffff) >> nzs, c1 = (key >> 16) >> nzs;
+    return (c1 - c0 >= 31 ? ~0u : (2u << (c1 - c0)) - 1u) << c0;
+}
+
 // Flush the lanes in `fm` (lanes whose run ended) into the histograms.
 // `stride` is the distance between the beams' histograms; bit c of the
 // lane's nzb is set for every chunk c (bins c << nzs ..) that receives a sum.
+// rng: the keys are bin ranges (first | last << 16).
 template <int G>
 __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const float* acc,
-                                  float* hist, int stride, unsigned& nzb, int nzs, int lane)
+                                  float* hist, int stride, unsigned& nzb, int nzs, int lane, bool rng)
 {
     unsigned long long m = fm;
     // lanes sharing a bin are reduced across the wave (a few bins per step)
@@ -222,15 +243,15 @@ __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const
         for (int g = 0; g < G; ++g) v[g] = in ? acc[g] : 0.0f;
         const float t = group_totals<G>(v);
         constexpr int span = 64 / G;
-        if (lane % span == 0 && t != 0.0f) atomicAdd(&hist[(lane / span) * stride + key], t);
-        nzb |= 1u << (key >> nzs);
+        if (lane % span == 0 && t != 0.0f) add_key(hist + (lane / span) * stride, key, t, rng);
+        nzb |= key_chunks(key, nzs, rng);
         m &= ~same;
     }
     if ((m >> lane) & 1ull) {
-        nzb |= 1u << (cur >> nzs);
+        nzb |= key_chunks(cur, nzs, rng);
 #pragma unroll
         for (int g = 0; g < G; ++g)
-            if (acc[g] != 0.0f) atomicAdd(&hist[g * stride + cur], acc[g]);
+            if (acc[g] != 0.0f) add_key(hist + g * stride, cur, acc[g], rng);
     }
 }
 
@@ -242,14 +263,41 @@ __device__ inline T ld16(const char* base, unsigned byte_off)
     return *(const T*)(base + byte_off);
 }
 
+// Time bin of one sample in LIDAR_RANGE_CORRECTED mode (FP64): the range on
+// the pixel's plane along the kernel cell's true direction v, d (p.n)/(v.n)
+// with the ratio limited to [1/2, 2] (2 where v misses the plane's facing
+// side).  p is the pixel centre direction (cos/sin of its azimuth cs and
+// elevation ce, se), v the same direction turned by the beam's offsets bc
+// {cos daz, sin daz, cos del, sin del} from its pixel centre; -1 past R.
+__device__ inline int corrected_bin(const float4& q, double2 cs, double ce, double se, const double4& bc,
+                                    double to_bin, int R)
+{
+    const double nx = q.y, ny = q.z, nz = q.w;
+    const double A = nx * cs.x + ny * cs.y;              // n along the azimuth direction
+    const double Bp = ny * cs.x - nx * cs.y;              // n along the azimuth tangent
+    const double pn = ce * A + se * nz;
+    const double h = bc.x * A + bc.y * Bp;
+    const double vn = bc.z * (ce * h + se * nz) + bc.w * (ce * nz - se * h);
+    double r = pn / vn;
+    if (!(r > 0.0)) r = 2.0;
+    r = (double)q.x * fmin(2.0, fmax(0.5, r));
+    const double k = floor(r * to_bin);
+    return k < (double)R ? (int)k : -1;
+}
+
 // Gather of the union footprint of G beams into their histograms (strips of
 // SH rows, 64/SH column phases) by nw waves, this one taking items it0,
-// it0 + nw, ...; adds this lane's per-beam sun sums to sacc.
-template <int G, int SH, bool SUN>
+// it0 + nw, ...; adds this lane's per-beam sun sums to sacc.  CORR (one
+// beam): every sample's bin is its corrected range's (bc: the beam's
+// offsets, R: bins); the pixel records still decide validity and shade.
+template <int G, int SH, bool SUN, bool CORR>
 __device__ __attribute__((always_inline)) inline void gather_group(
     const FrameDev& f, const int* ub, const int* vb, const bool* have, int r0, int r1, int q0, int q1,
-    float* hist, int stride, unsigned* nzmask, int nzs, int lane, int it0, int nw, float* sacc)
+    float* hist, int stride, unsigned* nzmask, int nzs, int lane, int it0, int nw, float* sacc,
+    const double4* bc = nullptr, int R = 0)
 {
+    static_assert(!CORR || G == 1, "corrected ranges differ per beam: one beam per group");
+    const bool rng = f.span != 0;
     constexpr int P = 64 / SH;                      // column phases per strip
     const int row_in = lane % SH, phase = lane / SH;
     const int nrows = r1 - r0 + 1;
@@ -298,6 +346,13 @@ __device__ __attribute__((always_inline)) inline void gather_group(
         const char* pbase = (const char*)(f.pix + (size_t)blk0 * f.H * 4);
         const char* sbase = SUN ? (const char*)(f.sun + (size_t)blk0 * f.H * 4) : nullptr;
         const unsigned pvo = (unsigned)vv * 32u, svo = (unsigned)vv * 16u;
+        const char* rbase = CORR ? (const char*)(f.rec4 + (size_t)blk0 * f.H * 4) : nullptr;
+        double cel = 0.0, sel = 0.0;                     // CORR: the row's elevation cos, sin
+        if (CORR) {
+            const double2 rc = f.row64[vv];
+            cel = rc.x;
+            sel = rc.y;
+        }
         // per beam: kernel copy (shift) and block of the first batch
         const char* kcopy[G];
         int kblk[G];
@@ -320,6 +375,8 @@ __device__ __attribute__((always_inline)) inline void gather_group(
             int4 ra, rb;
             float4 sq;
             float4 kq[G];
+            float4 r4[CORR ? 4 : 1];
+            int col;                                    // first column of the block read
         };
         auto fetch = [&](int i, Loads& L) {
             // this lane's block; with column phases the last round may run
@@ -330,6 +387,13 @@ __device__ __attribute__((always_inline)) inline void gather_group(
             const char* pq = pb + (size_t)i * P * pstep - back * pstep;
             L.ra = ld16<int4>(pq, pvo);
             L.rb = ld16<int4>(pq, pvo + 16u);
+            if (CORR) {
+                const size_t rstep = (size_t)f.H * 64u;
+                const char* rq = rbase + ((size_t)(act ? bi : nblk - 1)) * rstep;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) L.r4[j] = ld16<float4>(rq, (unsigned)vv * 64u + 16u * j);
+                L.col = 4 * (blk0 + (act ? bi : nblk - 1));
+            }
             L.sq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             if (SUN) L.sq = ld16<float4>(sb + (size_t)i * P * sstep - back * sstep, svo);
 #pragma unroll
@@ -350,9 +414,21 @@ __device__ __attribute__((always_inline)) inline void gather_group(
                 kv[2][g] = L.kq[g].z;
                 kv[3][g] = L.kq[g].w;
             }
-            const int bin[4] = {ra.x, ra.z, rb.x, rb.z};
-            const float sh[4] = {__int_as_float(ra.y), __int_as_float(ra.w),
-                                 __int_as_float(rb.y), __int_as_float(rb.w)};
+            int bin[4] = {ra.x, ra.z, rb.x, rb.z};
+            float sh[4] = {__int_as_float(ra.y), __int_as_float(ra.w),
+                           __int_as_float(rb.y), __int_as_float(rb.w)};
+            if (CORR) {
+                // valid pixels (centre bin >= 0) take their corrected bin;
+                // a sample past the last bin adds nothing
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (bin[j] >= 0) {
+                        const double2 cs = f.col64[min(L.col + j, f.W - 1)];
+                        bin[j] = corrected_bin(L.r4[j], cs, cel, sel, bc[0], f.to_bin, R);
+                        if (bin[j] < 0) sh[j] = 0.0f;
+                    }
+                }
+            }
             // fast path: accumulate without resets and detect breaks
             const int cur0 = cur;
             float acc0[G];
@@ -385,7 +461,7 @@ __device__ __attribute__((always_inline)) inline void gather_group(
                     for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, r[g]);
                     const bool fl = nr && any != 0u;            // sums are >= 0
                     const unsigned long long fm = __ballot(fl);
-                    if (fm) flush_runs<G>(fm, fl, c, r, hist, stride, nzb, nzs, lane);
+                    if (fm) flush_runs<G>(fm, fl, c, r, hist, stride, nzb, nzs, lane, rng);
 #pragma unroll
                     for (int g = 0; g < G; ++g) r[g] = (nr ? 0.0f : r[g]) + kv[j][g] * sh[j];
                     c = bin[j];
@@ -409,7 +485,7 @@ __device__ __attribute__((always_inline)) inline void gather_group(
         for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, acc[g]);
         const bool fl = any != 0u;
         const unsigned long long fm = __ballot(fl);
-        if (fm) flush_runs<G>(fm, fl, cur, acc, hist, stride, nzb, nzs, lane);
+        if (fm) flush_runs<G>(fm, fl, cur, acc, hist, stride, nzb, nzs, lane, rng);
     }
     // the wave's chunk flags, one LDS atomic per wave
     nzb = wave_or(nzb);
@@ -510,15 +586,19 @@ __device__ inline unsigned write_out8(float* h, float* kept, int k0, int R, floa
 // the threshold found with 64-bin ballots over the chunks flagged in am (bit
 // c of word w: chunk 32 w + c of 64 bins holds a bin above T; a run cannot
 // cross another chunk), their first maximum, crossings and pulse width
-// (section II-C, EPW paragraph); writes the first E echoes, the count of all
-// runs and the floor.
+// (section II-C, EPW paragraph); writes the first E echoes (or, with an echo
+// selection, the one selected run in slot 0), the count of all runs and the
+// floor.
 __device__ inline void detect_echoes(const FrameDev& f, const PathDev& p, int beam, const float* xh,
                                      const unsigned* am, float floor_b, int lane)
 {
     const int R = p.R;
     const float T = p.threshold;
     const float dt = (float)p.bin_ns;
+    const bool all = p.select == LIDAR_ECHO_ALL;
     lidar_echo* out = f.echoes + (size_t)beam * p.E;
+    lidar_echo sel = {};                                 // selected run (lane 0)
+    float sel_key = -INFINITY;
     int count = 0;
     int k0 = -1;                                         // first bin of the open run
     const int nw = (R + kPassBins - 1) / kPassBins;      // mask words of 32 chunks
@@ -547,7 +627,7 @@ __device__ inline void detect_echoes(const FrameDev& f, const PathDev& p, int be
             }
             ends &= ends - 1;
             const int k1 = base + pe;
-            if (count < p.E) {
+            if (!all || count < p.E) {
                 // first maximum of the run
                 float lbest = -INFINITY;                 // this lane's first maximum
                 int lbk = INT_MAX;
@@ -593,7 +673,18 @@ __device__ inline void detect_echoes(const FrameDev& f, const PathDev& p, int be
                     e.bin_first = k0;
                     e.bin_last = k1;
                     e.flags = flags;
-                    out[count] = e;
+                    if (all) {
+                        out[count] = e;
+                    } else {
+                        // strongest: largest peak; longest: widest pulse;
+                        // nearest: the first run (the first wins every tie)
+                        const float key = p.select == LIDAR_ECHO_STRONGEST ? best
+                                        : p.select == LIDAR_ECHO_LONGEST ? e.pulse_width_ns : 0.0f;
+                        if (count == 0 || key > sel_key) {
+                            sel = e;
+                            sel_key = key;
+                        }
+                    }
                 }
             }
             ++count;
@@ -601,11 +692,76 @@ __device__ inline void detect_echoes(const FrameDev& f, const PathDev& p, int be
         }
     }
     if (lane == 0) {
+        if (!all && count > 0) out[0] = sel;
         f.counts[beam] = count;
         f.beams[beam].floor = floor_b;
     }
     const lidar_echo z = {};
-    for (int i = count + lane; i < p.E; i += 64) out[i] = z;
+    const int written = all ? count : min(count, 1);
+    for (int i = written + lane; i < p.E; i += 64) out[i] = z;
+}
+
+// Echo selection on the raw signal (no pulse post-processing): the bin of
+// S_b xi[k] with the largest value (RAW_STRONGEST; the first of equal
+// maxima) or the first bin (RAW_NEAREST) at or above T, reported as a
+// one-bin echo; one wave per beam over the chunks the gather wrote (nzm,
+// chunks of 1 << nzs bins).  Also writes the count (1 or 0), the floor and,
+// with KEEP, the raw signal as the kept waveform.
+template <bool KEEP>
+__device__ inline void detect_raw(const FrameDev& f, const PathDev& p, int beam, const float* h,
+                                  unsigned nzm, int nzs, float scale, float floor_b, int lane)
+{
+    const int R = p.R;
+    const float T = p.threshold;
+    const bool nearest = p.select == LIDAR_ECHO_RAW_NEAREST;
+    float lbest = -INFINITY;
+    int lk = INT_MAX;
+    int found = -1;
+    for (unsigned bits = nzm; bits && found < 0;) {
+        const int c = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        const int end = min(R, (c + 1) << nzs);
+        for (int base = c << nzs; base < end; base += 64) {
+            const int k = base + lane;
+            const float v = k < R ? scale * h[k] : -INFINITY;
+            const bool above = v >= T;
+            if (nearest) {
+                const unsigned long long m = __ballot(above);
+                if (m) {
+                    found = base + __builtin_ctzll(m);
+                    break;
+                }
+            } else if (above && v > lbest) {
+                lbest = v;
+                lk = k;
+            }
+        }
+    }
+    if (!nearest) {
+        const float best = wave_maxf(lbest);
+        if (best >= T) found = wave_min(lbest == best ? lk : INT_MAX);
+    }
+    lidar_echo* out = f.echoes + (size_t)beam * p.E;
+    if (lane == 0) {
+        if (found >= 0) {
+            lidar_echo e;
+            e.range_m = ((double)found + 0.5) * p.half_c_dt;
+            e.time_ns = ((double)found + 0.5) * p.bin_ns;
+            e.intensity = scale * h[found];
+            e.pulse_width_ns = 0.0f;
+            e.bin_peak = e.bin_first = e.bin_last = found;
+            e.flags = 0;
+            out[0] = e;
+        }
+        f.counts[beam] = found >= 0 ? 1 : 0;
+        f.beams[beam].floor = floor_b;
+    }
+    const lidar_echo z = {};
+    for (int i = (found >= 0 ? 1 : 0) + lane; i < p.E; i += 64) out[i] = z;
+    if (KEEP) {
+        float* w = f.waves + (size_t)beam * R;
+        for (int k = lane; k < R; k += 64) w[k] = scale * h[k];
+    }
 }
 
 // LDS written by some lanes of this wave is read by others after this point.
@@ -621,7 +777,7 @@ __device__ inline void wave_sync()
 // each); bit c of *nzmask flags the chunks of 1 << nzs bins (chunk_shift) that
 // the gather wrote, amask the 64-bin chunks of
 // each waveform that hold a bin above the threshold.
-template <int G, bool SUN, bool KEEP>
+template <int G, bool SUN, bool KEEP, bool CORR = false>
 __device__ __attribute__((always_inline)) inline void process_group(const FrameDev& f, const PathDev& p, const int32_t* grp,
                               float* hist, const float* taps, float (*red)[kWaves],
                               unsigned* nzmask, unsigned (*amask)[kMaxBins / kPassBins + 1])
@@ -634,7 +790,7 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
 
     // group members (uniform over the workgroup: kept in scalar registers)
     int beam[G], ub[G], vb[G];
-    float scale[G];
+    float scale[G], given[G];
     bool have[G];
     int umin = INT_MAX, umax = INT_MIN, vmin = INT_MAX, vmax = INT_MIN;
 #pragma unroll
@@ -642,7 +798,7 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
         beam[g] = load_uniform(grp + g);
         have[g] = beam[g] >= 0;
         ub[g] = vb[g] = 0;
-        scale[g] = 0.0f;
+        scale[g] = given[g] = 0.0f;
         if (have[g]) {
             // pixel and scale are not written by this kernel (only the floor is)
             const lidar_beam_info bi = load_uniform(f.beams + beam[g]);
@@ -650,6 +806,7 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
             vb[g] = __builtin_amdgcn_readfirstlane(bi.pixel_v);
             scale[g] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
                 __builtin_bit_cast(int, bi.scale)));
+            given[g] = bi.floor;                        // the floor when f.floor_given
             umin = min(umin, ub[g]);
             umax = max(umax, ub[g]);
             vmin = min(vmin, vb[g]);
@@ -663,16 +820,18 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
     float sacc[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) sacc[g] = 0.0f;
+    double4 bc[1] = {make_double4(1.0, 0.0, 1.0, 0.0)};
+    if (CORR && have[0]) bc[0] = load_uniform(f.bcorr + beam[0]);
     if (r0 <= r1 && q0 <= q1) {
         if (f.tile == 64)
-            gather_group<G, 64, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane, wave,
-                                     kWaves, sacc);
+            gather_group<G, 64, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane,
+                                           wave, kWaves, sacc, bc, R);
         else if (f.tile == 16)
-            gather_group<G, 16, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane, wave,
-                                     kWaves, sacc);
+            gather_group<G, 16, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane,
+                                           wave, kWaves, sacc, bc, R);
         else
-            gather_group<G, 4, SUN>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane, wave,
-                                    kWaves, sacc);
+            gather_group<G, 4, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane,
+                                          wave, kWaves, sacc, bc, R);
     }
     if (SUN) {
 #pragma unroll
@@ -695,7 +854,15 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
             for (int w = 0; w < kWaves; ++w) t += red[g][w];
             fl += f.sun_scale * t;
         }
-        floor_b[g] = fl;
+        floor_b[g] = f.floor_given ? given[g] : fl;
+    }
+    if (p.select >= LIDAR_ECHO_RAW_STRONGEST) {
+        // single echo on the raw signal: no pulse convolution
+        const unsigned nzr = __builtin_amdgcn_readfirstlane(*nzmask);
+#pragma unroll 1
+        for (int g = wave; g < G; g += kWaves)
+            if (have[g]) detect_raw<KEEP>(f, p, beam[g], hist + g * RS, nzr, nzs, scale[g], floor_b[g], lane);
+        return;
     }
     constexpr int kPass = kPassBins;                    // 8 bins per thread and pass
     constexpr int kMaxPass = (kMaxBins + kPass - 1) / kPass;
@@ -771,16 +938,21 @@ __device__ __attribute__((always_inline)) inline void process_beam_wave(
     float sacc = 0.0f;
     if (r0 <= r1 && q0 <= q1) {
         if (f.tile == 64)
-            gather_group<1, 64, SUN>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
+            gather_group<1, 64, SUN, false>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
         else if (f.tile == 16)
-            gather_group<1, 16, SUN>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
+            gather_group<1, 16, SUN, false>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
         else
-            gather_group<1, 4, SUN>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
+            gather_group<1, 4, SUN, false>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
     }
     float floor_b = p.ambient;
     if (SUN) floor_b += f.sun_scale * wave_total(sacc);
+    if (f.floor_given) floor_b = bi.floor;
     wave_sync();                                         // the histogram is complete
     const unsigned nzm = __builtin_amdgcn_readfirstlane(*nzw);
+    if (p.select >= LIDAR_ECHO_RAW_STRONGEST) {
+        detect_raw<KEEP>(f, p, beam, hist, nzm, nzs, scale, floor_b, lane);
+        return;
+    }
     const int nb = conv_taps(p.J) / 8;
     float o[NP][8];
 #pragma unroll
@@ -844,6 +1016,70 @@ void k_footprint(FootprintArgs a)
     __syncthreads();
     process_group<G, SUN, KEEP>(a.f, a.p, a.groups + (size_t)gi * G, hist, taps, red, &nzmask,
                                 amask);
+}
+
+// LIDAR_RANGE_CORRECTED: the single-frame kernel with groups of one beam and
+// per-sample corrected bins.
+template <bool SUN, bool KEEP>
+__global__ __launch_bounds__(kFootprintThreads)
+void k_footprint_corr(FootprintArgs a)
+{
+    extern __shared__ float4 lds4[];
+    const int RS = conv_stride(a.p.R, a.p.J);
+    float* hist = (float*)lds4 + conv_pad(a.p.J);
+    float* taps = (float*)lds4 + RS;
+    __shared__ float red[1][kWaves];
+    __shared__ unsigned nzmask;
+    __shared__ unsigned amask[1][kMaxBins / kPassBins + 1];
+    const int slot = blockIdx.x;
+    const int gi = (slot % kXcds) * a.chunk + slot / kXcds;
+    if (gi >= a.n_groups) return;
+    const int tid = threadIdx.x;
+    clear_group(lds4, RS / 4, &nzmask, tid);
+    load_taps(taps, a.p.taps, a.p.J, tid);
+    __syncthreads();
+    process_group<1, SUN, KEEP, true>(a.f, a.p, a.groups + gi, hist, taps, red, &nzmask, amask);
+}
+
+// Sun floor of every beam from a collector-sensitivity table: A_b = ambient
+// + E_sun * sum over the kernel window (inside the image) of kappa(m, n) times
+// the pixel's sun shading Omega (rho/pi) max(0, n.s) (zero for invalid
+// pixels).  One workgroup per beam; lanes own rows, so the 16-byte loads of
+// the 4-column blocks of sun shading and kappa coalesce as in the gather.
+__global__ __launch_bounds__(256)
+void k_sun_floor(SunFloorArgs a)
+{
+    __shared__ float part[256 / 64];
+    const int b = blockIdx.x;
+    if (b >= a.B) return;
+    const lidar_beam_info bi = a.beams[b];
+    const int u = bi.pixel_u, v = bi.pixel_v;
+    const int r0 = (int)max(0L, (long)v - a.N), r1 = (int)min((long)a.H - 1, (long)v + a.N);
+    const int q0 = (int)max(0L, (long)u - a.M), q1 = (int)min((long)a.W - 1, (long)u + a.M);
+    float acc = 0.0f;
+    if (r0 <= r1 && q0 <= q1) {
+        const int nrows = r1 - r0 + 1, blk0 = q0 >> 2, nblk = (q1 >> 2) - blk0 + 1;
+        const size_t khp16 = (size_t)(a.KH + 1) * 4;      // floats per kernel block
+        for (int t = threadIdx.x; t < nrows * nblk; t += blockDim.x) {
+            const int row = r0 + t % nrows, blk = blk0 + t / nrows;
+            const float4 sv = *(const float4*)(a.sun + ((size_t)blk * a.H + row) * 4);
+            const int c0 = 4 * blk - u + a.M;              // kernel column of the block's first column
+            const int sft = c0 & 3;
+            const int kb = min(max(((c0 - sft) >> 2) + kBlockPad, 0), a.NB - 1);
+            const float4 kq = *(const float4*)(a.Kr + ((size_t)sft * a.NB + kb) * khp16 +
+                                               (size_t)(row - v + a.N) * 4);
+            acc += kq.x * sv.x + kq.y * sv.y + kq.z * sv.z + kq.w * sv.w;
+        }
+    }
+    const float w = wave_total(acc);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) part[wv] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int i = 0; i < (int)(blockDim.x / 64); ++i) t += part[i];
+        a.beams[b].floor = a.ambient + a.e_sun * t;
+    }
 }
 
 // Next ticket from the dispenser of a batch: kXcds counters kQueueStride ints
@@ -972,7 +1208,7 @@ static hipError_t launch_g(hipStream_t s, const FootprintArgs& a)
 {
     const int grid = kXcds * a.chunk;
     const size_t lds = group_lds_bytes(G, a.p.R, a.p.J);
-    const bool sun = a.f.sun != nullptr;
+    const bool sun = a.f.sun != nullptr && !a.f.floor_given;   // a supplied floor needs no sun sum
     const bool keep = a.f.waves != nullptr;
     if (sun && keep)
         hipLaunchKernelGGL((k_footprint<G, true, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
@@ -1050,6 +1286,30 @@ hipError_t launch_footprint_batch_wave(hipStream_t s, const BatchArgs& a, int gr
         else
             hipLaunchKernelGGL((k_footprint_batch_wave<kWavePasses, false, false>), dim3(grid), b, lds, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_footprint_corr(hipStream_t s, const FootprintArgs& a)
+{
+    if (a.G != 1) return hipErrorInvalidValue;
+    const int grid = kXcds * a.chunk;
+    const size_t lds = group_lds_bytes(1, a.p.R, a.p.J);
+    const bool sun = a.f.sun != nullptr && !a.f.floor_given, keep = a.f.waves != nullptr;
+    if (sun && keep)
+        hipLaunchKernelGGL((k_footprint_corr<true, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    else if (sun)
+        hipLaunchKernelGGL((k_footprint_corr<true, false>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    else if (keep)
+        hipLaunchKernelGGL((k_footprint_corr<false, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_footprint_corr<false, false>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sun_floor(hipStream_t s, const SunFloorArgs& a)
+{
+    if (a.B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sun_floor, dim3(a.B), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ struct PatternHost {
     double sigma[2] = {0, 0}, trunc = 0, half[2] = {0, 0};
     uint32_t nx = 0, ny = 0;
     std::vector<float> table;
+    std::vector<float> rx;             // optional kappa table (sun term), same grid as table
     std::vector<double> az, el;
 };
 
@@ -64,6 +65,13 @@ struct FrameState {
     DevBuf<float4> d_rowtab;
     DevBuf<int2> d_pix;
     DevBuf<float> d_sun;
+    // kappa table of the sun term: device copy, resampled grid, blocks
+    DevBuf<float> d_rx, d_Kr;
+    DevBuf<double> d_K64rx;
+    // range modes: FP64 direction tables, beam offsets, depth/normal records
+    DevBuf<double2> d_col64, d_row64, d_cole, d_rowe;
+    DevBuf<double4> d_bcorr;
+    DevBuf<float4> d_rec4;
     std::vector<int32_t> groups;       // [n_groups][G], -1 = empty slot
     std::vector<uint64_t> group_cost;  // samples of the group's beams
     int n_groups = 0;
@@ -304,6 +312,8 @@ lidar_status check_pattern(lidar_sim* h, const lidar_pattern_desc* pd, const std
         if (!is_fin(pd->beam_az_deg[i]) || !is_fin(pd->beam_el_deg[i]))
             return fail(h, LIDAR_E_INVALID, w + "non-finite beam angle");
     if (pd->kind == LIDAR_PATTERN_GAUSS) {
+        if (pd->rx_table)
+            return fail(h, LIDAR_E_INVALID, w + "rx_table needs a table pattern (its grid)");
         if (!(pd->sigma_deg[0] > 0) || !(pd->sigma_deg[1] > 0) || !is_fin(pd->sigma_deg[0]) ||
             !is_fin(pd->sigma_deg[1]) || !(pd->trunc_sigmas > 0) || !is_fin(pd->trunc_sigmas))
             return fail(h, LIDAR_E_INVALID, w + "Gaussian pattern needs sigma > 0 and trunc_sigmas > 0");
@@ -321,6 +331,12 @@ lidar_status check_pattern(lidar_sim* h, const lidar_pattern_desc* pd, const std
             any |= v > 0.0f;
         }
         if (!any) return fail(h, LIDAR_E_INVALID, w + "table is all zero (pattern integral is 0)");
+        if (pd->rx_table)
+            for (uint64_t i = 0; i < (uint64_t)pd->nx * pd->ny; ++i) {
+                const float v = pd->rx_table[i];
+                if (!std::isfinite(v) || v < 0.0f)
+                    return fail(h, LIDAR_E_INVALID, w + "rx_table values must be finite and >= 0");
+            }
     } else {
         return fail(h, LIDAR_E_INVALID, w + "unknown pattern kind");
     }
@@ -355,8 +371,24 @@ lidar_status check_params(const lidar_sim_params* p, std::string& why)
     if (!(p->bin_ns > 0.0) || !is_fin(p->bin_ns)) { why = "bin_ns must be > 0"; return LIDAR_E_INVALID; }
     if (!is_fin(p->threshold)) { why = "threshold must be finite"; return LIDAR_E_INVALID; }
     if (!(p->emit_power >= 0.0) || !is_fin(p->emit_power)) { why = "emit_power must be >= 0"; return LIDAR_E_INVALID; }
-    if (!(p->pulse_fwhm_ns > 0.0) || !is_fin(p->pulse_fwhm_ns)) { why = "pulse_fwhm_ns must be > 0"; return LIDAR_E_INVALID; }
-    if (!(p->pulse_trunc_sigmas > 0.0) || !is_fin(p->pulse_trunc_sigmas)) { why = "pulse_trunc_sigmas must be > 0"; return LIDAR_E_INVALID; }
+    if (p->pulse_taps) {
+        if (p->n_pulse_taps < 1 || p->n_pulse_taps > (uint32_t)kMaxTaps || p->n_pulse_taps % 2 == 0) {
+            why = "n_pulse_taps must be odd, 1..257";
+            return LIDAR_E_INVALID;
+        }
+        double sum = 0.0;
+        for (uint32_t i = 0; i < p->n_pulse_taps; ++i) {
+            const float t = p->pulse_taps[i];
+            if (!std::isfinite(t) || t < 0.0f) { why = "pulse_taps must be finite and >= 0"; return LIDAR_E_INVALID; }
+            sum += t;
+        }
+        if (!(sum > 0.0)) { why = "pulse_taps must have a positive sum"; return LIDAR_E_INVALID; }
+    } else {
+        if (!(p->pulse_fwhm_ns > 0.0) || !is_fin(p->pulse_fwhm_ns)) { why = "pulse_fwhm_ns must be > 0"; return LIDAR_E_INVALID; }
+        if (!(p->pulse_trunc_sigmas > 0.0) || !is_fin(p->pulse_trunc_sigmas)) { why = "pulse_trunc_sigmas must be > 0"; return LIDAR_E_INVALID; }
+    }
+    if (p->echo_select > (uint32_t)LIDAR_ECHO_RAW_NEAREST) { why = "unknown echo_select"; return LIDAR_E_INVALID; }
+    if (p->range_mode > (uint32_t)LIDAR_RANGE_INTERVAL) { why = "unknown range_mode"; return LIDAR_E_INVALID; }
     if (!is_fin(p->ambient_const) || !(p->sun_irradiance >= 0.0) || !is_fin(p->sun_irradiance)) {
         why = "ambient_const must be finite and sun_irradiance >= 0";
         return LIDAR_E_INVALID;
@@ -367,11 +399,30 @@ lidar_status check_params(const lidar_sim_params* p, std::string& why)
         why = "unknown flags";
         return LIDAR_E_INVALID;
     }
-    if (p->reserved != 0) { why = "reserved must be 0"; return LIDAR_E_INVALID; }
-    double sigma = p->pulse_fwhm_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
-    double J = std::ceil(p->pulse_trunc_sigmas * sigma / p->bin_ns);
-    if (!(2.0 * J + 1.0 <= kMaxTaps)) { why = "pulse longer than 257 taps"; return LIDAR_E_INVALID; }
+    if (!p->pulse_taps) {
+        double sigma = p->pulse_fwhm_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+        double J = std::ceil(p->pulse_trunc_sigmas * sigma / p->bin_ns);
+        if (!(2.0 * J + 1.0 <= kMaxTaps)) { why = "pulse longer than 257 taps"; return LIDAR_E_INVALID; }
+    }
     return LIDAR_OK;
+}
+
+// Half-width J of the pulse and, for a tabulated pulse, its taps at unit sum
+// (FP64 sum, rounded to FP32).
+int pulse_half_width(const lidar_sim_params* p)
+{
+    if (p->pulse_taps) return (int)(p->n_pulse_taps - 1) / 2;
+    double sigma = p->pulse_fwhm_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    return (int)std::ceil(p->pulse_trunc_sigmas * sigma / p->bin_ns);
+}
+
+std::vector<float> tabulated_taps(const lidar_sim_params* p)
+{
+    double sum = 0.0;
+    for (uint32_t i = 0; i < p->n_pulse_taps; ++i) sum += (double)p->pulse_taps[i];
+    std::vector<float> t(p->n_pulse_taps);
+    for (uint32_t i = 0; i < p->n_pulse_taps; ++i) t[i] = (float)((double)p->pulse_taps[i] / sum);
+    return t;
 }
 
 // ---- pattern copies and kernel set-up -----------------------------------
@@ -396,6 +447,10 @@ lidar_status copy_pattern(lidar_sim* h, FrameState& fs, const lidar_pattern_desc
         p.half[1] = pd->half_deg[1];
         p.table.assign(pd->table, pd->table + (size_t)pd->nx * pd->ny);
     }
+    if (pd->kind == LIDAR_PATTERN_TABLE && pd->rx_table)
+        p.rx.assign(pd->rx_table, pd->rx_table + (size_t)pd->nx * pd->ny);
+    else
+        p.rx.clear();
     hipStream_t s = h->stream;
     HIP_TRY(h, fs.d_az.ensure(B), "allocate beams");
     HIP_TRY(h, fs.d_el.ensure(B), "allocate beams");
@@ -405,6 +460,11 @@ lidar_status copy_pattern(lidar_sim* h, FrameState& fs, const lidar_pattern_desc
         HIP_TRY(h, fs.d_table.ensure(p.table.size()), "allocate table");
         HIP_TRY(h, hipMemcpyAsync(fs.d_table.p, p.table.data(), p.table.size() * sizeof(float),
                                   hipMemcpyHostToDevice, s), "copy table");
+    }
+    if (!p.rx.empty()) {
+        HIP_TRY(h, fs.d_rx.ensure(p.rx.size()), "allocate rx table");
+        HIP_TRY(h, hipMemcpyAsync(fs.d_rx.p, p.rx.data(), p.rx.size() * sizeof(float),
+                                  hipMemcpyHostToDevice, s), "copy rx table");
     }
     HIP_TRY(h, hipStreamSynchronize(s), "pattern copy synchronise");
     return LIDAR_OK;
@@ -563,6 +623,28 @@ lidar_status setup_frame(lidar_sim* h, FrameState& fs, lidar_beam_info* beams, c
     HIP_TRY(h, launch_beam_setup(s, r, k, fs.d_az.p, fs.d_el.p, (int)B, fs.d_rowsum.p,
                                  fs.d_prefix.p, fs.d_omega.p, h->prm.emit_power, beams),
             "beam setup launch");
+    if (!fs.pat.rx.empty()) {
+        // kappa on the same pixel-offset grid and in the same blocks as K
+        PatternDev prx = p;
+        prx.table = fs.d_rx.p;
+        HIP_TRY(h, fs.d_K64rx.ensure(cells), "allocate kappa grid");
+        HIP_TRY(h, fs.d_Kr.ensure((size_t)4 * kernel_blocks(k.KW) * (k.KH + 1) * 4), "allocate kappa blocks");
+        HIP_TRY(h, launch_kernel_grid(s, prx, r, k, fs.d_K64rx.p), "kappa grid launch");
+        HIP_TRY(h, launch_kernel_blocks(s, k, fs.d_K64rx.p, fs.d_Kr.p), "kappa blocks launch");
+    }
+    if (h->prm.range_mode != LIDAR_RANGE_CENTRE) {
+        HIP_TRY(h, fs.d_col64.ensure(g.width), "allocate range tables");
+        HIP_TRY(h, fs.d_row64.ensure(g.height), "allocate range tables");
+        HIP_TRY(h, fs.d_cole.ensure((size_t)g.width + 1), "allocate range tables");
+        HIP_TRY(h, fs.d_rowe.ensure((size_t)g.height + 1), "allocate range tables");
+        HIP_TRY(h, launch_range_tables(s, r, fs.d_col64.p, fs.d_row64.p, fs.d_cole.p, fs.d_rowe.p),
+                "range tables launch");
+    }
+    if (h->prm.range_mode == LIDAR_RANGE_CORRECTED) {
+        HIP_TRY(h, fs.d_bcorr.ensure(B), "allocate beam offsets");
+        HIP_TRY(h, launch_beam_corr(s, r, fs.d_az.p, fs.d_el.p, (int)B, beams, fs.d_bcorr.p),
+                "beam offsets launch");
+    }
     // the pattern's integral over the grid must be positive: checked once per
     // (pattern, raster), which synchronises the stream
     double kinfo[2];
@@ -592,6 +674,7 @@ lidar_status alloc_pixels(lidar_sim* h, FrameState& fs)
     const size_t npix = W4 * fs.gb.height;
     HIP_TRY(h, fs.d_pix.ensure(npix), "allocate pixel records");
     if (h->prm.sun_irradiance != 0.0) HIP_TRY(h, fs.d_sun.ensure(npix), "allocate sun shading");
+    if (h->prm.range_mode == LIDAR_RANGE_CORRECTED) HIP_TRY(h, fs.d_rec4.ensure(npix), "allocate depth records");
     return LIDAR_OK;
 }
 
@@ -619,7 +702,37 @@ PrepassArgs prepass_args(const lidar_sim* h, FrameState& fs)
     pa.sun_z = (float)h->prm.sun_dir[2];
     pa.pix = fs.d_pix.p;
     pa.sun = sun ? fs.d_sun.p : nullptr;
+    pa.range_mode = (int)h->prm.range_mode;
+    pa.rt.col = fs.d_col64.p;
+    pa.rt.row = fs.d_row64.p;
+    pa.rt.col_edge = fs.d_cole.p;
+    pa.rt.row_edge = fs.d_rowe.p;
+    pa.rec4 = h->prm.range_mode == LIDAR_RANGE_CORRECTED ? fs.d_rec4.p : nullptr;
     return pa;
+}
+
+// Sun floor from the frame's kappa table into beams[].floor (frames with
+// one; the footprint kernel then reads the floor instead of summing it).
+lidar_status enqueue_sun_floor(lidar_sim* h, FrameState& fs, lidar_beam_info* beams, hipStream_t s)
+{
+    const bool sun = h->prm.sun_irradiance != 0.0;
+    if (fs.pat.rx.empty() || !sun) return LIDAR_OK;
+    SunFloorArgs a;
+    a.sun = sun ? fs.d_sun.p : nullptr;
+    a.W = (int)fs.gb.width;
+    a.H = (int)fs.gb.height;
+    a.Kr = fs.d_Kr.p;
+    a.M = fs.k.M;
+    a.N = fs.k.N;
+    a.KW = fs.k.KW;
+    a.KH = fs.k.KH;
+    a.NB = kernel_blocks(fs.k.KW);
+    a.ambient = (float)h->prm.ambient_const;
+    a.e_sun = (float)h->prm.sun_irradiance;
+    a.beams = beams;
+    a.B = (int)fs.pat.az.size();
+    HIP_TRY(h, launch_sun_floor(s, a), "sun floor launch");
+    return LIDAR_OK;
 }
 
 lidar_status enqueue_prepass(lidar_sim* h, FrameState& fs, hipStream_t s)
@@ -634,8 +747,12 @@ lidar_status enqueue_prepass(lidar_sim* h, FrameState& fs, hipStream_t s)
 lidar_status enqueue_batch_prepass(lidar_sim* h, hipStream_t s)
 {
     HIP_TRY(h, launch_prepass_batch(s, h->b_prep.p, h->b_prep_off.p, (int)h->frames.size(),
-                                    h->b_prep_tiles, h->prm.sun_irradiance != 0.0),
+                                    h->b_prep_tiles, h->prm.sun_irradiance != 0.0,
+                                    (int)h->prm.range_mode),
             "batch pre-pass launch");
+    // floors of the frames with a kappa table
+    for (size_t i = 0; i < h->frames.size(); ++i)
+        LIDAR_TRY(enqueue_sun_floor(h, *h->frames[i], h->b_beams.p + h->beam_off[i], s));
     return LIDAR_OK;
 }
 
@@ -643,9 +760,19 @@ FrameDev frame_view(const lidar_sim* h, const FrameState& fs, lidar_beam_info* b
                     lidar_echo* echoes, int32_t* counts, float* waves)
 {
     const bool sun = h->prm.sun_irradiance != 0.0;
+    const bool given = !fs.pat.rx.empty() && sun;    // floor from the kappa kernel
     FrameDev f{};
     f.pix = fs.d_pix.p;
+    // the sun records stay addressable with a supplied floor: batch kernels
+    // run one SUN instantiation for all frames (the sum is then discarded)
     f.sun = sun ? fs.d_sun.p : nullptr;
+    f.span = h->prm.range_mode == LIDAR_RANGE_INTERVAL ? 1 : 0;
+    f.floor_given = given ? 1 : 0;
+    f.rec4 = fs.d_rec4.p;
+    f.col64 = fs.d_col64.p;
+    f.row64 = fs.d_row64.p;
+    f.bcorr = fs.d_bcorr.p;
+    f.to_bin = 2.0 / (kLight * (h->prm.bin_ns * 1e-9));
     f.W = (int)fs.gb.width;
     f.H = (int)fs.gb.height;
     f.Kb = fs.d_Kb.p;
@@ -671,6 +798,7 @@ PathDev path_view(const lidar_sim* h)
     p.J = h->J;
     p.R = (int)h->prm.n_bins;
     p.E = (int)h->prm.max_echoes;
+    p.select = (int)h->prm.echo_select;
     p.threshold = (float)h->prm.threshold;
     p.ambient = (float)h->prm.ambient_const;
     p.half_c_dt = 0.5 * kLight * (h->prm.bin_ns * 1e-9);
@@ -1219,6 +1347,8 @@ lidar_status simulate_static(const lidar_sim_params* prm, const lidar_pattern_de
     if (!echoes || !counts || !beams)
         return fail(h, LIDAR_E_INVALID, "simulate_static needs the device outputs echoes, "
                                         "n_echoes and beams");
+    if (prm->range_mode != LIDAR_RANGE_CENTRE || (pd->kind == LIDAR_PATTERN_TABLE && pd->rx_table))
+        return fail(h, LIDAR_E_UNSUPPORTED, "simulate_static runs centre ranges without an rx_table");
     // host copy of the pattern (as copy_pattern, without device buffers)
     FrameState fs;
     PatternHost& pat = fs.pat;
@@ -1254,7 +1384,8 @@ lidar_status simulate_static(const lidar_sim_params* prm, const lidar_pattern_de
     k.KH = 2 * k.N + 1;
     fs.k = k;
     const double sigma = prm->pulse_fwhm_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
-    const int J = (int)std::ceil(prm->pulse_trunc_sigmas * sigma / prm->bin_ns);
+    const int J = pulse_half_width(prm);
+    const std::vector<float> tab = prm->pulse_taps ? tabulated_taps(prm) : std::vector<float>();
     int G = 4;
     while (G > 1 && !footprint_group_fits(G, (int)prm->n_bins, J)) G /= 2;
     const bool sun = prm->sun_irradiance != 0.0;
@@ -1312,7 +1443,11 @@ lidar_status simulate_static(const lidar_sim_params* prm, const lidar_pattern_de
                                   hipMemcpyHostToDevice, s), "copy table");
     HIP_TRY(h, hipMemcpyAsync(groups, fs.groups.data(), fs.groups.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, s), "copy beam groups");
-    HIP_TRY(h, launch_pulse_taps(s, (float)sigma, (float)prm->bin_ns, J, taps), "pulse taps launch");
+    if (!tab.empty())
+        HIP_TRY(h, hipMemcpyAsync(taps, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, s),
+                "copy pulse taps");
+    else
+        HIP_TRY(h, launch_pulse_taps(s, (float)sigma, (float)prm->bin_ns, J, taps), "pulse taps launch");
     PatternDev pdev;
     pdev.kind = (int)pat.kind;
     pdev.sx = pat.sigma[0];
@@ -1357,6 +1492,9 @@ lidar_status simulate_static(const lidar_sim_params* prm, const lidar_pattern_de
     pa.sun_z = (float)prm->sun_dir[2];
     pa.pix = pix;
     pa.sun = sunb;
+    pa.range_mode = LIDAR_RANGE_CENTRE;
+    pa.rt = RangeTables{};
+    pa.rec4 = nullptr;
     HIP_TRY(h, launch_prepass(s, pa, sun), "pre-pass launch");
     FootprintArgs fa;
     FrameDev& f = fa.f;
@@ -1383,6 +1521,7 @@ lidar_status simulate_static(const lidar_sim_params* prm, const lidar_pattern_de
     pp.J = J;
     pp.R = (int)prm->n_bins;
     pp.E = (int)prm->max_echoes;
+    pp.select = (int)prm->echo_select;
     pp.threshold = (float)prm->threshold;
     pp.ambient = (float)prm->ambient_const;
     pp.half_c_dt = 0.5 * kLight * (prm->bin_ns * 1e-9);
@@ -1426,13 +1565,23 @@ lidar_status lidar_sim_create(const lidar_sim_params* params, void* hip_stream, 
             hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
             h->cus = n;
     }
+    // the handle keeps no pointer into the caller's table
+    h->prm.pulse_taps = nullptr;
     double sigma = params->pulse_fwhm_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
-    h->J = (int)std::ceil(params->pulse_trunc_sigmas * sigma / params->bin_ns);
-    h->G = 4;
+    h->J = pulse_half_width(params);
+    h->G = params->range_mode == LIDAR_RANGE_CORRECTED ? 1 : 4;
     while (h->G > 1 && !footprint_group_fits(h->G, (int)params->n_bins, h->J)) h->G /= 2;
     hipError_t e = h->d_taps.ensure(2 * h->J + 1);
-    if (e == hipSuccess)
-        e = launch_pulse_taps(h->stream, (float)sigma, (float)params->bin_ns, h->J, h->d_taps.p);
+    if (e == hipSuccess) {
+        if (params->pulse_taps) {
+            const std::vector<float> t = tabulated_taps(params);
+            e = hipMemcpyAsync(h->d_taps.p, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice,
+                               h->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        } else {
+            e = launch_pulse_taps(h->stream, (float)sigma, (float)params->bin_ns, h->J, h->d_taps.p);
+        }
+    }
     if (e != hipSuccess) {
         g_create_error = std::string("pulse taps: ") + hipGetErrorString(e);
         lidar_sim_destroy(h);
@@ -1538,11 +1687,15 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
         HIP_TRY(h, hipEventRecord(pp.a, s), "record event");
     }
     LIDAR_TRY(enqueue_prepass(h, fs, s));
+    LIDAR_TRY(enqueue_sun_floor(h, fs, h->d_beams.p, s));
     if (prof) {
         HIP_TRY(h, hipEventRecord(pp.b, s), "record event");
         HIP_TRY(h, hipEventRecord(fp.a, s), "record event");
     }
-    HIP_TRY(h, launch_footprint(s, fa), "footprint launch");
+    if (h->prm.range_mode == LIDAR_RANGE_CORRECTED)
+        HIP_TRY(h, launch_footprint_corr(s, fa), "footprint launch");
+    else
+        HIP_TRY(h, launch_footprint(s, fa), "footprint launch");
     if (prof) {
         HIP_TRY(h, hipEventRecord(fp.b, s), "record event");
         h->pending_pp.push_back(pp);
@@ -1556,9 +1709,21 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
 
 // The network on every beam, the gate, and the plain path on the groups of
 // the beams that fall back - all enqueued, no host round trip.
+// The surrogate's inputs and decoding assume the default path: every run
+// reported, centre ranges, kappa = K / max K.
+static lidar_status surrogate_supported(lidar_sim* h, const char* who)
+{
+    if (h->prm.echo_select != LIDAR_ECHO_ALL || h->prm.range_mode != LIDAR_RANGE_CENTRE ||
+        !h->single.pat.rx.empty())
+        return fail(h, LIDAR_E_UNSUPPORTED, std::string(who) + " needs echo_select ALL, range_mode "
+                                            "CENTRE and no rx_table");
+    return LIDAR_OK;
+}
+
 static lidar_status simulate_surrogate(lidar_sim* h)
 {
     if (!h->net.ready) return fail(h, LIDAR_E_STATE, "surrogate mode without surrogate weights");
+    LIDAR_TRY(surrogate_supported(h, "surrogate mode"));
     FrameState& fs = h->single;
     const int B = (int)fs.pat.az.size();
     const uint32_t R = h->prm.n_bins, E = h->prm.max_echoes;
@@ -1684,6 +1849,8 @@ lidar_status lidar_sim_simulate_batch(lidar_sim* h, const lidar_gbuffer_desc* fr
     if (!frames || !patterns || n_frames == 0)
         return fail(h, LIDAR_E_INVALID, "simulate_batch needs n_frames >= 1 and both arrays");
     if (n_frames > 65536) return fail(h, LIDAR_E_INVALID, "too many frames (max 65536)");
+    if (h->prm.range_mode == LIDAR_RANGE_CORRECTED)
+        return fail(h, LIDAR_E_UNSUPPORTED, "range_mode CORRECTED runs in simulate_frame only");
     bool same = h->batch_ok && h->batch_gb.size() == n_frames;
     for (uint32_t i = 0; same && i < n_frames; ++i)
         same = same_gbuffer(h->batch_gb[i], frames[i]) && same_pattern(h->batch_pd[i], patterns[i]);
@@ -1892,6 +2059,7 @@ lidar_status lidar_sim_surrogate_features(lidar_sim* h, void* x, float* labels, 
     if (labels && !(h->have_result && h->plain_result))
         return fail(h, LIDAR_E_STATE, "labels need a plain simulate_frame on these inputs");
     if (labels && h->prm.max_echoes < 3) return fail(h, LIDAR_E_INVALID, "labels need max_echoes >= 3");
+    LIDAR_TRY(surrogate_supported(h, "surrogate_features"));
     FrameState& fs = h->single;
     const int B = (int)fs.pat.az.size();
     LIDAR_TRY(sur_geometry(h, fs));

@@ -22,12 +22,43 @@ constexpr int kRowsPerPass = kThreads / kTileW;
 static_assert(kTileW % 4 == 0 && kTileH % kRowsPerPass == 0, "whole 4-column blocks and passes");
 }
 
-// One kTileW x kTileH tile of a frame, columns u0.., rows v0...
-template <bool SUN>
+// Range interval of pixel (u, v) of depth d and normal n (FP64): the plane
+// through the pixel's centre point with normal n met by its four corner rays
+// w, range d (p.n)/(w.n) with the ratio limited to [1/2, 2] (2 where w misses
+// the plane's facing side), together with d itself; returns the first and
+// last time bin of [min, max] (Alg. 1, pixelRangeInterval).
+__device__ inline void pixel_interval(const PrepassArgs& a, int u, int v, double d, double nx,
+                                      double ny, double nz, double* k0, double* k1)
+{
+#pragma clang fp contract(off)
+    const double2 cc = a.rt.col[u], rc = a.rt.row[v];
+    const double pn = (rc.x * cc.x) * nx + (rc.x * cc.y) * ny + rc.y * nz;
+    double lo = d, hi = d;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double2 ce = a.rt.col_edge[u + (c & 1)], re = a.rt.row_edge[v + (c >> 1)];
+        const double wn = (re.x * ce.x) * nx + (re.x * ce.y) * ny + re.y * nz;
+        double q = pn / wn;
+        if (!(q > 0.0)) q = 2.0;
+        q = fmin(2.0, fmax(0.5, q));
+        const double r = d * q;
+        lo = fmin(lo, r);
+        hi = fmax(hi, r);
+    }
+    *k0 = floor(lo * a.to_bin);
+    *k1 = floor(hi * a.to_bin);
+}
+
+// One kTileW x kTileH tile of a frame, columns u0.., rows v0...  MODE is the
+// range mode: CENTRE and CORRECTED store the centre bin (CORRECTED also the
+// depth and normal of every pixel), INTERVAL the pixel's first and last bin
+// packed as first | last << 16 with the shade divided by the interval's bins.
+template <bool SUN, int MODE>
 __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0)
 {
     __shared__ int2 trec[kTileH][kTileW + 1];
     __shared__ float tsun[kTileH][kTileW + 1];
+    __shared__ float4 tr4[MODE == LIDAR_RANGE_CORRECTED ? kTileH : 1][kTileW + 1];
     const int tx = threadIdx.x % kTileW, ty = threadIdx.x / kTileW;
     const float inv_pi = (float)(1.0 / kPi);
     // read rows (coalesced along u), shade, stage in LDS
@@ -37,30 +68,41 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0)
         int u = u0 + tx, v = v0 + vl;
         int bin = -1;
         float shade = 0.0f, sunv = 0.0f;
+        float4 r4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (u < a.W && v < a.H) {
             long px = (long)v * a.pitch + u;
             float d = a.depth[px];
             if (d > 0.0f && isfinite(d)) {
-                double kb = floor((double)d * a.to_bin);
+                float nx = a.nx[px], ny = a.ny[px], nz = a.nz[px];
+                double kb = floor((double)d * a.to_bin), k1 = kb;
+                if (MODE == LIDAR_RANGE_INTERVAL)
+                    pixel_interval(a, u, v, (double)d, (double)nx, (double)ny, (double)nz, &kb, &k1);
                 if (kb < (double)a.R) {
                     bin = (int)kb;
                     float2 cs = a.colcs[u];
                     float4 rt = a.rowtab[v];
                     float vx = rt.x * cs.x, vy = rt.x * cs.y, vz = rt.y;
-                    float nx = a.nx[px], ny = a.ny[px], nz = a.nz[px];
                     float ct = fmaxf(0.0f, -(nx * vx + ny * vy + nz * vz));
                     float rho = a.refl[px];
                     float g = a.gain[px];
                     shade = rt.z * (g * rho * inv_pi) * ct / (d * d);
+                    if (MODE == LIDAR_RANGE_INTERVAL) {
+                        // the interval's bins share the pixel's weight; bins
+                        // past the last are dropped
+                        shade = shade / (float)(k1 - kb + 1.0);
+                        bin |= (int)fmin(k1, (double)(a.R - 1)) << 16;
+                    }
                     if (SUN) {
                         float ns = fmaxf(0.0f, nx * a.sun_x + ny * a.sun_y + nz * a.sun_z);
                         sunv = rt.z * (rho * inv_pi) * ns;
                     }
+                    if (MODE == LIDAR_RANGE_CORRECTED) r4 = make_float4(d, nx, ny, nz);
                 }
             }
         }
         trec[vl][tx] = make_int2(bin, __float_as_int(shade));
         if (SUN) tsun[vl][tx] = sunv;
+        if (MODE == LIDAR_RANGE_CORRECTED) tr4[vl][tx] = r4;
     }
     __syncthreads();
     // write kTileW / 4 blocks of 4 columns x kTileH rows, each contiguous in memory
@@ -75,20 +117,21 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0)
             // columns past W (padding) were staged as sky above
             a.pix[o] = trec[r][bi * 4 + j];
             if (SUN) a.sun[o] = tsun[r][bi * 4 + j];
+            if (MODE == LIDAR_RANGE_CORRECTED) a.rec4[o] = tr4[r][bi * 4 + j];
         }
     }
 }
 
-template <bool SUN>
+template <bool SUN, int MODE>
 __global__ __launch_bounds__(kThreads)
 void k_prepass(PrepassArgs a)
 {
-    prepass_tile<SUN>(a, blockIdx.x * kTileW, blockIdx.y * kTileH);
+    prepass_tile<SUN, MODE>(a, blockIdx.x * kTileW, blockIdx.y * kTileH);
 }
 
 // All frames of a batch in one launch: block t is tile t of the frames' tiles
 // laid end to end (tile_off[f] = first tile of frame f, tile_off[n] = total).
-template <bool SUN>
+template <bool SUN, int MODE>
 __global__ __launch_bounds__(kThreads)
 void k_prepass_batch(const PrepassArgs* frames, const int* tile_off, int n)
 {
@@ -102,7 +145,7 @@ void k_prepass_batch(const PrepassArgs* frames, const int* tile_off, int n)
     const PrepassArgs a = frames[lo];
     const int lt = t - tile_off[lo];
     const int tiles_x = (a.W4 + kTileW - 1) / kTileW;
-    prepass_tile<SUN>(a, (lt % tiles_x) * kTileW, (lt / tiles_x) * kTileH);
+    prepass_tile<SUN, MODE>(a, (lt % tiles_x) * kTileW, (lt / tiles_x) * kTileH);
 }
 
 int prepass_tiles(const PrepassArgs& a)
@@ -111,14 +154,21 @@ int prepass_tiles(const PrepassArgs& a)
 }
 
 hipError_t launch_prepass_batch(hipStream_t s, const PrepassArgs* frames, const int* tile_off,
-                                int n, int total_tiles, bool with_sun)
+                                int n, int total_tiles, bool with_sun, int range_mode)
 {
     if (total_tiles <= 0) return hipSuccess;
-    dim3 block(kThreads);
-    if (with_sun)
-        hipLaunchKernelGGL(k_prepass_batch<true>, dim3(total_tiles), block, 0, s, frames, tile_off, n);
+    dim3 block(kThreads), grid(total_tiles);
+    constexpr int C = LIDAR_RANGE_CENTRE, I = LIDAR_RANGE_INTERVAL;
+    if (range_mode == C && with_sun)
+        hipLaunchKernelGGL((k_prepass_batch<true, C>), grid, block, 0, s, frames, tile_off, n);
+    else if (range_mode == C)
+        hipLaunchKernelGGL((k_prepass_batch<false, C>), grid, block, 0, s, frames, tile_off, n);
+    else if (range_mode == I && with_sun)
+        hipLaunchKernelGGL((k_prepass_batch<true, I>), grid, block, 0, s, frames, tile_off, n);
+    else if (range_mode == I)
+        hipLaunchKernelGGL((k_prepass_batch<false, I>), grid, block, 0, s, frames, tile_off, n);
     else
-        hipLaunchKernelGGL(k_prepass_batch<false>, dim3(total_tiles), block, 0, s, frames, tile_off, n);
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -126,10 +176,16 @@ hipError_t launch_prepass(hipStream_t s, const PrepassArgs& a, bool with_sun)
 {
     dim3 grid((a.W4 + kTileW - 1) / kTileW, (a.H + kTileH - 1) / kTileH);
     dim3 block(kThreads);
-    if (with_sun)
-        hipLaunchKernelGGL(k_prepass<true>, grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL(k_prepass<false>, grid, block, 0, s, a);
+    constexpr int C = LIDAR_RANGE_CENTRE, K = LIDAR_RANGE_CORRECTED, I = LIDAR_RANGE_INTERVAL;
+    switch (a.range_mode * 2 + (with_sun ? 1 : 0)) {
+    case 2 * C: hipLaunchKernelGGL((k_prepass<false, C>), grid, block, 0, s, a); break;
+    case 2 * C + 1: hipLaunchKernelGGL((k_prepass<true, C>), grid, block, 0, s, a); break;
+    case 2 * K: hipLaunchKernelGGL((k_prepass<false, K>), grid, block, 0, s, a); break;
+    case 2 * K + 1: hipLaunchKernelGGL((k_prepass<true, K>), grid, block, 0, s, a); break;
+    case 2 * I: hipLaunchKernelGGL((k_prepass<false, I>), grid, block, 0, s, a); break;
+    case 2 * I + 1: hipLaunchKernelGGL((k_prepass<true, I>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -170,6 +170,46 @@ __global__ void k_row_omega(RasterDev r, long v0, int n, double* omega)
     if (i < n) omega[i] = row_omega(r, v0 + i);
 }
 
+// FP64 cos and sin of the pixel-centre and edge angles of a raster (range
+// modes): col[u] of az_min + (u + 1/2) dphi, row[v] of el_max - (v + 1/2) de,
+// col_edge[u] of az_min + u dphi, row_edge[v] of el_max - v de.
+__global__ void k_range_tables(RasterDev r, double2* col, double2* row, double2* col_edge,
+                               double2* row_edge)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const double d2r = kPi / 180.0;
+    if (i < r.W) {
+        const double a = (r.az_min + ((double)i + 0.5) * r.dphi) * d2r;
+        col[i] = make_double2(cos(a), sin(a));
+    }
+    if (i <= r.W) {
+        const double a = (r.az_min + (double)i * r.dphi) * d2r;
+        col_edge[i] = make_double2(cos(a), sin(a));
+    }
+    if (i < r.H) {
+        const double e = (r.el_max - ((double)i + 0.5) * r.de) * d2r;
+        row[i] = make_double2(cos(e), sin(e));
+    }
+    if (i <= r.H) {
+        const double e = (r.el_max - (double)i * r.de) * d2r;
+        row_edge[i] = make_double2(cos(e), sin(e));
+    }
+}
+
+// Per beam: cos and sin of its azimuth and elevation offsets from the centre
+// of its pixel (radians).  A kernel cell's true direction is then the
+// direction of its pixel's centre turned by these offsets.
+__global__ void k_beam_corr(RasterDev r, const double* az, const double* el, int B,
+                            const lidar_beam_info* beams, double4* bcorr)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const double d2r = kPi / 180.0;
+    const double da = (az[b] - (r.az_min + ((double)beams[b].pixel_u + 0.5) * r.dphi)) * d2r;
+    const double de = (el[b] - (r.el_max - ((double)beams[b].pixel_v + 0.5) * r.de)) * d2r;
+    bcorr[b] = make_double4(cos(da), sin(da), cos(de), sin(de));
+}
+
 // Per beam: containing pixel (floor rounding), FP64 normalisation over every
 // kernel cell (on- and off-image rows), scale S_b = P_e / N_b, and the number
 // of non-zero kernel cells inside the image.  Row solid angles come from the
@@ -284,6 +324,23 @@ hipError_t launch_beam_setup(hipStream_t s, RasterDev r, KernelDev k, const doub
     hipLaunchKernelGGL(k_row_omega, dim3((n + 255) / 256), dim3(256), 0, s, r, v0, n, omega);
     hipLaunchKernelGGL(k_beam_setup, dim3((B + 127) / 128), dim3(128), 0, s, r, k, az, el, B,
                        rowsum, prefix, (const double*)omega, v0, n, emit_power, beams);
+    return hipGetLastError();
+}
+
+hipError_t launch_range_tables(hipStream_t s, RasterDev r, double2* col, double2* row,
+                               double2* col_edge, double2* row_edge)
+{
+    const int n = (r.W > r.H ? r.W : r.H) + 1;
+    hipLaunchKernelGGL(k_range_tables, dim3((n + 255) / 256), dim3(256), 0, s, r, col, row,
+                       col_edge, row_edge);
+    return hipGetLastError();
+}
+
+hipError_t launch_beam_corr(hipStream_t s, RasterDev r, const double* az, const double* el, int B,
+                            const lidar_beam_info* beams, double4* bcorr)
+{
+    hipLaunchKernelGGL(k_beam_corr, dim3((B + 127) / 128), dim3(128), 0, s, r, az, el, B, beams,
+                       bcorr);
     return hipGetLastError();
 }
 

@@ -115,3 +115,78 @@ def compare(gpu, ref, params, beam_idx=None, check_waveforms=True) -> Report:
         for i in range(min(int(g_cnt[b]), E), E):
             assert g_ech[b, i]["bin_last"] == 0 and g_ech[b, i]["range_m"] == 0.0
     return Report(B, int(ambiguous.sum()), max_err, count_mismatch, compared, off1)
+
+
+def _beam_checks(g_beams, ref, peak):
+    np.testing.assert_array_equal(g_beams["pixel_u"], ref.pixel[:, 0])
+    np.testing.assert_array_equal(g_beams["pixel_v"], ref.pixel[:, 1])
+    np.testing.assert_array_equal(g_beams["samples"], ref.samples)
+    np.testing.assert_allclose(g_beams["scale"], ref.scale, rtol=1e-6)
+    floor_err = np.abs(g_beams["floor"].astype(np.float64) - ref.floor)
+    assert np.all(floor_err <= WAVE_TOL * np.maximum(peak, ref.floor) + 1e-30)
+
+
+def compare_selection(gpu, ref, params) -> Report:
+    """Parity of one selected echo per beam (echo_select != ALL).
+
+    Runs of xi_hat (STRONGEST, NEAREST, LONGEST): on non-ambiguous beams the
+    counts of all runs agree, and slot 0 is the oracle's selected run (same
+    bins, FP64 range, intensity and EPW within the rules of ``compare``)
+    unless the oracle's selection is a near-tie: two runs whose peaks differ
+    by at most 2 WAVE_TOL max (STRONGEST) or whose pulse widths differ by at
+    most the EPW interpolation bound (LONGEST); then the GPU's run must be
+    one of the tied runs.  Raw modes: the waveform is the raw S_b xi, a beam
+    is ambiguous when some bin lies within WAVE_TOL max of T, and the chosen
+    bin is the oracle's or (RAW_STRONGEST) a bin within 2 WAVE_TOL max of the
+    maximum."""
+    import oracle as O
+    mode, T, dt, R = params.echo_select, params.threshold, params.bin_ns, params.n_bins
+    raw = mode >= 4
+    sig = ref.xi if raw else ref.xi_hat
+    peak = np.abs(sig).max(axis=1) + 1e-300
+    _beam_checks(gpu["beams"], ref, ref.xi_hat.max(axis=1))
+    max_err = 0.0
+    if gpu.get("waveforms") is not None:
+        err = np.abs(gpu["waveforms"].astype(np.float64) - sig).max(axis=1) / peak
+        max_err = float(err.max())
+        assert max_err <= WAVE_TOL, f"waveform error {max_err:.3e}"
+    amb = (np.abs(sig - T) <= WAVE_TOL * peak[:, None]).any(axis=1)
+    g_cnt, g_ech = gpu["n_echoes"], gpu["echoes"]
+    mism = int(((g_cnt != ref.n_echoes) & ~amb).sum())
+    assert mism == 0, f"{mism} non-ambiguous beams with another count"
+    compared = ties = 0
+    for b in np.nonzero(~amb & (ref.n_echoes > 0))[0]:
+        ge, re = g_ech[b, 0], ref.echoes[b, 0]
+        compared += 1
+        assert np.all(g_ech[b, 1:]["bin_last"] == 0)
+        if raw:
+            k = int(ge["bin_peak"])
+            assert ge["bin_first"] == ge["bin_last"] == k and ge["pulse_width_ns"] == 0.0
+            if k != re["bin_peak"]:
+                ties += 1
+                assert mode == 4 and abs(sig[b, k] - sig[b, re["bin_peak"]]) <= 2 * WAVE_TOL * peak[b]
+            assert abs(ge["intensity"] - sig[b, k]) <= WAVE_TOL * peak[b]
+            continue
+        if ge["bin_first"] != re["bin_first"]:
+            # a near-tie of the selection: the GPU's run must be tied with the
+            # oracle's choice
+            ties += 1
+            n_all, runs = O.detect(ref.xi_hat[b], T, ref.floor[b], dt, R)
+            match = [e for e in runs if e["bin_first"] == ge["bin_first"]]
+            assert match, (b, ge, re)
+            other = match[0]
+            if mode == 1:
+                assert abs(other["intensity"] - re["intensity"]) <= 2 * WAVE_TOL * peak[b], (b, ge, re)
+            elif mode == 3:
+                assert abs(other["pulse_width_ns"] - re["pulse_width_ns"]) <= 1e-3 * dt, (b, ge, re)
+            else:
+                raise AssertionError((b, ge, re))
+            re = other
+        assert ge["bin_first"] == re["bin_first"] and ge["bin_last"] == re["bin_last"]
+        assert abs(int(ge["bin_peak"]) - int(re["bin_peak"])) <= 1
+        if ge["bin_peak"] == re["bin_peak"]:
+            assert ge["range_m"] == re["range_m"]
+        xh = ref.xi_hat[b]
+        assert abs(ge["intensity"] - (xh[ge["bin_peak"]] - ref.floor[b])) <= WAVE_TOL * peak[b] * 1.01
+        assert abs(ge["pulse_width_ns"] - re["pulse_width_ns"]) <= 1e-3 * dt + 1e-5
+    return Report(len(g_cnt), int(amb.sum()), max_err, mism, compared, ties)
