@@ -9,7 +9,9 @@ only thing both consume is the seeded input arrays from ``scenes``.
 
 ``simulate`` wraps ``lidar_oracle.c`` (plain C, FP64, OpenMP over beams).
 ``range_stacking`` (module ``oracle.range_stacking``) is the paper's second
-algorithm (Alg. 2), used as an independent cross-check of the first.
+algorithm (Alg. 2), used as an independent cross-check of the first and as
+the reference of the GPU's range stacking.  ``oracle.pinhole`` reprojects a
+pinhole rendering with a z buffer onto the equiangular raster.
 """
 from __future__ import annotations
 

@@ -600,3 +600,114 @@ def surrogate_frame(seed: int, pattern: str = "gauss", n_lines: int = 64,
                   sigma_deg=(0.0425, 0.34), trunc_sigmas=3.0)
     return replace(w, pattern=pat, params=batch_params(),
                    name=f"surrogate-scan-{n_lines}x{n_cols}-gauss")
+
+
+# ----------------------------------------------------------------------------
+# Pinhole renderings (the renderer's side of a z buffer)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Pinhole:
+    """A pinhole rendering: intrinsics (image x = fx X/Z + cx, y = fy Y/Z + cy,
+    camera frame x right, y down, z forward; pixel (i, j) covers [i, i+1) x
+    [j, j+1)), camera-to-sensor rotation, depth in one of the formats of
+    ``oracle.pinhole`` (DEPTH_*), and reflectance, retro gain and normals
+    (camera frame) as [h][w] planes."""
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    rot: np.ndarray
+    fmt: int
+    near: float
+    far: float
+    depth: np.ndarray          # float32 (RANGE, EYE_Z, WINDOW_F32), uint16 or uint32
+    reflectance: np.ndarray
+    retro_gain: np.ndarray
+    normal: np.ndarray         # [3][h][w] float32, camera frame
+
+    def as_dict(self):
+        return dict(width=self.width, height=self.height, fx=self.fx, fy=self.fy, cx=self.cx,
+                    cy=self.cy, rot=self.rot, fmt=self.fmt, near=self.near, far=self.far,
+                    depth=self.depth, reflectance=self.reflectance, retro_gain=self.retro_gain,
+                    normal=self.normal)
+
+
+def yaw_pitch_rotation(yaw_deg: float = 0.0, pitch_deg: float = 0.0) -> np.ndarray:
+    """Camera-to-sensor rotation of a camera turned by yaw (to the left, about
+    z) and pitch (upwards) from looking along the sensor's x axis."""
+    fwd = np.array([[0.0, 0.0, 1.0], [-1.0, 0.0, 0.0], [0.0, -1.0, 0.0]])
+    a, b = math.radians(yaw_deg), math.radians(pitch_deg)
+    rz = np.array([[math.cos(a), -math.sin(a), 0.0], [math.sin(a), math.cos(a), 0.0], [0.0, 0.0, 1.0]])
+    ry = np.array([[math.cos(b), 0.0, -math.sin(b)], [0.0, 1.0, 0.0], [math.sin(b), 0.0, math.cos(b)]])
+    return rz @ ry @ fwd
+
+
+def encode_window_depth(z, near: float, far: float):
+    """Window depth of eye-space distances z (> 0) under an OpenGL
+    perspective projection: clip-space z / w mapped from [-1, 1] to [0, 1];
+    non-finite z (no hit) is the cleared far value 1."""
+    z = np.asarray(z, dtype=np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        # projection matrix row 3 applied to (.., .., -z, 1), divided by w = z
+        clip_z = (-(far + near) / (far - near)) * (-z) + (-2.0 * far * near / (far - near))
+        ndc = clip_z / z
+    w = np.clip(0.5 * ndc + 0.5, 0.0, 1.0)          # depth buffers clamp to [0, 1]
+    return np.where(np.isfinite(z) & (z > 0), w, 1.0)
+
+
+def pinhole_render(seed: int = 0, width: int = 640, height: int = 360, hfov_deg: float = 60.0,
+                   yaw_deg: float = 0.0, pitch_deg: float = 0.0, fmt: int = 0,
+                   near: float = 0.5, far: float = 500.0, n_boxes: int = 10,
+                   retro_frac: float = 0.02) -> Pinhole:
+    """Road plane (SENSOR_HEIGHT below the sensor) and boxes ray cast in FP64
+    through a pinhole camera; per object reflectance U(0.05, 0.9); a random
+    fraction of pixels retroreflective (gain 100); depth stored in format
+    ``fmt`` (0 radial range, 1 eye-space z, 2/3/4 window depth as float32 /
+    uint16 / 24 bits in uint32 between the near and far planes)."""
+    rng = np.random.default_rng(seed)
+    f = 0.5 * width / math.tan(math.radians(0.5 * hfov_deg))
+    cx, cy = 0.5 * width, 0.5 * height
+    R = yaw_pitch_rotation(yaw_deg, pitch_deg)
+    jj, ii = np.meshgrid(np.arange(height), np.arange(width), indexing="ij")
+    ray_c = np.stack([(ii + 0.5 - cx) / f, (jj + 0.5 - cy) / f, np.ones((height, width))])
+    norm = np.sqrt((ray_c ** 2).sum(0))
+    dirs = np.einsum("ij,jhw->ihw", R, ray_c / norm)                    # unit, sensor frame
+    z0 = -SENSOR_HEIGHT
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = np.where(dirs[2] < 0.0, z0 / dirs[2], np.inf)
+    normal = np.zeros((3, height, width))
+    normal[2] = 1.0
+    rho = np.full((height, width), rng.uniform(0.05, 0.9))
+    flat = dirs.reshape(3, -1)
+    for _ in range(n_boxes):
+        b = Box(center=np.array([rng.uniform(6.0, 80.0), rng.uniform(-12.0, 12.0)]),
+                yaw=rng.uniform(-0.4, 0.4), length=rng.uniform(3.0, 10.0),
+                width=rng.uniform(1.8, 2.6), height=rng.uniform(1.2, 3.0), rho=rng.uniform(0.05, 0.9))
+        tb, nb, _, _, _ = _ray_box(flat, b, z0)
+        tb = tb.reshape(height, width)
+        closer = tb < t
+        t = np.where(closer, tb, t)
+        normal[:, closer] = nb.reshape(3, height, width)[:, closer]
+        rho = np.where(closer, b.rho, rho)
+    hit = np.isfinite(t)
+    rho = np.where(hit, rho, 0.0)
+    gain = np.where(hit & (rng.uniform(size=t.shape) < retro_frac), 100.0, 1.0)
+    n_cam = np.einsum("ji,jhw->ihw", R, normal)                         # R^T n
+    z_eye = t / norm
+    if fmt == 0:
+        depth = t.astype(np.float32)
+    elif fmt == 1:
+        depth = z_eye.astype(np.float32)
+    else:
+        w = encode_window_depth(np.where(hit, z_eye, np.inf), near, far)
+        if fmt == 2:
+            depth = w.astype(np.float32)
+        elif fmt == 3:
+            depth = np.clip(np.rint(w * 65535.0), 0, 65535).astype(np.uint16)
+        else:
+            depth = np.clip(np.rint(w * 16777215.0), 0, 16777215).astype(np.uint32)
+    return Pinhole(width, height, f, f, cx, cy, R, fmt, near, far, depth,
+                   rho.astype(np.float32), gain.astype(np.float32), n_cam.astype(np.float32))
