@@ -400,6 +400,61 @@ lidar_status lidar_sim_surrogate_set_gate(lidar_sim* h, double c_min, double alp
  * labels - plain frame), LIDAR_E_INVALID, LIDAR_E_HIP, LIDAR_E_NOMEM. */
 lidar_status lidar_sim_surrogate_features(lidar_sim* h, void* x, float* labels, float* aux);
 
+/* ---- Pinhole renderings (section II-C: reprojection; section II-D: z buffer)
+ * A rasterising renderer gives a pinhole image; the beams need an
+ * equiangular raster.  Depth formats of lidar_pinhole_desc.depth: */
+enum { LIDAR_DEPTH_RANGE = 0,        /* float radial range along the pixel's centre ray */
+       LIDAR_DEPTH_EYE_Z = 1,        /* float eye-space z (along the optical axis) */
+       LIDAR_DEPTH_WINDOW_F32 = 2,   /* float window depth w in [0, 1): z = n f / (f - w (f - n)) */
+       LIDAR_DEPTH_WINDOW_U16 = 3,   /* uint16 window depth, w = q / 65535 */
+       LIDAR_DEPTH_WINDOW_U24 = 4 }; /* uint32 holding a 24-bit window depth, w = q / (2^24 - 1) */
+
+typedef struct {
+    uint32_t width, height;    /* pinhole image, >= 1 */
+    uint64_t pitch;            /* elements between rows of every plane, >= width */
+    double fx, fy, cx, cy;     /* intrinsics: image x = fx X/Z + cx, y = fy Y/Z + cy in the
+                                  camera frame (x right, y down, z forward); pixel (i, j)
+                                  covers [i, i+1) x [j, j+1); fx, fy > 0 */
+    double rot[9];             /* camera-to-sensor rotation, row-major (v_sensor = rot v_camera),
+                                  orthonormal */
+    uint32_t depth_format;     /* LIDAR_DEPTH_* */
+    uint32_t normal_correct;   /* 1: each output range is corrected from the pinhole pixel's
+                                  centre ray to the output direction with the normal,
+                                  r (p.n)/(v.n), ratio limited to [1/2, 2] (section II-D) */
+    double z_near, z_far;      /* clip planes of the window formats, 0 < near < far */
+    const void* depth;         /* device [height][pitch], float / uint16 / uint32 by format;
+                                  non-finite or <= 0 (range, z), w >= 1 or < 0: sky */
+    const float* reflectance;  /* device [height][pitch] planes (borrowed until the */
+    const float* retro_gain;   /*   reprojection has run on the stream) */
+    const float* normal_x;     /* unit normals in the camera frame */
+    const float* normal_y;
+    const float* normal_z;
+} lidar_pinhole_desc;
+
+/* Reproject a pinhole rendering onto an equiangular raster (width x height
+ * over [az_min, az_max] x [el_min, el_max], degrees) in library-owned device
+ * planes and make them the handle's G-buffer, as lidar_sim_set_gbuffer does.
+ * Every output pixel takes the pinhole pixel containing the projection of its
+ * centre direction as it is (no depth interpolation, which would put ranges
+ * between targets; section II-D); its depth is decoded to the radial range
+ * along that pixel's centre ray (optionally corrected to the output
+ * direction), reflectance and gain are copied, the normal is turned into the
+ * sensor frame; pixels that see no pinhole pixel are sky.  Index and range
+ * decisions in FP64.  Enqueued on the stream (asynchronous).
+ * Errors: LIDAR_E_INVALID (null planes, sizes, non-positive focal lengths,
+ * non-orthonormal rotation, unknown format, clip planes, raster as in
+ * set_gbuffer), LIDAR_E_NOMEM, LIDAR_E_HIP. */
+lidar_status lidar_sim_set_gbuffer_pinhole(lidar_sim* h, const lidar_pinhole_desc* src,
+                                           uint32_t width, uint32_t height, double az_min_deg,
+                                           double az_max_deg, double el_min_deg, double el_max_deg);
+
+/* Copy the library-owned G-buffer of the last set_gbuffer_pinhole out:
+ * planes [6][height][width] float32 (depth, reflectance, retro gain, normal
+ * x, y, z), host (synchronises) or device (dst_is_device != 0, enqueued).
+ * Errors: LIDAR_E_INVALID (null), LIDAR_E_STATE (the current G-buffer is the
+ * caller's), LIDAR_E_HIP. */
+lidar_status lidar_sim_read_gbuffer(lidar_sim* h, float* planes, int dst_is_device);
+
 /* Counters since create or the last reset (synchronises profiling events).
  * Errors: LIDAR_E_INVALID (null), LIDAR_E_HIP. */
 lidar_status lidar_sim_get_stats(lidar_sim* h, lidar_stats* out);

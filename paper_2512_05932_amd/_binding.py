@@ -41,7 +41,8 @@ EXPORTED = ["lidar_sim_create", "lidar_sim_destroy", "lidar_sim_set_pattern",
             "lidar_sim_surrogate_get_weights", "lidar_sim_surrogate_forward",
             "lidar_sim_surrogate_gradients", "lidar_sim_surrogate_train_step",
             "lidar_sim_surrogate_set_gate", "lidar_sim_surrogate_features", "lidar_sim_get_stats",
-            "lidar_sim_reset_stats", "lidar_sim_simulate_static", "lidar_sim_last_error"]
+            "lidar_sim_reset_stats", "lidar_sim_simulate_static", "lidar_sim_set_gbuffer_pinhole",
+            "lidar_sim_read_gbuffer", "lidar_sim_last_error"]
 
 SUR_IN, SUR_OUT, SUR_PARAMS = 1056, 16, 406288
 
@@ -70,6 +71,15 @@ class lidar_gbuffer_desc(C.Structure):
                 ("el_min_deg", C.c_double), ("el_max_deg", C.c_double),
                 ("depth", C.c_void_p), ("reflectance", C.c_void_p), ("retro_gain", C.c_void_p),
                 ("normal_x", C.c_void_p), ("normal_y", C.c_void_p), ("normal_z", C.c_void_p)]
+
+
+class lidar_pinhole_desc(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("pitch", C.c_uint64),
+                ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("rot", C.c_double * 9), ("depth_format", C.c_uint32), ("normal_correct", C.c_uint32),
+                ("z_near", C.c_double), ("z_far", C.c_double), ("depth", C.c_void_p),
+                ("reflectance", C.c_void_p), ("retro_gain", C.c_void_p), ("normal_x", C.c_void_p),
+                ("normal_y", C.c_void_p), ("normal_z", C.c_void_p)]
 
 
 class lidar_stats(C.Structure):
@@ -142,6 +152,9 @@ def load():
     lib.lidar_sim_reset_stats.argtypes = [V]
     lib.lidar_sim_simulate_static.argtypes = [P(lidar_sim_params), P(lidar_pattern_desc),
                                               P(lidar_gbuffer_desc), V, V, V, V]
+    lib.lidar_sim_set_gbuffer_pinhole.argtypes = [V, P(lidar_pinhole_desc), C.c_uint32, C.c_uint32,
+                                                  C.c_double, C.c_double, C.c_double, C.c_double]
+    lib.lidar_sim_read_gbuffer.argtypes = [V, V, C.c_int]
     lib.lidar_sim_last_error.argtypes = [V]
     lib.lidar_sim_last_error.restype = C.c_char_p
     for name in EXPORTED[:-1]:
@@ -303,6 +316,29 @@ class LidarSim:
         d = gbuffer_desc(raster, planes, pitch)
         self._check(self._lib.lidar_sim_set_gbuffer(self._h, C.byref(d)))
         self._keep = list(planes)
+
+    def set_gbuffer_pinhole(self, src, dev_planes, raster, correct: bool = False, pitch=None):
+        """src: an object with the pinhole fields (width, height, fx, fy, cx,
+        cy, rot, fmt, near, far); dev_planes: (depth, reflectance, retro_gain,
+        normal_x, normal_y, normal_z) device tensors [h][pitch]."""
+        rot = (C.c_double * 9)(*[float(x) for x in np.asarray(src.rot, dtype=np.float64).ravel()])
+        ptrs = [int(t.data_ptr()) for t in dev_planes]
+        d = lidar_pinhole_desc(int(src.width), int(src.height),
+                               int(pitch if pitch is not None else src.width), float(src.fx),
+                               float(src.fy), float(src.cx), float(src.cy), rot, int(src.fmt),
+                               1 if correct else 0, float(src.near), float(src.far), *ptrs)
+        self._check(self._lib.lidar_sim_set_gbuffer_pinhole(
+            self._h, C.byref(d), int(raster.width), int(raster.height), float(raster.az_min),
+            float(raster.az_max), float(raster.el_min), float(raster.el_max)))
+        self._keep = list(dev_planes)
+        self._gb_shape = (int(raster.height), int(raster.width))
+
+    def read_gbuffer(self) -> np.ndarray:
+        """The reprojected planes [6][H][W] (synchronises)."""
+        H, W = self._gb_shape
+        out = np.zeros((6, H, W), dtype=np.float32)
+        self._check(self._lib.lidar_sim_read_gbuffer(self._h, out.ctypes.data, 0))
+        return out
 
     def simulate_frame(self, mode: int = LIDAR_MODE_PLAIN):
         self._check(self._lib.lidar_sim_simulate_frame(self._h, int(mode)))

@@ -218,6 +218,23 @@ hipError_t launch_sun_floor(hipStream_t s, const SunFloorArgs& a);
 // whether G histograms of R bins plus the pulse taps fit the LDS budget
 bool footprint_group_fits(int G, int R, int J);
 
+// ---- reprojection of a pinhole rendering ---------------------------------
+struct ReprojectArgs {
+    int W, H;                   // output raster
+    double az_min, el_max, dphi, de;
+    int SW, SH;                 // pinhole image
+    long spitch;                // elements between pinhole rows
+    double fx, fy, cx, cy;
+    double rot[9];              // camera -> sensor, row-major
+    int fmt;                    // LIDAR_DEPTH_*
+    int correct;                // normal-based range correction to the output direction
+    double z_near, z_far;
+    const void* depth;
+    const float *refl, *gain, *nx, *ny, *nz;
+    float* out;                 // [6][H][W]: depth, reflectance, gain, normal x, y, z
+};
+hipError_t launch_reproject(hipStream_t s, const ReprojectArgs& a);
+
 // ---- host utility: a growable device buffer -----------------------------
 template <typename T>
 struct DevBuf {

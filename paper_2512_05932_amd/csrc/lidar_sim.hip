@@ -151,6 +151,10 @@ struct lidar_sim {
     float gate_alpha = 0.5f;
     bool plain_result = false;
 
+    // reprojected G-buffer (set_gbuffer_pinhole): [6][H][W]
+    DevBuf<float> rp_planes;
+    bool gb_owned = false;
+
     // stats
     lidar_stats st{};
     std::vector<EventPair> pending_fp, pending_pp, pending_bt, pending_sur, pool;
@@ -1626,6 +1630,103 @@ lidar_status lidar_sim_set_gbuffer(lidar_sim* h, const lidar_gbuffer_desc* g)
     if (h->setup_ok && !same_raster(h->single.gb, *g)) h->setup_ok = false;
     h->single.gb = *g;
     h->have_gbuffer = true;
+    h->gb_owned = false;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_set_gbuffer_pinhole(lidar_sim* h, const lidar_pinhole_desc* src,
+                                           uint32_t width, uint32_t height, double az_min_deg,
+                                           double az_max_deg, double el_min_deg, double el_max_deg)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!src) return fail(h, LIDAR_E_INVALID, "pinhole descriptor is NULL");
+    if (src->width == 0 || src->height == 0 || src->pitch < src->width ||
+        src->width > (1u << 20) || src->height > (1u << 20) || src->pitch > (1ull << 30))
+        return fail(h, LIDAR_E_INVALID, "pinhole image needs width, height >= 1 and pitch >= width");
+    if (!src->depth || !src->reflectance || !src->retro_gain || !src->normal_x || !src->normal_y ||
+        !src->normal_z)
+        return fail(h, LIDAR_E_INVALID, "pinhole plane pointer is NULL");
+    if (!(src->fx > 0) || !(src->fy > 0) || !is_fin(src->fx) || !is_fin(src->fy) || !is_fin(src->cx) ||
+        !is_fin(src->cy))
+        return fail(h, LIDAR_E_INVALID, "pinhole intrinsics need finite fx, fy > 0, cx, cy");
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double dot = 0.0;
+            for (int k = 0; k < 3; ++k) dot += src->rot[3 * k + r] * src->rot[3 * k + c];
+            if (!(std::fabs(dot - (r == c ? 1.0 : 0.0)) < 1e-6))
+                return fail(h, LIDAR_E_INVALID, "pinhole rotation must be orthonormal");
+        }
+    if (src->depth_format > (uint32_t)LIDAR_DEPTH_WINDOW_U24 || src->normal_correct > 1)
+        return fail(h, LIDAR_E_INVALID, "unknown pinhole depth format or correction flag");
+    if (src->depth_format >= (uint32_t)LIDAR_DEPTH_WINDOW_F32 &&
+        !(src->z_near > 0 && src->z_far > src->z_near && is_fin(src->z_far)))
+        return fail(h, LIDAR_E_INVALID, "window depth needs clip planes 0 < near < far");
+    lidar_gbuffer_desc g{};
+    g.width = width;
+    g.height = height;
+    g.pitch = width;
+    g.az_min_deg = az_min_deg;
+    g.az_max_deg = az_max_deg;
+    g.el_min_deg = el_min_deg;
+    g.el_max_deg = el_max_deg;
+    // placeholders for the plane check; the real pointers follow the allocation
+    const float* ph = (const float*)src->reflectance;
+    g.depth = g.reflectance = g.retro_gain = g.normal_x = g.normal_y = g.normal_z = ph;
+    LIDAR_TRY(check_gbuffer(h, &g, "output raster: "));
+    HIP_TRY(h, h->rp_planes.ensure((size_t)6 * width * height), "allocate reprojected planes");
+    float* out = h->rp_planes.p;
+    const size_t plane = (size_t)width * height;
+    g.depth = out;
+    g.reflectance = out + plane;
+    g.retro_gain = out + 2 * plane;
+    g.normal_x = out + 3 * plane;
+    g.normal_y = out + 4 * plane;
+    g.normal_z = out + 5 * plane;
+    const RasterDev r = raster_of(g);
+    ReprojectArgs a;
+    a.W = (int)width;
+    a.H = (int)height;
+    a.az_min = r.az_min;
+    a.el_max = r.el_max;
+    a.dphi = r.dphi;
+    a.de = r.de;
+    a.SW = (int)src->width;
+    a.SH = (int)src->height;
+    a.spitch = (long)src->pitch;
+    a.fx = src->fx;
+    a.fy = src->fy;
+    a.cx = src->cx;
+    a.cy = src->cy;
+    for (int i = 0; i < 9; ++i) a.rot[i] = src->rot[i];
+    a.fmt = (int)src->depth_format;
+    a.correct = (int)src->normal_correct;
+    a.z_near = src->z_near;
+    a.z_far = src->z_far;
+    a.depth = src->depth;
+    a.refl = src->reflectance;
+    a.gain = src->retro_gain;
+    a.nx = src->normal_x;
+    a.ny = src->normal_y;
+    a.nz = src->normal_z;
+    a.out = out;
+    HIP_TRY(h, launch_reproject(h->stream, a), "reprojection launch");
+    if (h->setup_ok && !same_raster(h->single.gb, g)) h->setup_ok = false;
+    h->single.gb = g;
+    h->have_gbuffer = true;
+    h->gb_owned = true;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_read_gbuffer(lidar_sim* h, float* planes, int dst_is_device)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!planes) return fail(h, LIDAR_E_INVALID, "planes is NULL");
+    if (!h->gb_owned) return fail(h, LIDAR_E_STATE, "the current G-buffer is not a reprojected one");
+    const size_t n = (size_t)6 * h->single.gb.width * h->single.gb.height;
+    HIP_TRY(h, hipMemcpyAsync(planes, h->rp_planes.p, n * sizeof(float),
+                              dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream),
+            "copy G-buffer");
+    if (!dst_is_device) HIP_TRY(h, hipStreamSynchronize(h->stream), "read synchronise");
     return LIDAR_OK;
 }
 

@@ -47,6 +47,7 @@ def test_struct_layout_matches_header(binding, tmp_path):
                "lidar_pattern_desc": binding.lidar_pattern_desc,
                "lidar_gbuffer_desc": binding.lidar_gbuffer_desc,
                "lidar_stats": binding.lidar_stats,
+               "lidar_pinhole_desc": binding.lidar_pinhole_desc,
                "lidar_batch_info": binding.lidar_batch_info}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"',
              "int main(void) {"]
