@@ -455,6 +455,29 @@ lidar_status lidar_sim_set_gbuffer_pinhole(lidar_sim* h, const lidar_pinhole_des
  * caller's), LIDAR_E_HIP. */
 lidar_status lidar_sim_read_gbuffer(lidar_sim* h, float* planes, int dst_is_device);
 
+/* ---- Range stacking (section II-C, Alg. 2) ---------------------------------
+ * The paper's second algorithm on the current G-buffer: the rendered
+ * intensities rho_hat Omega (as in the footprint weights, without S_b) are
+ * split into depth slices of one time bin; each slice is correlated with the
+ * separable kernel K[n][m] = V[n] H[m] (kappa*eta ~ H * V, the paper's
+ * speed-up for separable kernels; m along the columns, n along the rows, the
+ * kernel indexed by pixel minus centre as in Eq. 5); every pixel keeps the
+ * nearest slice whose correlation is >= rho_min and that value.  Slices that
+ * cannot reach rho_min anywhere (largest shade of the slice times sum H
+ * times sum V below rho_min) are skipped; a tile stops once every pixel has
+ * its slice.  Equivalent to the beam-iteration's raw nearest echo of a beam
+ * centred on the pixel with threshold rho_min S_b.
+ * row_kernel: host [2M+1] H, col_kernel: host [2N+1] V (finite, >= 0;
+ * M, N <= 127).  s_nearest: device [height][width] int32 slice (n_bins when no
+ * slice reaches rho_min); xi_nearest: device [height][width] float (0 there).
+ * Needs a G-buffer (set_gbuffer or set_gbuffer_pinhole), range_mode CENTRE.
+ * Enqueued on the stream (synchronises only when the kernel factors change).
+ * Errors: LIDAR_E_STATE (no G-buffer), LIDAR_E_INVALID, LIDAR_E_UNSUPPORTED
+ * (other range modes), LIDAR_E_NOMEM, LIDAR_E_HIP. */
+lidar_status lidar_sim_range_stacking(lidar_sim* h, const float* row_kernel, uint32_t M,
+                                      const float* col_kernel, uint32_t N, double rho_min,
+                                      int32_t* s_nearest, float* xi_nearest);
+
 /* Counters since create or the last reset (synchronises profiling events).
  * Errors: LIDAR_E_INVALID (null), LIDAR_E_HIP. */
 lidar_status lidar_sim_get_stats(lidar_sim* h, lidar_stats* out);

@@ -42,7 +42,7 @@ EXPORTED = ["lidar_sim_create", "lidar_sim_destroy", "lidar_sim_set_pattern",
             "lidar_sim_surrogate_gradients", "lidar_sim_surrogate_train_step",
             "lidar_sim_surrogate_set_gate", "lidar_sim_surrogate_features", "lidar_sim_get_stats",
             "lidar_sim_reset_stats", "lidar_sim_simulate_static", "lidar_sim_set_gbuffer_pinhole",
-            "lidar_sim_read_gbuffer", "lidar_sim_last_error"]
+            "lidar_sim_read_gbuffer", "lidar_sim_range_stacking", "lidar_sim_last_error"]
 
 SUR_IN, SUR_OUT, SUR_PARAMS = 1056, 16, 406288
 
@@ -155,6 +155,7 @@ def load():
     lib.lidar_sim_set_gbuffer_pinhole.argtypes = [V, P(lidar_pinhole_desc), C.c_uint32, C.c_uint32,
                                                   C.c_double, C.c_double, C.c_double, C.c_double]
     lib.lidar_sim_read_gbuffer.argtypes = [V, V, C.c_int]
+    lib.lidar_sim_range_stacking.argtypes = [V, V, C.c_uint32, V, C.c_uint32, C.c_double, V, V]
     lib.lidar_sim_last_error.argtypes = [V]
     lib.lidar_sim_last_error.restype = C.c_char_p
     for name in EXPORTED[:-1]:
@@ -332,6 +333,16 @@ class LidarSim:
             float(raster.az_max), float(raster.el_min), float(raster.el_max)))
         self._keep = list(dev_planes)
         self._gb_shape = (int(raster.height), int(raster.width))
+
+    def range_stacking(self, row_kernel, col_kernel, rho_min, s_nearest, xi_nearest):
+        """Alg. 2 on the current G-buffer with K[n][m] = col_kernel[n] *
+        row_kernel[m]; s_nearest / xi_nearest: device tensors [H][W] int32 /
+        float32 (enqueued)."""
+        hk = np.ascontiguousarray(row_kernel, dtype=np.float32)
+        vk = np.ascontiguousarray(col_kernel, dtype=np.float32)
+        self._check(self._lib.lidar_sim_range_stacking(
+            self._h, hk.ctypes.data, (hk.size - 1) // 2, vk.ctypes.data, (vk.size - 1) // 2,
+            float(rho_min), int(s_nearest.data_ptr()), int(xi_nearest.data_ptr())))
 
     def read_gbuffer(self) -> np.ndarray:
         """The reprojected planes [6][H][W] (synchronises)."""

@@ -10,7 +10,7 @@ CSRC = os.path.join(_HERE, "csrc")
 LIB_DIR = os.path.join(_HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "liblidar_sim.so")
 SOURCES = ["lidar_sim.hip", "setup.hip", "prepass.hip", "footprint.hip", "mlp.hip", "features.hip",
-           "reproject.hip"]
+           "reproject.hip", "range_stacking.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -218,6 +218,23 @@ hipError_t launch_sun_floor(hipStream_t s, const SunFloorArgs& a);
 // whether G histograms of R bins plus the pulse taps fit the LDS budget
 bool footprint_group_fits(int G, int R, int J);
 
+// ---- range stacking (Alg. 2) with a separable kernel --------------------
+constexpr int kRsMaxHalf = 127;         // half extents M, N of the separable kernel
+struct RangeStackArgs {
+    const int2* pix;            // pre-pass records [W4/4][H][4]
+    int W, H, W4, R;
+    const float* hk;            // [2M + 1] along the rows (columns m = -M..M)
+    const float* vk;            // [2N + 1] along the columns (rows n = -N..N)
+    int M, N;
+    float rho_min;
+    float bound;                // sum H * sum V (slice skipping)
+    const int* smax;            // [R] largest shade per slice (FP32 bits)
+    int32_t* s_nearest;         // [H][W]
+    float* xi_nearest;          // [H][W]
+};
+// smax_scratch: [R] ints
+hipError_t launch_range_stacking(hipStream_t s, const RangeStackArgs& a, int* smax_scratch);
+
 // ---- reprojection of a pinhole rendering ---------------------------------
 struct ReprojectArgs {
     int W, H;                   // output raster

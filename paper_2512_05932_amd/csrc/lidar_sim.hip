@@ -155,6 +155,12 @@ struct lidar_sim {
     DevBuf<float> rp_planes;
     bool gb_owned = false;
 
+    // range stacking: separable kernel factors (device, host copy), slice maxima
+    DevBuf<float> rs_k;
+    std::vector<float> rs_host;
+    uint32_t rs_M = ~0u, rs_N = ~0u;
+    DevBuf<int> rs_smax;
+
     // stats
     lidar_stats st{};
     std::vector<EventPair> pending_fp, pending_pp, pending_bt, pending_sur, pool;
@@ -1714,6 +1720,74 @@ lidar_status lidar_sim_set_gbuffer_pinhole(lidar_sim* h, const lidar_pinhole_des
     h->single.gb = g;
     h->have_gbuffer = true;
     h->gb_owned = true;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_range_stacking(lidar_sim* h, const float* row_kernel, uint32_t M,
+                                      const float* col_kernel, uint32_t N, double rho_min,
+                                      int32_t* s_nearest, float* xi_nearest)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!h->have_gbuffer) return fail(h, LIDAR_E_STATE, "range_stacking before set_gbuffer");
+    if (!row_kernel || !col_kernel || !s_nearest || !xi_nearest)
+        return fail(h, LIDAR_E_INVALID, "range_stacking needs both kernel factors and both outputs");
+    if (M > (uint32_t)kRsMaxHalf || N > (uint32_t)kRsMaxHalf)
+        return fail(h, LIDAR_E_INVALID, "range_stacking kernel half extents must be <= 127");
+    if (!(rho_min > 0.0) || !is_fin(rho_min)) return fail(h, LIDAR_E_INVALID, "rho_min must be > 0");
+    if (h->prm.range_mode != LIDAR_RANGE_CENTRE)
+        return fail(h, LIDAR_E_UNSUPPORTED, "range_stacking slices the pixels' centre ranges");
+    const size_t KW = 2 * (size_t)M + 1, KH = 2 * (size_t)N + 1;
+    double sh = 0.0, sv = 0.0;
+    std::vector<float> k(KW + KH);
+    for (size_t i = 0; i < KW; ++i) {
+        if (!std::isfinite(row_kernel[i]) || row_kernel[i] < 0.0f)
+            return fail(h, LIDAR_E_INVALID, "kernel factors must be finite and >= 0");
+        k[i] = row_kernel[i];
+        sh += row_kernel[i];
+    }
+    for (size_t i = 0; i < KH; ++i) {
+        if (!std::isfinite(col_kernel[i]) || col_kernel[i] < 0.0f)
+            return fail(h, LIDAR_E_INVALID, "kernel factors must be finite and >= 0");
+        k[KW + i] = col_kernel[i];
+        sv += col_kernel[i];
+    }
+    hipStream_t s = h->stream;
+    FrameState& fs = h->single;
+    const lidar_gbuffer_desc& g = fs.gb;
+    if (M != h->rs_M || N != h->rs_N || k != h->rs_host) {
+        // new factors: copied once (the stream is synchronised so that the
+        // host copy may change afterwards)
+        HIP_TRY(h, h->rs_k.ensure(k.size()), "allocate kernel factors");
+        h->rs_host = k;
+        h->rs_M = M;
+        h->rs_N = N;
+        HIP_TRY(h, hipMemcpyAsync(h->rs_k.p, h->rs_host.data(), k.size() * sizeof(float),
+                                  hipMemcpyHostToDevice, s), "copy kernel factors");
+        HIP_TRY(h, hipStreamSynchronize(s), "kernel factors synchronise");
+    }
+    // pixel records of the current G-buffer (raster tables, pre-pass)
+    HIP_TRY(h, fs.d_colcs.ensure(g.width), "allocate raster tables");
+    HIP_TRY(h, fs.d_rowtab.ensure(g.height), "allocate raster tables");
+    HIP_TRY(h, launch_raster_tables(s, raster_of(g), fs.d_colcs.p, fs.d_rowtab.p), "raster tables launch");
+    LIDAR_TRY(alloc_pixels(h, fs));
+    LIDAR_TRY(enqueue_prepass(h, fs, s));
+    HIP_TRY(h, h->rs_smax.ensure(h->prm.n_bins), "allocate slice maxima");
+    RangeStackArgs a;
+    a.pix = fs.d_pix.p;
+    a.W = (int)g.width;
+    a.H = (int)g.height;
+    a.W4 = (int)((g.width + 3) & ~3u);
+    a.R = (int)h->prm.n_bins;
+    a.hk = h->rs_k.p;
+    a.vk = h->rs_k.p + KW;
+    a.M = (int)M;
+    a.N = (int)N;
+    a.rho_min = (float)rho_min;
+    a.bound = (float)(sh * sv);
+    a.smax = nullptr;
+    a.s_nearest = s_nearest;
+    a.xi_nearest = xi_nearest;
+    HIP_TRY(h, launch_range_stacking(s, a, h->rs_smax.p), "range stacking launch");
     return LIDAR_OK;
 }
 

@@ -1,0 +1,163 @@
+// Range stacking (section II-C, Alg. 2) with a separable kernel
+// kappa*eta = H * V: the rendered intensities are split into depth slices
+// (time bins); every slice is correlated with the kernel, separably (a pass
+// along the rows with H, then along the columns with V); each pixel keeps
+// the nearest slice whose correlation reaches rho_min and that value.
+//
+// Work decomposition: one workgroup per output tile of kTileC x kTileR
+// pixels.  It first marks in an LDS bitmap the slices present in the tile's
+// input window (tile plus the kernel's half extents) that can reach rho_min
+// at all (slice skipping: the largest shade of a slice in the image times
+// sum H times sum V bounds every correlation of that slice), then visits
+// them from the nearest on: the masked window rows are staged in LDS eight
+// at a time and correlated with H into a column buffer, which is correlated
+// with V at the tile's pixels; a pixel takes the first slice that reaches
+// rho_min, and the tile stops once every pixel has one.
+#include <climits>
+
+#include "engine.h"
+
+namespace lidar {
+
+namespace {
+
+constexpr int kTileC = 32, kTileR = 16;       // output tile: columns x rows
+constexpr int kThreads = 256;
+constexpr int kStageRows = kThreads / kTileC;  // window rows correlated per step
+constexpr int kMaxHalf = kRsMaxHalf;           // M, N <= 127
+constexpr int kMaxWords = (kMaxBins + 31) / 32;
+
+static_assert(kTileC * kStageRows == kThreads && kTileC * kTileR == 2 * kThreads,
+              "a thread per staged output, two tile pixels per thread");
+
+// Largest shade of every slice (time bin) over the image: FP32 bits of
+// non-negative values compare as integers.
+__global__ void k_rs_slice_max(const int2* pix, long n, int R, int* smax)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int2 rec = pix[i];
+    if (rec.x >= 0 && rec.x < R && rec.y > 0) atomicMax(smax + rec.x, rec.y);
+}
+
+__global__ void k_rs_clear(int* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// Record of image pixel (u, v) in the 4-column blocks of the pre-pass.
+__device__ inline int2 record(const RangeStackArgs& a, int u, int v)
+{
+    return a.pix[(((long)(u >> 2) * a.H + v) << 2) + (u & 3)];
+}
+
+__global__ __launch_bounds__(kThreads)
+void k_range_stacking(RangeStackArgs a)
+{
+    __shared__ float hk[2 * kMaxHalf + 1], vk[2 * kMaxHalf + 1];
+    __shared__ unsigned present[kMaxWords];
+    __shared__ float stage[kStageRows][kTileC + 2 * kMaxHalf];
+    __shared__ float colbuf[kTileR + 2 * kMaxHalf][kTileC];
+    __shared__ int open_count;
+    const int tid = threadIdx.x;
+    const int u0 = blockIdx.x * kTileC, v0 = blockIdx.y * kTileR;
+    const int M = a.M, N = a.N, KW = 2 * M + 1, KH = 2 * N + 1;
+    const int words = (a.R + 31) / 32;
+    for (int i = tid; i < KW; i += kThreads) hk[i] = a.hk[i];
+    for (int i = tid; i < KH; i += kThreads) vk[i] = a.vk[i];
+    for (int i = tid; i < words; i += kThreads) present[i] = 0u;
+    if (tid == 0) open_count = 0;
+    __syncthreads();
+    // slices present in the window that can reach rho_min
+    const int wr0 = max(0, v0 - N), wr1 = min(a.H - 1, v0 + kTileR - 1 + N);
+    const int wc0 = max(0, u0 - M), wc1 = min(a.W - 1, u0 + kTileC - 1 + M);
+    const int wcols = wc1 - wc0 + 1, wrows = wr1 - wr0 + 1;
+    for (int i = tid; i < wcols * wrows; i += kThreads) {
+        const int v = wr0 + i / wcols, u = wc0 + i % wcols;
+        const int2 rec = record(a, u, v);
+        if (rec.x >= 0 && rec.x < a.R && rec.y > 0 &&
+            __int_as_float(a.smax[rec.x]) * a.bound >= a.rho_min)
+            atomicOr(&present[rec.x >> 5], 1u << (rec.x & 31));
+    }
+    // this thread's two tile pixels: column tc, rows tr and tr + kTileR / 2
+    const int tc = tid % kTileC, tr = tid / kTileC;
+    int best[2] = {a.R, a.R};
+    float bval[2] = {0.0f, 0.0f};
+    const bool mine[2] = {u0 + tc < a.W && v0 + tr < a.H, u0 + tc < a.W && v0 + tr + kTileR / 2 < a.H};
+    if (mine[0] || mine[1]) atomicAdd(&open_count, (int)mine[0] + (int)mine[1]);
+    __syncthreads();
+    const int srow = tid / kTileC, scol = tid % kTileC;       // staged output of this thread
+    for (int w = 0; w < words; ++w) {
+        unsigned bits = present[w];
+        while (bits) {
+            if (open_count == 0) break;                          // uniform (read after a barrier)
+            const int s = w * 32 + __builtin_ctz(bits);
+            bits &= bits - 1u;
+            // rows with H: window rows v0 - N .. v0 + kTileR - 1 + N, eight at a time
+            for (int r0 = 0; r0 < kTileR + 2 * N; r0 += kStageRows) {
+                const int scols = kTileC + 2 * M;
+                for (int i = tid; i < kStageRows * scols; i += kThreads) {
+                    const int rr = i / scols, cc = i % scols;
+                    const int v = v0 - N + r0 + rr, u = u0 - M + cc;
+                    float x = 0.0f;
+                    if (v >= 0 && v < a.H && u >= 0 && u < a.W) {
+                        const int2 rec = record(a, u, v);
+                        if (rec.x == s) x = __int_as_float(rec.y);
+                    }
+                    stage[rr][cc] = x;
+                }
+                __syncthreads();
+                if (r0 + srow < kTileR + 2 * N) {
+                    float acc = 0.0f;
+                    for (int m = 0; m < KW; ++m) acc += hk[m] * stage[srow][scol + m];
+                    colbuf[r0 + srow][scol] = acc;
+                }
+                __syncthreads();
+            }
+            // columns with V at the tile's pixels; the first slice that
+            // reaches rho_min is the pixel's nearest
+            int closed = 0;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int r = tr + k * (kTileR / 2);
+                if (!mine[k] || best[k] < a.R) continue;
+                float acc = 0.0f;
+                for (int n = 0; n < KH; ++n) acc += vk[n] * colbuf[r + n][tc];
+                if (acc >= a.rho_min) {
+                    best[k] = s;
+                    bval[k] = acc;
+                    ++closed;
+                }
+            }
+            if (closed) atomicSub(&open_count, closed);
+            __syncthreads();
+        }
+        if (open_count == 0) break;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (!mine[k]) continue;
+        const long o = (long)(v0 + tr + k * (kTileR / 2)) * a.W + (u0 + tc);
+        a.s_nearest[o] = best[k];
+        a.xi_nearest[o] = bval[k];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_range_stacking(hipStream_t s, const RangeStackArgs& a, int* smax_scratch)
+{
+    if (a.M > kMaxHalf || a.N > kMaxHalf || a.R > kMaxBins) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rs_clear, dim3((a.R + 255) / 256), dim3(256), 0, s, smax_scratch, a.R);
+    const long n = (long)a.W4 * a.H;
+    hipLaunchKernelGGL(k_rs_slice_max, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.pix, n,
+                       a.R, smax_scratch);
+    RangeStackArgs b = a;
+    b.smax = smax_scratch;
+    dim3 grid((a.W + kTileC - 1) / kTileC, (a.H + kTileR - 1) / kTileR);
+    hipLaunchKernelGGL(k_range_stacking, grid, dim3(kThreads), 0, s, b);
+    return hipGetLastError();
+}
+
+}  // namespace lidar

@@ -407,3 +407,32 @@ def test_corrected_range_of_an_offset_cell(oracle_mod):
         u, v = cen.pixel[b]
         assert list(np.flatnonzero(cen.xi[b])) == [math.floor(float(gb.depth[v - 1, u + 2]) * to_bin)]
     assert checked >= 35
+
+
+def test_range_stacking_with_a_separable_kernel():
+    """For kappa eta = H * V (section III-B, Alg. 2's separable speed-up) the
+    per-slice 2-D correlation with K[n][m] = V[n] H[m] equals a correlation
+    along the rows with H followed by one along the columns with V (library
+    1-D correlations); the nearest slice at or above rho_min follows."""
+    from scipy import ndimage
+    from oracle import range_stacking as rs
+    rng = np.random.default_rng(9)
+    inten = rng.uniform(0.0, 1.0, (40, 56)) * (rng.uniform(size=(40, 56)) < 0.6)
+    bins = rng.integers(0, 12, (40, 56))
+    Hk = rng.uniform(0.1, 1.0, 9)          # columns m = -4..4
+    Vk = rng.uniform(0.1, 1.0, 5)          # rows n = -2..2
+    K = np.outer(Vk, Hk)
+    for s in (0, 5, 11):
+        img = np.where(bins == s, inten, 0.0)
+        two = ndimage.correlate1d(ndimage.correlate1d(img, Hk, axis=1, mode="constant"), Vk, axis=0,
+                                  mode="constant")
+        np.testing.assert_allclose(rs.slice_correlations(inten, bins, K, 12, [s])[s], two,
+                                   rtol=1e-12, atol=1e-14)
+    rho = 1.5
+    s_near, xi_near = rs.nearest_above(inten, bins, K, 12, rho)
+    stack = np.stack([ndimage.correlate1d(ndimage.correlate1d(np.where(bins == s, inten, 0.0), Hk, axis=1,
+                                                              mode="constant"), Vk, axis=0, mode="constant")
+                      for s in range(12)])
+    above = stack >= rho
+    first = np.where(above.any(0), above.argmax(0), 12)
+    np.testing.assert_array_equal(s_near, first)
