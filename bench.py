@@ -24,13 +24,21 @@ if ROOT not in sys.path:
 
 METRIC = "beam-pixel samples/s + beams/s (1 GPU), surrogate vs plain at ≤1-bin range err"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 157.3          # vector FP32 with packed FMA (256 CU x 2.4 GHz x 256)
+FP32_UNPACKED_TFLOPS = 78.6       # one FMA per lane and clock (the build does not pack)
+FP64_PEAK_TFLOPS = 78.6
+LDS_PEAK_GBS = 256 * 2.4 * 128.0  # 128 B per clock per CU
+TA_PEAK_GBS = 256 * 2.4 * 64.0    # vector-memory data path: 64 B per clock per CU
 # algorithmic FP32 operations per beam-pixel sample: the weight
 # S_b * K * Omega * beta * cos(theta) / d^2 (5 multiplies) and its add into the
-# time bin; with the sun term also kappa * Omega * (rho/pi) * max(0, n.s)
-# (3 multiplies) and its add into the floor
+# time bin; with the sun term one more multiply-add (kappa times the pixel's
+# sun shading Omega (rho/pi) max(0, n.s), added into the floor)
 FLOPS_PER_SAMPLE = 6
-FLOPS_PER_SAMPLE_SUN = 4
+FLOPS_PER_SAMPLE_SUN = 2
+# FP64 operations of a sample's corrected range (range_mode CORRECTED): the
+# normal's azimuth components (2 x 3), p.n (3), the turned direction's v.n
+# (3 + 3 + 3 + 3), the ratio and its limits (3), range and bin (3)
+FP64_PER_CORRECTED_SAMPLE = 27
 
 
 def parse():
@@ -45,6 +53,13 @@ def parse():
                     default=os.path.join(ROOT, "profiles", "k_footprint_scan8192x512_traffic.json"),
                     help="JSON file with per-dispatch HBM bytes of the footprint kernel "
                          "(ignored when it was taken with another kernel source)")
+    ap.add_argument("--counters", type=str,
+                    default=os.path.join(ROOT, "profiles", "k_footprint_scan8192x512_counters.json"),
+                    help="JSON file with per-dispatch SQ/TA counters of the footprint kernel "
+                         "(ignored when taken with another kernel source)")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the measurements of the options and of range stacking")
+    ap.add_argument("--rows-only", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-frame batch measurement")
     ap.add_argument("--batch-only", action="store_true",
@@ -74,10 +89,9 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
 
 
-def measured_traffic(path):
-    """HBM bytes per launch of the footprint kernel from rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes (scaled by a plain-copy calibration), or None when the
-    counters were taken with a different kernel source."""
+def _profile_record(path):
+    """A profiles/ JSON record, or None when it was taken with a different
+    kernel source (its sha256 is stored with it)."""
     import hashlib
     if not path or not os.path.exists(path):
         return None
@@ -89,7 +103,48 @@ def measured_traffic(path):
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec.get("source_sha256"):
             return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def measured_traffic(path):
+    """HBM bytes per launch of the footprint kernel from rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (scaled by a plain-copy calibration), or None when the
+    counters were taken with a different kernel source."""
+    rec = _profile_record(path)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+VMEM_BYTES_PER_SAMPLE = 7.0       # 8 B pixel record + 4 B sun shading per 4 beams, 4 B kernel per beam
+
+
+def unit_figures(path, ms, samples):
+    """LDS and vector-memory figures of the footprint kernel at the measured
+    launch time, from its counter record (per dispatch, one rocprofv3 --pmc
+    pass of the same command): LDS bytes, at least 4 per lane of every LDS
+    instruction (SQ_INSTS_LDS x 64 x 4), against 128 B per clock and CU, with
+    the LDS busy and bank-conflict fractions; algorithmic bytes through the
+    vector-memory path (VMEM_BYTES_PER_SAMPLE per sample) against 64 B per
+    clock and CU, with the texture-address unit's busy fraction
+    (GRBM_TA_BUSY / GRBM_GUI_ACTIVE); VALU busy (SQ_INSTS_VALU x 4 cycles per
+    wave64 instruction over 1024 SIMDs)."""
+    rec = _profile_record(path)
+    if not rec or not ms:
+        return None
+    c = rec["counters"]
+    cycles = c["GRBM_GUI_ACTIVE"] / 8.0            # summed over the 8 XCDs
+    lds_bytes = c["SQ_INSTS_LDS"] * 64 * 4
+    vmem_bytes = samples * VMEM_BYTES_PER_SAMPLE
+    t = ms * 1e-3
+    return {
+        "lds": {"min_bytes_per_launch": lds_bytes, "achieved": lds_bytes / t / 1e9,
+                "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": lds_bytes / t / 1e9 / LDS_PEAK_GBS,
+                "busy_frac": c["SQ_LDS_IDX_ACTIVE"] / (cycles * 256),
+                "bank_conflict_frac_of_active": c["SQ_LDS_BANK_CONFLICT"] / max(1.0, c["SQ_LDS_IDX_ACTIVE"])},
+        "vmem": {"bytes_per_launch": vmem_bytes, "achieved": vmem_bytes / t / 1e9,
+                 "peak": TA_PEAK_GBS, "unit": "GB/s", "frac": vmem_bytes / t / 1e9 / TA_PEAK_GBS,
+                 "ta_busy_frac": c["GRBM_TA_BUSY"] / c["GRBM_GUI_ACTIVE"]},
+        "valu_busy_frac": c["SQ_INSTS_VALU"] * 4 / (cycles * 1024),
+        "counter_source": "profiles/" + os.path.basename(path)}
 
 
 def precision_report(w, planes, n_sample=240, seed=7):
@@ -287,6 +342,121 @@ def replayed_small_report(args, n_frames=32, steps=20):
             "beams_per_s": info["n_beams"] / (ms * 1e-3), "steps": steps}
 
 
+def _timed(stream, fn, n):
+    import torch
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(n):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / n
+
+
+def rows_report(args, steps=10):
+    """The path's options on the scanning workload (range-corrected and
+    interval ranges, raw and strongest echo selection), range stacking
+    (Alg. 2) on its workload, and the reprojection of a pinhole rendering;
+    per row the time per frame and the roofline of its dominant kernel."""
+    from dataclasses import replace
+    import numpy as np
+    import torch
+    import scenes
+    import paper_2512_05932_amd as lidar
+    stream = torch.cuda.current_stream()
+    out = {}
+    w = scenes.road_scan(args.seed)
+    planes = lidar.upload_gbuffer(w.gbuffer, "cuda:0")
+    sun = w.params.sun_irradiance != 0.0
+    modes = (("range_corrected", dict(range_mode=lidar.LIDAR_RANGE_CORRECTED)),
+             ("range_interval", dict(range_mode=lidar.LIDAR_RANGE_INTERVAL)),
+             ("echo_strongest", dict(echo_select=lidar.LIDAR_ECHO_STRONGEST)),
+             ("echo_raw_nearest", dict(echo_select=lidar.LIDAR_ECHO_RAW_NEAREST)))
+    for name, kw in modes:
+        prm = replace(w.params, **kw)
+        sim = lidar.LidarSim(prm, stream=stream, profile=True)
+        sim.set_pattern(w.pattern)
+        sim.set_gbuffer(w.gbuffer.raster, planes)
+        for _ in range(2):
+            sim.simulate_frame()
+        torch.cuda.synchronize()
+        sim.reset_stats()
+        ms = _timed(stream, sim.simulate_frame, steps)
+        st = sim.stats()
+        res = sim.read(beams=False)
+        sim.close()
+        fp = st["footprint_ms"] / max(1, st["footprint_launches"])
+        samples = st["samples_per_frame"]
+        flops = samples * (FLOPS_PER_SAMPLE + (FLOPS_PER_SAMPLE_SUN if sun else 0))
+        rec = {"workload": w.name, "ms_per_frame": ms, "footprint_ms": fp,
+               "samples_per_s": samples / (ms * 1e-3), "echoes_per_frame": int(res["n_echoes"].sum()),
+               "roofline": {"bound": "alu", "kernel": "k_footprint_corr" if "corrected" in name
+                            else "k_footprint", "achieved": flops / (fp * 1e-3) / 1e12,
+                            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": flops / (fp * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}}
+        if "corrected" in name:
+            f64 = samples * FP64_PER_CORRECTED_SAMPLE / (fp * 1e-3) / 1e12
+            rec["roofline_fp64"] = {"bound": "alu", "achieved": f64, "peak": FP64_PEAK_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": f64 / FP64_PEAK_TFLOPS,
+                                    "fp64_ops_per_sample": FP64_PER_CORRECTED_SAMPLE}
+        out[name] = rec
+    del planes
+    # range stacking (Alg. 2) on the paper's setting
+    sw = scenes.range_stacking_scene(args.seed)
+    H, W = sw.gbuffer.depth.shape
+    planes = lidar.upload_gbuffer(sw.gbuffer, "cuda:0")
+    s_out = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    x_out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    sim = lidar.LidarSim(sw.params, stream=stream)
+    sim.set_gbuffer(sw.gbuffer.raster, planes)
+    run = lambda: sim.range_stacking(sw.row_kernel, sw.col_kernel, sw.rho_min, s_out, x_out)
+    run()
+    ms = _timed(stream, run, steps)
+    sim.close()
+    s_np = s_out.cpu().numpy()
+    d = sw.gbuffer.depth.astype(np.float64)
+    with np.errstate(invalid="ignore"):
+        b = np.floor(d * 2.0 / (299792458.0 * sw.params.bin_ns * 1e-9))
+    present = np.unique(b[np.isfinite(b) & (b < sw.params.n_bins)]).size
+    KW, KH = sw.row_kernel.size, sw.col_kernel.size
+    ps = float(W * H) * present
+    eff = ps * 2.0 * (KW + KH) / (ms * 1e-3) / 1e12
+    out["range_stacking"] = {
+        "workload": sw.name, "ms_per_frame": ms, "slices": int(sw.params.n_bins),
+        "slices_present": int(present), "pixels_with_slice": float((s_np < sw.params.n_bins).mean()),
+        "pixel_slices_per_s": ps / (ms * 1e-3),
+        "roofline": {"bound": "alu", "kernel": "k_range_stacking", "achieved": eff,
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": eff / FP32_PEAK_TFLOPS,
+                     "note": "algorithmic: 2 (KW + KH) FLOP per pixel and present slice (separable "
+                             "correlation of every present slice over the whole image); the kernel "
+                             "skips tiles without the slice and stops tiles once resolved"},
+        "paper_context": "Alg. 2: 4.3 s per frame (1200 slices), 0.8 s with slice skipping, "
+                         "OpenCV on a 14-core i7-13800H"}
+    del planes
+    # reprojection of a pinhole rendering (z buffer, 24 bits) onto 4096 x 1024
+    ph = scenes.pinhole_render(args.seed, width=1920, height=1080, hfov_deg=90.0, pitch_deg=-2.0,
+                               fmt=4, near=0.3, far=1000.0, n_boxes=16)
+    dev = [torch.from_numpy(np.ascontiguousarray(a).view(np.int32) if a.dtype == np.uint32
+                            else np.ascontiguousarray(a)).to("cuda")
+           for a in (ph.depth, ph.reflectance, ph.retro_gain, ph.normal[0], ph.normal[1], ph.normal[2])]
+    r = scenes.Raster(4096, 1024, -45.0, 45.0, -22.5, 22.5)
+    sim = lidar.LidarSim(w.params, stream=stream)
+    run = lambda: sim.set_gbuffer_pinhole(ph, dev, r)
+    run()
+    ms = _timed(stream, run, steps)
+    sim.close()
+    nbytes = 24.0 * r.width * r.height * 2          # six planes written, six gathered
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out["reproject"] = {"workload": "pinhole 1920x1080 (90 deg, 24-bit z) -> 4096x1024 equiangular",
+                        "ms": ms, "pixels_per_s": r.width * r.height / (ms * 1e-3),
+                        "roofline": {"bound": "hbm", "kernel": "k_reproject", "achieved": gbs,
+                                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                                     "bytes_per_launch": nbytes}}
+    return out
+
+
 SUR_FLOPS_PER_BEAM = 2 * (1056 * 256 + 2 * 256 * 256 + 256 * 16)   # the network's products
 BF16_PEAK_TFLOPS = 2500.0
 
@@ -358,7 +528,7 @@ def surrogate_report(args, pattern="gauss", train_frames=None, steps=None, eval_
                     "surrogate_ms": times[lidar.LIDAR_MODE_SURROGATE],
                     "fallback": st["fallback_beams"] / max(1, st["surrogate_beams"]),
                     "within_1_bin_vs_plain": ag["within_1_bin"]})
-        if oracle_agree is None and oracle_sample:
+        if oracle_agree is None and oracle_sample and not args.no_cpu_baseline:
             import oracle
             idx = np.sort(np.random.default_rng(3).choice(w.pattern.n_beams, oracle_sample,
                                                           replace=False))
@@ -427,6 +597,9 @@ def main():
                               args, "table", train_frames=8, steps=1500, eval_frames=1,
                               oracle_sample=0)}), flush=True)
         return
+    if args.rows_only:
+        print(json.dumps({"rows": rows_report(args)}), flush=True)
+        return
     w = scenes.road_scan(args.seed)
     stream = torch.cuda.current_stream()
     planes = lidar.upload_gbuffer(w.gbuffer, "cuda:0")
@@ -447,7 +620,7 @@ def main():
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
     st = sim.stats()
-    out = sim.read()
+    out = sim.read(beams=True)
     sim.close()
     ms = total_ms / args.steps
     samples = st["samples_per_frame"]
@@ -472,11 +645,19 @@ def main():
                    "seed": args.seed},
         "beams_per_s": B * args.steps / (total_ms * 1e-3),
         "echoes_per_frame": int(out["n_echoes"].sum()),
+        "echo_stats": {"beams_with_echoes": float((out["n_echoes"] > 0).mean()),
+                       "beams_floor_above_threshold": float(
+                           (out["beams"]["floor"] > w.params.threshold).mean()),
+                       "runs_touching_both_edges": float(
+                           ((out["echoes"]["flags"][:, 0] == 3) & (out["n_echoes"] > 0)).mean())},
         "roofline": {"bound": "alu", "kernel": "k_footprint", "achieved": achieved,
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
-                     "avg_launch_ms": fp_ms,
-                     "flops_per_launch": flops},
+                     "avg_launch_ms": fp_ms, "flops_per_launch": flops,
+                     "flops_per_sample": FLOPS_PER_SAMPLE + (FLOPS_PER_SAMPLE_SUN if sun else 0),
+                     "peak_unpacked": FP32_UNPACKED_TFLOPS,
+                     "frac_unpacked": achieved / FP32_UNPACKED_TFLOPS,
+                     "units": unit_figures(args.counters, fp_ms, samples)},
         "prepass_ms": st["prepass_ms"] / max(1, st["prepass_launches"]),
     }
     # the HBM-bound parts: the pre-pass streams the G-buffer once per frame,
@@ -493,6 +674,8 @@ def main():
     }
     if not args.no_batch:
         rec["batch"] = batch_report(args)
+    if not args.no_rows:
+        rec["rows"] = rows_report(args)
     if not args.no_surrogate:
         rec["surrogate"] = surrogate_report(args)
         rec["surrogate_table_pattern"] = surrogate_report(args, "table", train_frames=8,

@@ -230,7 +230,11 @@ typedef struct {
 } lidar_stats;
 
 /* Create a handle with the given parameters on a HIP stream (void* =
- * hipStream_t, NULL = default stream).  *out receives the handle.
+ * hipStream_t, NULL = default stream).  *out receives the handle.  The
+ * parameters are the receiver's: time bins and bin width (the range
+ * resolution dr of Alg. 1), detection threshold T and pulse varpi of the EPW
+ * post-processing (section II-C), emitted power, ambient and sun terms
+ * (section II-A).
  * Errors: LIDAR_E_INVALID for null pointers or parameters out of range,
  * LIDAR_E_HIP, LIDAR_E_NOMEM.  No handle is returned on error. */
 lidar_status lidar_sim_create(const lidar_sim_params* params, void* hip_stream,
@@ -248,14 +252,19 @@ lidar_status lidar_sim_destroy(lidar_sim* h);
  * non-finite beam angles), LIDAR_E_NOMEM, LIDAR_E_HIP. */
 lidar_status lidar_sim_set_pattern(lidar_sim* h, const lidar_pattern_desc* pattern);
 
-/* Record the device planes and raster of the next frame (borrowed).
+/* Record the device planes and raster of the next frame (borrowed): the
+ * rendered ranges, BRDF terms and normals that Alg. 1 takes as input
+ * (rho_hat, varrho, nu), on the equiangular raster of section II-C.
  * Errors: LIDAR_E_INVALID (null planes, zero size, pitch < width, inverted or
  * non-finite angle ranges), LIDAR_E_NOMEM, LIDAR_E_HIP. */
 lidar_status lidar_sim_set_gbuffer(lidar_sim* h, const lidar_gbuffer_desc* gbuffer);
 
 /* Enqueue one frame on the handle's stream: kernel/normalisation set-up when
  * the pattern or raster changed, the G-buffer pre-pass, then the fused
- * footprint gather / time binning / ambient / pulse / echo kernel.
+ * footprint gather / time binning / ambient / pulse / echo kernel: for
+ * every beam the sum of Eq. 5 over its kernel cells (Alg. 1), the ambient
+ * floor (section II-A), xi_hat = varpi * xi and the echoes (section II-C, EPW
+ * paragraph).
  * mode LIDAR_MODE_SURROGATE (extension; needs surrogate weights): the
  * network predicts every beam's echoes from its inputs (see
  * lidar_sim_surrogate_features), the gate (lidar_sim_surrogate_set_gate)
@@ -267,7 +276,9 @@ lidar_status lidar_sim_set_gbuffer(lidar_sim* h, const lidar_gbuffer_desc* gbuff
  * weights), LIDAR_E_HIP. */
 lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode);
 
-/* Copy the last frame's results out.  echoes: [n_beams][max_echoes] (unused
+/* Copy the last frame's results out: the echoes (range, intensity, pulse
+ * width; section II-C) and, on request, the waveforms xi_hat[B][R] (Alg. 1's
+ * result, pulse-convolved).  echoes: [n_beams][max_echoes] (unused
  * slots zeroed), n_echoes: [n_beams] runs found (may exceed max_echoes),
  * waveforms: [n_beams][n_bins] xi_hat (needs LIDAR_KEEP_WAVEFORMS), beams:
  * [n_beams].  After a LIDAR_MODE_SURROGATE frame the waveform rows of the

@@ -210,51 +210,58 @@ __global__ void k_beam_corr(RasterDev r, const double* az, const double* el, int
     bcorr[b] = make_double4(cos(da), sin(da), cos(de), sin(de));
 }
 
-// Per beam: containing pixel (floor rounding), FP64 normalisation over every
-// kernel cell (on- and off-image rows), scale S_b = P_e / N_b, and the number
-// of non-zero kernel cells inside the image.  Row solid angles come from the
-// table omega (rows om_v0 .. om_v0 + om_n - 1, the same FP64 values) and are
-// computed directly for beams beyond it.
-__global__ void k_beam_setup(RasterDev r, KernelDev k, const double* az, const double* el,
-                             int B, const double* rowsum, const int32_t* prefix,
-                             const double* omega, long om_v0, int om_n,
-                             double emit_power, lidar_beam_info* beams)
+// Per beam (one wave per beam, lanes over the kernel rows): containing pixel
+// (floor rounding), FP64 normalisation over every kernel cell (on- and
+// off-image rows), scale S_b = P_e / N_b, and the number of non-zero kernel
+// cells inside the image.  Row solid angles come from the table omega (rows
+// om_v0 .. om_v0 + om_n - 1, the same FP64 values) and are computed directly
+// for beams beyond it.  The lanes' FP64 partial sums are added by lane
+// shuffles.
+__global__ __launch_bounds__(256)
+void k_beam_setup(RasterDev r, KernelDev k, const double* az, const double* el,
+                  int B, const double* rowsum, const int32_t* prefix,
+                  const double* omega, long om_v0, int om_n,
+                  double emit_power, lidar_beam_info* beams)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (b >= B) return;                              // the whole wave
     double fu = floor((az[b] - r.az_min) / r.dphi);
     double fv = floor((r.el_max - el[b]) / r.de);
     // beams far outside the image keep an empty footprint
     const double lim = 1073741824.0;
     fu = fmin(fmax(fu, -lim), lim);
     fv = fmin(fmax(fv, -lim), lim);
-    long ub = (long)fu, vb = (long)fv;
+    const long ub = (long)fu, vb = (long)fv;
+    const bool tab = vb - k.N >= om_v0 && vb + k.N < om_v0 + om_n;
     double nb = 0.0;
-    if (vb - k.N >= om_v0 && vb + k.N < om_v0 + om_n) {
-        const double* om = omega + (vb - k.N - om_v0);
-        for (int n = 0; n < k.KH; ++n) nb += rowsum[n] * om[n];
-    } else {
-        for (int n = -k.N; n <= k.N; ++n) nb += rowsum[n + k.N] * row_omega(r, vb + n);
+    for (int n = lane; n < k.KH; n += 64) {
+        const long v = vb - k.N + n;
+        nb += rowsum[n] * (tab ? omega[v - om_v0] : row_omega(r, v));
     }
+    for (int off = 32; off > 0; off >>= 1) nb += __shfl_xor(nb, off);
     uint32_t samples = 0;
-    long c_lo = (long)-k.M > -ub ? (long)-k.M : -ub;
-    long c_hi = (long)k.M < (long)r.W - 1 - ub ? (long)k.M : (long)r.W - 1 - ub;
+    const long c_lo = (long)-k.M > -ub ? (long)-k.M : -ub;
+    const long c_hi = (long)k.M < (long)r.W - 1 - ub ? (long)k.M : (long)r.W - 1 - ub;
     if (c_lo <= c_hi) {
-        for (int n = -k.N; n <= k.N; ++n) {
-            long v = vb + n;
+        for (int n = lane; n < k.KH; n += 64) {
+            const long v = vb - k.N + n;
             if (v < 0 || v >= r.H) continue;
-            const int32_t* pr = prefix + (long)(n + k.N) * (k.KW + 1);
+            const int32_t* pr = prefix + (long)n * (k.KW + 1);
             samples += (uint32_t)(pr[c_hi + k.M + 1] - pr[c_lo + k.M]);
         }
     }
-    lidar_beam_info bi;
-    bi.pixel_u = (int32_t)ub;
-    bi.pixel_v = (int32_t)vb;
-    bi.scale = (float)(emit_power / nb);
-    bi.floor = 0.0f;
-    bi.samples = samples;
-    bi.reserved = 0;
-    beams[b] = bi;
+    for (int off = 32; off > 0; off >>= 1) samples += (uint32_t)__shfl_xor((int)samples, off);
+    if (lane == 0) {
+        lidar_beam_info bi;
+        bi.pixel_u = (int32_t)ub;
+        bi.pixel_v = (int32_t)vb;
+        bi.scale = (float)(emit_power / nb);
+        bi.floor = 0.0f;
+        bi.samples = samples;
+        bi.reserved = 0;
+        beams[b] = bi;
+    }
 }
 
 // Centred Gaussian pulse sampled at the bin pitch, unit sum (FP32).
@@ -322,7 +329,7 @@ hipError_t launch_beam_setup(hipStream_t s, RasterDev r, KernelDev k, const doub
     const long v0 = -(long)k.KH;
     const int n = r.H + 2 * k.KH;
     hipLaunchKernelGGL(k_row_omega, dim3((n + 255) / 256), dim3(256), 0, s, r, v0, n, omega);
-    hipLaunchKernelGGL(k_beam_setup, dim3((B + 127) / 128), dim3(128), 0, s, r, k, az, el, B,
+    hipLaunchKernelGGL(k_beam_setup, dim3((B + 3) / 4), dim3(256), 0, s, r, k, az, el, B,
                        rowsum, prefix, (const double*)omega, v0, n, emit_power, beams);
     return hipGetLastError();
 }
