@@ -56,8 +56,19 @@ enum {
 enum {
     LIDAR_KEEP_WAVEFORMS = 1u,  /* keep xi_hat [n_beams][n_bins] for read_echoes */
     LIDAR_PROFILE = 2u,         /* time the footprint kernel with HIP events */
-    LIDAR_AUTOTUNE = 4u         /* batches: time the tile candidates per kernel-size
+    LIDAR_AUTOTUNE = 4u,        /* batches: time the tile candidates per kernel-size
                                    class when a batch is set up, keep the fastest */
+    LIDAR_DETERMINISTIC = 8u    /* bit-identical results when the same inputs are
+                                   simulated again on the same device: simulate_frame
+                                   (plain) runs groups of one beam whose four waves
+                                   gather into histograms of their own, summed in a
+                                   fixed order (about twice the frame time); the
+                                   surrogate's forward, gradients and AdamW steps run
+                                   without split-K atomics (the reported loss may
+                                   still differ in its last bits).  simulate_batch and
+                                   surrogate-mode frames return LIDAR_E_UNSUPPORTED;
+                                   create does when four histograms of n_bins do not
+                                   fit a workgroup's LDS. */
 };
 
 /* lidar_pattern_desc.kind */
@@ -117,7 +128,8 @@ typedef struct {
     double ambient_const;      /* constant floor added to every bin */
     double sun_irradiance;     /* E_sun, 0 = no sun term */
     double sun_dir[3];         /* unit vector towards the sun, sensor frame */
-    uint32_t flags;            /* LIDAR_KEEP_WAVEFORMS | LIDAR_PROFILE | LIDAR_AUTOTUNE */
+    uint32_t flags;            /* LIDAR_KEEP_WAVEFORMS | LIDAR_PROFILE | LIDAR_AUTOTUNE |
+                                  LIDAR_DETERMINISTIC */
     uint32_t echo_select;      /* LIDAR_ECHO_ALL .. LIDAR_ECHO_RAW_NEAREST */
     uint32_t range_mode;       /* LIDAR_RANGE_CENTRE | _CORRECTED | _INTERVAL */
     uint32_t n_pulse_taps;     /* with pulse_taps: odd, 1..257 */
@@ -207,6 +219,11 @@ typedef struct {
                                   item instead of one workgroup; see the frames'
                                   schedule in lidar_sim_simulate_batch) */
     double autotune_ms;        /* time spent in the trials */
+    uint32_t direct_frames;    /* frames gathered straight from their G-buffer planes
+                                  without a pre-pass: those on the wave schedule
+                                  whose beams hold at most one sample per two pixels
+                                  (range_mode CENTRE, no kappa table) */
+    uint32_t reserved;
 } lidar_batch_info;
 
 /* Counters of a handle since create or the last reset_stats. */
@@ -387,6 +404,31 @@ lidar_status lidar_sim_surrogate_gradients(lidar_sim* h, const void* x, const fl
 lidar_status lidar_sim_surrogate_train_step(lidar_sim* h, const void* x, const float* labels,
                                             uint32_t n, const lidar_train_hparams* hp,
                                             float* loss);
+
+/* The whole training loop inside the library: `steps` AdamW steps (the
+ * update of surrogate_train_step) over minibatches of b = min(batch, n) of
+ * the n rows (x: device [n][1056] bfloat16, labels: device [n][16]).  Rows
+ * are visited in epochs e = 0, 1, ...: step t takes the next b positions p of
+ * the current epoch, row P_e(p) each, and an epoch with fewer than b
+ * positions left ends there (its remainder is skipped).  P_e is a
+ * permutation of 0 .. n-1 computed on the device: with k = 2 h the smallest
+ * even number >= 2 with 2^k >= n, a four-round Feistel network on k-bit
+ * values (left and right halves of h bits; round r = 0..3 maps (L, R) to
+ * (R, L xor (mix(key_r xor R) and (2^h - 1))), key_r = seed xor ((4 e + r + 1)
+ * * 0x9e3779b97f4a7c15 mod 2^64), mix the SplitMix64 output function),
+ * applied again while the value is >= n (cycle walking).  The learning rate
+ * of step t is hp->lr + (lr_final - hp->lr) t / max(1, steps - 1).
+ * losses: device [ceil(steps / log_every)] (nullable; log_every >= 1 then):
+ * the loss of steps 0, log_every, 2 log_every, ... before their update.
+ * Enqueued on the stream (asynchronous); the minibatch buffers are the
+ * handle's.  Extension of the method (a learned surrogate).
+ * Errors: LIDAR_E_INVALID (null x or labels, n = 0 or >= 2^62, batch = 0,
+ * hyper-parameters as train_step, lr_final < 0 or non-finite, losses with
+ * log_every = 0), LIDAR_E_STATE (no weights), LIDAR_E_NOMEM, LIDAR_E_HIP. */
+lidar_status lidar_sim_surrogate_train(lidar_sim* h, const void* x, const float* labels, uint64_t n,
+                                       uint32_t batch, uint32_t steps, const lidar_train_hparams* hp,
+                                       double lr_final, uint64_t seed, float* losses,
+                                       uint32_t log_every);
 
 /* Gate of LIDAR_MODE_SURROGATE: a beam keeps the network's echoes when its
  * confidence sigmoid(y[12]) >= c_min and its tail estimate E_tail (the

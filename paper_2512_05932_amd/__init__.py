@@ -7,6 +7,7 @@ from ._binding import (LidarSim, LidarError, Batch, load, ECHO_DTYPE, BEAM_DTYPE
                        LIDAR_OK, LIDAR_E_INVALID, LIDAR_E_STATE, LIDAR_E_HIP, LIDAR_E_NOMEM,
                        LIDAR_E_UNSUPPORTED, LIDAR_PATTERN_GAUSS, LIDAR_PATTERN_TABLE,
                        LIDAR_MODE_PLAIN, LIDAR_MODE_SURROGATE, LIDAR_ECHO_SURROGATE, LIDAR_AUTOTUNE,
+                       LIDAR_DETERMINISTIC,
                        LIB_PATH, simulate_static, STATIC_SCRATCH_BYTES, LIDAR_ECHO_ALL,
                        LIDAR_ECHO_STRONGEST, LIDAR_ECHO_NEAREST, LIDAR_ECHO_LONGEST,
                        LIDAR_ECHO_RAW_STRONGEST, LIDAR_ECHO_RAW_NEAREST, LIDAR_RANGE_CENTRE,

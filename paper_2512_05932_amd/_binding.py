@@ -24,6 +24,7 @@ LIDAR_E_UNSUPPORTED = -5
 LIDAR_KEEP_WAVEFORMS = 1
 LIDAR_PROFILE = 2
 LIDAR_AUTOTUNE = 4
+LIDAR_DETERMINISTIC = 8
 LIDAR_PATTERN_GAUSS = 1
 LIDAR_PATTERN_TABLE = 2
 LIDAR_MODE_PLAIN = 0
@@ -40,6 +41,7 @@ EXPORTED = ["lidar_sim_create", "lidar_sim_destroy", "lidar_sim_set_pattern",
             "lidar_sim_reset_batch", "lidar_sim_surrogate_set_weights",
             "lidar_sim_surrogate_get_weights", "lidar_sim_surrogate_forward",
             "lidar_sim_surrogate_gradients", "lidar_sim_surrogate_train_step",
+            "lidar_sim_surrogate_train",
             "lidar_sim_surrogate_set_gate", "lidar_sim_surrogate_features", "lidar_sim_get_stats",
             "lidar_sim_reset_stats", "lidar_sim_simulate_static", "lidar_sim_set_gbuffer_pinhole",
             "lidar_sim_read_gbuffer", "lidar_sim_range_stacking", "lidar_sim_last_error"]
@@ -102,7 +104,7 @@ class lidar_batch_info(C.Structure):
     _fields_ = [("n_frames", C.c_uint32), ("group_size", C.c_uint32), ("n_beams", C.c_uint64),
                 ("n_items", C.c_uint64), ("samples", C.c_uint64), ("grid", C.c_uint32),
                 ("graph", C.c_uint32), ("autotuned", C.c_uint32), ("wave_items", C.c_uint32),
-                ("autotune_ms", C.c_double)]
+                ("autotune_ms", C.c_double), ("direct_frames", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 ECHO_DTYPE = np.dtype([("range_m", "<f8"), ("time_ns", "<f8"), ("intensity", "<f4"),
@@ -146,6 +148,9 @@ def load():
     lib.lidar_sim_surrogate_forward.argtypes = [V, V, V, C.c_uint32]
     lib.lidar_sim_surrogate_gradients.argtypes = [V, V, V, C.c_uint32, V, V]
     lib.lidar_sim_surrogate_train_step.argtypes = [V, V, V, C.c_uint32, P(lidar_train_hparams), V]
+    lib.lidar_sim_surrogate_train.argtypes = [V, V, V, C.c_uint64, C.c_uint32, C.c_uint32,
+                                              P(lidar_train_hparams), C.c_double, C.c_uint64, V,
+                                              C.c_uint32]
     lib.lidar_sim_surrogate_set_gate.argtypes = [V, C.c_double, C.c_double]
     lib.lidar_sim_surrogate_features.argtypes = [V, V, V, V]
     lib.lidar_sim_get_stats.argtypes = [V, P(lidar_stats)]
@@ -273,11 +278,12 @@ class LidarSim:
     """One engine handle on one HIP stream."""
 
     def __init__(self, params, stream=None, keep_waveforms: bool = False,
-                 profile: bool = False, autotune: bool = False):
+                 profile: bool = False, autotune: bool = False, deterministic: bool = False):
         self._lib = load()
         self.params = params
         flags = (LIDAR_KEEP_WAVEFORMS if keep_waveforms else 0) | \
-            (LIDAR_PROFILE if profile else 0) | (LIDAR_AUTOTUNE if autotune else 0)
+            (LIDAR_PROFILE if profile else 0) | (LIDAR_AUTOTUNE if autotune else 0) | \
+            (LIDAR_DETERMINISTIC if deterministic else 0)
         keep: list = []
         self._prm = make_params(params, flags, keep)
         self._h = C.c_void_p()
@@ -425,6 +431,17 @@ class LidarSim:
         self._check(self._lib.lidar_sim_surrogate_train_step(
             self._h, x.data_ptr(), labels.data_ptr(), x.shape[0], C.byref(hp),
             int(loss.data_ptr()) if loss is not None else None))
+
+    def train(self, x, labels, steps: int, batch: int = 4096, lr: float = 1e-3,
+              lr_final: float | None = None, weight_decay: float = 1e-4, seed: int = 0,
+              losses=None, log_every: int = 0, beta1=0.9, beta2=0.999, eps=1e-8):
+        """The library's training loop (lidar_sim_surrogate_train); losses: a
+        float32 device tensor of ceil(steps / log_every) entries or None."""
+        hp = lidar_train_hparams(lr, beta1, beta2, eps, weight_decay)
+        self._check(self._lib.lidar_sim_surrogate_train(
+            self._h, x.data_ptr(), labels.data_ptr(), x.shape[0], batch, steps, C.byref(hp),
+            lr / 10 if lr_final is None else lr_final, seed & (2 ** 64 - 1),
+            int(losses.data_ptr()) if losses is not None else None, log_every))
 
     def set_gate(self, c_min: float = 0.5, alpha: float = 0.5):
         self._check(self._lib.lidar_sim_surrogate_set_gate(self._h, float(c_min), float(alpha)))

@@ -116,6 +116,36 @@ struct PrepassArgs {
     RangeTables rt;             // range modes: FP64 direction tables
     float4* rec4;               // CORRECTED: [W4/4][H][4] {depth, nx, ny, nz} (or null)
 };
+// The per-pixel factors of the footprint weight, shared by the pre-pass and
+// the direct gather so that both give the same bits: shade Omega beta
+// cos(theta) / d^2 with beta = g rho / pi and cos(theta) = max(0, -n.v)
+// (rt: cos el, sin el, Omega of the row; cs: cos az, sin az of the column),
+// and the sun shading Omega (rho / pi) max(0, n.s).
+__device__ inline float pixel_shade(float4 rt, float2 cs, float nx, float ny, float nz, float rho,
+                                    float g, float d)
+{
+    const float inv_pi = (float)(1.0 / kPi);
+    const float vx = rt.x * cs.x, vy = rt.x * cs.y, vz = rt.y;
+    const float ct = fmaxf(0.0f, -(nx * vx + ny * vy + nz * vz));
+    return rt.z * (g * rho * inv_pi) * ct / (d * d);
+}
+__device__ inline float pixel_sun(float sx, float sy, float sz, float4 rt, float nx, float ny, float nz,
+                                  float rho)
+{
+    const float inv_pi = (float)(1.0 / kPi);
+    const float ns = fmaxf(0.0f, nx * sx + ny * sy + nz * sz);
+    return rt.z * (rho * inv_pi) * ns;
+}
+
+// A frame's G-buffer planes for the direct gather (the pre-pass inputs).
+struct DirectDev {
+    const float *depth, *refl, *gain, *nx, *ny, *nz;
+    long pitch;
+    const float2* colcs;        // [W] (cos az, sin az) of pixel centres
+    const float4* rowtab;       // [H] (cos el, sin el, Omega, 0) of pixel rows
+    float sun_x, sun_y, sun_z;
+    int pad;
+};
 hipError_t launch_prepass(hipStream_t s, const PrepassArgs& a, bool with_sun);
 // all frames of a batch in one launch (tile_off: [n + 1] prefix of prepass_tiles)
 int prepass_tiles(const PrepassArgs& a);
@@ -143,6 +173,9 @@ struct FrameDev {
     int wave;                   // batches: 1 = the frame's items go to the wave schedule
     int span;                   // 1: pixel keys are {first | last << 16} bin ranges
     int floor_given;            // 1: the floor A_b is in beams[].floor (kappa table)
+    // batches, wave schedule: frames whose beams touch few of their pixels
+    // gather straight from the planes (no pre-pass, pix and sun unused)
+    const DirectDev* direct;    // or null
     // LIDAR_RANGE_CORRECTED (one beam per group): records, FP64 tables, and
     // per beam (cos, sin) of the beam's azimuth and elevation offsets from its
     // pixel centre (radians)
@@ -198,8 +231,9 @@ hipError_t launch_footprint_batch(hipStream_t s, const BatchArgs& a, int grid, b
 hipError_t launch_footprint_batch_wave(hipStream_t s, const BatchArgs& a, int grid, bool sun,
                                        bool keep);
 hipError_t launch_reset_queue(hipStream_t s, int* counter, int n = 1);
-// LIDAR_RANGE_CORRECTED single frame: groups of one beam
-hipError_t launch_footprint_corr(hipStream_t s, const FootprintArgs& a);
+// single frame with groups of one beam: corr = LIDAR_RANGE_CORRECTED bins,
+// det = a histogram slot per wave summed in wave order (LIDAR_DETERMINISTIC)
+hipError_t launch_footprint_one(hipStream_t s, const FootprintArgs& a, bool corr, bool det);
 // per-beam offsets of the beams from their pixel centres (corrected range)
 hipError_t launch_beam_corr(hipStream_t s, RasterDev r, const double* az, const double* el, int B,
                             const lidar_beam_info* beams, double4* bcorr);
@@ -216,7 +250,7 @@ struct SunFloorArgs {
 };
 hipError_t launch_sun_floor(hipStream_t s, const SunFloorArgs& a);
 // whether G histograms of R bins plus the pulse taps fit the LDS budget
-bool footprint_group_fits(int G, int R, int J);
+bool footprint_group_fits(int G, int R, int J, size_t lds_max = 65536);
 
 // ---- range stacking (Alg. 2) with a separable kernel --------------------
 constexpr int kRsMaxHalf = 127;         // half extents M, N of the separable kernel
@@ -317,14 +351,20 @@ struct AdamArgs {
     float decay_factor;         // 1 - lr * weight_decay
     float inv_bc1, inv_bc2;     // 1 / (1 - beta^t)
 };
-hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g);
+// det: no split of K (atomic adds in any order), so the result has a fixed order
+hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g, bool det = false);
 hipError_t launch_bias_gelu(hipStream_t s, float* Z, const float* bias, uint16_t* H, long n, int C);
 hipError_t launch_bias(hipStream_t s, float* Y, const float* bias, long n, int C);
 hipError_t launch_loss(hipStream_t s, const float* Y, const float* lab, long n, uint16_t* dYb,
                        float* loss_sum);
 hipError_t launch_gelu_back(hipStream_t s, const float* dH, const float* Z, uint16_t* dZb, long count);
-hipError_t launch_colsum(hipStream_t s, const uint16_t* D, long n, int C, float* out);
+hipError_t launch_colsum(hipStream_t s, const uint16_t* D, long n, int C, float* out, bool det = false);
 hipError_t launch_zero_f32(hipStream_t s, float* p, long n);
+// minibatch rows perm_e(pos0 + i), i < b, of X [n][1056] BF16 and lab [n][16]
+// (perm_e: the seeded Feistel permutation of epoch e on values of 2 half bits)
+hipError_t launch_gather_rows(hipStream_t s, const uint16_t* X, const float* lab, long n, int half,
+                              unsigned long long seed, unsigned long long epoch, long pos0, int b,
+                              uint16_t* Xb, float* Lb);
 hipError_t launch_adamw(hipStream_t s, float* theta, const float* grad, float* m, float* v,
                         uint16_t* theta_b, long n, const AdamArgs& a);
 hipError_t launch_to_bf16(hipStream_t s, const float* x, uint16_t* y, long n);
@@ -443,6 +483,7 @@ struct SurNet {
     bool t_stale = true;
     long step = 0;
     bool ready = false;
+    bool det = false;                   // LIDAR_DETERMINISTIC: gradients in a fixed order
 };
 struct SurWork {                        // activations of up to `cap` rows
     long cap = 0;

@@ -492,6 +492,47 @@ __device__ __attribute__((always_inline)) inline void gather_group(
     if (lane == 0 && nzb) atomicOr(nzmask, nzb);
 }
 
+// Direct gather of one beam for frames whose beams touch few of their pixels
+// (the batch runs no pre-pass for them): the cells of the clipped footprint
+// window are dealt round the lanes; a cell with K > 0 on a valid pixel takes
+// the pixel's bin (FP64), shade and sun shading from the G-buffer planes with
+// the pre-pass's formulas and adds K * shade into the histogram with an LDS
+// atomic (such frames hold few samples; run sums would rarely pay).
+template <bool SUN>
+__device__ inline void gather_direct(const FrameDev& f, int R, int ub, int vb, int r0, int r1, int q0,
+                                     int q1, float* hist, unsigned* nzmask, int nzs, int lane, float* sacc)
+{
+    const DirectDev d = load_uniform(f.direct);
+    const int nc = q1 - q0 + 1, total = (r1 - r0 + 1) * nc;
+    const size_t khp = (size_t)f.KH + 1;
+    unsigned nzb = 0u;
+    float sun = 0.0f;
+    for (int i = lane; i < total; i += 64) {
+        const int dv = i / nc;
+        const int v = r0 + dv, u = q0 + (i - dv * nc);
+        const int c = u - ub + f.M, n = v - vb + f.N;          // kernel column and row
+        const float kv = f.Kb[(((size_t)(c >> 2) + kBlockPad) * khp + n) * 4 + (c & 3)];
+        if (!(kv > 0.0f)) continue;
+        const long px = (long)v * d.pitch + u;
+        const float dep = d.depth[px];
+        if (!(dep > 0.0f && isfinite(dep))) continue;
+        const double kb = floor((double)dep * f.to_bin);
+        if (!(kb < (double)R)) continue;
+        const float4 rt = d.rowtab[v];
+        const float nx = d.nx[px], ny = d.ny[px], nz = d.nz[px], rho = d.refl[px];
+        const float sh = pixel_shade(rt, d.colcs[u], nx, ny, nz, rho, d.gain[px], dep);
+        const int bin = (int)kb;
+        if (sh != 0.0f) {
+            atomicAdd(hist + bin, kv * sh);
+            nzb |= 1u << (bin >> nzs);
+        }
+        if (SUN) sun += kv * pixel_sun(d.sun_x, d.sun_y, d.sun_z, rt, nx, ny, nz, rho);
+    }
+    if (SUN) *sacc += sun;
+    nzb = wave_or(nzb);
+    if (lane == 0 && nzb) atomicOr(nzmask, nzb);
+}
+
 // Output bins k0 .. k0 + 7 of the pulse convolution, one block of 8 taps:
 // o[q] += w[j] * x[q - j] for the window lo (x[-8 .. -1]) and hi (x[0 .. 7])
 // relative to the block's first tap.
@@ -777,7 +818,7 @@ __device__ inline void wave_sync()
 // each); bit c of *nzmask flags the chunks of 1 << nzs bins (chunk_shift) that
 // the gather wrote, amask the 64-bin chunks of
 // each waveform that hold a bin above the threshold.
-template <int G, bool SUN, bool KEEP, bool CORR = false>
+template <int G, bool SUN, bool KEEP, bool CORR = false, bool DET = false>
 __device__ __attribute__((always_inline)) inline void process_group(const FrameDev& f, const PathDev& p, const int32_t* grp,
                               float* hist, const float* taps, float (*red)[kWaves],
                               unsigned* nzmask, unsigned (*amask)[kMaxBins / kPassBins + 1])
@@ -822,15 +863,18 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
     for (int g = 0; g < G; ++g) sacc[g] = 0.0f;
     double4 bc[1] = {make_double4(1.0, 0.0, 1.0, 0.0)};
     if (CORR && have[0]) bc[0] = load_uniform(f.bcorr + beam[0]);
+    static_assert(!DET || G == 1, "deterministic groups hold one beam");
+    // DET: every wave gathers into a histogram slot of its own
+    float* ghist = DET ? hist + wave * RS : hist;
     if (r0 <= r1 && q0 <= q1) {
         if (f.tile == 64)
-            gather_group<G, 64, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane,
+            gather_group<G, 64, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, ghist, RS, nzmask, nzs, lane,
                                            wave, kWaves, sacc, bc, R);
         else if (f.tile == 16)
-            gather_group<G, 16, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane,
+            gather_group<G, 16, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, ghist, RS, nzmask, nzs, lane,
                                            wave, kWaves, sacc, bc, R);
         else
-            gather_group<G, 4, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, hist, RS, nzmask, nzs, lane,
+            gather_group<G, 4, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, ghist, RS, nzmask, nzs, lane,
                                           wave, kWaves, sacc, bc, R);
     }
     if (SUN) {
@@ -841,6 +885,17 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
         }
     }
     __syncthreads();
+    if constexpr (DET) {
+        // the waves' slots summed into slot 0 in wave order: the waveform no
+        // longer depends on which wave's LDS atomics came first
+        for (int k = tid; k < R; k += kFootprintThreads) {
+            float t = hist[k];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) t += hist[w * RS + k];
+            hist[k] = t;
+        }
+        __syncthreads();
+    }
 
     // pulse convolution in place, 8 consecutive bins per thread and pass with
     // a sliding register window: xi_hat = S_b (varpi * hist) + A_b
@@ -936,7 +991,9 @@ __device__ __attribute__((always_inline)) inline void process_beam_wave(
     const int q0 = (int)max(0L, (long)u - f.M), q1 = (int)min((long)f.W - 1, (long)u + f.M);
     const bool one = true;
     float sacc = 0.0f;
-    if (r0 <= r1 && q0 <= q1) {
+    if (r0 <= r1 && q0 <= q1 && f.direct) {
+        gather_direct<SUN>(f, R, u, v, r0, r1, q0, q1, hist, nzw, nzs, lane, &sacc);
+    } else if (r0 <= r1 && q0 <= q1) {
         if (f.tile == 64)
             gather_group<1, 64, SUN, false>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
         else if (f.tile == 16)
@@ -1018,16 +1075,18 @@ void k_footprint(FootprintArgs a)
                                 amask);
 }
 
-// LIDAR_RANGE_CORRECTED: the single-frame kernel with groups of one beam and
-// per-sample corrected bins.
-template <bool SUN, bool KEEP>
+// The single-frame kernel with groups of one beam: CORR gives every sample
+// its corrected bin (LIDAR_RANGE_CORRECTED); DET (LIDAR_DETERMINISTIC) gives
+// every wave its own histogram slot, the slots summed in a fixed order.
+template <bool SUN, bool KEEP, bool CORR, bool DET>
 __global__ __launch_bounds__(kFootprintThreads)
-void k_footprint_corr(FootprintArgs a)
+void k_footprint_one(FootprintArgs a)
 {
     extern __shared__ float4 lds4[];
+    constexpr int S = DET ? kWaves : 1;             // histogram slots
     const int RS = conv_stride(a.p.R, a.p.J);
     float* hist = (float*)lds4 + conv_pad(a.p.J);
-    float* taps = (float*)lds4 + RS;
+    float* taps = (float*)lds4 + S * RS;
     __shared__ float red[1][kWaves];
     __shared__ unsigned nzmask;
     __shared__ unsigned amask[1][kMaxBins / kPassBins + 1];
@@ -1035,10 +1094,10 @@ void k_footprint_corr(FootprintArgs a)
     const int gi = (slot % kXcds) * a.chunk + slot / kXcds;
     if (gi >= a.n_groups) return;
     const int tid = threadIdx.x;
-    clear_group(lds4, RS / 4, &nzmask, tid);
+    clear_group(lds4, S * RS / 4, &nzmask, tid);
     load_taps(taps, a.p.taps, a.p.J, tid);
     __syncthreads();
-    process_group<1, SUN, KEEP, true>(a.f, a.p, a.groups + gi, hist, taps, red, &nzmask, amask);
+    process_group<1, SUN, KEEP, CORR, DET>(a.f, a.p, a.groups + gi, hist, taps, red, &nzmask, amask);
 }
 
 // Sun floor of every beam from a collector-sensitivity table: A_b = ambient
@@ -1236,9 +1295,9 @@ static hipError_t launch_batch_g(hipStream_t s, const BatchArgs& a, int grid, bo
     return hipGetLastError();
 }
 
-bool footprint_group_fits(int G, int R, int J)
+bool footprint_group_fits(int G, int R, int J, size_t lds_max)
 {
-    return group_lds_bytes(G, R, J) + 1024 <= 65536;     // + static LDS of the kernels
+    return group_lds_bytes(G, R, J) + 1024 <= lds_max;   // + static LDS of the kernels
 }
 
 hipError_t launch_footprint(hipStream_t s, const FootprintArgs& a)
@@ -1289,21 +1348,28 @@ hipError_t launch_footprint_batch_wave(hipStream_t s, const BatchArgs& a, int gr
     return hipGetLastError();
 }
 
-hipError_t launch_footprint_corr(hipStream_t s, const FootprintArgs& a)
+template <bool CORR, bool DET>
+static hipError_t launch_one(hipStream_t s, const FootprintArgs& a)
 {
-    if (a.G != 1) return hipErrorInvalidValue;
     const int grid = kXcds * a.chunk;
-    const size_t lds = group_lds_bytes(1, a.p.R, a.p.J);
+    const size_t lds = group_lds_bytes(DET ? kWaves : 1, a.p.R, a.p.J);
     const bool sun = a.f.sun != nullptr && !a.f.floor_given, keep = a.f.waves != nullptr;
     if (sun && keep)
-        hipLaunchKernelGGL((k_footprint_corr<true, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+        hipLaunchKernelGGL((k_footprint_one<true, true, CORR, DET>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
     else if (sun)
-        hipLaunchKernelGGL((k_footprint_corr<true, false>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+        hipLaunchKernelGGL((k_footprint_one<true, false, CORR, DET>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
     else if (keep)
-        hipLaunchKernelGGL((k_footprint_corr<false, true>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+        hipLaunchKernelGGL((k_footprint_one<false, true, CORR, DET>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
     else
-        hipLaunchKernelGGL((k_footprint_corr<false, false>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
+        hipLaunchKernelGGL((k_footprint_one<false, false, CORR, DET>), dim3(grid), dim3(kFootprintThreads), lds, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_footprint_one(hipStream_t s, const FootprintArgs& a, bool corr, bool det)
+{
+    if (a.G != 1) return hipErrorInvalidValue;
+    if (corr) return det ? launch_one<true, true>(s, a) : launch_one<true, false>(s, a);
+    return det ? launch_one<false, true>(s, a) : launch_one<false, false>(s, a);
 }
 
 hipError_t launch_sun_floor(hipStream_t s, const SunFloorArgs& a)

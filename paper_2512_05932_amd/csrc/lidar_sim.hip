@@ -77,6 +77,7 @@ struct FrameState {
     int n_groups = 0;
     int tile = 64;
     int wave = 0;                      // batches: wave schedule (one wave per group, see footprint.hip)
+    int direct = 0;                    // batches: gathered from the planes without a pre-pass
     // surrogate inputs
     SurGeom geom{};
     bool geom_ok = false;
@@ -97,6 +98,7 @@ struct lidar_sim {
     DevBuf<float> d_taps;
 
     int cus = 256;                     // compute units of the device (queried at create)
+    size_t lds_max = 65536;            // LDS of a workgroup on the device (queried at create)
 
     // single-frame mode
     bool have_pattern = false, have_gbuffer = false, setup_ok = false, have_result = false;
@@ -125,6 +127,7 @@ struct lidar_sim {
     int b_tickets_g = 0;               // tickets 0 .. b_tickets_g - 1: group schedule; the rest: wave
     uint64_t b_wave_items = 0;
     DevBuf<PrepassArgs> b_prep;        // [n_frames] pre-pass arguments of the batch's frames
+    DevBuf<DirectDev> b_direct;        // [n_frames] planes of the frames gathered directly
     DevBuf<int32_t> b_prep_off;        // [n_frames + 1] first pre-pass tile of each frame
     int b_prep_tiles = 0;
     int b_grid = 0;
@@ -138,6 +141,8 @@ struct lidar_sim {
     // surrogate network, inputs, gate and fallback
     SurNet net;
     SurWork work;
+    DevBuf<uint16_t> mb_x;             // minibatch of surrogate_train: inputs [b][1056]
+    DevBuf<float> mb_l;                //   and labels [b][16]
     DevBuf<uint16_t> s_X;
     DevBuf<SurAux> s_aux;
     DevBuf<int32_t> s_groups_fb;
@@ -405,7 +410,7 @@ lidar_status check_params(const lidar_sim_params* p, std::string& why)
     }
     for (double c : p->sun_dir)
         if (!is_fin(c)) { why = "sun_dir must be finite"; return LIDAR_E_INVALID; }
-    if (p->flags & ~(uint32_t)(LIDAR_KEEP_WAVEFORMS | LIDAR_PROFILE | LIDAR_AUTOTUNE)) {
+    if (p->flags & ~(uint32_t)(LIDAR_KEEP_WAVEFORMS | LIDAR_PROFILE | LIDAR_AUTOTUNE | LIDAR_DETERMINISTIC)) {
         why = "unknown flags";
         return LIDAR_E_INVALID;
     }
@@ -995,6 +1000,7 @@ lidar_status upload_frame_table(lidar_sim* h)
         fd[i] = frame_view(h, *h->frames[i], h->b_beams.p + o, h->b_echoes.p + o * E,
                            h->b_counts.p + o, keep ? h->b_waves.p + o * R : nullptr);
         fd[i].wave = h->frames[i]->wave;
+        fd[i].direct = h->frames[i]->direct ? h->b_direct.p + i : nullptr;
     }
     HIP_TRY(h, h->b_frames.ensure(fd.size()), "allocate frame table");
     HIP_TRY(h, hipMemcpyAsync(h->b_frames.p, fd.data(), fd.size() * sizeof(FrameDev),
@@ -1056,7 +1062,10 @@ lidar_status autotune_batch(lidar_sim* h, const std::vector<int2>& items, const 
     hipStream_t s = h->stream;
     LIDAR_TRY(enqueue_batch_prepass(h, s));
     std::map<int, std::vector<size_t>> by_class;
-    for (size_t j = 0; j < items.size(); ++j) by_class[height_class(h->frames[items[j].x]->k.KH)].push_back(j);
+    for (size_t j = 0; j < items.size(); ++j) {
+        const FrameState& fs = *h->frames[items[j].x];
+        if (!fs.direct) by_class[height_class(fs.k.KH)].push_back(j);   // direct frames: wave, no strips
+    }
     DevBuf<int2> d_trial;
     DevBuf<int32_t> d_tickets;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1100,7 +1109,7 @@ lidar_status autotune_batch(lidar_sim* h, const std::vector<int2>& items, const 
             for (int tile : {64, 16, 4}) {
                 if (tile == 64 && cls < 16) continue;   // strips 4x taller than the kernel
                 for (auto& fs : h->frames)
-                    if (height_class(fs->k.KH) == cls) {
+                    if (height_class(fs->k.KH) == cls && !fs->direct) {
                         fs->tile = tile;
                         fs->wave = mode;
                     }
@@ -1129,7 +1138,7 @@ lidar_status autotune_batch(lidar_sim* h, const std::vector<int2>& items, const 
         if (st != LIDAR_OK) break;
         h->tuned[cls] = {best_tile, best_wave};
         for (auto& fs : h->frames)
-            if (height_class(fs->k.KH) == cls) {
+            if (height_class(fs->k.KH) == cls && !fs->direct) {
                 fs->tile = best_tile;
                 fs->wave = best_wave;
             }
@@ -1193,11 +1202,25 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
     std::vector<int32_t> off(n + 1, 0);
     {
         uint64_t tiles = 0;
+        std::vector<DirectDev> dd(n);
         for (uint32_t i = 0; i < n; ++i) {
-            pa[i] = prepass_args(h, *h->frames[i]);
+            FrameState& fs = *h->frames[i];
+            pa[i] = prepass_args(h, fs);
             off[i] = (int32_t)tiles;
-            tiles += (uint64_t)prepass_tiles(pa[i]);
+            // frames whose beams touch few of their pixels (at most one
+            // sample per two pixels) skip the pre-pass: the wave schedule
+            // gathers them from the planes
+            fs.direct = wave_schedule_ok(h) && h->prm.range_mode == LIDAR_RANGE_CENTRE &&
+                        fs.pat.rx.empty() && 2 * fs.samples <= (uint64_t)fs.gb.width * fs.gb.height;
+            if (!fs.direct) tiles += (uint64_t)prepass_tiles(pa[i]);
+            dd[i] = DirectDev{pa[i].depth, pa[i].refl, pa[i].gain, pa[i].nx, pa[i].ny, pa[i].nz,
+                              pa[i].pitch, pa[i].colcs, pa[i].rowtab, pa[i].sun_x, pa[i].sun_y,
+                              pa[i].sun_z, 0};
         }
+        HIP_TRY(h, h->b_direct.ensure(n), "allocate direct-gather table");
+        HIP_TRY(h, hipMemcpyAsync(h->b_direct.p, dd.data(), n * sizeof(DirectDev), hipMemcpyHostToDevice,
+                                  h->stream), "copy direct-gather table");
+        HIP_TRY(h, hipStreamSynchronize(h->stream), "direct-gather table synchronise");
         if (tiles >= (1ull << 31)) return fail(h, LIDAR_E_INVALID, "batch has more than 2^31 pre-pass tiles");
         off[n] = (int32_t)tiles;
         h->b_prep_tiles = (int)tiles;
@@ -1248,6 +1271,8 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
     }
     if (!wave_schedule_ok(h))
         for (auto& fs : h->frames) fs->wave = 0;
+    for (auto& fs : h->frames)
+        if (fs->direct) fs->wave = 1;            // the direct gather runs in the wave schedule
     LIDAR_TRY(upload_frame_table(h));
     h->b_autotuned = false;
     h->b_autotune_ms = 0.0;
@@ -1570,17 +1595,30 @@ lidar_status lidar_sim_create(const lidar_sim_params* params, void* hip_stream, 
     h->prm = *params;
     h->stream = (hipStream_t)hip_stream;
     {
-        int dev = 0, n = 0;
+        int dev = 0, n = 0, l = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
             h->cus = n;
+        if (hipDeviceGetAttribute(&l, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            l >= 65536)
+            h->lds_max = (size_t)l;
     }
     // the handle keeps no pointer into the caller's table
     h->prm.pulse_taps = nullptr;
     double sigma = params->pulse_fwhm_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
     h->J = pulse_half_width(params);
-    h->G = params->range_mode == LIDAR_RANGE_CORRECTED ? 1 : 4;
-    while (h->G > 1 && !footprint_group_fits(h->G, (int)params->n_bins, h->J)) h->G /= 2;
+    const bool det = (params->flags & LIDAR_DETERMINISTIC) != 0;
+    // groups of one beam for corrected ranges (per-beam bins) and for the
+    // deterministic mode (a histogram slot per wave); otherwise the largest
+    // group whose workgroup leaves room for two per CU in the LDS
+    h->G = params->range_mode == LIDAR_RANGE_CORRECTED || det ? 1 : 4;
+    while (h->G > 1 && !footprint_group_fits(h->G, (int)params->n_bins, h->J, h->lds_max / 2)) h->G /= 2;
+    if (det && !footprint_group_fits(kWavesPerGroup, (int)params->n_bins, h->J, h->lds_max)) {
+        g_create_error = "LIDAR_DETERMINISTIC: four histograms of n_bins do not fit the LDS";
+        lidar_sim_destroy(h);
+        return LIDAR_E_UNSUPPORTED;
+    }
+    h->net.det = det;
     hipError_t e = h->d_taps.ensure(2 * h->J + 1);
     if (e == hipSuccess) {
         if (params->pulse_taps) {
@@ -1867,8 +1905,10 @@ lidar_status lidar_sim_simulate_frame(lidar_sim* h, uint32_t mode)
         HIP_TRY(h, hipEventRecord(pp.b, s), "record event");
         HIP_TRY(h, hipEventRecord(fp.a, s), "record event");
     }
-    if (h->prm.range_mode == LIDAR_RANGE_CORRECTED)
-        HIP_TRY(h, launch_footprint_corr(s, fa), "footprint launch");
+    const bool corr = h->prm.range_mode == LIDAR_RANGE_CORRECTED;
+    const bool det = (h->prm.flags & LIDAR_DETERMINISTIC) != 0;
+    if (corr || det)
+        HIP_TRY(h, launch_footprint_one(s, fa, corr, det), "footprint launch");
     else
         HIP_TRY(h, launch_footprint(s, fa), "footprint launch");
     if (prof) {
@@ -1899,6 +1939,8 @@ static lidar_status simulate_surrogate(lidar_sim* h)
 {
     if (!h->net.ready) return fail(h, LIDAR_E_STATE, "surrogate mode without surrogate weights");
     LIDAR_TRY(surrogate_supported(h, "surrogate mode"));
+    if (h->prm.flags & LIDAR_DETERMINISTIC)
+        return fail(h, LIDAR_E_UNSUPPORTED, "LIDAR_DETERMINISTIC covers simulate_frame (plain) only");
     FrameState& fs = h->single;
     const int B = (int)fs.pat.az.size();
     const uint32_t R = h->prm.n_bins, E = h->prm.max_echoes;
@@ -2026,6 +2068,8 @@ lidar_status lidar_sim_simulate_batch(lidar_sim* h, const lidar_gbuffer_desc* fr
     if (n_frames > 65536) return fail(h, LIDAR_E_INVALID, "too many frames (max 65536)");
     if (h->prm.range_mode == LIDAR_RANGE_CORRECTED)
         return fail(h, LIDAR_E_UNSUPPORTED, "range_mode CORRECTED runs in simulate_frame only");
+    if (h->prm.flags & LIDAR_DETERMINISTIC)
+        return fail(h, LIDAR_E_UNSUPPORTED, "LIDAR_DETERMINISTIC covers simulate_frame (plain) only");
     bool same = h->batch_ok && h->batch_gb.size() == n_frames;
     for (uint32_t i = 0; same && i < n_frames; ++i)
         same = same_gbuffer(h->batch_gb[i], frames[i]) && same_pattern(h->batch_pd[i], patterns[i]);
@@ -2092,6 +2136,7 @@ lidar_status lidar_sim_batch_info(lidar_sim* h, lidar_batch_info* out)
     bi.autotuned = h->b_autotuned ? 1u : 0u;
     bi.wave_items = (uint32_t)h->b_wave_items;
     bi.autotune_ms = h->b_autotune_ms;
+    for (const auto& fs : h->frames) bi.direct_frames += fs->direct ? 1u : 0u;
     *out = bi;
     return LIDAR_OK;
 }
@@ -2186,23 +2231,27 @@ lidar_status lidar_sim_surrogate_gradients(lidar_sim* h, const void* x, const fl
     return LIDAR_OK;
 }
 
-lidar_status lidar_sim_surrogate_train_step(lidar_sim* h, const void* x, const float* labels,
-                                            uint32_t n, const lidar_train_hparams* hp, float* loss)
+static bool hparams_ok(const lidar_train_hparams* hp)
 {
-    if (!h) return LIDAR_E_INVALID;
-    if (!hp || !(hp->lr > 0) || !(hp->beta1 >= 0 && hp->beta1 < 1) || !(hp->beta2 >= 0 && hp->beta2 < 1) ||
-        !(hp->eps > 0) || !(hp->weight_decay >= 0) || !is_fin(hp->lr) || !is_fin(hp->eps) ||
-        !is_fin(hp->weight_decay))
-        return fail(h, LIDAR_E_INVALID, "hyper-parameters out of range");
+    return hp && hp->lr > 0 && hp->beta1 >= 0 && hp->beta1 < 1 && hp->beta2 >= 0 && hp->beta2 < 1 &&
+           hp->eps > 0 && hp->weight_decay >= 0 && is_fin(hp->lr) && is_fin(hp->eps) &&
+           is_fin(hp->weight_decay);
+}
+
+// One AdamW step with learning rate lr on the rows (x, labels); the loss
+// before the step into *loss (device, nullable).
+static lidar_status adam_step(lidar_sim* h, const void* x, const float* labels, uint32_t n,
+                              const lidar_train_hparams* hp, double lr, float* loss)
+{
     LIDAR_TRY(sur_grads(h, x, labels, n));
     SurNet& net = h->net;
     const long t = ++net.step;
     AdamArgs a;
-    a.lr = (float)hp->lr;
+    a.lr = (float)lr;
     a.beta1 = (float)hp->beta1;
     a.beta2 = (float)hp->beta2;
     a.eps = (float)hp->eps;
-    a.decay_factor = (float)(1.0 - hp->lr * hp->weight_decay);
+    a.decay_factor = (float)(1.0 - lr * hp->weight_decay);
     a.inv_bc1 = (float)(1.0 / (1.0 - std::pow(hp->beta1, (double)t)));
     a.inv_bc2 = (float)(1.0 / (1.0 - std::pow(hp->beta2, (double)t)));
     HIP_TRY(h, launch_adamw(h->stream, net.theta.p, net.grad.p, net.m.p, net.v.p, net.theta_b.p,
@@ -2211,6 +2260,53 @@ lidar_status lidar_sim_surrogate_train_step(lidar_sim* h, const void* x, const f
     if (loss)
         HIP_TRY(h, hipMemcpyAsync(loss, h->work.loss.p, sizeof(float), hipMemcpyDeviceToDevice,
                                   h->stream), "copy loss");
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sim_surrogate_train_step(lidar_sim* h, const void* x, const float* labels,
+                                            uint32_t n, const lidar_train_hparams* hp, float* loss)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!hparams_ok(hp)) return fail(h, LIDAR_E_INVALID, "hyper-parameters out of range");
+    return adam_step(h, x, labels, n, hp, hp->lr, loss);
+}
+
+lidar_status lidar_sim_surrogate_train(lidar_sim* h, const void* x, const float* labels, uint64_t n,
+                                       uint32_t batch, uint32_t steps, const lidar_train_hparams* hp,
+                                       double lr_final, uint64_t seed, float* losses,
+                                       uint32_t log_every)
+{
+    if (!h) return LIDAR_E_INVALID;
+    if (!x || !labels || n == 0 || batch == 0)
+        return fail(h, LIDAR_E_INVALID, "surrogate_train needs x, labels, n >= 1 and batch >= 1");
+    if (n >= (1ull << 62)) return fail(h, LIDAR_E_INVALID, "surrogate_train: too many rows");
+    if (!hparams_ok(hp)) return fail(h, LIDAR_E_INVALID, "hyper-parameters out of range");
+    if (!(lr_final >= 0.0) || !is_fin(lr_final))
+        return fail(h, LIDAR_E_INVALID, "lr_final must be finite and >= 0");
+    if (losses && log_every == 0) return fail(h, LIDAR_E_INVALID, "losses need log_every >= 1");
+    if (!h->net.ready) return fail(h, LIDAR_E_STATE, "no surrogate weights set");
+    const uint32_t b = (uint32_t)std::min<uint64_t>(batch, n);
+    HIP_TRY(h, h->mb_x.ensure((size_t)b * kSurIn), "allocate minibatch");
+    HIP_TRY(h, h->mb_l.ensure((size_t)b * kSurOut), "allocate minibatch");
+    int half = 1;                                    // 2^(2 half) >= n
+    while ((1ull << (2 * half)) < n) ++half;
+    uint64_t epoch = 0, pos = 0;
+    for (uint32_t t = 0; t < steps; ++t) {
+        if (pos + b > n) {
+            ++epoch;
+            pos = 0;
+        }
+        HIP_TRY(h, launch_gather_rows(h->stream, (const uint16_t*)x, labels, (long)n, half, seed, epoch,
+                                      (long)pos, (int)b, h->mb_x.p, h->mb_l.p), "minibatch launch");
+        pos += b;
+        // linear decay, one rounding per operation (no fused multiply-add)
+        const double f = (double)t / (double)std::max<uint32_t>(1u, steps - 1);
+        const double span = lr_final - hp->lr;
+        const double step_lr = span * f;
+        const double lr = hp->lr + step_lr;
+        float* out = losses && t % log_every == 0 ? losses + t / log_every : nullptr;
+        LIDAR_TRY(adam_step(h, h->mb_x.p, h->mb_l.p, b, hp, lr, out));
+    }
     return LIDAR_OK;
 }
 

@@ -202,17 +202,18 @@ __global__ void k_gelu_back(const float* dH, const float* Z, uint16_t* dZb, long
 }
 
 // db[j] += sum over rows of the BF16 operand dZ[r][j]: a workgroup takes 64
-// columns x 256 rows (lane = column, wave = every 4th row), sums its waves in
-// LDS and adds into the zeroed output
-__global__ __launch_bounds__(256) void k_colsum(const uint16_t* D, long n, int C, float* out)
+// columns x `span` rows (lane = column, wave = every 4th row), sums its waves
+// in LDS and adds into the zeroed output (one workgroup per column block
+// when span covers every row: then the sum has a fixed order)
+__global__ __launch_bounds__(256) void k_colsum(const uint16_t* D, long n, int C, long span, float* out)
 {
     __shared__ float part[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + lane;
-    const long r0 = (long)blockIdx.y * 256;
+    const long r0 = (long)blockIdx.y * span;
     float s = 0.0f;
     if (j < C)
-        for (long r = r0 + wave; r < min(n, r0 + 256); r += 4) s += from_bf16(D[r * C + j]);
+        for (long r = r0 + wave; r < min(n, r0 + span); r += 4) s += from_bf16(D[r * C + j]);
     part[wave][lane] = s;
     __syncthreads();
     if (wave == 0 && j < C) atomicAdd(&out[j], part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
@@ -242,6 +243,51 @@ __global__ void k_adamw(float* theta, const float* grad, float* m, float* v, uin
     t -= a.lr * (mi * a.inv_bc1) / (sqrtf(vi * a.inv_bc2) + a.eps);
     theta[i] = t;
     theta_b[i] = to_bf16(t);
+}
+
+// ---- minibatches of the training loop -------------------------------------
+// Position p of epoch e maps to row perm(p): a four-round Feistel network on
+// k-bit values (k even, 2^k >= n; halves of k/2 bits), cycle-walked until the
+// value is below n (a bijection of 0 .. n-1).  Round r replaces (L, R) by
+// (R, L ^ (mix(key ^ R) & mask)), key = seed ^ ((4 e + r + 1) * golden),
+// mix the SplitMix64 output function.
+__device__ inline unsigned long long mix64(unsigned long long z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline unsigned long long feistel(unsigned long long x, int half, unsigned long long seed,
+                                             unsigned long long epoch)
+{
+    const unsigned long long mask = (1ull << half) - 1ull;
+    unsigned long long L = x >> half, R = x & mask;
+#pragma unroll
+    for (unsigned long long r = 0; r < 4; ++r) {
+        const unsigned long long key = seed ^ ((4ull * epoch + r + 1ull) * 0x9e3779b97f4a7c15ull);
+        const unsigned long long t = L ^ (mix64(key ^ R) & mask);
+        L = R;
+        R = t;
+    }
+    return (L << half) | R;
+}
+
+// Rows perm(pos0 + i), i < b, of X [n][1056] BF16 and lab [n][16] into Xb, Lb:
+// a wave per row (132 + 4 sixteen-byte pieces).
+__global__ __launch_bounds__(256) void k_gather_rows(const uint4* X, const uint4* lab, long n, int half,
+                                                     unsigned long long seed, unsigned long long epoch,
+                                                     long pos0, int b, uint4* Xb, uint4* Lb)
+{
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= b) return;
+    unsigned long long r = (unsigned long long)(pos0 + i);
+    do {
+        r = feistel(r, half, seed, epoch);
+    } while (r >= (unsigned long long)n);
+    constexpr int kRowX = kSurIn * 2 / 16, kRowL = kSurOut * 4 / 16;
+    for (int c = lane; c < kRowX; c += 64) Xb[(long)i * kRowX + c] = X[(long)r * kRowX + c];
+    if (lane < kRowL) Lb[(long)i * kRowL + lane] = lab[(long)r * kRowL + lane];
 }
 
 __global__ void k_to_bf16(const float* x, uint16_t* y, long n)
@@ -454,14 +500,15 @@ hipError_t launch_mlp_infer(hipStream_t s, const InferArgs& a)
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g0)
+hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g0, bool det)
 {
     if (g0.M <= 0 || g0.N <= 0) return hipSuccess;
     GemmArgs g = g0;
     const long tiles = (long)((g.N + kTileN - 1) / kTileN) * ((g.M + kTileM - 1) / kTileM);
     // few output tiles and a long K (weight gradients): split K over the grid
+    // (not when deterministic: the atomic adds of the parts come in any order)
     g.ksplit = 1;
-    while (tiles * g.ksplit < 512 && g.K / (g.ksplit * 2) >= 4 * kTileK) g.ksplit *= 2;
+    while (!det && tiles * g.ksplit < 512 && g.K / (g.ksplit * 2) >= 4 * kTileK) g.ksplit *= 2;
     if (g.ksplit > 1) {
         if (g.ldc != g.N) return hipErrorInvalidValue;   // split K needs a dense C to zero
         const hipError_t e = launch_zero_f32(s, g.C, (long)g.M * g.N);
@@ -502,11 +549,23 @@ hipError_t launch_gelu_back(hipStream_t s, const float* dH, const float* Z, uint
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(hipStream_t s, const uint16_t* D, long n, int C, float* out)
+hipError_t launch_colsum(hipStream_t s, const uint16_t* D, long n, int C, float* out, bool det)
 {
     hipError_t e = launch_zero_f32(s, out, C);
     if (e != hipSuccess || n == 0) return e;
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(C, 64), blocks(n, 256)), dim3(256), 0, s, D, n, C, out);
+    const long span = det ? n : 256;
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(C, 64), (unsigned)((n + span - 1) / span)), dim3(256), 0, s,
+                       D, n, C, span, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(hipStream_t s, const uint16_t* X, const float* lab, long n, int half,
+                              unsigned long long seed, unsigned long long epoch, long pos0, int b,
+                              uint16_t* Xb, float* Lb)
+{
+    if (b <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_rows, dim3((b + 3) / 4), dim3(256), 0, s, (const uint4*)X,
+                       (const uint4*)lab, n, half, seed, epoch, pos0, b, (uint4*)Xb, (uint4*)Lb);
     return hipGetLastError();
 }
 
@@ -556,23 +615,23 @@ hipError_t SurWork::ensure(long n)
 
 // Z = A W (+ bias, GELU) with A [n][k] row-major BF16 and W [k][c] BF16
 static hipError_t dense(hipStream_t s, const uint16_t* A, int k, const uint16_t* W, int c, long n,
-                        float* Z)
+                        float* Z, bool det)
 {
     GemmArgs g{A, k, 1, W, c, 1, Z, c, (int)n, c, k, 1};
-    return launch_gemm_bf16(s, g);
+    return launch_gemm_bf16(s, g, det);
 }
 
 hipError_t sur_forward(hipStream_t s, const SurNet& net, const uint16_t* X, long n, SurWork& w)
 {
     const uint16_t* Wb = net.theta_b.p;
     const float* th = net.theta.p;
-    TRY(dense(s, X, kSurIn, Wb + kSurOffW1, kSurHid, n, w.Z1.p));
+    TRY(dense(s, X, kSurIn, Wb + kSurOffW1, kSurHid, n, w.Z1.p, net.det));
     TRY(launch_bias_gelu(s, w.Z1.p, th + kSurOffB1, w.H1.p, n, kSurHid));
-    TRY(dense(s, w.H1.p, kSurHid, Wb + kSurOffW2, kSurHid, n, w.Z2.p));
+    TRY(dense(s, w.H1.p, kSurHid, Wb + kSurOffW2, kSurHid, n, w.Z2.p, net.det));
     TRY(launch_bias_gelu(s, w.Z2.p, th + kSurOffB2, w.H2.p, n, kSurHid));
-    TRY(dense(s, w.H2.p, kSurHid, Wb + kSurOffW3, kSurHid, n, w.Z3.p));
+    TRY(dense(s, w.H2.p, kSurHid, Wb + kSurOffW3, kSurHid, n, w.Z3.p, net.det));
     TRY(launch_bias_gelu(s, w.Z3.p, th + kSurOffB3, w.H3.p, n, kSurHid));
-    TRY(dense(s, w.H3.p, kSurHid, Wb + kSurOffW4, kSurOut, n, w.Y.p));
+    TRY(dense(s, w.H3.p, kSurHid, Wb + kSurOffW4, kSurOut, n, w.Y.p, net.det));
     TRY(launch_bias(s, w.Y.p, th + kSurOffB4, n, kSurOut));
     return hipSuccess;
 }
@@ -602,19 +661,19 @@ hipError_t sur_infer(hipStream_t s, SurNet& net, const uint16_t* X, long n, floa
 
 // dW = A^T D (A [n][in] BF16 activations, D [n][out] BF16), db = column sums
 static hipError_t weight_grad(hipStream_t s, const uint16_t* A, int in, const uint16_t* D, int out,
-                              long n, float* dW, float* db)
+                              long n, float* dW, float* db, bool det)
 {
     GemmArgs g{A, 1, in, D, out, 1, dW, out, in, out, (int)n, 1};
-    TRY(launch_gemm_bf16(s, g));
-    return launch_colsum(s, D, n, out, db);
+    TRY(launch_gemm_bf16(s, g, det));
+    return launch_colsum(s, D, n, out, db, det);
 }
 
 // dH = D W^T (D [n][out], W [in][out]) in FP32
 static hipError_t input_grad(hipStream_t s, const uint16_t* D, int out, const uint16_t* W, int in,
-                             long n, float* dH)
+                             long n, float* dH, bool det)
 {
     GemmArgs g{D, out, 1, W, 1, out, dH, in, (int)n, in, out, 1};
-    return launch_gemm_bf16(s, g);
+    return launch_gemm_bf16(s, g, det);
 }
 
 hipError_t sur_gradients(hipStream_t s, SurNet& net, const uint16_t* X, const float* lab, long n,
@@ -626,19 +685,19 @@ hipError_t sur_gradients(hipStream_t s, SurNet& net, const uint16_t* X, const fl
     float* g = net.grad.p;
     const long nh = n * kSurHid;
     // layer 4
-    TRY(weight_grad(s, w.H3.p, kSurHid, w.dYb.p, kSurOut, n, g + kSurOffW4, g + kSurOffB4));
-    TRY(input_grad(s, w.dYb.p, kSurOut, Wb + kSurOffW4, kSurHid, n, w.dH.p));
+    TRY(weight_grad(s, w.H3.p, kSurHid, w.dYb.p, kSurOut, n, g + kSurOffW4, g + kSurOffB4, net.det));
+    TRY(input_grad(s, w.dYb.p, kSurOut, Wb + kSurOffW4, kSurHid, n, w.dH.p, net.det));
     TRY(launch_gelu_back(s, w.dH.p, w.Z3.p, w.dZb.p, nh));
     // layer 3
-    TRY(weight_grad(s, w.H2.p, kSurHid, w.dZb.p, kSurHid, n, g + kSurOffW3, g + kSurOffB3));
-    TRY(input_grad(s, w.dZb.p, kSurHid, Wb + kSurOffW3, kSurHid, n, w.dH.p));
+    TRY(weight_grad(s, w.H2.p, kSurHid, w.dZb.p, kSurHid, n, g + kSurOffW3, g + kSurOffB3, net.det));
+    TRY(input_grad(s, w.dZb.p, kSurHid, Wb + kSurOffW3, kSurHid, n, w.dH.p, net.det));
     TRY(launch_gelu_back(s, w.dH.p, w.Z2.p, w.dZb.p, nh));
     // layer 2
-    TRY(weight_grad(s, w.H1.p, kSurHid, w.dZb.p, kSurHid, n, g + kSurOffW2, g + kSurOffB2));
-    TRY(input_grad(s, w.dZb.p, kSurHid, Wb + kSurOffW2, kSurHid, n, w.dH.p));
+    TRY(weight_grad(s, w.H1.p, kSurHid, w.dZb.p, kSurHid, n, g + kSurOffW2, g + kSurOffB2, net.det));
+    TRY(input_grad(s, w.dZb.p, kSurHid, Wb + kSurOffW2, kSurHid, n, w.dH.p, net.det));
     TRY(launch_gelu_back(s, w.dH.p, w.Z1.p, w.dZb.p, nh));
     // layer 1
-    TRY(weight_grad(s, X, kSurIn, w.dZb.p, kSurHid, n, g + kSurOffW1, g + kSurOffB1));
+    TRY(weight_grad(s, X, kSurIn, w.dZb.p, kSurHid, n, g + kSurOffW1, g + kSurOffB1, net.det));
     return hipSuccess;
 }
 

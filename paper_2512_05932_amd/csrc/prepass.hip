@@ -60,7 +60,6 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0)
     __shared__ float tsun[kTileH][kTileW + 1];
     __shared__ float4 tr4[MODE == LIDAR_RANGE_CORRECTED ? kTileH : 1][kTileW + 1];
     const int tx = threadIdx.x % kTileW, ty = threadIdx.x / kTileW;
-    const float inv_pi = (float)(1.0 / kPi);
     // read rows (coalesced along u), shade, stage in LDS
 #pragma unroll
     for (int p = 0; p < kTileH / kRowsPerPass; ++p) {
@@ -79,23 +78,17 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0)
                     pixel_interval(a, u, v, (double)d, (double)nx, (double)ny, (double)nz, &kb, &k1);
                 if (kb < (double)a.R) {
                     bin = (int)kb;
-                    float2 cs = a.colcs[u];
-                    float4 rt = a.rowtab[v];
-                    float vx = rt.x * cs.x, vy = rt.x * cs.y, vz = rt.y;
-                    float ct = fmaxf(0.0f, -(nx * vx + ny * vy + nz * vz));
-                    float rho = a.refl[px];
-                    float g = a.gain[px];
-                    shade = rt.z * (g * rho * inv_pi) * ct / (d * d);
+                    const float2 cs = a.colcs[u];
+                    const float4 rt = a.rowtab[v];
+                    const float rho = a.refl[px];
+                    shade = pixel_shade(rt, cs, nx, ny, nz, rho, a.gain[px], d);
                     if (MODE == LIDAR_RANGE_INTERVAL) {
                         // the interval's bins share the pixel's weight; bins
                         // past the last are dropped
                         shade = shade / (float)(k1 - kb + 1.0);
                         bin |= (int)fmin(k1, (double)(a.R - 1)) << 16;
                     }
-                    if (SUN) {
-                        float ns = fmaxf(0.0f, nx * a.sun_x + ny * a.sun_y + nz * a.sun_z);
-                        sunv = rt.z * (rho * inv_pi) * ns;
-                    }
+                    if (SUN) sunv = pixel_sun(a.sun_x, a.sun_y, a.sun_z, rt, nx, ny, nz, rho);
                     if (MODE == LIDAR_RANGE_CORRECTED) r4 = make_float4(d, nx, ny, nz);
                 }
             }

@@ -2,8 +2,9 @@
 marshalling around the C-ABI: every step runs in the library's kernels).
 
 ``make_dataset`` runs the plain path on frames and collects the network
-inputs and labels on the device; ``train`` runs AdamW steps over shuffled
-minibatches; ``echo_agreement`` compares the echoes of two runs beam by beam.
+inputs and labels on the device; ``train`` calls the library's training loop
+(AdamW steps over shuffled minibatches); ``echo_agreement`` compares the
+echoes of two runs beam by beam.
 """
 from __future__ import annotations
 
@@ -33,41 +34,24 @@ def make_dataset(sim, frames, device="cuda"):
 
 def train(sim, X, L, steps: int, batch: int = 4096, lr: float = 1e-3, weight_decay: float = 1e-4,
           seed: int = 0, lr_final: float | None = None, log_every: int = 0):
-    """AdamW over shuffled minibatches of (X, L); returns the loss of every
-    ``log_every``-th step (device values read at the end).  The learning rate
-    decays linearly to ``lr_final`` (default lr / 10)."""
+    """AdamW over shuffled minibatches of (X, L) by the library's training
+    loop; returns the loss of every ``log_every``-th step (device values read
+    at the end).  The learning rate decays linearly to ``lr_final`` (default
+    lr / 10)."""
     import torch
-    n = X.shape[0]
-    g = torch.Generator(device=X.device)
-    g.manual_seed(seed)
-    lr_final = lr / 10 if lr_final is None else lr_final
-    losses = []
-    loss = torch.zeros(max(1, steps // max(1, log_every) + 1) if log_every else 1,
-                       dtype=torch.float32, device=X.device)
-    perm = torch.randperm(n, generator=g, device=X.device)
-    pos = 0
-    for step in range(steps):
-        if pos + batch > n:
-            perm = torch.randperm(n, generator=g, device=X.device)
-            pos = 0
-        idx = perm[pos:pos + min(batch, n)]
-        pos += batch
-        xb = X.index_select(0, idx)
-        lb = L.index_select(0, idx)
-        f = step / max(1, steps - 1)
-        out = None
-        if log_every and step % log_every == 0:
-            out = loss[step // log_every:step // log_every + 1]
-        sim.train_step(xb, lb, lr=lr + (lr_final - lr) * f, weight_decay=weight_decay, loss=out)
+    losses = None
     if log_every:
-        losses = loss.cpu().numpy().tolist()[:(steps - 1) // log_every + 1]
-    return losses
+        losses = torch.zeros((steps + log_every - 1) // log_every, dtype=torch.float32, device=X.device)
+    sim.train(X, L, steps, batch=batch, lr=lr, lr_final=lr_final, weight_decay=weight_decay,
+              seed=seed, losses=losses, log_every=log_every)
+    return losses.cpu().numpy().tolist() if log_every else []
 
 
-def echo_agreement(ref: dict, got: dict, max_echoes: int = 3) -> dict:
+def echo_agreement(ref: dict, got: dict, max_echoes: int = 3, per_beam: bool = False):
     """Per-beam agreement of two results (read() dicts): the same number of
     echoes among the first ``max_echoes`` and every such echo's peak bin
-    within one bin.  Returns the fraction of agreeing beams and its parts."""
+    within one bin.  Returns the fraction of agreeing beams and its parts, or
+    with ``per_beam`` the boolean agreement of every beam."""
     n_r = np.minimum(ref["n_echoes"], max_echoes)
     n_g = np.minimum(got["n_echoes"], max_echoes)
     same_n = n_r == n_g
@@ -77,5 +61,7 @@ def echo_agreement(ref: dict, got: dict, max_echoes: int = 3) -> dict:
         d = np.abs(ref["echoes"]["bin_peak"][:, e].astype(np.int64) -
                    got["echoes"]["bin_peak"][:, e].astype(np.int64))
         ok &= ~has | (d <= 1)
+    if per_beam:
+        return ok
     return {"within_1_bin": float(ok.mean()), "count_agree": float(same_n.mean()),
             "beams": int(len(ok))}

@@ -602,6 +602,13 @@ def surrogate_frame(seed: int, pattern: str = "gauss", n_lines: int = 64,
                    name=f"surrogate-scan-{n_lines}x{n_cols}-gauss")
 
 
+def core_only_pattern(pattern: Pattern) -> Pattern:
+    """The scanning workload's tabulated pattern without its 1e-4 tails (the
+    same beams and elliptic core), to tell which echoes the tails decide."""
+    return Pattern(PATTERN_TABLE, pattern.beam_az, pattern.beam_el,
+                   table=elliptic_table(tail=0.0), half_deg=(2.0, 2.0))
+
+
 # ----------------------------------------------------------------------------
 # Pinhole renderings (the renderer's side of a z buffer)
 # ----------------------------------------------------------------------------

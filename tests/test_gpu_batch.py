@@ -76,8 +76,9 @@ def test_batch_every_beam_matches_oracle(oracle_mod):
 def test_batch_wave_schedule_single_beam_groups(oracle_mod, sun):
     """Frames whose beam groups all hold a single beam (three 1024x512
     i.i.d. frames, 1000 beams each, footprints far apart) go to the wave
-    schedule; every beam is compared with the oracle, on two replays; with
-    and without the sun term."""
+    schedule and, touching few of their pixels, are gathered straight from
+    the G-buffer planes; every beam is compared with the oracle, on two
+    replays; with and without the sun term."""
     import torch
     import paper_2512_05932_amd as lidar
     frames = [scenes.iid_frame(s) for s in range(3)]
@@ -96,11 +97,41 @@ def test_batch_wave_schedule_single_beam_groups(oracle_mod, sun):
             sim.simulate_batch(batch)
             info = sim.batch_info()
             assert info["wave_items"] == info["n_items"] == 3000
+            # 89 samples per beam over 524288 pixels: gathered from the planes
+            assert info["direct_frames"] == 3
             reps = _check_all(sim, bw, bw.params, oracle_mod, f"wave-iid-3 sun={sun} replay {rep}")
             assert sum(r.echoes_compared for r in reps) > 6000
         if sun:
             floors = np.concatenate([sim.read_batch(i)["beams"]["floor"] for i in range(3)])
             assert np.count_nonzero(floors > params.ambient_const) > 0.8 * floors.size
+    finally:
+        sim.close()
+
+
+def test_batch_wave_schedule_from_pixel_records(oracle_mod):
+    """Single-beam groups on frames that their beams cover densely enough
+    (sigma 0.2 deg: about 314 samples per beam, more than one per two pixels)
+    take the wave schedule over the pre-pass records, not the direct gather."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    frames = []
+    for s in (8, 9):
+        f = scenes.iid_frame(s)
+        pat = replace(f.pattern, sigma_deg=(0.2, 0.2))
+        frames.append(replace(f, pattern=pat))
+    bw = scenes.BatchWorkload("iid-2-wide", frames, frames[0].params)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(bw.params, stream=torch.cuda.current_stream(), keep_waveforms=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        sim.simulate_batch(batch)
+        info = sim.batch_info()
+        print(f"[batch] wide iid: {info}", flush=True)
+        assert info["wave_items"] == info["n_items"] == 2000
+        assert info["direct_frames"] == 0
+        reps = _check_all(sim, bw, bw.params, oracle_mod, "wave-iid-2 records")
+        assert sum(r.echoes_compared for r in reps) > 3000
     finally:
         sim.close()
 
