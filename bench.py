@@ -65,12 +65,14 @@ def parse():
     ap.add_argument("--batch-only", action="store_true",
                     help="only measure the 64-frame batch (for profiler runs)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-scene", choices=("all", "iid", "road"), default="all",
+                    help="restrict the batch to its i.i.d.-surface or its road frames (profiling)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate training and inference measurement")
     ap.add_argument("--surrogate-only", action="store_true")
     ap.add_argument("--sur-train-frames", type=int, default=16)
     ap.add_argument("--sur-steps", type=int, default=3000)
-    ap.add_argument("--sur-eval-frames", type=int, default=4)
+    ap.add_argument("--sur-eval-frames", type=int, default=32)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the "
                          "reference for scaling the HBM byte counters")
@@ -239,6 +241,9 @@ def batch_report(args):
     import paper_2512_05932_amd as lidar
     t0 = time.perf_counter()
     bw = scenes.frame_batch(args.seed)
+    if args.batch_scene != "all":
+        bw = scenes.BatchWorkload(f"{bw.name}-{args.batch_scene}",
+                                  [f for f in bw.frames if f.meta["scene"] == args.batch_scene], bw.params)
     gen_s = time.perf_counter() - t0
     planes = [lidar.upload_gbuffer(f.gbuffer, "cuda:0") for f in bw.frames]
     stream = torch.cuda.current_stream()
@@ -263,6 +268,7 @@ def batch_report(args):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.batch_steps
     st = sim.stats()
+    fixed = sim.batch_info()              # counters of the last replay
     echoes = sum(int(sim.read_batch(i, beams=False)["n_echoes"].sum())
                  for i in range(len(bw.frames)))
     sim.close()
@@ -275,7 +281,8 @@ def batch_report(args):
     gbs = compulsory / (ms * 1e-3) / 1e9
     return {"workload": bw.name, "frames": info["n_frames"], "beams": info["n_beams"],
             "samples": info["samples"], "work_items": info["n_items"],
-            "wave_schedule_items": info["wave_items"],
+            "wave_schedule_items": info["wave_items"], "direct_frames": info["direct_frames"],
+            "fixed_point_beams": fixed["fixed_point_beams"], "fixed_point_redone": fixed["fixed_point_redone"],
             "grid": info["grid"], "ms_per_batch": ms,
             "compulsory_bytes": compulsory, "achieved_GBs": gbs, "peak_GBs": HBM_PEAK_GBS,
             "hbm_frac": gbs / HBM_PEAK_GBS,
@@ -303,11 +310,36 @@ def prepass_bytes(w):
     return 4 * d.size + 20 * int(valid.sum()) + out * W4 * H
 
 
+def touched_pixels(w):
+    """Pixels of a frame inside some beam's truncated Gaussian footprint
+    (host geometry: the containing pixel of each beam and the cells of the
+    3-sigma ellipse on the pixel-offset grid)."""
+    import numpy as np
+    r = w.gbuffer.raster
+    dphi = (r.az_max - r.az_min) / r.width
+    de = (r.el_max - r.el_min) / r.height
+    sx, sy = w.pattern.sigma_deg
+    t = w.pattern.trunc_sigmas
+    M, N = int(t * sx / dphi), int(t * sy / de)
+    m, n = np.meshgrid(np.arange(-M, M + 1), np.arange(-N, N + 1))
+    cell = (m * dphi / sx) ** 2 + (n * de / sy) ** 2 <= t * t
+    mask = np.zeros((r.height, r.width), dtype=bool)
+    u = np.floor((w.pattern.beam_az - r.az_min) / dphi).astype(np.int64)
+    v = np.floor((r.el_max - w.pattern.beam_el) / de).astype(np.int64)
+    mm, nn = m[cell], n[cell]
+    for ub, vb in zip(u, v):
+        uu, vv = ub + mm, vb + nn
+        ok = (uu >= 0) & (uu < r.width) & (vv >= 0) & (vv < r.height)
+        mask[vv[ok], uu[ok]] = True
+    return int(mask.sum())
+
+
 def replayed_small_report(args, n_frames=32, steps=20):
-    """HBM-bound case: n_frames 1024x512 frames of i.i.d. surfaces, each
-    with 1000 Gaussian beams of 89 cells, as one replayed graph.  Each frame's
-    compulsory traffic is its G-buffer read once (24 B per pixel) and its
-    echoes and counts written; the fraction is against 8 TB/s."""
+    """n_frames 1024x512 frames of i.i.d. surfaces, each with 1000 Gaussian
+    beams of 89 cells, as one replayed graph.  Two byte counts against 8 TB/s:
+    every G-buffer read once (24 B per pixel) with the echoes and counts
+    written, and only the pixels some beam's kernel touches (the frames are
+    gathered straight from their planes, so the rest is never read)."""
     import torch
     import scenes
     import paper_2512_05932_amd as lidar
@@ -335,9 +367,13 @@ def replayed_small_report(args, n_frames=32, steps=20):
     E = frames[0].params.max_echoes
     compulsory = sum(24 * f.gbuffer.depth.size + f.pattern.n_beams * (40 * E + 4) for f in frames)
     gbs = compulsory / (ms * 1e-3) / 1e9
+    touched = sum(24 * touched_pixels(f) + f.pattern.n_beams * (40 * E + 4) for f in frames)
     return {"workload": f"{n_frames} x 1024x512 i.i.d. frames (40x25 beams), one graph replay",
             "ms_per_batch": ms, "compulsory_bytes": compulsory, "achieved_GBs": gbs,
             "peak_GBs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
+            "touched_bytes": touched, "touched_GBs": touched / (ms * 1e-3) / 1e9,
+            "touched_frac": touched / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "direct_frames": info["direct_frames"],
             "samples_per_s": info["samples"] / (ms * 1e-3),
             "beams_per_s": info["n_beams"] / (ms * 1e-3), "steps": steps}
 
@@ -457,6 +493,17 @@ def rows_report(args, steps=10):
     return out
 
 
+def clopper_pearson(k, n, conf=0.95):
+    """Exact two-sided binomial interval of a rate k / n."""
+    from scipy.stats import beta
+    if n == 0:
+        return (None, None)
+    a = 1.0 - conf
+    lo = 0.0 if k == 0 else float(beta.ppf(a / 2, k, n - k + 1))
+    hi = 1.0 if k == n else float(beta.ppf(1 - a / 2, k + 1, n - k))
+    return (lo, hi)
+
+
 SUR_FLOPS_PER_BEAM = 2 * (1056 * 256 + 2 * 256 * 256 + 256 * 16)   # the network's products
 BF16_PEAK_TFLOPS = 2500.0
 
@@ -504,7 +551,10 @@ def surrogate_report(args, pattern="gauss", train_frames=None, steps=None, eval_
     del X, L
     sim.set_gate(0.95, 0.5)
     res = []
-    oracle_agree = None
+    oracle_ok, oracle_acc, tail_dec = [], [], []
+    nb = ws[-1].pattern.n_beams
+    xbuf = torch.empty((nb, 1056), dtype=torch.int16, device="cuda")
+    auxbuf = torch.empty((nb, 4), dtype=torch.float32, device="cuda")
     for w, p in zip(ws[train_frames:], planes[train_frames:]):
         sim.set_pattern(w.pattern)
         sim.set_gbuffer(w.gbuffer.raster, p)
@@ -528,19 +578,34 @@ def surrogate_report(args, pattern="gauss", train_frames=None, steps=None, eval_
                     "surrogate_ms": times[lidar.LIDAR_MODE_SURROGATE],
                     "fallback": st["fallback_beams"] / max(1, st["surrogate_beams"]),
                     "within_1_bin_vs_plain": ag["within_1_bin"]})
-        if oracle_agree is None and oracle_sample and not args.no_cpu_baseline:
+        if oracle_sample and not args.no_cpu_baseline:
+            # a sample of every evaluated frame's beams against the FP64
+            # oracle (with the pattern's tails, and for a table pattern also
+            # without them: beams whose echoes change are decided by the tails)
             import oracle
-            idx = np.sort(np.random.default_rng(3).choice(w.pattern.n_beams, oracle_sample,
-                                                          replace=False))
-            ref = oracle.simulate(w.gbuffer, scenes.subset_beams(w, idx).pattern, w.params,
-                                  want_xi=False, want_xi_hat=False)
+            k = -(-oracle_sample // eval_frames)
+            idx = np.sort(np.random.default_rng(w.meta["seed"] + 3).choice(w.pattern.n_beams, k,
+                                                                           replace=False))
+            sub = scenes.subset_beams(w, idx).pattern
+            ref = oracle.simulate(w.gbuffer, sub, w.params, want_xi=False, want_xi_hat=False)
             got = outs[lidar.LIDAR_MODE_SURROGATE]
-            oracle_agree = sur.echo_agreement(
-                {"n_echoes": ref.n_echoes, "echoes": ref.echoes},
-                {"n_echoes": got["n_echoes"][idx], "echoes": got["echoes"][idx]})["within_1_bin"]
+            acc = sur.echo_agreement({"n_echoes": ref.n_echoes, "echoes": ref.echoes},
+                                     {"n_echoes": got["n_echoes"][idx], "echoes": got["echoes"][idx]},
+                                     per_beam=True)
+            # the gate's decisions of the last surrogate frame (aux column 3)
+            sim.surrogate_features(xbuf, aux=auxbuf)
+            accepted = auxbuf[:, 3].cpu().numpy()[idx] > 0.5
+            oracle_ok.append(acc)
+            oracle_acc.append(accepted)
+            if pattern == "table":
+                core = scenes.core_only_pattern(sub)
+                ref0 = oracle.simulate(w.gbuffer, core, w.params, want_xi=False, want_xi_hat=False)
+                tail_dec.append(~sur.echo_agreement({"n_echoes": ref.n_echoes, "echoes": ref.echoes},
+                                                    {"n_echoes": ref0.n_echoes, "echoes": ref0.echoes},
+                                                    per_beam=True))
     # the fused network kernel alone, on the last frame's inputs
     B = ws[-1].pattern.n_beams
-    xin = torch.empty((B, 1056), dtype=torch.int16, device="cuda")
+    xin = xbuf
     yout = torch.empty((B, 16), dtype=torch.float32, device="cuda")
     sim.surrogate_features(xin)
     sim.surrogate_forward(xin, yout)
@@ -556,6 +621,22 @@ def surrogate_report(args, pattern="gauss", train_frames=None, steps=None, eval_
     torch.cuda.empty_cache()
     tp = float(np.mean([r["plain_ms"] for r in res]))
     ts = float(np.mean([r["surrogate_ms"] for r in res]))
+    orc = None
+    if oracle_ok:
+        ok = np.concatenate(oracle_ok)
+        accd = np.concatenate(oracle_acc)
+        lo, hi = clopper_pearson(int(ok.sum()), ok.size)
+        orc = {"beams": int(ok.size), "within_1_bin": float(ok.mean()),
+               "clopper_pearson_95": [lo, hi],
+               "accepted_beams": int(accd.sum()),
+               "within_1_bin_accepted": float(ok[accd].mean()) if accd.any() else None,
+               "clopper_pearson_95_accepted": list(clopper_pearson(int(ok[accd].sum()), int(accd.sum())))
+               if accd.any() else None}
+        if tail_dec:
+            td = np.concatenate(tail_dec)
+            orc["tail_decided"] = float(td.mean())
+            orc["tail_decided_among_fallback"] = float(td[~accd].mean()) if (~accd).any() else None
+            orc["tail_decided_among_accepted"] = float(td[accd].mean()) if accd.any() else None
     mlp_tflops = SUR_FLOPS_PER_BEAM * B / (mlp_ms * 1e-3) / 1e12
     return {"workload": ws[-1].name, "beams_per_frame": B, "pattern": pattern,
             "train_frames": train_frames, "train_rows": n_rows, "train_steps": steps,
@@ -565,7 +646,8 @@ def surrogate_report(args, pattern="gauss", train_frames=None, steps=None, eval_
             "beams_per_s_surrogate": B / (ts * 1e-3), "beams_per_s_plain": B / (tp * 1e-3),
             "fallback": float(np.mean([r["fallback"] for r in res])),
             "within_1_bin_vs_plain": float(np.min([r["within_1_bin_vs_plain"] for r in res])),
-            "within_1_bin_vs_oracle": oracle_agree, "oracle_sample_beams": oracle_sample,
+            "within_1_bin_vs_oracle": orc["within_1_bin"] if orc else None,
+            "oracle": orc, "oracle_sample_beams": orc["beams"] if orc else 0,
             "mlp_ms": mlp_ms, "mlp_tflops": mlp_tflops, "mlp_frac_bf16_peak": mlp_tflops / BF16_PEAK_TFLOPS,
             "generate_s": gen_s, "dataset_s": data_s}
 
@@ -592,10 +674,10 @@ def main():
         print(json.dumps({"batch": batch_report(args)}), flush=True)
         return
     if args.surrogate_only:
-        print(json.dumps({"surrogate": surrogate_report(args),
+        print(json.dumps({"surrogate": surrogate_report(args, oracle_sample=10000),
                           "surrogate_table_pattern": surrogate_report(
-                              args, "table", train_frames=8, steps=1500, eval_frames=1,
-                              oracle_sample=0)}), flush=True)
+                              args, "table", train_frames=8, steps=1500, oracle_sample=10000)}),
+              flush=True)
         return
     if args.rows_only:
         print(json.dumps({"rows": rows_report(args)}), flush=True)
@@ -677,10 +759,9 @@ def main():
     if not args.no_rows:
         rec["rows"] = rows_report(args)
     if not args.no_surrogate:
-        rec["surrogate"] = surrogate_report(args)
+        rec["surrogate"] = surrogate_report(args, oracle_sample=10000)
         rec["surrogate_table_pattern"] = surrogate_report(args, "table", train_frames=8,
-                                                          steps=1500, eval_frames=1,
-                                                          oracle_sample=0)
+                                                          steps=1500, oracle_sample=10000)
     if not args.no_cpu_baseline:
         rec["precision"] = precision_report(w, planes)
         rec["cpu_baseline"] = cpu_baseline(w)

@@ -223,6 +223,13 @@ typedef struct {
                                   without a pre-pass: those on the wave schedule
                                   whose beams hold at most one sample per two pixels
                                   (range_mode CENTRE, no kappa table) */
+    uint32_t fixed_point_beams;    /* last run (synchronises): beams of the wave
+                                      schedule accumulated as 64-bit fixed-point
+                                      integers (range_mode CENTRE, the frame's bins
+                                      spanning at most n_bins / 2) */
+    uint32_t fixed_point_redone;   /* of those, beams run again with FP32 atomics
+                                      because the fixed-point truncation bound
+                                      exceeded 1e-6 of their waveform's maximum */
     uint32_t reserved;
 } lidar_batch_info;
 

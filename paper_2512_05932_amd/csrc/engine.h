@@ -115,6 +115,10 @@ struct PrepassArgs {
                                 // and the shade per bin; CORRECTED also writes rec4
     RangeTables rt;             // range modes: FP64 direction tables
     float4* rec4;               // CORRECTED: [W4/4][H][4] {depth, nx, ny, nz} (or null)
+    // CENTRE batches: per tile (row-major over the frame's tiles) the
+    // statistics {largest shade (FP32 bits), first bin, last bin, 0} of its
+    // valid pixels (or null)
+    int* stats;
 };
 // The per-pixel factors of the footprint weight, shared by the pre-pass and
 // the direct gather so that both give the same bits: shade Omega beta
@@ -151,6 +155,9 @@ hipError_t launch_prepass(hipStream_t s, const PrepassArgs& a, bool with_sun);
 int prepass_tiles(const PrepassArgs& a);
 hipError_t launch_prepass_batch(hipStream_t s, const PrepassArgs* frames, const int* tile_off,
                                 int n, int total_tiles, bool with_sun, int range_mode);
+// frame statistics of n frames ({largest shade bits, first bin, last bin, 0}
+// each) from the tiles' records, then four zero counters
+hipError_t launch_reduce_stats(hipStream_t s, const int* tiles, const int* tile_off, int* stats, int n);
 
 // Kernel table in 4-column blocks, in four copies shifted by one column:
 // copy s, block b, row n holds K(c, n) for the kernel columns
@@ -176,6 +183,11 @@ struct FrameDev {
     // batches, wave schedule: frames whose beams touch few of their pixels
     // gather straight from the planes (no pre-pass, pix and sun unused)
     const DirectDev* direct;    // or null
+    // batches, wave schedule: the pre-pass statistics of the frame (see
+    // PrepassArgs::stats; null: FP32 accumulation) and the kernel's maximum
+    const int* fstats;
+    float kmax;
+    int* fcount;                // {beams in fixed point, beams run again in FP32} (or null)
     // LIDAR_RANGE_CORRECTED (one beam per group): records, FP64 tables, and
     // per beam (cos, sin) of the beam's azimuth and elevation offsets from its
     // pixel centre (radians)

@@ -42,6 +42,7 @@
 // ballots over the flagged chunks, one wave per beam (section II-C, EPW
 // paragraph).
 #include <climits>
+#include <type_traits>
 
 #include "engine.h"
 
@@ -95,6 +96,16 @@ __device__ inline float wave_maxf(float x)
     x = dpp_maxf<0x142, 0xa>(x);
     x = dpp_maxf<0x143, 0xc>(x);
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+__device__ inline unsigned long long wave_max_u64(unsigned long long x)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const unsigned long long y = __shfl_xor(x, m);
+        x = y > x ? y : x;
+    }
+    return x;
 }
 
 __device__ inline int wave_max(int x)
@@ -201,10 +212,33 @@ __device__ inline float group_totals(const float* v)
     return dpp_add<0x140, 0xf>(x);
 }
 
+// Fixed-point accumulation (batches): bin lo + j held as the 64-bit integer
+// j at floats lo + 2j, lo + 2j + 1 of the histogram (lo even, so the
+// integers are 8-byte aligned), in units of 2^-s, s chosen so that no bin
+// can exceed 2^61 units; integer LDS atomics run at the full LDS rate, FP32
+// ones do not (frames whose every pixel starts a run are bound by them).
+// scale = 2^s.
+struct IntAcc {
+    float scale;
+    int lo;
+};
+
+// t >= 0 in units of 2^-s, truncated (t * scale <= 2^61: exact scaling, then
+// the integer part)
+__device__ inline unsigned long long to_units(float t, float scale)
+{
+    return (unsigned long long)(t * scale);
+}
+
 // Add t into the bins of a pixel key: the bin itself, or with range keys
 // (pixel range intervals) every bin first .. last of key = first | last << 16.
-__device__ inline void add_key(float* h, int key, float t, bool rng)
+template <bool IACC = false>
+__device__ inline void add_key(float* h, int key, float t, bool rng, IntAcc ia = IntAcc{})
 {
+    if constexpr (IACC) {
+        atomicAdd((unsigned long long*)(h + ia.lo) + (key - ia.lo), to_units(t, ia.scale));
+        return;
+    }
     if (!rng) {
         atomicAdd(h + key, t);
         return;
@@ -225,9 +259,10 @@ __device__ inline unsigned key_chunks(int key, int nzs, bool rng)
 // `stride` is the distance between the beams' histograms; bit c of the
 // lane's nzb is set for every chunk c (bins c << nzs ..) that receives a sum.
 // rng: the keys are bin ranges (first | last << 16).
-template <int G>
+template <int G, bool IACC = false>
 __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const float* acc,
-                                  float* hist, int stride, unsigned& nzb, int nzs, int lane, bool rng)
+                                  float* hist, int stride, unsigned& nzb, int nzs, int lane, bool rng,
+                                  IntAcc ia = IntAcc{})
 {
     unsigned long long m = fm;
     // lanes sharing a bin are reduced across the wave (a few bins per step)
@@ -243,7 +278,7 @@ __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const
         for (int g = 0; g < G; ++g) v[g] = in ? acc[g] : 0.0f;
         const float t = group_totals<G>(v);
         constexpr int span = 64 / G;
-        if (lane % span == 0 && t != 0.0f) add_key(hist + (lane / span) * stride, key, t, rng);
+        if (lane % span == 0 && t != 0.0f) add_key<IACC>(hist + (lane / span) * stride, key, t, rng, ia);
         nzb |= key_chunks(key, nzs, rng);
         m &= ~same;
     }
@@ -251,7 +286,7 @@ __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const
         nzb |= key_chunks(cur, nzs, rng);
 #pragma unroll
         for (int g = 0; g < G; ++g)
-            if (acc[g] != 0.0f) add_key(hist + g * stride, cur, acc[g], rng);
+            if (acc[g] != 0.0f) add_key<IACC>(hist + g * stride, cur, acc[g], rng, ia);
     }
 }
 
@@ -290,12 +325,13 @@ __device__ inline int corrected_bin(const float4& q, double2 cs, double ce, doub
 // it0 + nw, ...; adds this lane's per-beam sun sums to sacc.  CORR (one
 // beam): every sample's bin is its corrected range's (bc: the beam's
 // offsets, R: bins); the pixel records still decide validity and shade.
-template <int G, int SH, bool SUN, bool CORR>
+template <int G, int SH, bool SUN, bool CORR, bool IACC = false>
 __device__ __attribute__((always_inline)) inline void gather_group(
     const FrameDev& f, const int* ub, const int* vb, const bool* have, int r0, int r1, int q0, int q1,
     float* hist, int stride, unsigned* nzmask, int nzs, int lane, int it0, int nw, float* sacc,
-    const double4* bc = nullptr, int R = 0)
+    const double4* bc = nullptr, int R = 0, IntAcc ia = IntAcc{})
 {
+    static_assert(!IACC || !CORR, "fixed point: centre bins");
     static_assert(!CORR || G == 1, "corrected ranges differ per beam: one beam per group");
     const bool rng = f.span != 0;
     constexpr int P = 64 / SH;                      // column phases per strip
@@ -461,7 +497,7 @@ __device__ __attribute__((always_inline)) inline void gather_group(
                     for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, r[g]);
                     const bool fl = nr && any != 0u;            // sums are >= 0
                     const unsigned long long fm = __ballot(fl);
-                    if (fm) flush_runs<G>(fm, fl, c, r, hist, stride, nzb, nzs, lane, rng);
+                    if (fm) flush_runs<G, IACC>(fm, fl, c, r, hist, stride, nzb, nzs, lane, rng, ia);
 #pragma unroll
                     for (int g = 0; g < G; ++g) r[g] = (nr ? 0.0f : r[g]) + kv[j][g] * sh[j];
                     c = bin[j];
@@ -485,7 +521,7 @@ __device__ __attribute__((always_inline)) inline void gather_group(
         for (int g = 1; g < G; ++g) any |= __builtin_bit_cast(unsigned, acc[g]);
         const bool fl = any != 0u;
         const unsigned long long fm = __ballot(fl);
-        if (fm) flush_runs<G>(fm, fl, cur, acc, hist, stride, nzb, nzs, lane, rng);
+        if (fm) flush_runs<G, IACC>(fm, fl, cur, acc, hist, stride, nzb, nzs, lane, rng, ia);
     }
     // the wave's chunk flags, one LDS atomic per wave
     nzb = wave_or(nzb);
@@ -812,13 +848,66 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// One wave turns a fixed-point histogram of n integers into FP32 bins in
+// place, in chunks of 64 integers: chunk c (integers 64c ..) writes floats
+// lo + 64c .. lo + 64c + 63, which held integers 32c .. 32c + 31, already
+// read by this chunk (before its writes) or an earlier one.  The floats past
+// the bins, which held integers, are zeroed.  Returns the largest bin (every
+// lane).
+__device__ inline float fixed_to_float(float* h, int n, IntAcc ia, int lane)
+{
+    const float inv = 1.0f / ia.scale;                   // a power of two
+    unsigned long long qmax = 0;
+    for (int c = 0; c < n; c += 64) {                    // uniform
+        const int j = c + lane;
+        const unsigned long long q = j < n ? *(const unsigned long long*)(h + ia.lo + 2 * j) : 0ull;
+        qmax = q > qmax ? q : qmax;
+        wave_sync();
+        if (j < n) h[ia.lo + j] = (float)q * inv;
+        wave_sync();
+    }
+    for (int k = ia.lo + n + lane; k < ia.lo + 2 * n; k += 64) h[k] = 0.0f;
+    wave_sync();
+    return (float)wave_max_u64(qmax) * inv;
+}
+
+// The fixed-point unit of beams with at most `samples` cells each: no bin
+// can exceed U = samples x max K x the frame's largest shade, so units of
+// 2^-s with U < 2^(61 - s) cannot overflow.  Returns the number of integers
+// (0: FP32 accumulation: no statistics, the integers would not fit the slot,
+// or U out of range).
+__device__ inline int fixed_unit(const FrameDev& f, float samples, int R, IntAcc* ia)
+{
+    if (!f.fstats) return 0;
+    const int lo = f.fstats[1] & ~1, hi = f.fstats[2];
+    const float U = samples * f.kmax * __int_as_float(f.fstats[0]);
+    int e = 0;
+    (void)frexpf(U, &e);                                 // U < 2^e
+    // the integers of bins lo .. hi end inside the slot's R floats
+    if (!(hi >= lo && lo + 2 * (hi - lo + 1) <= R && U > 0.0f && U < 1e30f && 61 - e <= 120)) return 0;
+    ia->scale = ldexpf(1.0f, 61 - e);
+    ia->lo = lo;
+    return hi - lo + 1;
+}
+
+// Whether the truncation error of a fixed-point histogram (under one unit per
+// flush, at most `samples` flushes into a bin) exceeds 1e-6 of the least the
+// waveform's maximum can be: the pulse's centre tap times the largest bin
+// (S_b applied), or the floor.
+__device__ inline bool fixed_too_coarse(float samples, IntAcc ia, float vmax, float tc, float scale,
+                                        float floor_b)
+{
+    const float err = samples / ia.scale;
+    return !(err * scale <= 1e-6f * (tc * vmax * scale + floor_b));
+}
+
 // The whole group after the histograms were zeroed: gather, floor, pulse,
 // echoes.  All threads of the workgroup call it with the same group.  hist is
 // beam 0's histogram, beam g's starts RS floats further (zero padding around
 // each); bit c of *nzmask flags the chunks of 1 << nzs bins (chunk_shift) that
 // the gather wrote, amask the 64-bin chunks of
 // each waveform that hold a bin above the threshold.
-template <int G, bool SUN, bool KEEP, bool CORR = false, bool DET = false>
+template <int G, bool SUN, bool KEEP, bool CORR = false, bool DET = false, bool FX = false>
 __device__ __attribute__((always_inline)) inline void process_group(const FrameDev& f, const PathDev& p, const int32_t* grp,
                               float* hist, const float* taps, float (*red)[kWaves],
                               unsigned* nzmask, unsigned (*amask)[kMaxBins / kPassBins + 1])
@@ -833,6 +922,7 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
     int beam[G], ub[G], vb[G];
     float scale[G], given[G];
     bool have[G];
+    float samples = 0.0f;                               // the most cells of a member (FX)
     int umin = INT_MAX, umax = INT_MIN, vmin = INT_MAX, vmax = INT_MIN;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -848,6 +938,7 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
             scale[g] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
                 __builtin_bit_cast(int, bi.scale)));
             given[g] = bi.floor;                        // the floor when f.floor_given
+            samples = fmaxf(samples, (float)bi.samples);
             umin = min(umin, ub[g]);
             umax = max(umax, ub[g]);
             vmin = min(vmin, vb[g]);
@@ -864,18 +955,33 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
     double4 bc[1] = {make_double4(1.0, 0.0, 1.0, 0.0)};
     if (CORR && have[0]) bc[0] = load_uniform(f.bcorr + beam[0]);
     static_assert(!DET || G == 1, "deterministic groups hold one beam");
+    static_assert(!FX || (!CORR && !DET && G <= kWaves), "fixed point: centre bins, a wave per member");
     // DET: every wave gathers into a histogram slot of its own
     float* ghist = DET ? hist + wave * RS : hist;
-    if (r0 <= r1 && q0 <= q1) {
+    // FX (batches): the members' histograms in fixed point with one unit
+    IntAcc ia{0.0f, 0};
+    const int span = FX && r0 <= r1 && q0 <= q1 ? fixed_unit(f, samples, R, &ia) : 0;
+    auto gather = [&](auto iacc, float* acc) {
+        constexpr bool I = decltype(iacc)::value;
         if (f.tile == 64)
-            gather_group<G, 64, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, ghist, RS, nzmask, nzs, lane,
-                                           wave, kWaves, sacc, bc, R);
+            gather_group<G, 64, SUN, CORR, I>(f, ub, vb, have, r0, r1, q0, q1, ghist, RS, nzmask, nzs, lane,
+                                              wave, kWaves, acc, bc, R, ia);
         else if (f.tile == 16)
-            gather_group<G, 16, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, ghist, RS, nzmask, nzs, lane,
-                                           wave, kWaves, sacc, bc, R);
+            gather_group<G, 16, SUN, CORR, I>(f, ub, vb, have, r0, r1, q0, q1, ghist, RS, nzmask, nzs, lane,
+                                              wave, kWaves, acc, bc, R, ia);
         else
-            gather_group<G, 4, SUN, CORR>(f, ub, vb, have, r0, r1, q0, q1, ghist, RS, nzmask, nzs, lane,
-                                          wave, kWaves, sacc, bc, R);
+            gather_group<G, 4, SUN, CORR, I>(f, ub, vb, have, r0, r1, q0, q1, ghist, RS, nzmask, nzs, lane,
+                                             wave, kWaves, acc, bc, R, ia);
+    };
+    if (r0 <= r1 && q0 <= q1) {
+        bool done = false;
+        if constexpr (FX) {
+            if (span) {
+                gather(std::true_type{}, sacc);
+                done = true;
+            }
+        }
+        if (!done) gather(std::false_type{}, sacc);
     }
     if (SUN) {
 #pragma unroll
@@ -910,6 +1016,52 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
             fl += f.sun_scale * t;
         }
         floor_b[g] = f.floor_given ? given[g] : fl;
+    }
+    if constexpr (FX) {
+        if (span) {
+            // wave g turns member g's integers into FP32 bins; if any member's
+            // truncation bound is too coarse, the group runs again with FP32
+            // atomics
+            __shared__ int fx_redo;
+            if (tid == 0) fx_redo = 0;
+            __syncthreads();
+            float sc = 0.0f, fb = 0.0f;
+            int mb = -1;                                 // this wave's member
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (g == wave && have[g]) {
+                    sc = scale[g];
+                    fb = floor_b[g];
+                    mb = beam[g];
+                }
+            if (mb >= 0) {
+                const float ns = (float)load_uniform(f.beams + mb).samples;
+                const float vm = fixed_to_float(hist + wave * RS, span, ia, lane);
+                const bool bad = fixed_too_coarse(ns, ia, vm, taps[conv_shift(p.J) + p.J], sc, fb);
+                if (lane == 0) {
+                    if (f.fcount) atomicAdd(f.fcount, 1);
+                    if (bad) fx_redo = 1;
+                }
+            }
+            __syncthreads();
+            if (fx_redo) {
+                if (tid == 0 && f.fcount) {
+                    int n = 0;
+#pragma unroll
+                    for (int g = 0; g < G; ++g) n += have[g] ? 1 : 0;
+                    atomicAdd(f.fcount + 1, n);
+                }
+                float4* h4 = (float4*)(hist - conv_pad(p.J));
+                for (int k = tid; k < G * RS / 4; k += kFootprintThreads) h4[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (tid == 0) *nzmask = 0u;
+                __syncthreads();
+                float s2[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) s2[g] = 0.0f;
+                if (r0 <= r1 && q0 <= q1) gather(std::false_type{}, s2);
+                __syncthreads();
+            }
+        }
     }
     if (p.select >= LIDAR_ECHO_RAW_STRONGEST) {
         // single echo on the raw signal: no pulse convolution
@@ -990,21 +1142,60 @@ __device__ __attribute__((always_inline)) inline void process_beam_wave(
     const int r0 = (int)max(0L, (long)v - f.N), r1 = (int)min((long)f.H - 1, (long)v + f.N);
     const int q0 = (int)max(0L, (long)u - f.M), q1 = (int)min((long)f.W - 1, (long)u + f.M);
     const bool one = true;
-    float sacc = 0.0f;
-    if (r0 <= r1 && q0 <= q1 && f.direct) {
-        gather_direct<SUN>(f, R, u, v, r0, r1, q0, q1, hist, nzw, nzs, lane, &sacc);
-    } else if (r0 <= r1 && q0 <= q1) {
+    const bool win = r0 <= r1 && q0 <= q1;
+    // fixed point when the frame's bins fit the slot as 64-bit integers (not
+    // in the instance for waveforms of up to 512 bins, whose registers are
+    // budgeted for eight waves per SIMD)
+    IntAcc ia{0.0f, 0};
+    const int span = NP > 1 && win ? fixed_unit(f, (float)bi.samples, R, &ia) : 0;
+    auto gather = [&](auto iacc, float* acc) {
+        constexpr bool I = decltype(iacc)::value;
         if (f.tile == 64)
-            gather_group<1, 64, SUN, false>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
+            gather_group<1, 64, SUN, false, I>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1,
+                                               acc, nullptr, 0, ia);
         else if (f.tile == 16)
-            gather_group<1, 16, SUN, false>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
+            gather_group<1, 16, SUN, false, I>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1,
+                                               acc, nullptr, 0, ia);
         else
-            gather_group<1, 4, SUN, false>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1, &sacc);
+            gather_group<1, 4, SUN, false, I>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1,
+                                              acc, nullptr, 0, ia);
+    };
+    float sacc = 0.0f;
+    if (win && f.direct)
+        gather_direct<SUN>(f, R, u, v, r0, r1, q0, q1, hist, nzw, nzs, lane, &sacc);
+    else if (win) {
+        bool done = false;
+        if constexpr (NP > 1) {
+            if (span) {
+                gather(std::true_type{}, &sacc);
+                done = true;
+            }
+        }
+        if (!done) gather(std::false_type{}, &sacc);
     }
     float floor_b = p.ambient;
     if (SUN) floor_b += f.sun_scale * wave_total(sacc);
     if (f.floor_given) floor_b = bi.floor;
     wave_sync();                                         // the histogram is complete
+    if (NP > 1 && span) {
+        // integers to FP32 bins in place; a beam whose truncation bound is
+        // too coarse runs again with FP32 atomics
+        const float vmax = fixed_to_float(hist, span, ia, lane);
+        const bool redo = fixed_too_coarse((float)bi.samples, ia, vmax, taps[conv_shift(p.J) + p.J], scale,
+                                           floor_b);
+        if (lane == 0 && f.fcount) {
+            atomicAdd(f.fcount, 1);
+            if (redo) atomicAdd(f.fcount + 1, 1);
+        }
+        if (redo) {
+            for (int k = ia.lo + lane; k < ia.lo + 2 * span; k += 64) hist[k] = 0.0f;
+            if (lane == 0) *nzw = 0u;
+            wave_sync();
+            float s2 = 0.0f;
+            gather(std::false_type{}, &s2);
+            wave_sync();
+        }
+    }
     const unsigned nzm = __builtin_amdgcn_readfirstlane(*nzw);
     if (p.select >= LIDAR_ECHO_RAW_STRONGEST) {
         detect_raw<KEEP>(f, p, beam, hist, nzm, nzs, scale, floor_b, lane);
@@ -1202,8 +1393,8 @@ void k_footprint_batch(BatchArgs a)
             }
             const int2 it = load_uniform(a.items + item);       // read-only tables
             const FrameDev f = load_uniform(a.frames + it.x);
-            process_group<G, SUN, KEEP>(f, a.p, a.groups + (size_t)it.y * G, hist, taps, red,
-                                        &nzmask, amask);
+            process_group<G, SUN, KEEP, false, false, true>(f, a.p, a.groups + (size_t)it.y * G, hist, taps,
+                                                            red, &nzmask, amask);
             __syncthreads();                             // histograms and item_sh reused
         }
     }

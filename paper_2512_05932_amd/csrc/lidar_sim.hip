@@ -128,6 +128,8 @@ struct lidar_sim {
     uint64_t b_wave_items = 0;
     DevBuf<PrepassArgs> b_prep;        // [n_frames] pre-pass arguments of the batch's frames
     DevBuf<DirectDev> b_direct;        // [n_frames] planes of the frames gathered directly
+    DevBuf<int> b_fstats;              // [n_frames][4] pre-pass statistics (fixed-point accumulation)
+    DevBuf<int> b_tstats;              // [pre-pass tiles][4] the tiles' statistics
     DevBuf<int32_t> b_prep_off;        // [n_frames + 1] first pre-pass tile of each frame
     int b_prep_tiles = 0;
     int b_grid = 0;
@@ -697,7 +699,7 @@ PrepassArgs prepass_args(const lidar_sim* h, FrameState& fs)
 {
     const lidar_gbuffer_desc& g = fs.gb;
     const bool sun = h->prm.sun_irradiance != 0.0;
-    PrepassArgs pa;
+    PrepassArgs pa{};
     pa.depth = g.depth;
     pa.refl = g.reflectance;
     pa.gain = g.retro_gain;
@@ -723,6 +725,7 @@ PrepassArgs prepass_args(const lidar_sim* h, FrameState& fs)
     pa.rt.col_edge = fs.d_cole.p;
     pa.rt.row_edge = fs.d_rowe.p;
     pa.rec4 = h->prm.range_mode == LIDAR_RANGE_CORRECTED ? fs.d_rec4.p : nullptr;
+    pa.stats = nullptr;
     return pa;
 }
 
@@ -757,8 +760,10 @@ lidar_status enqueue_prepass(lidar_sim* h, FrameState& fs, hipStream_t s)
     return LIDAR_OK;
 }
 
+bool fixed_point_ok(const lidar_sim* h);
+
 // The pre-pass of every frame of the batch in one launch (tables built by
-// setup_batch).
+// setup_batch), then the frames' statistics for fixed-point accumulation.
 lidar_status enqueue_batch_prepass(lidar_sim* h, hipStream_t s)
 {
     HIP_TRY(h, launch_prepass_batch(s, h->b_prep.p, h->b_prep_off.p, (int)h->frames.size(),
@@ -768,6 +773,9 @@ lidar_status enqueue_batch_prepass(lidar_sim* h, hipStream_t s)
     // floors of the frames with a kappa table
     for (size_t i = 0; i < h->frames.size(); ++i)
         LIDAR_TRY(enqueue_sun_floor(h, *h->frames[i], h->b_beams.p + h->beam_off[i], s));
+    if (h->b_fstats.p && fixed_point_ok(h))
+        HIP_TRY(h, launch_reduce_stats(s, h->b_tstats.p, h->b_prep_off.p, h->b_fstats.p, (int)h->frames.size()),
+                "statistics launch");
     return LIDAR_OK;
 }
 
@@ -1001,6 +1009,9 @@ lidar_status upload_frame_table(lidar_sim* h)
                            h->b_counts.p + o, keep ? h->b_waves.p + o * R : nullptr);
         fd[i].wave = h->frames[i]->wave;
         fd[i].direct = h->frames[i]->direct ? h->b_direct.p + i : nullptr;
+        fd[i].fstats = !h->frames[i]->direct && fixed_point_ok(h) ? h->b_fstats.p + 4 * i : nullptr;
+        fd[i].kmax = (float)h->frames[i]->kmax;
+        fd[i].fcount = fd[i].fstats ? h->b_fstats.p + 4 * h->frames.size() : nullptr;
     }
     HIP_TRY(h, h->b_frames.ensure(fd.size()), "allocate frame table");
     HIP_TRY(h, hipMemcpyAsync(h->b_frames.p, fd.data(), fd.size() * sizeof(FrameDev),
@@ -1049,6 +1060,13 @@ uint64_t wave_ticket_cost(const lidar_sim* h)
 bool wave_schedule_ok(const lidar_sim* h)
 {
     return h->G == kWavesPerGroup && (int)h->prm.n_bins <= kWaveMaxBins;
+}
+
+// Whether the wave schedule may accumulate in fixed point (pixel keys are
+// single bins: centre ranges).
+bool fixed_point_ok(const lidar_sim* h)
+{
+    return wave_schedule_ok(h) && h->prm.range_mode == LIDAR_RANGE_CENTRE;
 }
 
 // Autotuner: for every kernel-height class of the batch, time the persistent
@@ -1203,15 +1221,20 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
     {
         uint64_t tiles = 0;
         std::vector<DirectDev> dd(n);
+        if (fixed_point_ok(h)) HIP_TRY(h, h->b_fstats.ensure(4 * (size_t)n + 4), "allocate frame statistics");
         for (uint32_t i = 0; i < n; ++i) {
             FrameState& fs = *h->frames[i];
             pa[i] = prepass_args(h, fs);
             off[i] = (int32_t)tiles;
             // frames whose beams touch few of their pixels (at most one
-            // sample per two pixels) skip the pre-pass: the wave schedule
-            // gathers them from the planes
+            // sample per two pixels) with small footprints (at most 256
+            // samples per beam: one wave walks a beam's cells, with an
+            // atomic per cell) skip the pre-pass: the wave schedule gathers
+            // them from the planes
+            const uint64_t nb = fs.pat.az.size();
             fs.direct = wave_schedule_ok(h) && h->prm.range_mode == LIDAR_RANGE_CENTRE &&
-                        fs.pat.rx.empty() && 2 * fs.samples <= (uint64_t)fs.gb.width * fs.gb.height;
+                        fs.pat.rx.empty() && 2 * fs.samples <= (uint64_t)fs.gb.width * fs.gb.height &&
+                        fs.samples <= 256 * nb;
             if (!fs.direct) tiles += (uint64_t)prepass_tiles(pa[i]);
             dd[i] = DirectDev{pa[i].depth, pa[i].refl, pa[i].gain, pa[i].nx, pa[i].ny, pa[i].nz,
                               pa[i].pitch, pa[i].colcs, pa[i].rowtab, pa[i].sun_x, pa[i].sun_y,
@@ -1222,6 +1245,12 @@ lidar_status setup_batch(lidar_sim* h, const lidar_gbuffer_desc* gbs, const lida
                                   h->stream), "copy direct-gather table");
         HIP_TRY(h, hipStreamSynchronize(h->stream), "direct-gather table synchronise");
         if (tiles >= (1ull << 31)) return fail(h, LIDAR_E_INVALID, "batch has more than 2^31 pre-pass tiles");
+        // the tiles' statistics records, frame i's from its first tile on
+        if (fixed_point_ok(h)) {
+            HIP_TRY(h, h->b_tstats.ensure(4 * std::max<uint64_t>(tiles, 1)), "allocate tile statistics");
+            for (uint32_t i = 0; i < n; ++i)
+                if (!h->frames[i]->direct) pa[i].stats = h->b_tstats.p + 4 * (size_t)off[i];
+        }
         off[n] = (int32_t)tiles;
         h->b_prep_tiles = (int)tiles;
         HIP_TRY(h, h->b_prep.ensure(n), "allocate pre-pass table");
@@ -1506,8 +1535,10 @@ lidar_status simulate_static(const lidar_sim_params* prm, const lidar_pattern_de
     if (!(kinfo[1] > 0.0) || !is_fin(kinfo[1]) || !(kinfo[0] > 0.0))
         return fail(h, LIDAR_E_INVALID, "pattern integral over the kernel grid is not positive "
                                         "(kernel narrower than one pixel or all-zero table)");
-    // the frame: pre-pass, then the fused footprint kernel (asynchronous)
-    PrepassArgs pa;
+    // the frame: pre-pass, then the fused footprint kernel (asynchronous);
+    // value-initialised, so the pointers it does not set (statistics,
+    // range tables) are null
+    PrepassArgs pa{};
     pa.depth = gb->depth;
     pa.refl = gb->reflectance;
     pa.gain = gb->retro_gain;
@@ -1530,6 +1561,7 @@ lidar_status simulate_static(const lidar_sim_params* prm, const lidar_pattern_de
     pa.range_mode = LIDAR_RANGE_CENTRE;
     pa.rt = RangeTables{};
     pa.rec4 = nullptr;
+    pa.stats = nullptr;
     HIP_TRY(h, launch_prepass(s, pa, sun), "pre-pass launch");
     FootprintArgs fa;
     FrameDev& f = fa.f;
@@ -2137,6 +2169,14 @@ lidar_status lidar_sim_batch_info(lidar_sim* h, lidar_batch_info* out)
     bi.wave_items = (uint32_t)h->b_wave_items;
     bi.autotune_ms = h->b_autotune_ms;
     for (const auto& fs : h->frames) bi.direct_frames += fs->direct ? 1u : 0u;
+    if (h->b_fstats.p && fixed_point_ok(h)) {
+        int c[2] = {0, 0};
+        HIP_TRY(h, hipMemcpyAsync(c, h->b_fstats.p + 4 * h->frames.size(), sizeof(c), hipMemcpyDeviceToHost,
+                                  h->stream), "copy fixed-point counters");
+        HIP_TRY(h, hipStreamSynchronize(h->stream), "batch info synchronise");
+        bi.fixed_point_beams = (uint32_t)c[0];
+        bi.fixed_point_redone = (uint32_t)c[1];
+    }
     *out = bi;
     return LIDAR_OK;
 }

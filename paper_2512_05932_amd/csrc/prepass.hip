@@ -11,6 +11,8 @@
 // columns of its row with one 16-byte access, and the 64 lanes of a wave
 // (64 consecutive rows) read one contiguous span; the transpose goes through
 // a 64x16 LDS tile.  Columns between W and the next multiple of 4 are sky.
+#include <climits>
+
 #include "engine.h"
 
 namespace lidar {
@@ -54,12 +56,14 @@ __device__ inline void pixel_interval(const PrepassArgs& a, int u, int v, double
 // depth and normal of every pixel), INTERVAL the pixel's first and last bin
 // packed as first | last << 16 with the shade divided by the interval's bins.
 template <bool SUN, int MODE>
-__device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0)
+__device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0, int tile)
 {
     __shared__ int2 trec[kTileH][kTileW + 1];
     __shared__ float tsun[kTileH][kTileW + 1];
     __shared__ float4 tr4[MODE == LIDAR_RANGE_CORRECTED ? kTileH : 1][kTileW + 1];
     const int tx = threadIdx.x % kTileW, ty = threadIdx.x / kTileW;
+    float st_shade = 0.0f;                      // frame statistics of this thread's pixels
+    int st_lo = INT_MAX, st_hi = INT_MIN;
     // read rows (coalesced along u), shade, stage in LDS
 #pragma unroll
     for (int p = 0; p < kTileH / kRowsPerPass; ++p) {
@@ -93,9 +97,43 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0)
                 }
             }
         }
+        if (MODE == LIDAR_RANGE_CENTRE && bin >= 0) {
+            st_shade = fmaxf(st_shade, shade);
+            st_lo = min(st_lo, bin);
+            st_hi = max(st_hi, bin);
+        }
         trec[vl][tx] = make_int2(bin, __float_as_int(shade));
         if (SUN) tsun[vl][tx] = sunv;
         if (MODE == LIDAR_RANGE_CORRECTED) tr4[vl][tx] = r4;
+    }
+    if (MODE == LIDAR_RANGE_CENTRE && a.stats) {
+        // the tile's statistics (wave reductions, the waves combined in LDS)
+        // into its own record; k_reduce_stats combines a frame's records.
+        // Shades are >= 0, so their FP32 bits order as integers.
+        __shared__ int tstat[3][kThreads / 64];
+        int sb = __float_as_int(st_shade);
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            sb = max(sb, __shfl_xor(sb, m));
+            st_lo = min(st_lo, __shfl_xor(st_lo, m));
+            st_hi = max(st_hi, __shfl_xor(st_hi, m));
+        }
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            tstat[0][w] = sb;
+            tstat[1][w] = st_lo;
+            tstat[2][w] = st_hi;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int i = 1; i < kThreads / 64; ++i) {
+                sb = max(sb, tstat[0][i]);
+                st_lo = min(st_lo, tstat[1][i]);
+                st_hi = max(st_hi, tstat[2][i]);
+            }
+            reinterpret_cast<int4*>(a.stats)[tile] = make_int4(sb, st_lo, st_hi, 0);
+        }
     }
     __syncthreads();
     // write kTileW / 4 blocks of 4 columns x kTileH rows, each contiguous in memory
@@ -119,7 +157,7 @@ template <bool SUN, int MODE>
 __global__ __launch_bounds__(kThreads)
 void k_prepass(PrepassArgs a)
 {
-    prepass_tile<SUN, MODE>(a, blockIdx.x * kTileW, blockIdx.y * kTileH);
+    prepass_tile<SUN, MODE>(a, blockIdx.x * kTileW, blockIdx.y * kTileH, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // All frames of a batch in one launch: block t is tile t of the frames' tiles
@@ -138,7 +176,53 @@ void k_prepass_batch(const PrepassArgs* frames, const int* tile_off, int n)
     const PrepassArgs a = frames[lo];
     const int lt = t - tile_off[lo];
     const int tiles_x = (a.W4 + kTileW - 1) / kTileW;
-    prepass_tile<SUN, MODE>(a, (lt % tiles_x) * kTileW, (lt / tiles_x) * kTileH);
+    prepass_tile<SUN, MODE>(a, (lt % tiles_x) * kTileW, (lt / tiles_x) * kTileH, lt);
+}
+
+// Frame statistics from the tiles' records: a workgroup per frame over
+// tiles tile_off[f] .. tile_off[f + 1] - 1 of the batch's records; frames
+// without records (no pre-pass) get {0, INT_MAX, INT_MIN, 0}.  Workgroup 0
+// also zeroes the four counters after the n frames' statistics.
+__global__ __launch_bounds__(256) void k_reduce_stats(const int4* tiles, const int* tile_off, int* stats,
+                                                      int n)
+{
+    __shared__ int red[3][256 / 64];
+    const int f = blockIdx.x, tid = threadIdx.x;
+    int sb = 0, lo = INT_MAX, hi = INT_MIN;
+    for (int t = tile_off[f] + tid; t < tile_off[f + 1]; t += 256) {
+        const int4 r = tiles[t];
+        sb = max(sb, r.x);
+        lo = min(lo, r.y);
+        hi = max(hi, r.z);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        sb = max(sb, __shfl_xor(sb, m));
+        lo = min(lo, __shfl_xor(lo, m));
+        hi = max(hi, __shfl_xor(hi, m));
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = sb;
+        red[1][tid >> 6] = lo;
+        red[2][tid >> 6] = hi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int i = 1; i < 256 / 64; ++i) {
+            sb = max(sb, red[0][i]);
+            lo = min(lo, red[1][i]);
+            hi = max(hi, red[2][i]);
+        }
+        reinterpret_cast<int4*>(stats)[f] = make_int4(sb, lo, hi, 0);
+        if (f == 0) reinterpret_cast<int4*>(stats)[n] = make_int4(0, 0, 0, 0);
+    }
+}
+
+hipError_t launch_reduce_stats(hipStream_t s, const int* tiles, const int* tile_off, int* stats, int n)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_stats, dim3(n), dim3(256), 0, s, (const int4*)tiles, tile_off, stats, n);
+    return hipGetLastError();
 }
 
 int prepass_tiles(const PrepassArgs& a)

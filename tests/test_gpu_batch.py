@@ -114,11 +114,7 @@ def test_batch_wave_schedule_from_pixel_records(oracle_mod):
     take the wave schedule over the pre-pass records, not the direct gather."""
     import torch
     import paper_2512_05932_amd as lidar
-    frames = []
-    for s in (8, 9):
-        f = scenes.iid_frame(s)
-        pat = replace(f.pattern, sigma_deg=(0.2, 0.2))
-        frames.append(replace(f, pattern=pat))
+    frames = _wide_iid((8, 9), scenes.iid_frame(0).params)
     bw = scenes.BatchWorkload("iid-2-wide", frames, frames[0].params)
     planes = _upload(bw)
     sim = lidar.LidarSim(bw.params, stream=torch.cuda.current_stream(), keep_waveforms=True)
@@ -132,6 +128,96 @@ def test_batch_wave_schedule_from_pixel_records(oracle_mod):
         assert info["direct_frames"] == 0
         reps = _check_all(sim, bw, bw.params, oracle_mod, "wave-iid-2 records")
         assert sum(r.echoes_compared for r in reps) > 3000
+    finally:
+        sim.close()
+
+
+def _wide_iid(seeds, params):
+    frames = []
+    for s in seeds:
+        f = scenes.iid_frame(s)
+        frames.append(replace(f, pattern=replace(f.pattern, sigma_deg=(0.2, 0.2)), params=params))
+    return frames
+
+
+def test_batch_fixed_point_accumulation(oracle_mod):
+    """Frames whose bins span at most half the waveform (i.i.d. depths of 5-60
+    m in 2048 bins of 0.5 ns) accumulate their wave-schedule histograms in
+    64-bit fixed point; every beam against the oracle."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    params = scenes.batch_params()
+    frames = _wide_iid((10, 11), params)
+    bw = scenes.BatchWorkload("iid-2-fixed", frames, params)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(params, stream=torch.cuda.current_stream(), keep_waveforms=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        for rep in range(2):
+            sim.simulate_batch(batch)
+            info = sim.batch_info()
+            print(f"[batch] fixed point: {info}", flush=True)
+            assert info["wave_items"] == info["n_items"] == 2000 and info["direct_frames"] == 0
+            assert info["fixed_point_beams"] == 2000
+            reps = _check_all(sim, bw, params, oracle_mod, f"fixed-point replay {rep}")
+            assert sum(r.echoes_compared for r in reps) > 1500
+    finally:
+        sim.close()
+
+
+def test_batch_fixed_point_in_the_group_schedule(oracle_mod):
+    """Beams closer than a kernel width (sigma 0.5 deg) form groups of up to
+    four on the group schedule; their histograms accumulate in fixed point
+    too (one unit per group); every beam against the oracle."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    params = scenes.batch_params()
+    frames = []
+    for s in (13, 14):
+        f = scenes.iid_frame(s)
+        frames.append(replace(f, pattern=replace(f.pattern, sigma_deg=(0.5, 0.5)), params=params))
+    bw = scenes.BatchWorkload("iid-2-groups", frames, params)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(params, stream=torch.cuda.current_stream(), keep_waveforms=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        sim.simulate_batch(batch)
+        info = sim.batch_info()
+        print(f"[batch] groups in fixed point: {info}", flush=True)
+        assert info["wave_items"] == 0 and info["n_items"] < 2000
+        assert info["fixed_point_beams"] == 2000
+        reps = _check_all(sim, bw, params, oracle_mod, "fixed-point groups")
+        assert sum(r.echoes_compared for r in reps) > 1500
+    finally:
+        sim.close()
+
+
+def test_batch_fixed_point_falls_back_where_its_bound_is_loose(oracle_mod):
+    """One pixel 10^15 times brighter than the rest sets a coarse fixed-point
+    unit for every beam of its frame; without ambient light the beams that
+    see only ordinary pixels fail the truncation bound and run again with
+    FP32 atomics, and every beam still matches the oracle."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    params = replace(scenes.batch_params(), ambient_const=0.0)
+    frames = _wide_iid((12,), params)
+    gb = frames[0].gbuffer
+    gain = gb.retro_gain.copy()
+    gain[100, 100] = 1e15
+    frames[0] = replace(frames[0], gbuffer=replace(gb, retro_gain=gain))
+    bw = scenes.BatchWorkload("iid-1-bright", frames, params)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(params, stream=torch.cuda.current_stream(), keep_waveforms=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        sim.simulate_batch(batch)
+        info = sim.batch_info()
+        print(f"[batch] bright pixel: {info}", flush=True)
+        assert info["fixed_point_beams"] == 1000 and info["fixed_point_redone"] > 900
+        _check_all(sim, bw, params, oracle_mod, "fixed-point fallback")
     finally:
         sim.close()
 
