@@ -509,7 +509,7 @@ BF16_PEAK_TFLOPS = 2500.0
 
 
 def surrogate_report(args, pattern="gauss", train_frames=None, steps=None, eval_frames=None,
-                     oracle_sample=2000):
+                     oracle_sample=2000, gate=(0.95, 0.5)):
     """Surrogate on scanning frames (road + boxes, 8192x512, 64 x 2000 = 128k
     beams): the network is trained from scratch by the library's kernels on
     the plain path's echoes of ``train_frames`` frames (AdamW, batch 4096),
@@ -549,7 +549,7 @@ def surrogate_report(args, pattern="gauss", train_frames=None, steps=None, eval_
     train_ms = ev0.elapsed_time(ev1)
     n_rows = int(X.shape[0])
     del X, L
-    sim.set_gate(0.95, 0.5)
+    sim.set_gate(*gate)
     res = []
     oracle_ok, oracle_acc, tail_dec = [], [], []
     nb = ws[-1].pattern.n_beams
@@ -641,7 +641,7 @@ def surrogate_report(args, pattern="gauss", train_frames=None, steps=None, eval_
     return {"workload": ws[-1].name, "beams_per_frame": B, "pattern": pattern,
             "train_frames": train_frames, "train_rows": n_rows, "train_steps": steps,
             "batch": 4096, "train_ms": train_ms, "train_rows_per_s": steps * 4096 / (train_ms * 1e-3),
-            "losses": losses, "gate": {"c_min": 0.95, "alpha": 0.5},
+            "losses": losses, "gate": {"c_min": gate[0], "alpha": gate[1]},
             "eval": res, "plain_ms": tp, "surrogate_ms": ts, "speedup": tp / ts,
             "beams_per_s_surrogate": B / (ts * 1e-3), "beams_per_s_plain": B / (tp * 1e-3),
             "fallback": float(np.mean([r["fallback"] for r in res])),
@@ -675,8 +675,7 @@ def main():
         return
     if args.surrogate_only:
         print(json.dumps({"surrogate": surrogate_report(args, oracle_sample=10000),
-                          "surrogate_table_pattern": surrogate_report(
-                              args, "table", train_frames=8, steps=1500, oracle_sample=10000)}),
+                          "surrogate_table_pattern": surrogate_report(args, "table", oracle_sample=10000)}),
               flush=True)
         return
     if args.rows_only:
@@ -760,8 +759,7 @@ def main():
         rec["rows"] = rows_report(args)
     if not args.no_surrogate:
         rec["surrogate"] = surrogate_report(args, oracle_sample=10000)
-        rec["surrogate_table_pattern"] = surrogate_report(args, "table", train_frames=8,
-                                                          steps=1500, oracle_sample=10000)
+        rec["surrogate_table_pattern"] = surrogate_report(args, "table", oracle_sample=10000)
     if not args.no_cpu_baseline:
         rec["precision"] = precision_report(w, planes)
         rec["cpu_baseline"] = cpu_baseline(w)
