@@ -365,6 +365,13 @@ struct AdamArgs {
 };
 // det: no split of K (atomic adds in any order), so the result has a fixed order
 hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g, bool det = false);
+// Library GEMMs (hipBLASLt) for the training products; blas_gemm returns
+// hipErrorNotSupported for layouts without a unit stride or when the library
+// has no algorithm (the caller then runs launch_gemm_bf16)
+struct BlasCtx;
+BlasCtx* blas_create();                 // null when the library cannot start
+void blas_destroy(BlasCtx* c);
+hipError_t blas_gemm(BlasCtx* c, hipStream_t s, const GemmArgs& g);
 hipError_t launch_bias_gelu(hipStream_t s, float* Z, const float* bias, uint16_t* H, long n, int C);
 hipError_t launch_bias(hipStream_t s, float* Y, const float* bias, long n, int C);
 hipError_t launch_loss(hipStream_t s, const float* Y, const float* lab, long n, uint16_t* dYb,
@@ -501,7 +508,13 @@ struct SurWork {                        // activations of up to `cap` rows
     long cap = 0;
     DevBuf<float> Z1, Z2, Z3, Y, dH, loss;
     DevBuf<uint16_t> H1, H2, H3, dYb, dZb;
+    BlasCtx* blas = nullptr;            // library GEMMs of the training products (or null)
+    bool blas_tried = false;
     hipError_t ensure(long n);
+    SurWork() = default;
+    SurWork(const SurWork&) = delete;
+    SurWork& operator=(const SurWork&) = delete;
+    ~SurWork() { blas_destroy(blas); }
 };
 // Y (w.Y, [n][16] FP32) of the rows X ([n][1056] BF16), keeping the
 // activations for the backward pass

@@ -2237,6 +2237,12 @@ static lidar_status sur_check(lidar_sim* h, const void* x, const void* y, uint32
     if (!x || !y || n == 0) return fail(h, LIDAR_E_INVALID, "surrogate call needs x, outputs and n >= 1");
     if (!h->net.ready) return fail(h, LIDAR_E_STATE, "no surrogate weights set");
     HIP_TRY(h, h->work.ensure((long)n), "allocate surrogate workspace");
+    if (!h->work.blas_tried && !h->net.det) {
+        // the library GEMMs of the training products (the own kernel runs
+        // where the library cannot start)
+        h->work.blas = blas_create();
+        h->work.blas_tried = true;
+    }
     return LIDAR_OK;
 }
 

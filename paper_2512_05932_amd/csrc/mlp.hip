@@ -613,25 +613,37 @@ hipError_t SurWork::ensure(long n)
         if (e_ != hipSuccess) return e_;              \
     } while (0)
 
+// A training product: the library GEMM where it runs (not in the
+// deterministic mode, whose products keep a fixed summation order), else the
+// own MFMA kernel
+static hipError_t gemm(hipStream_t s, const GemmArgs& g, bool det, BlasCtx* blas)
+{
+    if (!det && blas) {
+        const hipError_t e = blas_gemm(blas, s, g);
+        if (e != hipErrorNotSupported) return e;
+    }
+    return launch_gemm_bf16(s, g, det);
+}
+
 // Z = A W (+ bias, GELU) with A [n][k] row-major BF16 and W [k][c] BF16
 static hipError_t dense(hipStream_t s, const uint16_t* A, int k, const uint16_t* W, int c, long n,
-                        float* Z, bool det)
+                        float* Z, bool det, BlasCtx* blas)
 {
     GemmArgs g{A, k, 1, W, c, 1, Z, c, (int)n, c, k, 1};
-    return launch_gemm_bf16(s, g, det);
+    return gemm(s, g, det, blas);
 }
 
 hipError_t sur_forward(hipStream_t s, const SurNet& net, const uint16_t* X, long n, SurWork& w)
 {
     const uint16_t* Wb = net.theta_b.p;
     const float* th = net.theta.p;
-    TRY(dense(s, X, kSurIn, Wb + kSurOffW1, kSurHid, n, w.Z1.p, net.det));
+    TRY(dense(s, X, kSurIn, Wb + kSurOffW1, kSurHid, n, w.Z1.p, net.det, w.blas));
     TRY(launch_bias_gelu(s, w.Z1.p, th + kSurOffB1, w.H1.p, n, kSurHid));
-    TRY(dense(s, w.H1.p, kSurHid, Wb + kSurOffW2, kSurHid, n, w.Z2.p, net.det));
+    TRY(dense(s, w.H1.p, kSurHid, Wb + kSurOffW2, kSurHid, n, w.Z2.p, net.det, w.blas));
     TRY(launch_bias_gelu(s, w.Z2.p, th + kSurOffB2, w.H2.p, n, kSurHid));
-    TRY(dense(s, w.H2.p, kSurHid, Wb + kSurOffW3, kSurHid, n, w.Z3.p, net.det));
+    TRY(dense(s, w.H2.p, kSurHid, Wb + kSurOffW3, kSurHid, n, w.Z3.p, net.det, w.blas));
     TRY(launch_bias_gelu(s, w.Z3.p, th + kSurOffB3, w.H3.p, n, kSurHid));
-    TRY(dense(s, w.H3.p, kSurHid, Wb + kSurOffW4, kSurOut, n, w.Y.p, net.det));
+    TRY(dense(s, w.H3.p, kSurHid, Wb + kSurOffW4, kSurOut, n, w.Y.p, net.det, w.blas));
     TRY(launch_bias(s, w.Y.p, th + kSurOffB4, n, kSurOut));
     return hipSuccess;
 }
@@ -661,19 +673,19 @@ hipError_t sur_infer(hipStream_t s, SurNet& net, const uint16_t* X, long n, floa
 
 // dW = A^T D (A [n][in] BF16 activations, D [n][out] BF16), db = column sums
 static hipError_t weight_grad(hipStream_t s, const uint16_t* A, int in, const uint16_t* D, int out,
-                              long n, float* dW, float* db, bool det)
+                              long n, float* dW, float* db, bool det, BlasCtx* blas)
 {
     GemmArgs g{A, 1, in, D, out, 1, dW, out, in, out, (int)n, 1};
-    TRY(launch_gemm_bf16(s, g, det));
+    TRY(gemm(s, g, det, blas));
     return launch_colsum(s, D, n, out, db, det);
 }
 
 // dH = D W^T (D [n][out], W [in][out]) in FP32
 static hipError_t input_grad(hipStream_t s, const uint16_t* D, int out, const uint16_t* W, int in,
-                             long n, float* dH, bool det)
+                             long n, float* dH, bool det, BlasCtx* blas)
 {
     GemmArgs g{D, out, 1, W, 1, out, dH, in, (int)n, in, out, 1};
-    return launch_gemm_bf16(s, g, det);
+    return gemm(s, g, det, blas);
 }
 
 hipError_t sur_gradients(hipStream_t s, SurNet& net, const uint16_t* X, const float* lab, long n,
@@ -685,19 +697,19 @@ hipError_t sur_gradients(hipStream_t s, SurNet& net, const uint16_t* X, const fl
     float* g = net.grad.p;
     const long nh = n * kSurHid;
     // layer 4
-    TRY(weight_grad(s, w.H3.p, kSurHid, w.dYb.p, kSurOut, n, g + kSurOffW4, g + kSurOffB4, net.det));
-    TRY(input_grad(s, w.dYb.p, kSurOut, Wb + kSurOffW4, kSurHid, n, w.dH.p, net.det));
+    TRY(weight_grad(s, w.H3.p, kSurHid, w.dYb.p, kSurOut, n, g + kSurOffW4, g + kSurOffB4, net.det, w.blas));
+    TRY(input_grad(s, w.dYb.p, kSurOut, Wb + kSurOffW4, kSurHid, n, w.dH.p, net.det, w.blas));
     TRY(launch_gelu_back(s, w.dH.p, w.Z3.p, w.dZb.p, nh));
     // layer 3
-    TRY(weight_grad(s, w.H2.p, kSurHid, w.dZb.p, kSurHid, n, g + kSurOffW3, g + kSurOffB3, net.det));
-    TRY(input_grad(s, w.dZb.p, kSurHid, Wb + kSurOffW3, kSurHid, n, w.dH.p, net.det));
+    TRY(weight_grad(s, w.H2.p, kSurHid, w.dZb.p, kSurHid, n, g + kSurOffW3, g + kSurOffB3, net.det, w.blas));
+    TRY(input_grad(s, w.dZb.p, kSurHid, Wb + kSurOffW3, kSurHid, n, w.dH.p, net.det, w.blas));
     TRY(launch_gelu_back(s, w.dH.p, w.Z2.p, w.dZb.p, nh));
     // layer 2
-    TRY(weight_grad(s, w.H1.p, kSurHid, w.dZb.p, kSurHid, n, g + kSurOffW2, g + kSurOffB2, net.det));
-    TRY(input_grad(s, w.dZb.p, kSurHid, Wb + kSurOffW2, kSurHid, n, w.dH.p, net.det));
+    TRY(weight_grad(s, w.H1.p, kSurHid, w.dZb.p, kSurHid, n, g + kSurOffW2, g + kSurOffB2, net.det, w.blas));
+    TRY(input_grad(s, w.dZb.p, kSurHid, Wb + kSurOffW2, kSurHid, n, w.dH.p, net.det, w.blas));
     TRY(launch_gelu_back(s, w.dH.p, w.Z1.p, w.dZb.p, nh));
     // layer 1
-    TRY(weight_grad(s, X, kSurIn, w.dZb.p, kSurHid, n, g + kSurOffW1, g + kSurOffB1, net.det));
+    TRY(weight_grad(s, X, kSurIn, w.dZb.p, kSurHid, n, g + kSurOffW1, g + kSurOffB1, net.det, w.blas));
     return hipSuccess;
 }
 
