@@ -187,7 +187,6 @@ struct FrameDev {
     // PrepassArgs::stats; null: FP32 accumulation) and the kernel's maximum
     const int* fstats;
     float kmax;
-    int* fcount;                // {beams in fixed point, beams run again in FP32} (or null)
     // LIDAR_RANGE_CORRECTED (one beam per group): records, FP64 tables, and
     // per beam (cos, sin) of the beam's azimuth and elevation offsets from its
     // pixel centre (radians)
@@ -235,6 +234,7 @@ struct BatchArgs {
     // tickets[t + 1]) (non-empty); else one item per queue step
     const int* tickets;         // [n_tickets + 1]
     int n_tickets;
+    int* fcount;                // {beams in fixed point, beams run again in FP32} (or null)
 };
 hipError_t launch_footprint_batch(hipStream_t s, const BatchArgs& a, int grid, bool sun,
                                   bool keep);

@@ -908,7 +908,7 @@ __device__ inline bool fixed_too_coarse(float samples, IntAcc ia, float vmax, fl
 // the gather wrote, amask the 64-bin chunks of
 // each waveform that hold a bin above the threshold.
 template <int G, bool SUN, bool KEEP, bool CORR = false, bool DET = false, bool FX = false>
-__device__ __attribute__((always_inline)) inline void process_group(const FrameDev& f, const PathDev& p, const int32_t* grp,
+__device__ __attribute__((always_inline)) inline int2 process_group(const FrameDev& f, const PathDev& p, const int32_t* grp,
                               float* hist, const float* taps, float (*red)[kWaves],
                               unsigned* nzmask, unsigned (*amask)[kMaxBins / kPassBins + 1])
 {
@@ -923,6 +923,7 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
     float scale[G], given[G];
     bool have[G];
     float samples = 0.0f;                               // the most cells of a member (FX)
+    int2 fxc = make_int2(0, 0);                          // this wave's counts {fixed point, redone} (FX)
     int umin = INT_MAX, umax = INT_MIN, vmin = INT_MAX, vmax = INT_MIN;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -1038,18 +1039,14 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
                 const float ns = (float)load_uniform(f.beams + mb).samples;
                 const float vm = fixed_to_float(hist + wave * RS, span, ia, lane);
                 const bool bad = fixed_too_coarse(ns, ia, vm, taps[conv_shift(p.J) + p.J], sc, fb);
-                if (lane == 0) {
-                    if (f.fcount) atomicAdd(f.fcount, 1);
-                    if (bad) fx_redo = 1;
-                }
+                fxc.x = 1;
+                if (lane == 0 && bad) fx_redo = 1;
             }
             __syncthreads();
             if (fx_redo) {
-                if (tid == 0 && f.fcount) {
-                    int n = 0;
+                if (wave == 0) {
 #pragma unroll
-                    for (int g = 0; g < G; ++g) n += have[g] ? 1 : 0;
-                    atomicAdd(f.fcount + 1, n);
+                    for (int g = 0; g < G; ++g) fxc.y += have[g] ? 1 : 0;
                 }
                 float4* h4 = (float4*)(hist - conv_pad(p.J));
                 for (int k = tid; k < G * RS / 4; k += kFootprintThreads) h4[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -1069,7 +1066,7 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
 #pragma unroll 1
         for (int g = wave; g < G; g += kWaves)
             if (have[g]) detect_raw<KEEP>(f, p, beam[g], hist + g * RS, nzr, nzs, scale[g], floor_b[g], lane);
-        return;
+        return fxc;
     }
     constexpr int kPass = kPassBins;                    // 8 bins per thread and pass
     constexpr int kMaxPass = (kMaxBins + kPass - 1) / kPass;
@@ -1118,6 +1115,7 @@ __device__ __attribute__((always_inline)) inline void process_group(const FrameD
 #pragma unroll 1
     for (int g = wave; g < G; g += kWaves)
         if (have[g]) detect_echoes(f, p, beam[g], hist + g * RS, amask[g], floor_b[g], lane);
+    return fxc;
 }
 
 // One beam by one wave (the wave schedule of a batch), after the wave zeroed
@@ -1128,7 +1126,7 @@ constexpr int kWavePassBins = 512;
 constexpr int kWavePasses = kWaveMaxBins / kWavePassBins;
 
 template <int NP, bool SUN, bool KEEP>
-__device__ __attribute__((always_inline)) inline void process_beam_wave(
+__device__ __attribute__((always_inline)) inline int process_beam_wave(
     const FrameDev& f, const PathDev& p, int beam, float* hist, int RS, const float* taps, unsigned* nzw,
     unsigned* am, int lane)
 {
@@ -1177,16 +1175,14 @@ __device__ __attribute__((always_inline)) inline void process_beam_wave(
     if (SUN) floor_b += f.sun_scale * wave_total(sacc);
     if (f.floor_given) floor_b = bi.floor;
     wave_sync();                                         // the histogram is complete
+    int fx = 0;                                          // 1: fixed point, 3: fixed point run again
     if (NP > 1 && span) {
         // integers to FP32 bins in place; a beam whose truncation bound is
         // too coarse runs again with FP32 atomics
         const float vmax = fixed_to_float(hist, span, ia, lane);
         const bool redo = fixed_too_coarse((float)bi.samples, ia, vmax, taps[conv_shift(p.J) + p.J], scale,
                                            floor_b);
-        if (lane == 0 && f.fcount) {
-            atomicAdd(f.fcount, 1);
-            if (redo) atomicAdd(f.fcount + 1, 1);
-        }
+        fx = __builtin_amdgcn_readfirstlane(redo ? 3 : 1);
         if (redo) {
             for (int k = ia.lo + lane; k < ia.lo + 2 * span; k += 64) hist[k] = 0.0f;
             if (lane == 0) *nzw = 0u;
@@ -1199,7 +1195,7 @@ __device__ __attribute__((always_inline)) inline void process_beam_wave(
     const unsigned nzm = __builtin_amdgcn_readfirstlane(*nzw);
     if (p.select >= LIDAR_ECHO_RAW_STRONGEST) {
         detect_raw<KEEP>(f, p, beam, hist, nzm, nzs, scale, floor_b, lane);
-        return;
+        return fx;
     }
     const int nb = conv_taps(p.J) / 8;
     float o[NP][8];
@@ -1219,6 +1215,7 @@ __device__ __attribute__((always_inline)) inline void process_beam_wave(
     if (lane == 0) am[0] = word;
     wave_sync();
     detect_echoes(f, p, beam, hist, am, floor_b, lane);
+    return fx;
 }
 
 }  // namespace
@@ -1374,6 +1371,12 @@ void k_footprint_batch(BatchArgs a)
     load_taps(taps, a.p.taps, a.p.J, tid);
     const int n_tickets = a.tickets ? a.n_tickets : (a.n_items_dev ? *a.n_items_dev : a.n_items);
     int qc = blockIdx.x % kXcds;                         // this workgroup's XCD (round-robin dispatch)
+    // this wave's counts {beams in fixed point, beams run again}, added to the
+    // batch's counters when the workgroup exits (one atomic per wave, not per
+    // beam: contended atomics on one address cost more than small beams)
+    __shared__ int fxn[kWaves][2];
+    const int wave = tid >> 6;
+    if ((tid & 63) < 2) fxn[wave][tid & 63] = 0;
     for (;;) {
         if (tid == 0) item_sh = a.tickets ? next_ticket(a.next_item, qc, n_tickets) : atomicAdd(a.next_item, 1);
         clear_group(lds4, G * RS / 4, &nzmask, tid);
@@ -1393,10 +1396,18 @@ void k_footprint_batch(BatchArgs a)
             }
             const int2 it = load_uniform(a.items + item);       // read-only tables
             const FrameDev f = load_uniform(a.frames + it.x);
-            process_group<G, SUN, KEEP, false, false, true>(f, a.p, a.groups + (size_t)it.y * G, hist, taps,
-                                                            red, &nzmask, amask);
+            const int2 c = process_group<G, SUN, KEEP, false, false, true>(f, a.p, a.groups + (size_t)it.y * G,
+                                                                           hist, taps, red, &nzmask, amask);
+            if ((tid & 63) == 0) {
+                fxn[wave][0] += c.x;
+                fxn[wave][1] += c.y;
+            }
             __syncthreads();                             // histograms and item_sh reused
         }
+    }
+    if ((tid & 63) == 0 && a.fcount) {
+        if (fxn[wave][0]) atomicAdd(a.fcount, fxn[wave][0]);
+        if (fxn[wave][1]) atomicAdd(a.fcount + 1, fxn[wave][1]);
     }
 }
 
@@ -1424,6 +1435,10 @@ void k_footprint_batch_wave(BatchArgs a)
     float4* slot4 = lds4 + wave * (RS / 4);             // RS is a multiple of 4
     float* hist = (float*)slot4 + conv_pad(a.p.J);
     int qc = blockIdx.x % kXcds;                         // this workgroup's XCD (round-robin dispatch)
+    // this wave's counts {beams in fixed point, beams run again}, added to the
+    // batch's counters when the wave exits
+    __shared__ int fxn[kWaves][2];
+    if (lane < 2) fxn[wave][lane] = 0;
     for (;;) {
         int t = 0;
         if (lane == 0) t = next_ticket(a.next_item, qc, a.n_tickets);
@@ -1441,10 +1456,19 @@ void k_footprint_batch_wave(BatchArgs a)
                 for (int k = lane; k < RS / 4; k += 64) slot4[k] = z;
                 if (lane == 0) nzw[wave] = 0u;
                 wave_sync();
-                process_beam_wave<NP, SUN, KEEP>(f, a.p, beam, hist, RS, taps, &nzw[wave], amask[wave], lane);
+                const int fx = process_beam_wave<NP, SUN, KEEP>(f, a.p, beam, hist, RS, taps, &nzw[wave],
+                                                                amask[wave], lane);
+                if (lane == 0 && fx) {
+                    fxn[wave][0] += 1;
+                    fxn[wave][1] += fx >> 1;
+                }
                 wave_sync();                             // the slot is reused
             }
         }
+    }
+    if (lane == 0 && a.fcount) {
+        if (fxn[wave][0]) atomicAdd(a.fcount, fxn[wave][0]);
+        if (fxn[wave][1]) atomicAdd(a.fcount + 1, fxn[wave][1]);
     }
 }
 

@@ -973,7 +973,7 @@ lidar_status enqueue_batch(lidar_sim* h, hipStream_t s, const int2* items, uint6
     if (n_group < 0) n_group = n_tickets;
     if (with_prepass) LIDAR_TRY(enqueue_batch_prepass(h, s));
     HIP_TRY(h, launch_reset_queue(s, h->b_queue.p, 2 * kQueueInts), "queue reset launch");
-    BatchArgs ba;
+    BatchArgs ba{};
     ba.frames = h->b_frames.p;
     ba.p = path_view(h);
     ba.groups = h->b_groups.p;
@@ -984,6 +984,7 @@ lidar_status enqueue_batch(lidar_sim* h, hipStream_t s, const int2* items, uint6
     ba.n_items_dev = nullptr;
     ba.tickets = tickets;
     ba.n_tickets = n_group;
+    ba.fcount = fixed_point_ok(h) && h->b_fstats.p ? h->b_fstats.p + 4 * h->frames.size() : nullptr;
     const bool sun = h->prm.sun_irradiance != 0.0;
     const bool keep = (h->prm.flags & LIDAR_KEEP_WAVEFORMS) != 0;
     if (!tickets || n_group > 0)
@@ -1011,7 +1012,6 @@ lidar_status upload_frame_table(lidar_sim* h)
         fd[i].direct = h->frames[i]->direct ? h->b_direct.p + i : nullptr;
         fd[i].fstats = !h->frames[i]->direct && fixed_point_ok(h) ? h->b_fstats.p + 4 * i : nullptr;
         fd[i].kmax = (float)h->frames[i]->kmax;
-        fd[i].fcount = fd[i].fstats ? h->b_fstats.p + 4 * h->frames.size() : nullptr;
     }
     HIP_TRY(h, h->b_frames.ensure(fd.size()), "allocate frame table");
     HIP_TRY(h, hipMemcpyAsync(h->b_frames.p, fd.data(), fd.size() * sizeof(FrameDev),
@@ -2036,7 +2036,7 @@ static lidar_status simulate_surrogate(lidar_sim* h)
                                   hipMemcpyHostToDevice, s), "copy frame table");
         HIP_TRY(h, hipStreamSynchronize(s), "frame table synchronise");
     }
-    BatchArgs ba;
+    BatchArgs ba{};
     ba.frames = h->s_frame.p;
     ba.p = path_view(h);
     ba.groups = h->s_groups_fb.p;
