@@ -283,6 +283,7 @@ def batch_report(args):
             "samples": info["samples"], "work_items": info["n_items"],
             "wave_schedule_items": info["wave_items"], "direct_frames": info["direct_frames"],
             "fixed_point_beams": fixed["fixed_point_beams"], "fixed_point_redone": fixed["fixed_point_redone"],
+            "short_run_frames": fixed["short_run_frames"],
             "grid": info["grid"], "ms_per_batch": ms,
             "compulsory_bytes": compulsory, "achieved_GBs": gbs, "peak_GBs": HBM_PEAK_GBS,
             "hbm_frac": gbs / HBM_PEAK_GBS,

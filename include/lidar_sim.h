@@ -223,14 +223,17 @@ typedef struct {
                                   without a pre-pass: those on the wave schedule
                                   whose beams hold at most one sample per two pixels
                                   (range_mode CENTRE, no kappa table) */
-    uint32_t fixed_point_beams;    /* last run (synchronises): beams of the wave
-                                      schedule accumulated as 64-bit fixed-point
-                                      integers (range_mode CENTRE, the frame's bins
-                                      spanning at most n_bins / 2) */
+    uint32_t fixed_point_beams;    /* last run (synchronises): beams accumulated as
+                                      64-bit fixed-point integers (range_mode CENTRE,
+                                      the frame's bins spanning at most n_bins / 2) */
     uint32_t fixed_point_redone;   /* of those, beams run again with FP32 atomics
                                       because the fixed-point truncation bound
                                       exceeded 1e-6 of their waveform's maximum */
-    uint32_t reserved;
+    uint32_t short_run_frames;     /* last run (synchronises): frames whose fixed-point
+                                      gathers add every sample on its own instead of
+                                      summing runs of equal bins, because more than half
+                                      of their valid pixels fall in another bin than
+                                      their left neighbour */
 } lidar_batch_info;
 
 /* Counters of a handle since create or the last reset_stats. */

@@ -105,7 +105,7 @@ class lidar_batch_info(C.Structure):
                 ("n_items", C.c_uint64), ("samples", C.c_uint64), ("grid", C.c_uint32),
                 ("graph", C.c_uint32), ("autotuned", C.c_uint32), ("wave_items", C.c_uint32),
                 ("autotune_ms", C.c_double), ("direct_frames", C.c_uint32), ("fixed_point_beams", C.c_uint32),
-                ("fixed_point_redone", C.c_uint32), ("reserved", C.c_uint32)]
+                ("fixed_point_redone", C.c_uint32), ("short_run_frames", C.c_uint32)]
 
 
 ECHO_DTYPE = np.dtype([("range_m", "<f8"), ("time_ns", "<f8"), ("intensity", "<f4"),

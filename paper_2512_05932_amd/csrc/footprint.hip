@@ -221,6 +221,7 @@ __device__ inline float group_totals(const float* v)
 struct IntAcc {
     float scale;
     int lo;
+    bool each;      // every sample its own add (no run sums): frames whose runs are short
 };
 
 // t >= 0 in units of 2^-s, truncated (t * scale <= 2^61: exact scaling, then
@@ -325,13 +326,17 @@ __device__ inline int corrected_bin(const float4& q, double2 cs, double ce, doub
 // it0 + nw, ...; adds this lane's per-beam sun sums to sacc.  CORR (one
 // beam): every sample's bin is its corrected range's (bc: the beam's
 // offsets, R: bins); the pixel records still decide validity and shade.
-template <int G, int SH, bool SUN, bool CORR, bool IACC = false>
+// EACH (fixed point only): every sample is added on its own, with no run
+// sums, for frames where neighbouring pixels mostly fall in different bins
+// (there the run logic costs more than the adds it saves).
+template <int G, int SH, bool SUN, bool CORR, bool IACC = false, bool EACH = false>
 __device__ __attribute__((always_inline)) inline void gather_group(
     const FrameDev& f, const int* ub, const int* vb, const bool* have, int r0, int r1, int q0, int q1,
     float* hist, int stride, unsigned* nzmask, int nzs, int lane, int it0, int nw, float* sacc,
     const double4* bc = nullptr, int R = 0, IntAcc ia = IntAcc{})
 {
     static_assert(!IACC || !CORR, "fixed point: centre bins");
+    static_assert(!EACH || IACC, "per-sample adds: fixed point");
     static_assert(!CORR || G == 1, "corrected ranges differ per beam: one beam per group");
     const bool rng = f.span != 0;
     constexpr int P = 64 / SH;                      // column phases per strip
@@ -464,6 +469,21 @@ __device__ __attribute__((always_inline)) inline void gather_group(
                         if (bin[j] < 0) sh[j] = 0.0f;
                     }
                 }
+            }
+            if constexpr (EACH) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        const float t = kv[j][g] * sh[j];
+                        if (t != 0.0f) {
+                            add_key<true>(hist + g * stride, bin[j], t, rng, ia);
+                            nzb |= key_chunks(bin[j], nzs, rng);
+                        }
+                        if (SUN) sacc[g] += kv[j][g] * sv[j];
+                    }
+                }
+                return;
             }
             // fast path: accumulate without resets and detect breaks
             const int cur0 = cur;
@@ -887,6 +907,7 @@ __device__ inline int fixed_unit(const FrameDev& f, float samples, int R, IntAcc
     if (!(hi >= lo && lo + 2 * (hi - lo + 1) <= R && U > 0.0f && U < 1e30f && 61 - e <= 120)) return 0;
     ia->scale = ldexpf(1.0f, 61 - e);
     ia->lo = lo;
+    ia->each = f.fstats[3] != 0;
     return hi - lo + 1;
 }
 
@@ -960,8 +981,9 @@ __device__ __attribute__((always_inline)) inline int2 process_group(const FrameD
     // DET: every wave gathers into a histogram slot of its own
     float* ghist = DET ? hist + wave * RS : hist;
     // FX (batches): the members' histograms in fixed point with one unit
-    IntAcc ia{0.0f, 0};
+    IntAcc ia{0.0f, 0, false};
     const int span = FX && r0 <= r1 && q0 <= q1 ? fixed_unit(f, samples, R, &ia) : 0;
+    // (run sums throughout: the per-sample adds are the wave schedule's)
     auto gather = [&](auto iacc, float* acc) {
         constexpr bool I = decltype(iacc)::value;
         if (f.tile == 64)
@@ -1144,19 +1166,19 @@ __device__ __attribute__((always_inline)) inline int process_beam_wave(
     // fixed point when the frame's bins fit the slot as 64-bit integers (not
     // in the instance for waveforms of up to 512 bins, whose registers are
     // budgeted for eight waves per SIMD)
-    IntAcc ia{0.0f, 0};
+    IntAcc ia{0.0f, 0, false};
     const int span = NP > 1 && win ? fixed_unit(f, (float)bi.samples, R, &ia) : 0;
-    auto gather = [&](auto iacc, float* acc) {
-        constexpr bool I = decltype(iacc)::value;
+    auto gather = [&](auto iacc, auto each, float* acc) {
+        constexpr bool I = decltype(iacc)::value, E = decltype(each)::value;
         if (f.tile == 64)
-            gather_group<1, 64, SUN, false, I>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1,
-                                               acc, nullptr, 0, ia);
+            gather_group<1, 64, SUN, false, I, E>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0,
+                                                  1, acc, nullptr, 0, ia);
         else if (f.tile == 16)
-            gather_group<1, 16, SUN, false, I>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1,
-                                               acc, nullptr, 0, ia);
+            gather_group<1, 16, SUN, false, I, E>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0,
+                                                  1, acc, nullptr, 0, ia);
         else
-            gather_group<1, 4, SUN, false, I>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0, 1,
-                                              acc, nullptr, 0, ia);
+            gather_group<1, 4, SUN, false, I, E>(f, &u, &v, &one, r0, r1, q0, q1, hist, RS, nzw, nzs, lane, 0,
+                                                 1, acc, nullptr, 0, ia);
     };
     float sacc = 0.0f;
     if (win && f.direct)
@@ -1165,11 +1187,12 @@ __device__ __attribute__((always_inline)) inline int process_beam_wave(
         bool done = false;
         if constexpr (NP > 1) {
             if (span) {
-                gather(std::true_type{}, &sacc);
+                if (ia.each) gather(std::true_type{}, std::true_type{}, &sacc);
+                else gather(std::true_type{}, std::false_type{}, &sacc);
                 done = true;
             }
         }
-        if (!done) gather(std::false_type{}, &sacc);
+        if (!done) gather(std::false_type{}, std::false_type{}, &sacc);
     }
     float floor_b = p.ambient;
     if (SUN) floor_b += f.sun_scale * wave_total(sacc);
@@ -1188,7 +1211,7 @@ __device__ __attribute__((always_inline)) inline int process_beam_wave(
             if (lane == 0) *nzw = 0u;
             wave_sync();
             float s2 = 0.0f;
-            gather(std::false_type{}, &s2);
+            gather(std::false_type{}, std::false_type{}, &s2);
             wave_sync();
         }
     }

@@ -2170,12 +2170,17 @@ lidar_status lidar_sim_batch_info(lidar_sim* h, lidar_batch_info* out)
     bi.autotune_ms = h->b_autotune_ms;
     for (const auto& fs : h->frames) bi.direct_frames += fs->direct ? 1u : 0u;
     if (h->b_fstats.p && fixed_point_ok(h)) {
-        int c[2] = {0, 0};
-        HIP_TRY(h, hipMemcpyAsync(c, h->b_fstats.p + 4 * h->frames.size(), sizeof(c), hipMemcpyDeviceToHost,
+        // the frames' statistics {shade, first bin, last bin, short runs},
+        // then the counters {fixed-point beams, redone}
+        const size_t n = h->frames.size();
+        std::vector<int> c(4 * n + 2);
+        HIP_TRY(h, hipMemcpyAsync(c.data(), h->b_fstats.p, c.size() * sizeof(int), hipMemcpyDeviceToHost,
                                   h->stream), "copy fixed-point counters");
         HIP_TRY(h, hipStreamSynchronize(h->stream), "batch info synchronise");
-        bi.fixed_point_beams = (uint32_t)c[0];
-        bi.fixed_point_redone = (uint32_t)c[1];
+        bi.fixed_point_beams = (uint32_t)c[4 * n];
+        bi.fixed_point_redone = (uint32_t)c[4 * n + 1];
+        for (size_t i = 0; i < n; ++i)
+            bi.short_run_frames += !h->frames[i]->direct && c[4 * i + 3] ? 1u : 0u;
     }
     *out = bi;
     return LIDAR_OK;

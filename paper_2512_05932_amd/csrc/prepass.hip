@@ -109,20 +109,38 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0, int ti
     if (MODE == LIDAR_RANGE_CENTRE && a.stats) {
         // the tile's statistics (wave reductions, the waves combined in LDS)
         // into its own record; k_reduce_stats combines a frame's records.
-        // Shades are >= 0, so their FP32 bits order as integers.
-        __shared__ int tstat[3][kThreads / 64];
-        int sb = __float_as_int(st_shade);
+        // Shades are >= 0, so their FP32 bits order as integers.  Run
+        // breaks: valid pixels (past the tile's first column) whose bin
+        // differs from their left neighbour's, counted with those pixels
+        // as brk | valid << 16 (at most kTileW x kTileH each).
+        __shared__ int tstat[4][kThreads / 64];
+        __syncthreads();                            // the tile's records are staged
+        int nbrk = 0, nval = 0;
+        if (tx > 0) {
+#pragma unroll
+            for (int p = 0; p < kTileH / kRowsPerPass; ++p) {
+                const int vl = ty + p * kRowsPerPass;
+                const int b = trec[vl][tx].x;
+                if (b >= 0) {
+                    ++nval;
+                    nbrk += trec[vl][tx - 1].x != b ? 1 : 0;
+                }
+            }
+        }
+        int sb = __float_as_int(st_shade), cnt = nbrk | nval << 16;
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) {
             sb = max(sb, __shfl_xor(sb, m));
             st_lo = min(st_lo, __shfl_xor(st_lo, m));
             st_hi = max(st_hi, __shfl_xor(st_hi, m));
+            cnt += __shfl_xor(cnt, m);
         }
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
             tstat[0][w] = sb;
             tstat[1][w] = st_lo;
             tstat[2][w] = st_hi;
+            tstat[3][w] = cnt;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -131,8 +149,9 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0, int ti
                 sb = max(sb, tstat[0][i]);
                 st_lo = min(st_lo, tstat[1][i]);
                 st_hi = max(st_hi, tstat[2][i]);
+                cnt += tstat[3][i];
             }
-            reinterpret_cast<int4*>(a.stats)[tile] = make_int4(sb, st_lo, st_hi, 0);
+            reinterpret_cast<int4*>(a.stats)[tile] = make_int4(sb, st_lo, st_hi, cnt);
         }
     }
     __syncthreads();
@@ -180,31 +199,42 @@ void k_prepass_batch(const PrepassArgs* frames, const int* tile_off, int n)
 }
 
 // Frame statistics from the tiles' records: a workgroup per frame over
-// tiles tile_off[f] .. tile_off[f + 1] - 1 of the batch's records; frames
-// without records (no pre-pass) get {0, INT_MAX, INT_MIN, 0}.  Workgroup 0
-// also zeroes the four counters after the n frames' statistics.
+// tiles tile_off[f] .. tile_off[f + 1] - 1 of the batch's records, as
+// {largest shade bits, first bin, last bin, short runs}; short runs = 1 when
+// more than half of the valid pixels with a left neighbour in their tile
+// fall in another bin than it.  Frames without records (no pre-pass) get
+// {0, INT_MAX, INT_MIN, 0}.  Workgroup 0 also zeroes the four counters after
+// the n frames' statistics.
 __global__ __launch_bounds__(256) void k_reduce_stats(const int4* tiles, const int* tile_off, int* stats,
                                                       int n)
 {
     __shared__ int red[3][256 / 64];
+    __shared__ long long redc[2][256 / 64];
     const int f = blockIdx.x, tid = threadIdx.x;
     int sb = 0, lo = INT_MAX, hi = INT_MIN;
+    long long brk = 0, val = 0;
     for (int t = tile_off[f] + tid; t < tile_off[f + 1]; t += 256) {
         const int4 r = tiles[t];
         sb = max(sb, r.x);
         lo = min(lo, r.y);
         hi = max(hi, r.z);
+        brk += r.w & 0xffff;
+        val += r.w >> 16;
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
         sb = max(sb, __shfl_xor(sb, m));
         lo = min(lo, __shfl_xor(lo, m));
         hi = max(hi, __shfl_xor(hi, m));
+        brk += __shfl_xor(brk, m);
+        val += __shfl_xor(val, m);
     }
     if ((tid & 63) == 0) {
         red[0][tid >> 6] = sb;
         red[1][tid >> 6] = lo;
         red[2][tid >> 6] = hi;
+        redc[0][tid >> 6] = brk;
+        redc[1][tid >> 6] = val;
     }
     __syncthreads();
     if (tid == 0) {
@@ -212,8 +242,10 @@ __global__ __launch_bounds__(256) void k_reduce_stats(const int4* tiles, const i
             sb = max(sb, red[0][i]);
             lo = min(lo, red[1][i]);
             hi = max(hi, red[2][i]);
+            brk += redc[0][i];
+            val += redc[1][i];
         }
-        reinterpret_cast<int4*>(stats)[f] = make_int4(sb, lo, hi, 0);
+        reinterpret_cast<int4*>(stats)[f] = make_int4(sb, lo, hi, 2 * brk > val ? 1 : 0);
         if (f == 0) reinterpret_cast<int4*>(stats)[n] = make_int4(0, 0, 0, 0);
     }
 }

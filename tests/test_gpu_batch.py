@@ -160,8 +160,42 @@ def test_batch_fixed_point_accumulation(oracle_mod):
             print(f"[batch] fixed point: {info}", flush=True)
             assert info["wave_items"] == info["n_items"] == 2000 and info["direct_frames"] == 0
             assert info["fixed_point_beams"] == 2000
+            # i.i.d. depths: nearly every pixel starts a new bin, so both
+            # frames add every sample on its own
+            assert info["short_run_frames"] == 2
             reps = _check_all(sim, bw, params, oracle_mod, f"fixed-point replay {rep}")
             assert sum(r.echoes_compared for r in reps) > 1500
+    finally:
+        sim.close()
+
+
+def test_batch_fixed_point_run_sums_on_smooth_frames(oracle_mod):
+    """A frame whose depth changes slowly along its rows (a tilted plane with
+    a gentle ripple: about 0.16 bins per pixel) keeps summing runs of equal
+    bins in fixed point; every beam against the oracle."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    params = scenes.batch_params()
+    frames = _wide_iid((15,), params)
+    gb = frames[0].gbuffer
+    H, W = gb.depth.shape
+    u = np.arange(W)[None, :]
+    v = np.arange(H)[:, None]
+    depth = (20.0 + 10.0 * v / H + 2.0 * np.sin(2.0 * np.pi * u / W)).astype(np.float32)
+    frames[0] = replace(frames[0], gbuffer=replace(gb, depth=depth))
+    bw = scenes.BatchWorkload("smooth-1-fixed", frames, params)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(params, stream=torch.cuda.current_stream(), keep_waveforms=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        sim.simulate_batch(batch)
+        info = sim.batch_info()
+        print(f"[batch] smooth frame: {info}", flush=True)
+        assert info["wave_items"] == info["n_items"] == 1000
+        assert info["fixed_point_beams"] == 1000 and info["short_run_frames"] == 0
+        reps = _check_all(sim, bw, params, oracle_mod, "fixed-point run sums")
+        assert sum(r.echoes_compared for r in reps) > 500
     finally:
         sim.close()
 
