@@ -15,6 +15,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxBins = 8000;                  // one padded waveform + taps fit the LDS of a group
 constexpr int kMaxTaps = 257;
 constexpr int kPassBins = 2048;                 // bins per convolution pass (8 per thread)
+constexpr int kMaxEchoes = 8;                   // largest max_echoes
 constexpr int kWaveMaxBins = 2048;              // longest waveform of the wave schedule (in registers)
 // chunks of 1 << chunk_shift(R) bins (at least 64) cover R bins with at most 32
 __host__ __device__ constexpr int chunk_shift(int R)

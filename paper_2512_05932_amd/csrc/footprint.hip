@@ -651,10 +651,10 @@ __device__ inline void conv_out8(const float* h, const float* taps, const PathDe
 }
 
 // xi_hat = scale * o8 + floor into bins k0 .. k0 + 7 (below R) of h, in place,
-// and of the kept waveform; bit q of the result: bin k0 + q is above T.
+// of the kept waveform and of o8; bit q of the result: bin k0 + q is above T.
 template <bool KEEP>
 __device__ inline unsigned write_out8(float* h, float* kept, int k0, int R, float scale, float floor_b,
-                                      float T, const float* o8)
+                                      float T, float* o8)
 {
     float val[8];
     unsigned m8 = 0;
@@ -676,6 +676,8 @@ __device__ inline unsigned write_out8(float* h, float* kept, int k0, int R, floa
         for (int q = 0; q < 8; ++q)
             if (k0 + q < R) kept[k0 + q] = val[q];
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o8[q] = val[q];
     return m8;
 }
 
@@ -866,6 +868,140 @@ __device__ inline void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+}
+
+// The wave schedule's convolution runs in passes of 512 bins (8 per lane).
+constexpr int kWavePassBins = 512;
+constexpr int kWavePasses = kWaveMaxBins / kWavePassBins;
+
+// Lanes below this one with their bit set in m.
+__device__ inline int lanes_below(unsigned long long m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// 64-bit key of a bin of a run: the value's bits in an order-preserving form,
+// then the complement of the bin, so that the largest key is the run's
+// largest value at its smallest bin (its first maximum).
+__device__ inline unsigned long long peak_key(float v, int k)
+{
+    const unsigned u = __float_as_uint(v);
+    const unsigned o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return (unsigned long long)o << 32 | (0xffffffffu - (unsigned)k);
+}
+
+__device__ inline float peak_value(unsigned long long key)
+{
+    const unsigned o = (unsigned)(key >> 32);
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+// Echoes of the first runs of one waveform by one wave, for LIDAR_ECHO_ALL
+// (the first E runs) and LIDAR_ECHO_NEAREST (the first run), found pass by
+// pass as the convolution's outputs are written (runs_pass), then written out
+// (runs_finish).  Bit q of lane l's above-threshold mask m8 in pass ps is bin
+// ps * kWavePassBins + 8 l + q.  Run starts and ends come from the bits and
+// a neighbour ballot (a run reaching the pass's last bin ends there until a
+// later pass continues it and overwrites its end), a run's index from the
+// starts before it (per-lane counts and a wave prefix), and each wanted run's
+// first maximum from one 64-bit LDS max per bin (peak_key) into rk; rb
+// receives its first and last bin.  Every run is counted.  The echoes, count
+// and floor are those detect_echoes writes for the same waveform (section
+// II-C, EPW paragraph).
+struct RunScan {
+    int want;           // runs that give echoes
+    int base;           // runs started in earlier passes (uniform)
+    unsigned carry;     // the bin before this pass is above T (uniform)
+};
+
+__device__ inline void runs_pass(RunScan& rs, int ps, unsigned m, const float* val, int lane,
+                                 unsigned long long* rk, int2* rb)
+{
+    const unsigned long long b7 = __ballot((m >> 7) & 1u), b0 = __ballot(m & 1u);
+    const unsigned prev = ((unsigned)((b7 << 1) >> lane) & 1u) | (lane == 0 ? rs.carry : 0u);
+    const unsigned nxt = (unsigned)((b0 >> 1) >> lane) & 1u;
+    const unsigned st = m & ~((m << 1) | prev);
+    const unsigned en = m & ~((m >> 1) | (nxt << 7));
+    const int ns = __popc(st);                           // at most 4
+    const unsigned long long c0 = __ballot(ns & 1), c1 = __ballot(ns & 2), c2 = __ballot(ns & 4);
+    // uniform: a wanted run starts here or continues from the last pass
+    if (rs.base - (int)rs.carry < rs.want) {
+        // bins before this lane's first start continue the previous run
+        int id = rs.base + lanes_below(c0) + 2 * lanes_below(c1) + 4 * lanes_below(c2) - 1;
+        // the lane's first bin, opaque to the optimiser: the keys' bin words
+        // depend only on the lane, and hoisted out of the beam loop they
+        // would hold 8 registers per pass for the kernel's lifetime
+        int k8 = ps * kWavePassBins + lane * 8;
+        asm volatile("" : "+v"(k8));
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            id += (st >> q) & 1u;
+            if (((m >> q) & 1u) && id < rs.want) {
+                const int k = k8 + q;
+                atomicMax(rk + id, peak_key(val[q], k));
+                if ((st >> q) & 1u) rb[id].x = k;
+                if ((en >> q) & 1u) rb[id].y = k;
+            }
+        }
+    }
+    rs.base += __popcll(c0) + 2 * __popcll(c1) + 4 * __popcll(c2);
+    rs.carry = (unsigned)(b7 >> 63);
+}
+
+// After every pass and a wave_sync: the echoes of the first runs from rk, rb
+// and the crossings' bins in xh (xi_hat in LDS), the count, the floor.
+__device__ inline void runs_finish(const RunScan& rs, const FrameDev& f, const PathDev& p, int beam,
+                                   const float* xh, float floor_b, int lane, const unsigned long long* rk,
+                                   const int2* rb)
+{
+    const int R = p.R;
+    const float T = p.threshold;
+    const int count = rs.base;
+    const int nrun = min(count, rs.want);
+    lidar_echo* out = f.echoes + (size_t)beam * p.E;
+    if (lane < nrun) {
+        const unsigned long long key = rk[lane];
+        const int2 kk = rb[lane];
+        const int k0 = kk.x, k1 = kk.y;
+        const int bk = (int)(0xffffffffu - (unsigned)key);
+        const float best = peak_value(key);
+        const float dt = (float)p.bin_ns;
+        // threshold crossings between bin centres, as fractions of a bin
+        // from the centre of the bin before the run and from the centre of
+        // its last bin
+        float f_up, f_dn;
+        uint32_t flags = 0;
+        if (k0 == 0) {
+            f_up = 0.5f;
+            flags |= LIDAR_ECHO_AT_FIRST_BIN;
+        } else {
+            const float xa = xh[k0 - 1], xb = xh[k0];
+            f_up = (T - xa) / (xb - xa);
+        }
+        if (k1 == R - 1) {
+            f_dn = 0.5f;
+            flags |= LIDAR_ECHO_AT_LAST_BIN;
+        } else {
+            const float xa = xh[k1], xb = xh[k1 + 1];
+            f_dn = (xa - T) / (xa - xb);
+        }
+        lidar_echo e;
+        e.range_m = ((double)bk + 0.5) * p.half_c_dt;
+        e.time_ns = ((double)bk + 0.5) * p.bin_ns;
+        e.intensity = best - floor_b;
+        e.pulse_width_ns = ((float)(k1 - k0 + 1) + f_dn - f_up) * dt;
+        e.bin_peak = bk;
+        e.bin_first = k0;
+        e.bin_last = k1;
+        e.flags = flags;
+        out[lane] = e;
+    }
+    if (lane == 0) {
+        f.counts[beam] = count;
+        f.beams[beam].floor = floor_b;
+    }
+    const lidar_echo z = {};
+    for (int i = nrun + lane; i < p.E; i += 64) out[i] = z;
 }
 
 // One wave turns a fixed-point histogram of n integers into FP32 bins in
@@ -1102,7 +1238,7 @@ __device__ __attribute__((always_inline)) inline int2 process_group(const FrameD
     // xi_hat of pass ps for beam g in place (after every read of it), the
     // kept waveform and the chunks above the threshold (this wave's 512 bins
     // are chunks 8 * wave .. 8 * wave + 7 of the pass)
-    auto write_pass = [&](int g, int ps, const float* o8) {
+    auto write_pass = [&](int g, int ps, float* o8) {
         if (ps * kPass >= R) return;                     // uniform
         const unsigned m8 = write_out8<KEEP>(hist + g * RS, KEEP ? f.waves + (size_t)beam[g] * R : nullptr,
                                              ps * kPass + tid * 8, R, scale[g], floor_b[g], T, o8);
@@ -1144,13 +1280,11 @@ __device__ __attribute__((always_inline)) inline int2 process_group(const FrameD
 // its histogram slot hist (zero padding around it) and its chunk flags nzw:
 // the steps of process_group with wave-local ordering only, the convolution in
 // NP passes of 512 bins (8 per lane; R <= kWavePassBins * NP).
-constexpr int kWavePassBins = 512;
-constexpr int kWavePasses = kWaveMaxBins / kWavePassBins;
 
 template <int NP, bool SUN, bool KEEP>
 __device__ __attribute__((always_inline)) inline int process_beam_wave(
     const FrameDev& f, const PathDev& p, int beam, float* hist, int RS, const float* taps, unsigned* nzw,
-    unsigned* am, int lane)
+    unsigned* am, int lane, unsigned long long* rk, int2* rb)
 {
     const int R = p.R;
     const int nzs = chunk_shift(R);
@@ -1225,6 +1359,10 @@ __device__ __attribute__((always_inline)) inline int process_beam_wave(
 #pragma unroll
     for (int ps = 0; ps < NP; ++ps)
         conv_out8(hist, taps, p, nb, ps * kWavePassBins + lane * 8, nzm, nzs, o[ps]);
+    // the first runs are found as the passes are written (ALL, NEAREST)
+    const bool first = p.select == LIDAR_ECHO_ALL || p.select == LIDAR_ECHO_NEAREST;
+    RunScan rs{p.select == LIDAR_ECHO_ALL ? p.E : 1, 0, 0u};
+    if (first && lane < rs.want) rk[lane] = 0ull;
     wave_sync();                                         // every read of the histogram is done
     unsigned word = 0;                                   // chunks above the threshold
 #pragma unroll
@@ -1233,7 +1371,13 @@ __device__ __attribute__((always_inline)) inline int process_beam_wave(
         const unsigned m8 = write_out8<KEEP>(hist, KEEP ? f.waves + (size_t)beam * R : nullptr,
                                              ps * kWavePassBins + lane * 8, R, scale, floor_b,
                                              p.threshold, o[ps]);
-        word |= bytes_any(__ballot(m8 != 0u)) << (8 * ps);
+        if (first) runs_pass(rs, ps, m8, o[ps], lane, rk, rb);
+        else word |= bytes_any(__ballot(m8 != 0u)) << (8 * ps);
+    }
+    if (first) {
+        wave_sync();
+        runs_finish(rs, f, p, beam, hist, floor_b, lane, rk, rb);
+        return fx;
     }
     if (lane == 0) am[0] = word;
     wave_sync();
@@ -1450,6 +1594,8 @@ void k_footprint_batch_wave(BatchArgs a)
     float* taps = (float*)lds4 + G * RS;
     __shared__ unsigned nzw[kWaves];
     __shared__ unsigned amask[kWaves][kMaxBins / kPassBins + 1];
+    __shared__ unsigned long long rkey[kWaves][kMaxEchoes];   // first runs: peak keys, bins
+    __shared__ int2 rbin[kWaves][kMaxEchoes];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     load_taps(taps, a.p.taps, a.p.J, tid);
@@ -1480,7 +1626,7 @@ void k_footprint_batch_wave(BatchArgs a)
                 if (lane == 0) nzw[wave] = 0u;
                 wave_sync();
                 const int fx = process_beam_wave<NP, SUN, KEEP>(f, a.p, beam, hist, RS, taps, &nzw[wave],
-                                                                amask[wave], lane);
+                                                                amask[wave], lane, rkey[wave], rbin[wave]);
                 if (lane == 0 && fx) {
                     fxn[wave][0] += 1;
                     fxn[wave][1] += fx >> 1;

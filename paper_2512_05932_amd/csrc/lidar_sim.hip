@@ -384,7 +384,10 @@ lidar_status check_params(const lidar_sim_params* p, std::string& why)
         why = "n_bins must be in [1, 8000]";
         return LIDAR_E_INVALID;
     }
-    if (p->max_echoes < 1 || p->max_echoes > 8) { why = "max_echoes must be in [1, 8]"; return LIDAR_E_INVALID; }
+    if (p->max_echoes < 1 || p->max_echoes > (uint32_t)kMaxEchoes) {
+        why = "max_echoes must be in [1, 8]";
+        return LIDAR_E_INVALID;
+    }
     if (!(p->bin_ns > 0.0) || !is_fin(p->bin_ns)) { why = "bin_ns must be > 0"; return LIDAR_E_INVALID; }
     if (!is_fin(p->threshold)) { why = "threshold must be finite"; return LIDAR_E_INVALID; }
     if (!(p->emit_power >= 0.0) || !is_fin(p->emit_power)) { why = "emit_power must be >= 0"; return LIDAR_E_INVALID; }

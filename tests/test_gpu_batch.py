@@ -169,6 +169,61 @@ def test_batch_fixed_point_accumulation(oracle_mod):
         sim.close()
 
 
+@pytest.mark.parametrize("select,n_echoes,n_bins,t_scale", [
+    (scenes.ECHO_SELECT_ALL, 1, 2048, 1.0),
+    (scenes.ECHO_SELECT_ALL, 8, 2048, 1.0),
+    (scenes.ECHO_SELECT_NEAREST, 3, 2048, 1.0),
+    (scenes.ECHO_SELECT_STRONGEST, 3, 2048, 1.0),
+    (scenes.ECHO_SELECT_LONGEST, 2, 2048, 1.0),
+    (scenes.ECHO_SELECT_ALL, 3, 2048, 0.0),
+    (scenes.ECHO_SELECT_ALL, 3, 700, 1.0),
+])
+def test_batch_wave_schedule_echo_modes(oracle_mod, select, n_echoes, n_bins, t_scale):
+    """Echoes of the wave schedule (one beam per wave; the first runs of ALL
+    and NEAREST found from the passes' above-threshold bits as they are
+    written) for every selection on i.i.d. frames with ~10 runs per beam, a
+    threshold below the floor (one run over every bin, both edge flags) and a
+    waveform whose last pass is partial (700 bins); every beam against the
+    oracle."""
+    import torch
+    import paper_2512_05932_amd as lidar
+    from .parity import compare_selection
+    params = replace(scenes.batch_params(), echo_select=select, max_echoes=n_echoes, n_bins=n_bins)
+    if t_scale == 0.0:
+        params = replace(params, threshold=0.5 * params.ambient_const)
+    frames = _wide_iid((16,), params)
+    bw = scenes.BatchWorkload("iid-1-echo-modes", frames, params)
+    planes = _upload(bw)
+    sim = lidar.LidarSim(params, stream=torch.cuda.current_stream(), keep_waveforms=True)
+    try:
+        batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
+                            [f.pattern for f in bw.frames])
+        sim.simulate_batch(batch)
+        info = sim.batch_info()
+        print(f"[batch] echo modes {select}/{n_echoes}/{n_bins}/{t_scale}: {info}", flush=True)
+        assert info["wave_items"] == info["n_items"] == 1000
+        got = sim.read_batch(0, waveforms=True)
+        ref = oracle_mod.simulate(frames[0].gbuffer, frames[0].pattern, params)
+        if select == scenes.ECHO_SELECT_ALL:
+            rep = compare(got, ref, params)
+        else:
+            rep = compare_selection(got, ref, params)
+        print(f"[batch] echo modes: {rep.echoes_compared} echoes compared, counts "
+              f"{int(ref.n_echoes.sum())}", flush=True)
+        # one echo per beam where a single run is selected or kept (beams
+        # with a bin within the tolerance of T are not compared)
+        single = select != scenes.ECHO_SELECT_ALL or n_echoes == 1
+        assert rep.echoes_compared > (200 if single else 500)
+        if t_scale == 0.0:
+            assert (got["n_echoes"] == 1).all()
+            flags = got["echoes"][:, 0]["flags"]
+            assert ((flags & 3) == 3).all()
+        elif select == scenes.ECHO_SELECT_ALL and n_bins == 2048:
+            assert (ref.n_echoes > n_echoes).sum() > 100
+    finally:
+        sim.close()
+
+
 def test_batch_fixed_point_run_sums_on_smooth_frames(oracle_mod):
     """A frame whose depth changes slowly along its rows (a tilted plane with
     a gentle ripple: about 0.16 bins per pixel) keeps summing runs of equal
