@@ -171,6 +171,33 @@ __device__ inline T load_uniform(const T* p)
     return __builtin_bit_cast(T, w);
 }
 
+// A generic pointer into device memory as a global-address-space pointer:
+// its accesses become global loads and stores.  Pointers read from a table
+// (a batch's frames) are generic, and flat accesses also count against the
+// LDS counter, so that every wait for a load would wait for the LDS
+// atomics too (and the reverse).
+// (The host pass, which only checks these functions, keeps generic pointers:
+// it has no assignment operators for objects in another address space.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+__device__ inline const __attribute__((address_space(1))) T* gptr(const T* p)
+{
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T* gptr(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+#else
+template <typename T>
+__device__ inline T* gptr(T* p)
+{
+    return p;
+}
+#endif
+
 // Sum of two registers' 32-lane halves: lanes 0-31 get a(l) + a(l + 32),
 // lanes 32-63 get b(l - 32) + b(l) (one v_permlane32_swap).
 __device__ inline float swap_sum32(float a, float b)
@@ -296,7 +323,7 @@ __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const
 template <typename T>
 __device__ inline T ld16(const char* base, unsigned byte_off)
 {
-    return *(const T*)(base + byte_off);
+    return *gptr((const T*)(base + byte_off));
 }
 
 // Time bin of one sample in LIDAR_RANGE_CORRECTED mode (FP64): the range on
@@ -369,7 +396,8 @@ __device__ __attribute__((always_inline)) inline void gather_group(
             const bool ok = rowok && have[g] && n >= -f.N && n <= f.N;
             // lanes with nothing to add read the zero guard row
             kvo[g] = (unsigned)(ok ? n + f.N : f.KH) * 16u;
-            const int2 rr = ok ? f.rowrange[n + f.N] : make_int2(INT_MAX, INT_MIN);
+            int2 rr = make_int2(INT_MAX, INT_MIN);
+            if (ok) rr = gptr(f.rowrange)[n + f.N];
             const int wlo = wave_min(rr.x), whi = wave_max(rr.y);
             // absolute columns where this beam can have K > 0 in the strip
             lo[g] = __builtin_amdgcn_readfirstlane(wlo == INT_MAX ? INT_MAX : wlo + ub[g]);
@@ -530,10 +558,14 @@ __device__ __attribute__((always_inline)) inline void gather_group(
         Loads A, B;
         if (niter > 0) fetch(0, A);
         for (int i = 0; i < niter; i += 2) {
-            if (i + 1 < niter) fetch(i + 1, B);
+            // EACH: the next batch is fetched unconditionally (past the
+            // strip it repeats the last batch, from the cache), so that the
+            // wait before a batch's adds does not also wait for the next
+            // batch's loads
+            if (EACH || i + 1 < niter) fetch(min(i + 1, niter - 1), B);
             process(A);
             if (i + 1 >= niter) break;
-            if (i + 2 < niter) fetch(i + 2, A);
+            if (EACH || i + 2 < niter) fetch(min(i + 2, niter - 1), A);
             process(B);
         }
         unsigned any = __builtin_bit_cast(unsigned, acc[0]);
@@ -674,7 +706,7 @@ __device__ inline unsigned write_out8(float* h, float* kept, int k0, int R, floa
     if (KEEP) {
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-            if (k0 + q < R) kept[k0 + q] = val[q];
+            if (k0 + q < R) gptr(kept)[k0 + q] = val[q];
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) o8[q] = val[q];
@@ -695,7 +727,7 @@ __device__ inline void detect_echoes(const FrameDev& f, const PathDev& p, int be
     const float T = p.threshold;
     const float dt = (float)p.bin_ns;
     const bool all = p.select == LIDAR_ECHO_ALL;
-    lidar_echo* out = f.echoes + (size_t)beam * p.E;
+    auto out = gptr(f.echoes + (size_t)beam * p.E);
     lidar_echo sel = {};                                 // selected run (lane 0)
     float sel_key = -INFINITY;
     int count = 0;
@@ -792,8 +824,8 @@ __device__ inline void detect_echoes(const FrameDev& f, const PathDev& p, int be
     }
     if (lane == 0) {
         if (!all && count > 0) out[0] = sel;
-        f.counts[beam] = count;
-        f.beams[beam].floor = floor_b;
+        gptr(f.counts)[beam] = count;
+        gptr(f.beams)[beam].floor = floor_b;
     }
     const lidar_echo z = {};
     const int written = all ? count : min(count, 1);
@@ -840,7 +872,7 @@ __device__ inline void detect_raw(const FrameDev& f, const PathDev& p, int beam,
         const float best = wave_maxf(lbest);
         if (best >= T) found = wave_min(lbest == best ? lk : INT_MAX);
     }
-    lidar_echo* out = f.echoes + (size_t)beam * p.E;
+    auto out = gptr(f.echoes + (size_t)beam * p.E);
     if (lane == 0) {
         if (found >= 0) {
             lidar_echo e;
@@ -852,13 +884,13 @@ __device__ inline void detect_raw(const FrameDev& f, const PathDev& p, int beam,
             e.flags = 0;
             out[0] = e;
         }
-        f.counts[beam] = found >= 0 ? 1 : 0;
-        f.beams[beam].floor = floor_b;
+        gptr(f.counts)[beam] = found >= 0 ? 1 : 0;
+        gptr(f.beams)[beam].floor = floor_b;
     }
     const lidar_echo z = {};
     for (int i = (found >= 0 ? 1 : 0) + lane; i < p.E; i += 64) out[i] = z;
     if (KEEP) {
-        float* w = f.waves + (size_t)beam * R;
+        auto w = gptr(f.waves + (size_t)beam * R);
         for (int k = lane; k < R; k += 64) w[k] = scale * h[k];
     }
 }
@@ -958,7 +990,7 @@ __device__ inline void runs_finish(const RunScan& rs, const FrameDev& f, const P
     const float T = p.threshold;
     const int count = rs.base;
     const int nrun = min(count, rs.want);
-    lidar_echo* out = f.echoes + (size_t)beam * p.E;
+    auto out = gptr(f.echoes + (size_t)beam * p.E);
     if (lane < nrun) {
         const unsigned long long key = rk[lane];
         const int2 kk = rb[lane];
@@ -997,8 +1029,8 @@ __device__ inline void runs_finish(const RunScan& rs, const FrameDev& f, const P
         out[lane] = e;
     }
     if (lane == 0) {
-        f.counts[beam] = count;
-        f.beams[beam].floor = floor_b;
+        gptr(f.counts)[beam] = count;
+        gptr(f.beams)[beam].floor = floor_b;
     }
     const lidar_echo z = {};
     for (int i = nrun + lane; i < p.E; i += 64) out[i] = z;
