@@ -307,11 +307,11 @@ __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const
         const float t = group_totals<G>(v);
         constexpr int span = 64 / G;
         if (lane % span == 0 && t != 0.0f) add_key<IACC>(hist + (lane / span) * stride, key, t, rng, ia);
-        nzb |= key_chunks(key, nzs, rng);
+        nzb |= key_chunks(key, nzs, IACC ? false : rng);   // fixed point: centre bins
         m &= ~same;
     }
     if ((m >> lane) & 1ull) {
-        nzb |= key_chunks(cur, nzs, rng);
+        nzb |= key_chunks(cur, nzs, IACC ? false : rng);
 #pragma unroll
         for (int g = 0; g < G; ++g)
             if (acc[g] != 0.0f) add_key<IACC>(hist + g * stride, cur, acc[g], rng, ia);
@@ -506,7 +506,7 @@ __device__ __attribute__((always_inline)) inline void gather_group(
                         const float t = kv[j][g] * sh[j];
                         if (t != 0.0f) {
                             add_key<true>(hist + g * stride, bin[j], t, rng, ia);
-                            nzb |= key_chunks(bin[j], nzs, rng);
+                            nzb |= key_chunks(bin[j], nzs, false);   // fixed point: centre bins
                         }
                         if (SUN) sacc[g] += kv[j][g] * sv[j];
                     }
