@@ -59,6 +59,8 @@ void k_range_stacking(RangeStackArgs a)
     __shared__ unsigned present[kMaxWords];
     __shared__ float stage[kStageRows][kTileC + 2 * kMaxHalf];
     __shared__ float colbuf[kTileR + 2 * kMaxHalf][kTileC];
+    __shared__ int rowany[kStageRows];                 // a staged row holds a pixel of the slice
+    __shared__ int rlo, rhi;                           // the slice's first and last window rows
     __shared__ int open_count;
     const int tid = threadIdx.x;
     const int u0 = blockIdx.x * kTileC, v0 = blockIdx.y * kTileR;
@@ -95,8 +97,14 @@ void k_range_stacking(RangeStackArgs a)
             const int s = w * 32 + __builtin_ctz(bits);
             bits &= bits - 1u;
             // rows with H: window rows v0 - N .. v0 + kTileR - 1 + N, eight at a time
+            if (tid == 0) {
+                rlo = INT_MAX;
+                rhi = -1;
+            }
             for (int r0 = 0; r0 < kTileR + 2 * N; r0 += kStageRows) {
                 const int scols = kTileC + 2 * M;
+                if (tid < kStageRows) rowany[tid] = 0;
+                __syncthreads();
                 for (int i = tid; i < kStageRows * scols; i += kThreads) {
                     const int rr = i / scols, cc = i % scols;
                     const int v = v0 - N + r0 + rr, u = u0 - M + cc;
@@ -106,15 +114,26 @@ void k_range_stacking(RangeStackArgs a)
                         if (rec.x == s) x = __int_as_float(rec.y);
                     }
                     stage[rr][cc] = x;
+                    if (x != 0.0f) rowany[rr] = 1;
                 }
                 __syncthreads();
+                // a slice usually holds a few of the window's rows: the
+                // correlation of an empty row is zero
                 if (r0 + srow < kTileR + 2 * N) {
                     float acc = 0.0f;
-                    for (int m = 0; m < KW; ++m) acc += hk[m] * stage[srow][scol + m];
+                    if (rowany[srow])
+                        for (int m = 0; m < KW; ++m) acc += hk[m] * stage[srow][scol + m];
                     colbuf[r0 + srow][scol] = acc;
+                }
+                if (tid < kStageRows && rowany[tid]) {
+                    atomicMin(&rlo, r0 + tid);
+                    atomicMax(&rhi, r0 + tid);
                 }
                 __syncthreads();
             }
+            // only the window rows rlo .. rhi hold the slice: the other
+            // terms of the column correlation are zero
+            const int wlo = rlo, whi = rhi;
             // columns with V at the tile's pixels; the first slice that
             // reaches rho_min is the pixel's nearest
             int closed = 0;
@@ -123,7 +142,8 @@ void k_range_stacking(RangeStackArgs a)
                 const int r = tr + k * (kTileR / 2);
                 if (!mine[k] || best[k] < a.R) continue;
                 float acc = 0.0f;
-                for (int n = 0; n < KH; ++n) acc += vk[n] * colbuf[r + n][tc];
+                const int n0 = max(0, wlo - r), n1 = min(KH - 1, whi - r);
+                for (int n = n0; n <= n1; ++n) acc += vk[n] * colbuf[r + n][tc];
                 if (acc >= a.rho_min) {
                     best[k] = s;
                     bval[k] = acc;
