@@ -1308,10 +1308,46 @@ __device__ __attribute__((always_inline)) inline int2 process_group(const FrameD
     return fxc;
 }
 
+// Whether pass ps (bins ps * kWavePassBins ..) of the wave schedule's
+// convolution reads no chunk the gather wrote (nzm): every output of it is
+// then zero (the union of conv_out8's per-lane chunk tests, widened).
+__device__ inline bool pass_quiet(unsigned nzm, int nzs, int ps, int J, int R)
+{
+    const int k0 = ps * kWavePassBins;
+    const int c0 = max(0, k0 - J) >> nzs, c1 = min(R - 1, k0 + kWavePassBins - 1 + J) >> nzs;
+    const unsigned span = c1 - c0 >= 31 ? ~0u : (2u << (c1 - c0)) - 1u;
+    return ((nzm >> c0) & span) == 0u;
+}
+
+// Zero what a beam of the wave schedule left in its histogram slot: the bins
+// of the passes in `dirty` and the first and last bins of the passes in
+// `edges` (process_beam_wave's return, bits 8 .. and 16 ..); the zero padding
+// around the bins is never written.
+template <int NP>
+__device__ inline void clear_passes(float* hist, int R, unsigned dirty, unsigned edges, int lane)
+{
+#pragma unroll
+    for (int ps = 0; ps < NP; ++ps) {
+        const int k0 = ps * kWavePassBins, k1 = min(R, k0 + kWavePassBins);
+        if ((dirty >> ps) & 1u)
+            for (int k = k0 + lane; k < k1; k += 64) hist[k] = 0.0f;
+        if (((edges >> ps) & 1u) && lane == 0) {
+            hist[k0] = 0.0f;
+            hist[k1 - 1] = 0.0f;
+        }
+    }
+}
+
 // One beam by one wave (the wave schedule of a batch), after the wave zeroed
 // its histogram slot hist (zero padding around it) and its chunk flags nzw:
 // the steps of process_group with wave-local ordering only, the convolution in
-// NP passes of 512 bins (8 per lane; R <= kWavePassBins * NP).
+// NP passes of 512 bins (8 per lane; R <= kWavePassBins * NP).  Returns the
+// fixed-point outcome (bit 0: fixed point, bit 1: run again in FP32) and what
+// the beam left in its slot for clear_passes: bit 8 + ps for a pass whose bins
+// were written, bit 16 + ps for a quiet pass of which only the first and last
+// bins were (ALL and NEAREST with the floor at or below T: such a pass is the
+// floor throughout, holds no run, and only its edge bins can be read, as the
+// crossings of runs in the neighbouring passes).
 
 template <int NP, bool SUN, bool KEEP>
 __device__ __attribute__((always_inline)) inline int process_beam_wave(
@@ -1382,9 +1418,10 @@ __device__ __attribute__((always_inline)) inline int process_beam_wave(
         }
     }
     const unsigned nzm = __builtin_amdgcn_readfirstlane(*nzw);
+    const unsigned all_passes = ((1u << ((R + kWavePassBins - 1) / kWavePassBins)) - 1u) << 8;
     if (p.select >= LIDAR_ECHO_RAW_STRONGEST) {
         detect_raw<KEEP>(f, p, beam, hist, nzm, nzs, scale, floor_b, lane);
-        return fx;
+        return fx | (int)all_passes;
     }
     const int nb = conv_taps(p.J) / 8;
     float o[NP][8];
@@ -1397,9 +1434,28 @@ __device__ __attribute__((always_inline)) inline int process_beam_wave(
     if (first && lane < rs.want) rk[lane] = 0ull;
     wave_sync();                                         // every read of the histogram is done
     unsigned word = 0;                                   // chunks above the threshold
+    unsigned slot = 0;                                   // what the beam leaves in its slot
+    const bool quiet_ok = first && !(floor_b > p.threshold);
 #pragma unroll
     for (int ps = 0; ps < NP; ++ps) {
         if (ps * kWavePassBins >= R) break;              // uniform
+        if (quiet_ok && pass_quiet(nzm, nzs, ps, p.J, R)) {
+            // xi_hat is the floor throughout: no run; the edge bins for the
+            // crossings of runs in the neighbouring passes
+            const int k0 = ps * kWavePassBins, k1 = min(R, k0 + kWavePassBins) - 1;
+            if (lane == 0) {
+                hist[k0] = floor_b;
+                hist[k1] = floor_b;
+            }
+            if (KEEP) {
+                auto w = gptr(f.waves + (size_t)beam * R);
+                for (int k = k0 + lane; k <= k1; k += 64) w[k] = floor_b;
+            }
+            rs.carry = 0u;
+            slot |= 1u << (16 + ps);
+            continue;
+        }
+        slot |= 1u << (8 + ps);
         const unsigned m8 = write_out8<KEEP>(hist, KEEP ? f.waves + (size_t)beam * R : nullptr,
                                              ps * kWavePassBins + lane * 8, R, scale, floor_b,
                                              p.threshold, o[ps]);
@@ -1409,12 +1465,12 @@ __device__ __attribute__((always_inline)) inline int process_beam_wave(
     if (first) {
         wave_sync();
         runs_finish(rs, f, p, beam, hist, floor_b, lane, rk, rb);
-        return fx;
+        return fx | (int)slot;
     }
     if (lane == 0) am[0] = word;
     wave_sync();
     detect_echoes(f, p, beam, hist, am, floor_b, lane);
-    return fx;
+    return fx | (int)slot;
 }
 
 }  // namespace
@@ -1640,6 +1696,7 @@ void k_footprint_batch_wave(BatchArgs a)
     // batch's counters when the wave exits
     __shared__ int fxn[kWaves][2];
     if (lane < 2) fxn[wave][lane] = 0;
+    int left = 0;                                        // what the last beam left in the slot
     for (;;) {
         int t = 0;
         if (lane == 0) t = next_ticket(a.next_item, qc, a.n_tickets);
@@ -1653,15 +1710,15 @@ void k_footprint_batch_wave(BatchArgs a)
             for (int m = 0; m < G; ++m) {
                 const int beam = load_uniform(a.groups + (size_t)it.y * G + m);
                 if (beam < 0) continue;                  // uniform
-                const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                for (int k = lane; k < RS / 4; k += 64) slot4[k] = z;
+                clear_passes<NP>(hist, a.p.R, (unsigned)left >> 8 & 0xffu, (unsigned)left >> 16 & 0xffu, lane);
                 if (lane == 0) nzw[wave] = 0u;
                 wave_sync();
                 const int fx = process_beam_wave<NP, SUN, KEEP>(f, a.p, beam, hist, RS, taps, &nzw[wave],
                                                                 amask[wave], lane, rkey[wave], rbin[wave]);
-                if (lane == 0 && fx) {
+                left = fx;
+                if (lane == 0 && (fx & 1)) {
                     fxn[wave][0] += 1;
-                    fxn[wave][1] += fx >> 1;
+                    fxn[wave][1] += (fx >> 1) & 1;
                 }
                 wave_sync();                             // the slot is reused
             }
