@@ -88,31 +88,45 @@ __global__ void k_kernel_blocks(KernelDev k, const double* K64, float* Kb)
 
 // Per kernel row: FP64 sum, max, first/last non-zero column offset, and the
 // prefix counts of non-zero cells (prefix[row][c] = non-zero cells in
-// columns [0, c) of the row).
-__global__ void k_kernel_rows(KernelDev k, const double* K64, double* rowsum, double* rowmax,
-                              int2* rowrange, int32_t* prefix)
+// columns [0, c) of the row).  A wave per row, lanes over the columns in
+// chunks of 64 (coalesced reads and writes; the counts from ballots); the
+// lanes' FP64 partial sums are added by lane shuffles.
+__global__ __launch_bounds__(256)
+void k_kernel_rows(KernelDev k, const double* K64, double* rowsum, double* rowmax,
+                   int2* rowrange, int32_t* prefix)
 {
-    int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= k.KH) return;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (row >= k.KH) return;                             // the whole wave
     const double* kr = K64 + (long)row * k.KW;
     int32_t* pr = prefix + (long)row * (k.KW + 1);
     double s = 0.0, mx = 0.0;
-    int lo = k.KW, hi = -1, cnt = 0;
-    pr[0] = 0;
-    for (int c = 0; c < k.KW; ++c) {
-        double v = kr[c];
+    int lo = INT_MAX, hi = -1, cnt = 0;
+    if (lane == 0) pr[0] = 0;
+    for (int c0 = 0; c0 < k.KW; c0 += 64) {
+        const int c = c0 + lane;
+        const double v = c < k.KW ? kr[c] : 0.0;
         s += v;
-        if (v > mx) mx = v;
-        if (v > 0.0) {
-            if (c < lo) lo = c;
-            hi = c;
-            ++cnt;
+        mx = fmax(mx, v);
+        const unsigned long long nz = __ballot(v > 0.0);
+        if (nz) {
+            lo = min(lo, c0 + __builtin_ctzll(nz));
+            hi = c0 + 63 - __builtin_clzll(nz);
         }
-        pr[c + 1] = cnt;
+        const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(nz >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((unsigned)nz, 0u));
+        if (c < k.KW) pr[c + 1] = cnt + below + (v > 0.0 ? 1 : 0);
+        cnt += __popcll(nz);
     }
-    rowsum[row] = s;
-    rowmax[row] = mx;
-    rowrange[row] = hi < 0 ? make_int2(INT_MAX, INT_MIN) : make_int2(lo - k.M, hi - k.M);
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off);
+        mx = fmax(mx, __shfl_xor(mx, off));
+    }
+    if (lane == 0) {
+        rowsum[row] = s;
+        rowmax[row] = mx;
+        rowrange[row] = hi < 0 ? make_int2(INT_MAX, INT_MIN) : make_int2(lo - k.M, hi - k.M);
+    }
 }
 
 // kinfo[0] = max K, kinfo[1] = sum K over the grid (one block).
@@ -210,22 +224,26 @@ __global__ void k_beam_corr(RasterDev r, const double* az, const double* el, int
     bcorr[b] = make_double4(cos(da), sin(da), cos(de), sin(de));
 }
 
-// Per beam (one wave per beam, lanes over the kernel rows): containing pixel
-// (floor rounding), FP64 normalisation over every kernel cell (on- and
-// off-image rows), scale S_b = P_e / N_b, and the number of non-zero kernel
-// cells inside the image.  Row solid angles come from the table omega (rows
-// om_v0 .. om_v0 + om_n - 1, the same FP64 values) and are computed directly
-// for beams beyond it.  The lanes' FP64 partial sums are added by lane
-// shuffles.
+// Per beam (kSetupLanes lanes per beam, each over every kSetupLanes-th kernel
+// row): containing pixel (floor rounding), FP64 normalisation over every
+// kernel cell (on- and off-image rows), scale S_b = P_e / N_b, and the number
+// of non-zero kernel cells inside the image.  Row solid angles come from the
+// table omega (rows om_v0 .. om_v0 + om_n - 1, the same FP64 values) and are
+// computed directly for beams beyond it; the lanes' partial sums are added by
+// lane shuffles.  A beam not clipped at the image's left or right edge takes
+// a row's whole count.
+constexpr int kSetupLanes = 8;
+
 __global__ __launch_bounds__(256)
 void k_beam_setup(RasterDev r, KernelDev k, const double* az, const double* el,
                   int B, const double* rowsum, const int32_t* prefix,
                   const double* omega, long om_v0, int om_n,
                   double emit_power, lidar_beam_info* beams)
 {
-    const int lane = threadIdx.x & 63;
-    const int b = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    if (b >= B) return;                              // the whole wave
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sub = t % kSetupLanes;
+    const int b = min(t / kSetupLanes, B - 1);           // the lanes past B repeat the last beam
+    const bool own = t / kSetupLanes < B;
     double fu = floor((az[b] - r.az_min) / r.dphi);
     double fv = floor((r.el_max - el[b]) / r.de);
     // beams far outside the image keep an empty footprint
@@ -234,34 +252,32 @@ void k_beam_setup(RasterDev r, KernelDev k, const double* az, const double* el,
     fv = fmin(fmax(fv, -lim), lim);
     const long ub = (long)fu, vb = (long)fv;
     const bool tab = vb - k.N >= om_v0 && vb + k.N < om_v0 + om_n;
-    double nb = 0.0;
-    for (int n = lane; n < k.KH; n += 64) {
-        const long v = vb - k.N + n;
-        nb += rowsum[n] * (tab ? omega[v - om_v0] : row_omega(r, v));
-    }
-    for (int off = 32; off > 0; off >>= 1) nb += __shfl_xor(nb, off);
-    uint32_t samples = 0;
     const long c_lo = (long)-k.M > -ub ? (long)-k.M : -ub;
     const long c_hi = (long)k.M < (long)r.W - 1 - ub ? (long)k.M : (long)r.W - 1 - ub;
-    if (c_lo <= c_hi) {
-        for (int n = lane; n < k.KH; n += 64) {
-            const long v = vb - k.N + n;
-            if (v < 0 || v >= r.H) continue;
+    const bool cols = c_lo <= c_hi, whole = c_lo == -k.M && c_hi == k.M;
+    double nb = 0.0;
+    uint32_t samples = 0;
+    for (int n = sub; n < k.KH; n += kSetupLanes) {
+        const long v = vb - k.N + n;
+        nb += rowsum[n] * (tab ? omega[v - om_v0] : row_omega(r, v));
+        if (cols && v >= 0 && v < r.H) {
             const int32_t* pr = prefix + (long)n * (k.KW + 1);
-            samples += (uint32_t)(pr[c_hi + k.M + 1] - pr[c_lo + k.M]);
+            samples += (uint32_t)(whole ? pr[k.KW] : pr[c_hi + k.M + 1] - pr[c_lo + k.M]);
         }
     }
-    for (int off = 32; off > 0; off >>= 1) samples += (uint32_t)__shfl_xor((int)samples, off);
-    if (lane == 0) {
-        lidar_beam_info bi;
-        bi.pixel_u = (int32_t)ub;
-        bi.pixel_v = (int32_t)vb;
-        bi.scale = (float)(emit_power / nb);
-        bi.floor = 0.0f;
-        bi.samples = samples;
-        bi.reserved = 0;
-        beams[b] = bi;
+    for (int off = kSetupLanes / 2; off > 0; off >>= 1) {
+        nb += __shfl_xor(nb, off);
+        samples += (uint32_t)__shfl_xor((int)samples, off);
     }
+    if (sub != 0 || !own) return;
+    lidar_beam_info bi;
+    bi.pixel_u = (int32_t)ub;
+    bi.pixel_v = (int32_t)vb;
+    bi.scale = (float)(emit_power / nb);
+    bi.floor = 0.0f;
+    bi.samples = samples;
+    bi.reserved = 0;
+    beams[b] = bi;
 }
 
 // Centred Gaussian pulse sampled at the bin pitch, unit sum (FP32).
@@ -301,7 +317,7 @@ hipError_t launch_kernel_blocks(hipStream_t s, KernelDev k, const double* K64, f
 hipError_t launch_kernel_rows(hipStream_t s, KernelDev k, const double* K64, double* rowsum,
                               double* rowmax, int2* rowrange, int32_t* prefix)
 {
-    hipLaunchKernelGGL(k_kernel_rows, dim3((k.KH + 63) / 64), dim3(64), 0, s, k, K64, rowsum,
+    hipLaunchKernelGGL(k_kernel_rows, dim3((k.KH + 3) / 4), dim3(256), 0, s, k, K64, rowsum,
                        rowmax, rowrange, prefix);
     return hipGetLastError();
 }
@@ -329,8 +345,9 @@ hipError_t launch_beam_setup(hipStream_t s, RasterDev r, KernelDev k, const doub
     const long v0 = -(long)k.KH;
     const int n = r.H + 2 * k.KH;
     hipLaunchKernelGGL(k_row_omega, dim3((n + 255) / 256), dim3(256), 0, s, r, v0, n, omega);
-    hipLaunchKernelGGL(k_beam_setup, dim3((B + 3) / 4), dim3(256), 0, s, r, k, az, el, B,
-                       rowsum, prefix, (const double*)omega, v0, n, emit_power, beams);
+    const long threads = (long)B * kSetupLanes;
+    hipLaunchKernelGGL(k_beam_setup, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, r, k, az, el,
+                       B, rowsum, prefix, (const double*)omega, v0, n, emit_power, beams);
     return hipGetLastError();
 }
 
