@@ -56,15 +56,19 @@ def _gauss(half, sigma, shift=0.0):
     return np.exp(-0.5 * ((x - shift) / sigma) ** 2).astype(np.float32)
 
 
-@pytest.mark.parametrize("seed,half", [(0, (4, 2)), (1, (9, 6)), (2, (0, 0))])
-def test_every_pixel_of_small_images(lidar, oracle_mod, seed, half):
+@pytest.mark.parametrize("seed,half,n_bins", [(0, (4, 2), 96), (1, (9, 6), 96), (2, (0, 0), 96),
+                                             (3, (127, 40), 4000)])
+def test_every_pixel_of_small_images(lidar, oracle_mod, seed, half, n_bins):
+    """Every pixel against Alg. 2.  The last case has the largest kernel
+    (wider and taller than the image) and 4000 bins, so the per-row slice
+    bitmaps do not fit the workgroup's LDS and every window row is staged."""
     rng = np.random.default_rng(seed)
     r = scenes.Raster(70, 37, -7.0, 7.0, -3.0, 4.4)
     gb = scenes.random_gbuffer(r, rng, depth_range=(3.0, 12.0), retro_frac=0.05)
     d = gb.depth.copy()
     d[rng.uniform(size=d.shape) < 0.1] = np.inf
     gb = scenes.GBuffer(r, d, gb.reflectance, gb.retro_gain, gb.normal)
-    p = scenes.SensorParams(n_bins=96, bin_ns=1.0, max_echoes=3, threshold=1e-6, emit_power=1.0,
+    p = scenes.SensorParams(n_bins=n_bins, bin_ns=1.0, max_echoes=3, threshold=1e-6, emit_power=1.0,
                             pulse_fwhm_ns=4.0)
     Hk = _gauss(half[0], max(half[0], 1) / 2.0, 0.4 * half[0])
     Vk = _gauss(half[1], max(half[1], 1) / 2.0, -0.5 * half[1])
