@@ -175,16 +175,18 @@ def test_batch_fixed_point_accumulation(oracle_mod):
     (scenes.ECHO_SELECT_NEAREST, 3, 2048, 1.0),
     (scenes.ECHO_SELECT_STRONGEST, 3, 2048, 1.0),
     (scenes.ECHO_SELECT_LONGEST, 2, 2048, 1.0),
+    (scenes.ECHO_SELECT_RAW_STRONGEST, 3, 2048, 1.0),
+    (scenes.ECHO_SELECT_RAW_NEAREST, 3, 2048, 1.0),
     (scenes.ECHO_SELECT_ALL, 3, 2048, 0.0),
     (scenes.ECHO_SELECT_ALL, 3, 700, 1.0),
 ])
 def test_batch_wave_schedule_echo_modes(oracle_mod, select, n_echoes, n_bins, t_scale):
     """Echoes of the wave schedule (one beam per wave; the first runs of ALL
     and NEAREST found from the passes' above-threshold bits as they are
-    written) for every selection on i.i.d. frames with ~10 runs per beam, a
-    threshold below the floor (one run over every bin, both edge flags) and a
-    waveform whose last pass is partial (700 bins); every beam against the
-    oracle."""
+    written) for every selection, the raw ones included, on i.i.d. frames with
+    ~10 runs per beam, a threshold below the floor (one run over every bin,
+    both edge flags) and a waveform whose last pass is partial (700 bins);
+    every beam against the oracle."""
     import torch
     import paper_2512_05932_amd as lidar
     from .parity import compare_selection
