@@ -176,9 +176,13 @@ __device__ inline T load_uniform(const T* p)
 // (a batch's frames) are generic, and flat accesses also count against the
 // LDS counter, so that every wait for a load would wait for the LDS
 // atomics too (and the reverse).
-// (The host pass, which only checks these functions, keeps generic pointers:
-// it has no assignment operators for objects in another address space.)
-#if defined(__HIP_DEVICE_COMPILE__)
+// (HIP's vector and record types have no constructor or assignment from an
+// object in another address space: vectors are read as builtin vectors and
+// converted, records are written field by field.)
+typedef int gint2 __attribute__((ext_vector_type(2)));
+typedef int gint4 __attribute__((ext_vector_type(4)));
+typedef float gfloat2 __attribute__((ext_vector_type(2)));
+typedef float gfloat4 __attribute__((ext_vector_type(4)));
 template <typename T>
 __device__ inline const __attribute__((address_space(1))) T* gptr(const T* p)
 {
@@ -190,13 +194,22 @@ __device__ inline __attribute__((address_space(1))) T* gptr(T* p)
 {
     return (__attribute__((address_space(1))) T*)p;
 }
-#else
-template <typename T>
-__device__ inline T* gptr(T* p)
+
+// An echo record stored field by field through a global-address-space
+// pointer (a global store: a flat one would also count against the LDS
+// counter, and the wave's next LDS wait would wait for it).
+__device__ inline void store_echo(lidar_echo* dst, const lidar_echo& e)
 {
-    return p;
+    auto o = gptr(dst);
+    o->range_m = e.range_m;
+    o->time_ns = e.time_ns;
+    o->intensity = e.intensity;
+    o->pulse_width_ns = e.pulse_width_ns;
+    o->bin_peak = e.bin_peak;
+    o->bin_first = e.bin_first;
+    o->bin_last = e.bin_last;
+    o->flags = e.flags;
 }
-#endif
 
 // Sum of two registers' 32-lane halves: lanes 0-31 get a(l) + a(l + 32),
 // lanes 32-63 get b(l - 32) + b(l) (one v_permlane32_swap).
@@ -323,7 +336,14 @@ __device__ inline void flush_runs(unsigned long long fm, bool fl, int cur, const
 template <typename T>
 __device__ inline T ld16(const char* base, unsigned byte_off)
 {
-    return *gptr((const T*)(base + byte_off));
+    if constexpr (std::is_same_v<T, int4>) {
+        const gint4 v = *gptr((const gint4*)(base + byte_off));
+        return make_int4(v.x, v.y, v.z, v.w);
+    } else {
+        static_assert(std::is_same_v<T, float4>, "16-byte int4 or float4");
+        const gfloat4 v = *gptr((const gfloat4*)(base + byte_off));
+        return make_float4(v.x, v.y, v.z, v.w);
+    }
 }
 
 // Time bin of one sample in LIDAR_RANGE_CORRECTED mode (FP64): the range on
@@ -397,7 +417,10 @@ __device__ __attribute__((always_inline)) inline void gather_group(
             // lanes with nothing to add read the zero guard row
             kvo[g] = (unsigned)(ok ? n + f.N : f.KH) * 16u;
             int2 rr = make_int2(INT_MAX, INT_MIN);
-            if (ok) rr = gptr(f.rowrange)[n + f.N];
+            if (ok) {
+                const gint2 t = *gptr((const gint2*)(f.rowrange + n + f.N));
+                rr = make_int2(t.x, t.y);
+            }
             const int wlo = wave_min(rr.x), whi = wave_max(rr.y);
             // absolute columns where this beam can have K > 0 in the strip
             lo[g] = __builtin_amdgcn_readfirstlane(wlo == INT_MAX ? INT_MAX : wlo + ub[g]);
@@ -599,16 +622,18 @@ __device__ inline void gather_direct(const FrameDev& f, int R, int ub, int vb, i
         const int dv = i / nc;
         const int v = r0 + dv, u = q0 + (i - dv * nc);
         const int c = u - ub + f.M, n = v - vb + f.N;          // kernel column and row
-        const float kv = f.Kb[(((size_t)(c >> 2) + kBlockPad) * khp + n) * 4 + (c & 3)];
+        const float kv = gptr(f.Kb)[(((size_t)(c >> 2) + kBlockPad) * khp + n) * 4 + (c & 3)];
         if (!(kv > 0.0f)) continue;
         const long px = (long)v * d.pitch + u;
-        const float dep = d.depth[px];
+        const float dep = gptr(d.depth)[px];
         if (!(dep > 0.0f && isfinite(dep))) continue;
         const double kb = floor((double)dep * f.to_bin);
         if (!(kb < (double)R)) continue;
-        const float4 rt = d.rowtab[v];
-        const float nx = d.nx[px], ny = d.ny[px], nz = d.nz[px], rho = d.refl[px];
-        const float sh = pixel_shade(rt, d.colcs[u], nx, ny, nz, rho, d.gain[px], dep);
+        const gfloat4 rt4 = *gptr((const gfloat4*)(d.rowtab + v));
+        const float4 rt = make_float4(rt4.x, rt4.y, rt4.z, rt4.w);
+        const float nx = gptr(d.nx)[px], ny = gptr(d.ny)[px], nz = gptr(d.nz)[px], rho = gptr(d.refl)[px];
+        const gfloat2 cs2 = *gptr((const gfloat2*)(d.colcs + u));
+        const float sh = pixel_shade(rt, make_float2(cs2.x, cs2.y), nx, ny, nz, rho, gptr(d.gain)[px], dep);
         const int bin = (int)kb;
         if (sh != 0.0f) {
             atomicAdd(hist + bin, kv * sh);
@@ -727,7 +752,7 @@ __device__ inline void detect_echoes(const FrameDev& f, const PathDev& p, int be
     const float T = p.threshold;
     const float dt = (float)p.bin_ns;
     const bool all = p.select == LIDAR_ECHO_ALL;
-    auto out = gptr(f.echoes + (size_t)beam * p.E);
+    lidar_echo* out = f.echoes + (size_t)beam * p.E;
     lidar_echo sel = {};                                 // selected run (lane 0)
     float sel_key = -INFINITY;
     int count = 0;
@@ -805,7 +830,7 @@ __device__ inline void detect_echoes(const FrameDev& f, const PathDev& p, int be
                     e.bin_last = k1;
                     e.flags = flags;
                     if (all) {
-                        out[count] = e;
+                        store_echo(out + count, e);
                     } else {
                         // strongest: largest peak; longest: widest pulse;
                         // nearest: the first run (the first wins every tie)
@@ -823,13 +848,13 @@ __device__ inline void detect_echoes(const FrameDev& f, const PathDev& p, int be
         }
     }
     if (lane == 0) {
-        if (!all && count > 0) out[0] = sel;
+        if (!all && count > 0) store_echo(out, sel);
         gptr(f.counts)[beam] = count;
         gptr(f.beams)[beam].floor = floor_b;
     }
     const lidar_echo z = {};
     const int written = all ? count : min(count, 1);
-    for (int i = written + lane; i < p.E; i += 64) out[i] = z;
+    for (int i = written + lane; i < p.E; i += 64) store_echo(out + i, z);
 }
 
 // Echo selection on the raw signal (no pulse post-processing): the bin of
@@ -872,7 +897,7 @@ __device__ inline void detect_raw(const FrameDev& f, const PathDev& p, int beam,
         const float best = wave_maxf(lbest);
         if (best >= T) found = wave_min(lbest == best ? lk : INT_MAX);
     }
-    auto out = gptr(f.echoes + (size_t)beam * p.E);
+    lidar_echo* out = f.echoes + (size_t)beam * p.E;
     if (lane == 0) {
         if (found >= 0) {
             lidar_echo e;
@@ -882,13 +907,13 @@ __device__ inline void detect_raw(const FrameDev& f, const PathDev& p, int beam,
             e.pulse_width_ns = 0.0f;
             e.bin_peak = e.bin_first = e.bin_last = found;
             e.flags = 0;
-            out[0] = e;
+            store_echo(out, e);
         }
         gptr(f.counts)[beam] = found >= 0 ? 1 : 0;
         gptr(f.beams)[beam].floor = floor_b;
     }
     const lidar_echo z = {};
-    for (int i = (found >= 0 ? 1 : 0) + lane; i < p.E; i += 64) out[i] = z;
+    for (int i = (found >= 0 ? 1 : 0) + lane; i < p.E; i += 64) store_echo(out + i, z);
     if (KEEP) {
         auto w = gptr(f.waves + (size_t)beam * R);
         for (int k = lane; k < R; k += 64) w[k] = scale * h[k];
@@ -990,7 +1015,7 @@ __device__ inline void runs_finish(const RunScan& rs, const FrameDev& f, const P
     const float T = p.threshold;
     const int count = rs.base;
     const int nrun = min(count, rs.want);
-    auto out = gptr(f.echoes + (size_t)beam * p.E);
+    lidar_echo* out = f.echoes + (size_t)beam * p.E;
     if (lane < nrun) {
         const unsigned long long key = rk[lane];
         const int2 kk = rb[lane];
@@ -1026,14 +1051,14 @@ __device__ inline void runs_finish(const RunScan& rs, const FrameDev& f, const P
         e.bin_first = k0;
         e.bin_last = k1;
         e.flags = flags;
-        out[lane] = e;
+        store_echo(out + lane, e);
     }
     if (lane == 0) {
         gptr(f.counts)[beam] = count;
         gptr(f.beams)[beam].floor = floor_b;
     }
     const lidar_echo z = {};
-    for (int i = nrun + lane; i < p.E; i += 64) out[i] = z;
+    for (int i = nrun + lane; i < p.E; i += 64) store_echo(out + i, z);
 }
 
 // One wave turns a fixed-point histogram of n integers into FP32 bins in
