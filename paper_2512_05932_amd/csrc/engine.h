@@ -99,6 +99,30 @@ struct RangeTables {
 hipError_t launch_range_tables(hipStream_t s, RasterDev r, double2* col, double2* row,
                                double2* col_edge, double2* row_edge);
 
+// A generic pointer into device memory as a global-address-space pointer:
+// its accesses become global loads and stores.  Pointers read from a table
+// (a batch's frames) are generic, and flat accesses also count against the
+// LDS counter, so that every wait for a load would wait for the LDS
+// atomics too (and the reverse).
+// (HIP's vector and record types have no constructor or assignment from an
+// object in another address space: vectors are read as builtin vectors and
+// converted, records are written field by field.)
+typedef int gint2 __attribute__((ext_vector_type(2)));
+typedef int gint4 __attribute__((ext_vector_type(4)));
+typedef float gfloat2 __attribute__((ext_vector_type(2)));
+typedef float gfloat4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ inline const __attribute__((address_space(1))) T* gptr(const T* p)
+{
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T* gptr(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // ---- per frame ----
 struct PrepassArgs {
     const float *depth, *refl, *gain, *nx, *ny, *nz;

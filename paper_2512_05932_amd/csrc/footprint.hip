@@ -171,30 +171,6 @@ __device__ inline T load_uniform(const T* p)
     return __builtin_bit_cast(T, w);
 }
 
-// A generic pointer into device memory as a global-address-space pointer:
-// its accesses become global loads and stores.  Pointers read from a table
-// (a batch's frames) are generic, and flat accesses also count against the
-// LDS counter, so that every wait for a load would wait for the LDS
-// atomics too (and the reverse).
-// (HIP's vector and record types have no constructor or assignment from an
-// object in another address space: vectors are read as builtin vectors and
-// converted, records are written field by field.)
-typedef int gint2 __attribute__((ext_vector_type(2)));
-typedef int gint4 __attribute__((ext_vector_type(4)));
-typedef float gfloat2 __attribute__((ext_vector_type(2)));
-typedef float gfloat4 __attribute__((ext_vector_type(4)));
-template <typename T>
-__device__ inline const __attribute__((address_space(1))) T* gptr(const T* p)
-{
-    return (const __attribute__((address_space(1))) T*)p;
-}
-
-template <typename T>
-__device__ inline __attribute__((address_space(1))) T* gptr(T* p)
-{
-    return (__attribute__((address_space(1))) T*)p;
-}
-
 // An echo record stored field by field through a global-address-space
 // pointer (a global store: a flat one would also count against the LDS
 // counter, and the wave's next LDS wait would wait for it).

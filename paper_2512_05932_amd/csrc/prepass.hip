@@ -74,18 +74,20 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0, int ti
         float4 r4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (u < a.W && v < a.H) {
             long px = (long)v * a.pitch + u;
-            float d = a.depth[px];
+            float d = gptr(a.depth)[px];
             if (d > 0.0f && isfinite(d)) {
-                float nx = a.nx[px], ny = a.ny[px], nz = a.nz[px];
+                float nx = gptr(a.nx)[px], ny = gptr(a.ny)[px], nz = gptr(a.nz)[px];
                 double kb = floor((double)d * a.to_bin), k1 = kb;
                 if (MODE == LIDAR_RANGE_INTERVAL)
                     pixel_interval(a, u, v, (double)d, (double)nx, (double)ny, (double)nz, &kb, &k1);
                 if (kb < (double)a.R) {
                     bin = (int)kb;
-                    const float2 cs = a.colcs[u];
-                    const float4 rt = a.rowtab[v];
-                    const float rho = a.refl[px];
-                    shade = pixel_shade(rt, cs, nx, ny, nz, rho, a.gain[px], d);
+                    const gfloat2 c2 = *gptr((const gfloat2*)(a.colcs + u));
+                    const gfloat4 rw = *gptr((const gfloat4*)(a.rowtab + v));
+                    const float2 cs = make_float2(c2.x, c2.y);
+                    const float4 rt = make_float4(rw.x, rw.y, rw.z, rw.w);
+                    const float rho = gptr(a.refl)[px];
+                    shade = pixel_shade(rt, cs, nx, ny, nz, rho, gptr(a.gain)[px], d);
                     if (MODE == LIDAR_RANGE_INTERVAL) {
                         // the interval's bins share the pixel's weight; bins
                         // past the last are dropped
@@ -151,7 +153,7 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0, int ti
                 st_hi = max(st_hi, tstat[2][i]);
                 cnt += tstat[3][i];
             }
-            reinterpret_cast<int4*>(a.stats)[tile] = make_int4(sb, st_lo, st_hi, cnt);
+            *gptr((gint4*)a.stats + tile) = gint4{sb, st_lo, st_hi, cnt};
         }
     }
     __syncthreads();
@@ -165,9 +167,13 @@ __device__ inline void prepass_tile(const PrepassArgs& a, int u0, int v0, int ti
         if (u < a.W4 && v < a.H) {
             const long o = (((long)(u >> 2) * a.H + v) << 2) + (u & 3);
             // columns past W (padding) were staged as sky above
-            a.pix[o] = trec[r][bi * 4 + j];
-            if (SUN) a.sun[o] = tsun[r][bi * 4 + j];
-            if (MODE == LIDAR_RANGE_CORRECTED) a.rec4[o] = tr4[r][bi * 4 + j];
+            const int2 rec = trec[r][bi * 4 + j];
+            *gptr((gint2*)(a.pix + o)) = gint2{rec.x, rec.y};
+            if (SUN) gptr(a.sun)[o] = tsun[r][bi * 4 + j];
+            if (MODE == LIDAR_RANGE_CORRECTED) {
+                const float4 q = tr4[r][bi * 4 + j];
+                *gptr((gfloat4*)(a.rec4 + o)) = gfloat4{q.x, q.y, q.z, q.w};
+            }
         }
     }
 }
