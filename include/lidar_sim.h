@@ -229,11 +229,12 @@ typedef struct {
     uint32_t fixed_point_redone;   /* of those, beams run again with FP32 atomics
                                       because the fixed-point truncation bound
                                       exceeded 1e-6 of their waveform's maximum */
-    uint32_t short_run_frames;     /* last run (synchronises): frames whose fixed-point
-                                      gathers add every sample on its own instead of
-                                      summing runs of equal bins, because more than half
-                                      of their valid pixels fall in another bin than
-                                      their left neighbour */
+    uint32_t short_run_frames;     /* last run (synchronises): frames flagged as short-run
+                                      because more than half of their valid pixels fall
+                                      in another bin than their left neighbour; on the
+                                      wave schedule their fixed-point gathers add every
+                                      sample on its own instead of summing runs of equal
+                                      bins (the group schedule keeps run sums) */
 } lidar_batch_info;
 
 /* Counters of a handle since create or the last reset_stats. */
