@@ -143,7 +143,8 @@ def _wide_iid(seeds, params):
 def test_batch_fixed_point_accumulation(oracle_mod):
     """Frames whose bins span at most half the waveform (i.i.d. depths of 5-60
     m in 2048 bins of 0.5 ns) accumulate their wave-schedule histograms in
-    64-bit fixed point; every beam against the oracle."""
+    64-bit fixed point; every beam against the oracle.  Integer additions do
+    not depend on their order, so two replays give the same bits."""
     import torch
     import paper_2512_05932_amd as lidar
     params = scenes.batch_params()
@@ -154,6 +155,7 @@ def test_batch_fixed_point_accumulation(oracle_mod):
     try:
         batch = lidar.Batch([(f.gbuffer.raster, p) for f, p in zip(bw.frames, planes)],
                             [f.pattern for f in bw.frames])
+        outs = []
         for rep in range(2):
             sim.simulate_batch(batch)
             info = sim.batch_info()
@@ -165,6 +167,10 @@ def test_batch_fixed_point_accumulation(oracle_mod):
             assert info["short_run_frames"] == 2
             reps = _check_all(sim, bw, params, oracle_mod, f"fixed-point replay {rep}")
             assert sum(r.echoes_compared for r in reps) > 1500
+            outs.append([sim.read_batch(i, waveforms=True) for i in range(len(bw.frames))])
+        for a, b in zip(*outs):
+            assert a["waveforms"].tobytes() == b["waveforms"].tobytes()
+            assert a["echoes"].tobytes() == b["echoes"].tobytes()
     finally:
         sim.close()
 
